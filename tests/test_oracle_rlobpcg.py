@@ -1,0 +1,210 @@
+"""Pins for oracle.rlobpcg: dense SVD on small inputs, planted spectra, the
+theory's inequalities (Fact prop:randomized_preconditioning, Fact
+prop:sketch_and_solve, eq:lobpcg_psd_compare, Thm. thm:rlobpcg_convergence),
+LOBPCG invariants and exact transformations of A."""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import rlobpcg, sparsestack
+from oracle.rlobpcg import default_tau
+from workloads import planted_numpy, spectrum_gap, spectrum_logspace_tail
+
+U = 2.0 ** -53
+
+
+def _sin_angle(Va, Vb):
+    """Largest principal angle sine between span(Va) and span(Vb)."""
+    Qa, _ = np.linalg.qr(Va)
+    Qb, _ = np.linalg.qr(Vb)
+    return float(np.linalg.norm(Qb - Qa @ (Qa.conj().T @ Qb), 2))
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    s = spectrum_logspace_tail(50, 1e-3, 1e-6)
+    A, V, s = planted_numpy(4000, 50, s, 1001)
+    return A, V, s
+
+
+def _dense(A):
+    _, sv, Vh = np.linalg.svd(A, full_matrices=False)
+    return sv, Vh.conj().T
+
+
+def test_default_tau_and_arguments():
+    assert default_tau(100) == 2.0 * 10.0 * 2.0 ** -52
+    A = np.zeros((10, 6))
+    for bad in (dict(k=0), dict(k=3, block=2), dict(k=3)):
+        with pytest.raises(ValueError):
+            rlobpcg(A, **bad)
+    with pytest.raises(ValueError):
+        rlobpcg(np.zeros((5, 6)), 1)
+
+
+def test_single_vector_vs_dense_svd_and_planted(cfg1):
+    A, Vp, s = cfg1
+    sv, Vd = _dense(A)
+    r = rlobpcg(A, 1, seed=2001)
+    assert r.status == 0
+    assert abs(r.sigma[0] - sv[-1]) <= 1e-12 * sv[0]
+    assert abs(r.sigma[0] - s[-1]) <= 1e-12 * sv[0]
+    assert _sin_angle(r.V, Vd[:, -1:]) <= 1e-10
+    # backward-stable floors the paper compares against (Sec. 4): RLOBPCG beats them
+    gap_abs = (sv[-2] - sv[-1]) / sv[0]
+    assert abs(r.sigma[0] - sv[-1]) / sv[-1] <= U * sv[0] / sv[-1]
+    assert _sin_angle(r.V, Vd[:, -1:]) <= U / gap_abs
+    # left vector: A v = sigma u with a unit u
+    assert np.linalg.norm(A @ r.V[:, 0] - r.sigma[0] * r.U[:, 0]) <= 1e-12 * sv[0]
+    assert abs(np.linalg.norm(r.U[:, 0]) - 1.0) < 1e-8
+
+
+@pytest.mark.parametrize("is_complex", [False, True])
+def test_block_vs_dense_svd(is_complex):
+    m, n, k = (3000, 60, 3) if not is_complex else (2000, 42, 2)
+    s = spectrum_gap(n, k, 1e-9, 10.0)
+    A, _, s = planted_numpy(m, n, s, 7 + is_complex, is_complex=is_complex)
+    sv, Vd = _dense(A)
+    r = rlobpcg(A, k, seed=3, max_iter=60)
+    assert np.all(np.diff(r.sigma) >= 0)
+    assert np.max(np.abs(r.sigma - sv[::-1][:k])) <= 1e-12 * sv[0]
+    assert _sin_angle(r.V, Vd[:, -k:]) <= 1e-10
+    res = A @ r.V - r.U * r.sigma[None, :]
+    assert np.linalg.norm(res, axis=0).max() <= 1e-12 * sv[0]
+
+
+def _eta_scale_free(A, d, zeta, seed):
+    """Distortion of S on range(A), after the best rescaling of S."""
+    Qa, _ = np.linalg.qr(A)
+    SQ = sparsestack.sketch(Qa, d, zeta, seed)
+    sv = np.linalg.svd(SQ, compute_uv=False)
+    c2 = 2.0 / (sv.max() ** 2 + sv.min() ** 2)          # best scale: 1-eta = c2 smin^2
+    return 1.0 - c2 * sv.min() ** 2, c2
+
+
+def test_randomized_preconditioning_and_sketch_and_solve_bounds():
+    """Fact prop:randomized_preconditioning: sigma(AP)^2 in [1/(1+eta), 1/(1-eta)];
+    Fact prop:sketch_and_solve: ||A v_0||^2 <= (1+eta)/(1-eta) sigma_min^2."""
+    m, n, d, zeta, seed = 6000, 40, 160, 8, 11
+    s = spectrum_gap(n, 1, 1e-8, 10.0)
+    A, _, s = planted_numpy(m, n, s, 5)
+    eta, c2 = _eta_scale_free(A, d, zeta, seed)
+    assert 0 < eta < 1
+    SA = sparsestack.sketch(A, d, zeta, seed) * math.sqrt(c2)
+    _, St, Vth = np.linalg.svd(SA, full_matrices=False)
+    P = Vth.T / St[None, :]
+    sap = np.linalg.svd(A @ P, compute_uv=False) ** 2
+    assert sap.min() >= 1 / (1 + eta) * (1 - 1e-6)
+    assert sap.max() <= 1 / (1 - eta) * (1 + 1e-6)
+    v0 = Vth.T[:, -1]
+    assert np.linalg.norm(A @ v0) ** 2 <= (1 + eta) / (1 - eta) * s[-1] ** 2 * (1 + 1e-6)
+
+
+def test_convergence_theorem_bound_single_vector():
+    """Thm. thm:rlobpcg_convergence: with eta < gap/(2+gap),
+    (||A v_k||^2 - sigma_n^2)/sigma_n^2 <= C gap q^{2k} (until the FP64 floor)."""
+    m, n, d, zeta, seed = 8000, 40, 160, 8, 17
+    s = spectrum_gap(n, 1, 1e-6, 10.0)
+    A, _, s = planted_numpy(m, n, s, 23)
+    eta, _ = _eta_scale_free(A, d, zeta, seed)
+    gap = (s[-2] ** 2 - s[-1] ** 2) / s[-1] ** 2
+    assert eta < gap / (2 + gap)
+    C = 2 * eta / ((1 - eta) * gap - 2 * eta)
+    q = eta + (1 - eta) / (1 + gap)
+    sv = np.linalg.svd(A, compute_uv=False)
+    r = rlobpcg(A, 1, d=d, zeta=zeta, seed=seed, rule="none", max_iter=25)
+    floor = 1e3 * U * sv[0] / sv[-1]
+    for kk, th in enumerate(r.theta_hist[1:], start=1):
+        rel = (th[0] ** 2 - sv[-1] ** 2) / sv[-1] ** 2
+        assert rel <= C * gap * q ** (2 * kk) + floor
+
+
+def test_lobpcg_step_beats_steepest_descent_and_invariants():
+    """eq:lobpcg_psd_compare: the minimiser over span{v_old, v, w} is at least as
+    good as over span{v, w}; T orthonormal; Ritz values monotone; Galerkin
+    V^* R ~ 0; maintained A_T equals A T up to rounding drift."""
+    m, n, k = 3000, 45, 2
+    s = spectrum_gap(n, k, 1e-7, 10.0)
+    A, _, s = planted_numpy(m, n, s, 41)
+    normA = s[0]
+    log = []
+
+    def cb(**kw):
+        log.append({key: np.array(v, copy=True) for key, v in kw.items() if key != "i"})
+
+    r = rlobpcg(A, k, seed=5, rule="none", max_iter=12, callback=cb)
+    prev = r.theta_hist[0]
+    for it, st in enumerate(log):
+        T, AT, C, V, AV, R = st["T"], st["AT"], st["C"], st["V"], st["AV"], st["R"]
+        b = V.shape[1]
+        t = T.shape[1]
+        assert np.linalg.norm(T.conj().T @ T - np.eye(t)) <= 1e-13
+        # PSD trial space: [V_i, W_i] = first b and last b columns of T
+        psd = np.hstack([AT[:, :b], AT[:, t - b:]])
+        psd_min = np.linalg.svd(psd, compute_uv=False)[::-1][:b]
+        theta = np.sort(r.theta_hist[it + 1])
+        assert np.all(theta <= psd_min * (1 + 1e-10) + 1e3 * U * normA)
+        assert np.all(theta <= np.sort(prev) * (1 + 1e-10) + 1e3 * U * normA)
+        prev = r.theta_hist[it + 1]
+        assert np.linalg.norm(V.conj().T @ R) <= 1e3 * U * np.linalg.norm(AT, 2) ** 2 * t
+        drift = np.linalg.norm(AT - A @ T, 2)
+        assert drift <= 50 * (it + 1) * U * normA * math.sqrt(n)
+
+
+def test_exact_transformations():
+    m, n = 3000, 40
+    s = spectrum_gap(n, 1, 1e-7, 10.0)
+    A, _, s = planted_numpy(m, n, s, 51)
+    base = rlobpcg(A, 1, seed=6)
+    # scaling A by c scales sigma by |c|, same V
+    sc = rlobpcg(-4.0 * A, 1, seed=6)
+    assert abs(sc.sigma[0] - 4.0 * base.sigma[0]) <= 1e-12 * 4.0 * s[0]
+    assert _sin_angle(sc.V, base.V) <= 1e-10
+    # a column permutation permutes V's rows
+    perm = np.random.default_rng(0).permutation(n)
+    pc = rlobpcg(A[:, perm], 1, seed=6)
+    assert abs(pc.sigma[0] - base.sigma[0]) <= 1e-12 * s[0]
+    assert _sin_angle(pc.V, base.V[perm]) <= 1e-10
+    # a real A passed as complex gives the same triplet
+    cc = rlobpcg(A.astype(np.complex128), 1, seed=6)
+    assert abs(cc.sigma[0] - base.sigma[0]) <= 1e-12 * s[0]
+    assert _sin_angle(cc.V, base.V.astype(np.complex128)) <= 1e-10
+    # a row permutation changes the sketch, not the answer
+    rp = rlobpcg(A[np.random.default_rng(1).permutation(m)], 1, seed=6)
+    assert abs(rp.sigma[0] - base.sigma[0]) <= 1e-12 * s[0]
+    assert _sin_angle(rp.V, base.V) <= 1e-10
+
+
+def test_qr_preconditioner_is_the_same_operator():
+    """P P^* from the SVD route equals (R^* R)^{-1} from the QR route
+    (Sec. 1, footnote), and both routes reach the same triplets."""
+    m, n, d = 2000, 30, 120
+    s = spectrum_gap(n, 2, 1e-5, 10.0)
+    A, _, s = planted_numpy(m, n, s, 61)
+    SA = sparsestack.sketch(A, d, 8, 4)
+    _, St, Vth = np.linalg.svd(SA, full_matrices=False)
+    P = Vth.T / St[None, :]
+    R = np.linalg.qr(SA, mode="r")
+    Rinv = np.linalg.inv(R)
+    M1, M2 = P @ P.T, Rinv @ Rinv.T
+    assert np.linalg.norm(M1 - M2) <= 1e-10 * np.linalg.norm(M1)
+    a = rlobpcg(A, 2, d=d, seed=4, precond="svd")
+    b = rlobpcg(A, 2, d=d, seed=4, precond="qr")
+    assert np.max(np.abs(a.sigma - b.sigma)) <= 1e-12 * s[0]
+    assert _sin_angle(a.V, b.V) <= 1e-10
+
+
+def test_block_of_one_equals_single_vector_start():
+    """With b = 1 the start is v_0 = V~(:, n) with theta_0 = inf (Alg. rlopcg);
+    the first iterate's theta equals the minimum over span{v_0, w_0}."""
+    m, n = 2000, 30
+    s = spectrum_gap(n, 1, 1e-6, 10.0)
+    A, _, s = planted_numpy(m, n, s, 71)
+    r = rlobpcg(A, 1, seed=2, rule="none", max_iter=3)
+    assert math.isinf(r.theta_hist[0][0])
+    SA = sparsestack.sketch(A, 4 * n, 8, 2)
+    v0 = np.linalg.svd(SA)[2][-1]
+    r0 = A.T @ (A @ v0) - np.linalg.norm(A @ v0) ** 2 * v0
+    assert abs(np.linalg.norm(r0) - r.rnorm_hist[0][0]) <= 1e-6 * np.linalg.norm(r0)
