@@ -11,12 +11,22 @@ Published algorithms, restated:
               the dot product computed as if in twice the working precision
               and rounded once; error <= u|x'y| + gamma_n^2 |x|'|y|.
 
+  Dot2 tree  The same transformations applied pairwise along the long axis
+              (TwoSum of pairs, errors carried and summed in working
+              precision): exact partial sums plus an error term, so the
+              result is again within u|x'y| + O(log2(n) u^2) |x|'|y|.  Used for
+              A^* Y, whose sums run over the m >> n rows.
+
 Why the oracle needs Dot2: on tall matrices whose smallest singular values sit
 far below ||A||, a plain FP64 product A*v is accurate only to about
 u*||row||*||v|| per entry, which is far above |(Av)_i|; that rounding noise
 alone moves the computed minimum singular vector by up to
-u*||A||_F / (sqrt(m) * sigma_{n-1}) (Sec. 4, accuracy floors).  Computing the
-products with A as Dot2 removes that floor on both the oracle and the GPU side.
+u*||A||_F / (sqrt(m) * sigma_{n-1}) (Sec. 4, accuracy floors).  The residual
+A^*(A v) - theta^2 v of the search direction has the same problem: computed
+with a plain A^*, its rounding floor keeps two otherwise identical runs (two
+sketch seeds) about 2e-9 apart in angle on a 6e4 x 200 matrix with
+sigma_{n-1}/sigma_n = 10 and sigma_n = 1e-12, and about 6e-16 apart when A^* is
+applied as Dot2 as well.
 """
 
 from __future__ import annotations
@@ -112,4 +122,57 @@ def matmul(A, W, row_chunk: int = 16384) -> np.ndarray:
             XT = np.ascontiguousarray(np.asarray(blk, dtype=np.float64).T)
             for j in range(b):
                 out[r0:r0 + blk.shape[0], j] = _dot2_rows(XT, W[:, j].astype(np.float64))
+    return out[:, 0] if vec else out
+
+
+def _tree_sum(P: np.ndarray, E: np.ndarray):
+    """Sum P + E along axis 0: TwoSum on pairs, errors carried in E (exact in P)."""
+    while P.shape[0] > 1:
+        if P.shape[0] % 2:
+            P = np.concatenate([P, np.zeros_like(P[:1])], axis=0)
+            E = np.concatenate([E, np.zeros_like(E[:1])], axis=0)
+        s, t = two_sum(P[0::2], P[1::2])
+        E = (E[0::2] + E[1::2]) + t
+        P = s
+    return P[0], E[0]
+
+
+def _dot2_cols(X: np.ndarray, y: np.ndarray, row_chunk: int):
+    """sum_r X[r, c] * y[r] for every column c, Dot2-class (real X, y)."""
+    n = X.shape[1]
+    acc_s = np.zeros(n)
+    acc_e = np.zeros(n)
+    for r0 in range(0, X.shape[0], row_chunk):
+        blk = X[r0:r0 + row_chunk]
+        yb = y[r0:r0 + row_chunk][:, None]
+        P, E = two_prod(blk, yb)
+        ps, pe = _tree_sum(P, E)
+        acc_s, t = two_sum(acc_s, ps)
+        acc_e = acc_e + pe + t
+    return acc_s + acc_e
+
+
+def matmul_h(A, Y, row_chunk: int = 8192) -> np.ndarray:
+    """A^* @ Y (A m x n, Y m x b) with every entry Dot2-class accurate."""
+    A = np.asarray(A)
+    Y = np.asarray(Y)
+    vec = Y.ndim == 1
+    if vec:
+        Y = Y[:, None]
+    n, b = A.shape[1], Y.shape[1]
+    cplx = np.iscomplexobj(A) or np.iscomplexobj(Y)
+    out = np.empty((n, b), dtype=np.complex128 if cplx else np.float64)
+    if cplx:
+        A = np.asarray(A, dtype=np.complex128)
+        # conj(a) y: Re = [ar; ai] . [yr; yi], Im = [ar; -ai] . [yi; yr] (sums over 2m terms)
+        Xs = np.concatenate([A.real, A.imag], axis=0)
+        Xt = np.concatenate([A.real, -A.imag], axis=0)
+        for j in range(b):
+            y = Y[:, j].astype(np.complex128)
+            re = _dot2_cols(Xs, np.concatenate([y.real, y.imag]), row_chunk)
+            im = _dot2_cols(Xt, np.concatenate([y.imag, y.real]), row_chunk)
+            out[:, j] = re + 1j * im
+    else:
+        for j in range(b):
+            out[:, j] = _dot2_cols(np.asarray(A, dtype=np.float64), Y[:, j].astype(np.float64), row_chunk)
     return out[:, 0] if vec else out

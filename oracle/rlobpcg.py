@@ -33,8 +33,10 @@ Readings where the paper is silent (each listed in the design doc):
   * ``precond="qr"`` uses R from S A = Q R with P = R^{-1}; P P^* = (R^* R)^{-1}
     = ((S A)^* S A)^{-1} = V~ Sigma~^{-2} V~^*, the same operator as the SVD
     route (Sec. 1, footnote on QR), with V_0 taken from the SVD of R.
-  * ``dot2=True`` computes every product with A (A V_0, A W, the refresh) as
-    Dot2 (``oracle.eft``); products with A^* stay plain FP64.
+  * ``dot2=True`` computes every product with A (A V_0, A W, the refresh) and
+    the residual's A^* A_V as Dot2-class sums (``oracle.eft``); without it the
+    FP64 rounding floor of those products, not the iteration, limits the
+    attainable angle on strongly graded spectra (Sec. 4, accuracy floors).
 """
 
 from __future__ import annotations
@@ -112,7 +114,7 @@ def rlobpcg(A, k: int, *, block: int | None = None, d: int | None = None,
         return eft.matmul(A, M) if dot2 else A @ M
 
     def mulAh(M):
-        return _ct(A) @ M
+        return eft.matmul_h(A, M) if dot2 else _ct(A) @ M
 
     # Steps 1-2: embedding, sketch, factorisation.
     SA = sparsestack.sketch(A, d, zeta, seed)

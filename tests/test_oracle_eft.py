@@ -77,3 +77,46 @@ def test_matmul_real_and_complex_match_scalar_dot2_and_exact():
             assert abs(Fraction(float(gc[i, j].imag)) - im) <= Fraction(U * abs(float(im)) + 2 * g * g * scale_i)
     v = eft.matmul(A, W[:, 0])
     assert v.shape == (70,) and np.array_equal(v, got[:, 0])
+
+
+def test_matmul_h_tree_dot2_against_exact():
+    """A^* Y summed over the long axis with the pairwise TwoSum tree."""
+    rng = np.random.default_rng(4)
+    m, n = 3001, 7
+    A = rng.standard_normal((m, n)) * 2.0 ** rng.integers(-30, 30, (m, n))
+    y = rng.standard_normal(m)
+    half = m // 2
+    A[half:2 * half] = -A[:half]
+    y[half:2 * half] = y[:half] * (1 + rng.standard_normal(half) * 2.0 ** -45)
+    got = eft.matmul_h(A, y, row_chunk=500)
+    g = 2 * np.log2(m) * U
+    for c in range(n):
+        exact = sum(Fraction(float(a)) * Fraction(float(b)) for a, b in zip(A[:, c], y))
+        bound = U * abs(float(exact)) + g * g * float(np.sum(np.abs(A[:, c] * y)))
+        assert abs(Fraction(float(got[c])) - exact) <= Fraction(bound)
+    # plain summation misses that bound on these inputs
+    plain = A.T @ y
+    misses = sum(abs(Fraction(float(plain[c])) - sum(Fraction(float(a)) * Fraction(float(b))
+                                                    for a, b in zip(A[:, c], y))) >
+                 Fraction(U * 1e-3 * float(np.sum(np.abs(A[:, c] * y)))) for c in range(n))
+    assert misses >= 1
+
+
+def test_matmul_h_complex_against_exact():
+    rng = np.random.default_rng(6)
+    m, n = 257, 3
+    A = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    Y = rng.standard_normal((m, 2)) + 1j * rng.standard_normal((m, 2))
+    got = eft.matmul_h(A, Y, row_chunk=64)
+    for c in range(n):
+        for j in range(2):
+            a, y = A[:, c], Y[:, j]
+            re = sum(Fraction(float(p.real)) * Fraction(float(q.real)) + Fraction(float(p.imag)) * Fraction(float(q.imag))
+                     for p, q in zip(a, y))
+            im = sum(Fraction(float(p.real)) * Fraction(float(q.imag)) - Fraction(float(p.imag)) * Fraction(float(q.real))
+                     for p, q in zip(a, y))
+            sc = float(np.sum(np.abs(a) * np.abs(y))) * 2
+            g = 2 * np.log2(2 * m) * U
+            assert abs(Fraction(float(got[c, j].real)) - re) <= Fraction(U * abs(float(re)) + g * g * sc)
+            assert abs(Fraction(float(got[c, j].imag)) - im) <= Fraction(U * abs(float(im)) + g * g * sc)
+    assert np.allclose(got, A.conj().T @ Y, rtol=1e-12, atol=1e-12)
