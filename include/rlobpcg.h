@@ -1,0 +1,146 @@
+/* rlobpcg.h -- C-ABI of the MI355X (gfx950) RLOBPCG library.
+ *
+ * RLOBPCG (Epperly, Park, Nakatsukasa, "Fast, high-accuracy, randomized
+ * nullspace computations for tall matrices") returns a few of the smallest
+ * singular triplets of a tall A in C^{m x n}, m >> n (Sec. 1): a SparseStack
+ * sketch S*A (Sec. 2.2) gives a preconditioner P with P P^* = ((S A)^* S A)^{-1}
+ * and a sketch-and-solve start; LOBPCG on A^* A with that preconditioner then
+ * refines the block (Alg. rlopcg for b = 1, Alg. rlobpcg for b > 1) until the
+ * tolerance rule (eq:est_conv_criterion) and the stagnation checks
+ * (eq:stagnation-check) hold.
+ *
+ * Conventions for every call:
+ *   - Matrices are row-major.  A has leading dimension lda >= n (elements).
+ *     Complex data (the _z calls) are interleaved (re, im) doubles, the layout
+ *     of C99 double _Complex and of torch.complex128; sigma stays real.
+ *   - Pointers named "device" are HIP device pointers that the caller
+ *     allocated and owns; the library never frees or retains them past the
+ *     call.  Pointers named "host" are ordinary host memory.
+ *   - Work is enqueued on the handle's stream.  A solve call returns after its
+ *     results are in the caller's buffers (it synchronises on its stream).
+ *   - Every call returns an int status; no exception crosses the ABI.
+ */
+#ifndef RLOBPCG_H
+#define RLOBPCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define RL_OK 0
+#define RL_NOT_CONVERGED 1    /* max_iter reached; outputs hold the last iterate (after the loop of Alg. rlopcg) */
+#define RL_ERR_ARG (-1)       /* k < 1, b < k, 3b > n, n > m, d < n, zeta < 1 or > d, bad lda/ldv/ldu, null pointer */
+#define RL_ERR_DEVICE (-2)    /* a HIP call failed */
+#define RL_ERR_NOMEM (-3)     /* device workspace allocation failed */
+#define RL_ERR_NONFINITE (-4) /* NaN/Inf in S*A or in R^{-1} (S*A numerically rank deficient) */
+#define RL_ERR_UNSUPPORTED (-7) /* a shape outside the compiled kernels (n > 1024 or b > 10) */
+
+/* Stopping rules (oracle.termination documents the same three). */
+#define RL_STOP_PAPER 0 /* at i = 0 mod check_every: tolerance and both stagnation checks, every column */
+#define RL_STOP_TOL 1   /* the tolerance alone, every iteration (Alg. rlobpcg as typeset) */
+#define RL_STOP_NONE 2  /* run max_iter iterations */
+
+typedef struct rl_ctx* rl_handle;
+
+/* Options.  rl_default_opts fills the paper's defaults. */
+typedef struct {
+  int64_t d;          /* sketch rows; default 4n (Alg. rlopcg uses 4n; Sec. 2.2 recommends 2n..4n) */
+  int32_t zeta;       /* nonzeros per column of S; default 8 */
+  int32_t block;      /* block size b >= k; default k */
+  uint64_t seed;      /* SparseStack counter seed */
+  double tau;         /* tolerance; default 2 sqrt(n) 2^-52 (Sec. 2.1) */
+  int32_t max_iter;   /* default 200 for b = 1, 100 for b > 1 (Alg. rlopcg, Alg. rlobpcg) */
+  int32_t check_every;/* stagnation-check cadence; default 5 (Alg. rlopcg) */
+  int32_t stop_rule;  /* RL_STOP_*; default RL_STOP_PAPER */
+  int32_t dot2;       /* 1: row products of A accumulated as Dot2 (real and complex); default 1 */
+  int32_t init_iters; /* inverse-subspace-iteration steps for the start block; default 10 */
+  int32_t lanczos_steps; /* Golub-Kahan steps for Sigma~(1,1); default min(n, 64) */
+  int32_t profile;    /* 1: time every A-stream launch with HIP events (rl_info.t_astream_us) */
+  int32_t reserved[5];
+} rl_opts;
+
+/* Per-solve report (host).  theta_hist / rnorm_hist are optional host arrays
+ * of hist_cap*b doubles that receive theta_j and ||r_j(:, c)|| for iterates
+ * j = 0 .. iters (row j, column c; theta_0 = +inf when b = 1). */
+typedef struct {
+  int32_t status;      /* RL_OK or RL_NOT_CONVERGED */
+  int32_t iters;       /* loop iterations executed */
+  int32_t a_passes;    /* full passes over A (sketch + start + one per iteration) */
+  int32_t degenerate;  /* a Normalize/Orth met a zero vector */
+  int32_t zero_theta;  /* some returned sigma is exactly 0 (its U column is 0) */
+  int32_t block;       /* b used */
+  double sigma1;       /* Sigma~(1,1) estimate used in the tolerance */
+  double t_setup_us;   /* sketch, QR, R^{-1}, Sigma~(1,1), start block, first Rayleigh-Ritz */
+  double t_iter_us;    /* the LOBPCG loop */
+  double t_final_us;   /* outputs */
+  int64_t bytes_a;     /* bytes of A read by the solve (a_passes * m * n * element size) */
+  int32_t hist_cap;    /* capacity (rows) of the history arrays below; 0 = none */
+  int32_t n_astream;   /* A-stream launches timed (opts.profile) */
+  double t_astream_us; /* summed duration of those launches */
+  double* theta_hist;  /* host, may be NULL */
+  double* rnorm_hist;  /* host, may be NULL */
+} rl_info;
+
+/* Handle: one per (device, stream).  stream may be NULL (the null stream). */
+int rl_create(rl_handle* h, int device, void* hip_stream);
+int rl_destroy(rl_handle h);
+int rl_set_stream(rl_handle h, void* hip_stream);
+
+/* Fill defaults for an m x n problem with k wanted triplets (host only). */
+int rl_default_opts(rl_opts* o, int64_t m, int64_t n, int32_t k);
+
+/* The k smallest singular triplets of A (Sec. 1, "a small number, say 1 to
+ * 10, of minimum singular vectors"; Alg. rlopcg / Alg. rlobpcg).
+ *   A      device, m x n, row-major, leading dimension lda
+ *   sigma  device, k doubles, ascending
+ *   V      device, n x k (ldv >= k): right singular vectors, column j <-> sigma[j]
+ *   U      device, m x k (ldu >= k) or NULL: U(:, j) = A V(:, j) / sigma[j]
+ *          from the final Rayleigh-Ritz basis
+ *   opts   host, may be NULL (defaults); info host, may be NULL
+ * Vectors are defined up to a unit phase per column, and inside a cluster of
+ * equal sigma only their span is defined. */
+int rl_svds_smallest_d(rl_handle h, int64_t m, int64_t n, const double* A, int64_t lda, int32_t k,
+                       const rl_opts* opts, double* sigma, double* V, int64_t ldv, double* U, int64_t ldu,
+                       rl_info* info);
+int rl_svds_smallest_z(rl_handle h, int64_t m, int64_t n, const double* A, int64_t lda, int32_t k,
+                       const rl_opts* opts, double* sigma, double* V, int64_t ldv, double* U, int64_t ldu,
+                       rl_info* info);
+
+/* ---- Step entry points: one step of the path, for checking it in isolation.
+ * is_complex selects real FP64 (0) or interleaved complex FP64 (1) data. */
+
+/* Y = S*A for the SparseStack S of (d, zeta, seed) (Sec. 2.2).
+ *   A device m x n (lda); Y device d x n row-major (ldy >= n). */
+int rl_step_sketch(rl_handle h, int is_complex, int64_t m, int64_t n, const double* A, int64_t lda, int64_t d,
+                   int32_t zeta, uint64_t seed, double* Y, int64_t ldy);
+
+/* R from the Householder QR of Y (d x n, row-major, ldy) and R^{-1}
+ * (Sec. 1 footnote: QR of the sketch).  R and Rinv are device n x n row-major
+ * (upper triangular; R has a real diagonal). */
+int rl_step_qr(rl_handle h, int is_complex, int64_t d, int64_t n, const double* Y, int64_t ldy, double* R,
+               double* Rinv);
+
+/* One pass over A (Alg. rlopcg, the product with the trial space, and the
+ * residual's A^*): AW = A W and G = A^* AW.  W device n x b, AW device m x b,
+ * G device n x b (all row-major, dense).  dot2 = 1 accumulates the row
+ * products of A W as Dot2 (real and imaginary parts separately). */
+int rl_step_astream(rl_handle h, int is_complex, int64_t m, int64_t n, const double* A, int64_t lda, int32_t b,
+                    const double* W, double* AW, double* G, int32_t dot2);
+
+/* Rayleigh-Ritz data of a tall m x t block P (row-major, dense, t <= 32):
+ * singular values (descending, device t doubles) and right singular vectors
+ * C (device t x t row-major, column j <-> sigma[j]) via TSQR + one-sided Jacobi
+ * (Alg. rlopcg, svd of A_T). */
+int rl_step_tall_svd(rl_handle h, int is_complex, int64_t m, int32_t t, const double* P, double* sigma, double* C);
+
+const char* rl_status_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RLOBPCG_H */

@@ -1,0 +1,331 @@
+"""Python binding of the gfx950 RLOBPCG library (argument marshalling only).
+
+Every computation runs in the HIP kernels of ``libpaper_2602_16797_amd.so``;
+this module only checks shapes, allocates the output tensors with torch on the
+caller's device and passes raw pointers and the current HIP stream through the
+C-ABI declared in ``include/rlobpcg.h``.  There is no CPU fallback: if the
+library is missing or no GPU is visible, every call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpaper_2602_16797_amd.so")
+
+RL_OK = 0
+RL_NOT_CONVERGED = 1
+RL_ERR_ARG = -1
+RL_ERR_DEVICE = -2
+RL_ERR_NOMEM = -3
+RL_ERR_NONFINITE = -4
+RL_ERR_UNSUPPORTED = -7
+STOP_RULES = {"paper": 0, "tol": 1, "none": 2}
+
+EXPORTED = (
+    "rl_create", "rl_destroy", "rl_set_stream", "rl_default_opts",
+    "rl_svds_smallest_d", "rl_svds_smallest_z",
+    "rl_step_sketch", "rl_step_qr", "rl_step_astream", "rl_step_tall_svd",
+    "rl_status_string",
+)
+
+
+class RlOpts(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int64),
+        ("zeta", ctypes.c_int32),
+        ("block", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("tau", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("check_every", ctypes.c_int32),
+        ("stop_rule", ctypes.c_int32),
+        ("dot2", ctypes.c_int32),
+        ("init_iters", ctypes.c_int32),
+        ("lanczos_steps", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
+    ]
+
+
+class RlInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("iters", ctypes.c_int32),
+        ("a_passes", ctypes.c_int32),
+        ("degenerate", ctypes.c_int32),
+        ("zero_theta", ctypes.c_int32),
+        ("block", ctypes.c_int32),
+        ("sigma1", ctypes.c_double),
+        ("t_setup_us", ctypes.c_double),
+        ("t_iter_us", ctypes.c_double),
+        ("t_final_us", ctypes.c_double),
+        ("bytes_a", ctypes.c_int64),
+        ("hist_cap", ctypes.c_int32),
+        ("n_astream", ctypes.c_int32),
+        ("t_astream_us", ctypes.c_double),
+        ("theta_hist", ctypes.POINTER(ctypes.c_double)),
+        ("rnorm_hist", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class RlError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__(f"{what}: {status_string(code)} ({code})")
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Load the built library (no GPU is touched)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run python -m paper_2602_16797_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I64, I32, U64, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
+    lib.rl_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, P]
+    lib.rl_destroy.argtypes = [P]
+    lib.rl_set_stream.argtypes = [P, P]
+    lib.rl_default_opts.argtypes = [ctypes.POINTER(RlOpts), I64, I64, I32]
+    for name in ("rl_svds_smallest_d", "rl_svds_smallest_z"):
+        getattr(lib, name).argtypes = [P, I64, I64, P, I64, I32, ctypes.POINTER(RlOpts), P, P, I64, P, I64,
+                                       ctypes.POINTER(RlInfo)]
+    lib.rl_step_sketch.argtypes = [P, ctypes.c_int, I64, I64, P, I64, I64, I32, U64, P, I64]
+    lib.rl_step_qr.argtypes = [P, ctypes.c_int, I64, I64, P, I64, P, P]
+    lib.rl_step_astream.argtypes = [P, ctypes.c_int, I64, I64, P, I64, I32, P, P, P, I32]
+    lib.rl_step_tall_svd.argtypes = [P, ctypes.c_int, I64, I32, P, P, P]
+    lib.rl_status_string.argtypes = [ctypes.c_int]
+    lib.rl_status_string.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name != "rl_status_string":
+            getattr(lib, name).restype = ctypes.c_int
+    _ = D
+    _lib = lib
+    return lib
+
+
+def status_string(code: int) -> str:
+    return load_library().rl_status_string(int(code)).decode()
+
+
+def default_opts(m: int, n: int, k: int) -> RlOpts:
+    o = RlOpts()
+    rc = load_library().rl_default_opts(ctypes.byref(o), m, n, k)
+    if rc != RL_OK:
+        raise RlError(rc, "rl_default_opts")
+    return o
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_2602_16797_amd needs a ROCm GPU: torch.cuda.is_available() is False")
+    return torch
+
+
+class Handle:
+    """One library handle on one device, bound to the current torch stream."""
+
+    def __init__(self, device: int = 0):
+        torch = _torch()
+        self.lib = load_library()
+        self.device = device
+        with torch.cuda.device(device):
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = ctypes.c_void_p()
+        rc = self.lib.rl_create(ctypes.byref(h), device, ctypes.c_void_p(stream))
+        if rc != RL_OK:
+            raise RlError(rc, "rl_create")
+        self.h = h
+
+    def sync_stream(self):
+        torch = _torch()
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self.lib.rl_set_stream(self.h, ctypes.c_void_p(s))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_handles: dict[int, Handle] = {}
+
+
+def handle(device: int = 0) -> Handle:
+    h = _handles.get(device)
+    if h is None or h.h is None:
+        h = Handle(device)
+        _handles[device] = h
+    h.sync_stream()
+    return h
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_matrix(A, torch):
+    if not A.is_cuda:
+        raise ValueError("A must be a device tensor")
+    if A.dim() != 2:
+        raise ValueError("A must be 2-D")
+    if A.dtype not in (torch.float64, torch.complex128):
+        raise ValueError("A must be float64 or complex128")
+    if A.stride(1) != 1:
+        raise ValueError("A must be row-major with unit column stride")
+
+
+@dataclass
+class SolveResult:
+    sigma: object
+    V: object
+    U: object
+    status: int
+    iters: int
+    a_passes: int
+    sigma1: float
+    degenerate: bool
+    zero_theta: bool
+    t_setup_us: float
+    t_iter_us: float
+    t_final_us: float
+    bytes_a: int
+    n_astream: int = 0
+    t_astream_us: float = 0.0
+    theta_hist: np.ndarray = field(default=None)
+    rnorm_hist: np.ndarray = field(default=None)
+
+
+def make_opts(m: int, n: int, k: int, *, block=None, d=None, zeta=None, seed=0, tau=None, max_iter=None,
+              check_every=None, rule="paper", dot2=None, init_iters=None, lanczos_steps=None,
+              profile=False) -> RlOpts:
+    o = default_opts(m, n, k if block is None else block)
+    o.block = k if block is None else block
+    if block is not None:
+        o.max_iter = 200 if block == 1 else 100
+    if d is not None:
+        o.d = d
+    if zeta is not None:
+        o.zeta = zeta
+    o.seed = seed
+    if tau is not None:
+        o.tau = tau
+    if max_iter is not None:
+        o.max_iter = max_iter
+    if check_every is not None:
+        o.check_every = check_every
+    o.stop_rule = STOP_RULES[rule]
+    if dot2 is not None:
+        o.dot2 = int(bool(dot2))
+    if init_iters is not None:
+        o.init_iters = init_iters
+    if lanczos_steps is not None:
+        o.lanczos_steps = lanczos_steps
+    o.profile = int(bool(profile))
+    return o
+
+
+def rl_svds_smallest(A, k: int, *, want_u: bool = True, history: bool = True, **kw) -> SolveResult:
+    """k smallest singular triplets of the device matrix A (C-ABI rl_svds_smallest_d/_z)."""
+    torch = _torch()
+    _check_matrix(A, torch)
+    m, n = A.shape
+    dev = A.device.index or 0
+    h = handle(dev)
+    o = make_opts(m, n, k, **kw)
+    cplx = A.dtype == torch.complex128
+    sigma = torch.empty(k, dtype=torch.float64, device=A.device)
+    V = torch.empty((n, k), dtype=A.dtype, device=A.device)
+    U = torch.empty((m, k), dtype=A.dtype, device=A.device) if want_u else None
+    info = RlInfo()
+    cap = o.max_iter + 1
+    th = np.full((cap, o.block), np.nan)
+    rn = np.full((cap, o.block), np.nan)
+    if history:
+        info.hist_cap = cap
+        info.theta_hist = th.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        info.rnorm_hist = rn.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    fn = h.lib.rl_svds_smallest_z if cplx else h.lib.rl_svds_smallest_d
+    rc = fn(h.h, m, n, _ptr(A), A.stride(0), k, ctypes.byref(o), _ptr(sigma), _ptr(V), k,
+            _ptr(U) if U is not None else None, k, ctypes.byref(info))
+    if rc not in (RL_OK, RL_NOT_CONVERGED):
+        raise RlError(rc, "rl_svds_smallest")
+    it = info.iters
+    return SolveResult(sigma=sigma, V=V, U=U, status=rc, iters=it, a_passes=info.a_passes, sigma1=info.sigma1,
+                       degenerate=bool(info.degenerate), zero_theta=bool(info.zero_theta),
+                       t_setup_us=info.t_setup_us, t_iter_us=info.t_iter_us, t_final_us=info.t_final_us,
+                       bytes_a=info.bytes_a, n_astream=info.n_astream, t_astream_us=info.t_astream_us,
+                       theta_hist=th[: it + 1].copy() if history else None,
+                       rnorm_hist=rn[: it + 1].copy() if history else None)
+
+
+def rl_step_sketch(A, d: int, zeta: int, seed: int):
+    torch = _torch()
+    _check_matrix(A, torch)
+    m, n = A.shape
+    h = handle(A.device.index or 0)
+    Y = torch.empty((d, n), dtype=A.dtype, device=A.device)
+    rc = h.lib.rl_step_sketch(h.h, int(A.is_complex()), m, n, _ptr(A), A.stride(0), d, zeta,
+                              ctypes.c_uint64(seed), _ptr(Y), n)
+    if rc != RL_OK:
+        raise RlError(rc, "rl_step_sketch")
+    return Y
+
+
+def rl_step_qr(Y):
+    torch = _torch()
+    _check_matrix(Y, torch)
+    d, n = Y.shape
+    h = handle(Y.device.index or 0)
+    R = torch.empty((n, n), dtype=Y.dtype, device=Y.device)
+    Rinv = torch.empty((n, n), dtype=Y.dtype, device=Y.device)
+    rc = h.lib.rl_step_qr(h.h, int(Y.is_complex()), d, n, _ptr(Y), Y.stride(0), _ptr(R), _ptr(Rinv))
+    if rc != RL_OK:
+        raise RlError(rc, "rl_step_qr")
+    return R, Rinv
+
+
+def rl_step_astream(A, W, dot2: bool = False):
+    torch = _torch()
+    _check_matrix(A, torch)
+    m, n = A.shape
+    W = W.contiguous()
+    b = W.shape[1]
+    h = handle(A.device.index or 0)
+    AW = torch.empty((m, b), dtype=A.dtype, device=A.device)
+    G = torch.empty((n, b), dtype=A.dtype, device=A.device)
+    rc = h.lib.rl_step_astream(h.h, int(A.is_complex()), m, n, _ptr(A), A.stride(0), b, _ptr(W), _ptr(AW),
+                               _ptr(G), int(bool(dot2)))
+    if rc != RL_OK:
+        raise RlError(rc, "rl_step_astream")
+    return AW, G
+
+
+def rl_step_tall_svd(P):
+    torch = _torch()
+    P = P.contiguous()
+    m, t = P.shape
+    h = handle(P.device.index or 0)
+    sigma = torch.empty(t, dtype=torch.float64, device=P.device)
+    C = torch.empty((t, t), dtype=P.dtype, device=P.device)
+    rc = h.lib.rl_step_tall_svd(h.h, int(P.is_complex()), m, t, _ptr(P), _ptr(sigma), _ptr(C))
+    if rc != RL_OK:
+        raise RlError(rc, "rl_step_tall_svd")
+    return sigma, C

@@ -1,0 +1,56 @@
+// Launchers of the HIP kernels (host side); one definition per .hip file.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace rl {
+
+// sketch.hip
+int sketch_plan_ct(int d, int64_t lds_budget);
+int64_t sketch_partial_doubles(int64_t m, int64_t ncols_d, int d, int64_t lds_budget, int* nchunk_out,
+                               int64_t* rows_out);
+hipError_t launch_sketch(hipStream_t st, const double* A, int64_t lda_d, int64_t m, int64_t ncols_d, int es, int d,
+                         int zeta, uint64_t seed, double scale, double* part, double* Ycol, Ctl* ctl,
+                         int64_t lds_budget);
+
+// qr.hip
+hipError_t launch_qr(hipStream_t st, bool cplx, void* Y, int d, int n, void* Tm, void* Rrow, void* RH, void* Rinv,
+                     void* RinvH);
+
+// astream.hip
+int astream_ns(int n);
+int64_t astream_blocks(int64_t m, int n, int B, int es_d);
+int64_t astream_part_doubles(int64_t m, int n, int B, int es_d);
+int64_t astream_tmp_doubles(int64_t m, int n, int B, int es_d);
+hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const void* A, int64_t lda, int64_t m, int n,
+                          const void* W, void* AW, const void* AVp, const void* AXp, int init, double* Gpart,
+                          double* tmp, double* G3, const Ctl* ctl);
+hipError_t launch_panel(hipStream_t st, bool cplx, void* AV, void* AX, const void* AW, int64_t m, int B,
+                        const void* CV, const void* CX, const Ctl* ctl);
+hipError_t launch_final_u(hipStream_t st, bool cplx, const void* AV, const void* AX, const void* AW, int64_t m, int B,
+                          int k, const void* CV, const double* thb, void* U, int64_t ldu, const Ctl* ctl);
+
+// tsqr.hip
+int64_t tsqr_groups(int64_t m, int t);
+hipError_t launch_tsqr(hipStream_t st, bool cplx, const void* P0, int b0, const void* P1, int b1, const void* P2,
+                       int b2, int64_t m, void* bufA, void* bufB, void** Rfinal, const Ctl* ctl, int check_done);
+
+// nside.hip
+hipError_t launch_trmv(hipStream_t st, bool cplx, int B, const void* M, int n, int lower, const void* X, void* Y,
+                       const Ctl* ctl, int check_done);
+hipError_t launch_orth(hipStream_t st, bool cplx, int n, int B, const void* V, const void* X, int project, int with_x,
+                       void* W, Ctl* ctl, int check_done);
+hipError_t launch_rr(hipStream_t st, bool cplx, int n, int B, int init_mode, int with_x, const void* Rt, void* V,
+                     void* X, const void* W, const void* G3, void* Vn, void* Rres, void* CV, void* CX, double* thb,
+                     double* ht, double* hr, Ctl* ctl);
+hipError_t launch_randblk(hipStream_t st, bool cplx, void* Wb, int64_t count, uint64_t seed);
+hipError_t launch_lanczos(hipStream_t st, bool cplx, int n, const void* Ycol, int ld, const void* Rrow, void* Ub,
+                          void* Vb, int KL, uint64_t seed, Ctl* ctl);
+hipError_t launch_final_n(hipStream_t st, bool cplx, int n, int B, int k, const void* V, const double* thb,
+                          double* sigma, void* Vout, int64_t ldv, Ctl* ctl);
+hipError_t launch_rt_svd(hipStream_t st, bool cplx, int t, const void* Rt, double* sigma, void* C);
+
+}  // namespace rl

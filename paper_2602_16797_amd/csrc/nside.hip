@@ -1,0 +1,777 @@
+// n-side steps of RLOBPCG: everything whose size is n x (a few b), run by one
+// or a few workgroups (latency-bound, not bandwidth-bound).
+//
+// k_trmv     Y = M X with M an n x n triangular matrix (row-major, upper or
+//            lower) and X an n x B block; the preconditioner application
+//            W = P (P^* R) of eq:search-direction is two of these with
+//            P = R^{-1} (upper) and P^* = R^{-*} (lower).
+// k_orth     BCGS2 of W against [V X] (two classical Gram-Schmidt passes,
+//            Alg. rlobpcg) followed by Orth(W) as column-wise CGS2 (b = 1:
+//            Normalize, Alg. rlopcg).
+// k_rr       Rayleigh-Ritz from R_T (the TSQR factor of A_T): one-sided Jacobi
+//            SVD of R_T gives Theta and C (descending, as MATLAB's svd); then
+//            V = T C(:, t-b+1:t), the residual R = G_T C(:, t-b+1:t) - V Theta_b^2
+//            with G_T = A^* [A_V A_X A_W] from the same iteration's A-stream
+//            pass (= A^* A_V(new) - V Theta^2), its column norms, the stopping
+//            rule (eq:est_conv_criterion and eq:stagnation-check), and
+//            Q = Orth(C(1:b, 1:t-b)^*), X = T C(:, 1:t-b) Q (eq:x-defining).
+// k_lanczos  Sigma~(1,1) = ||R||_2 by Golub-Kahan-Lanczos bidiagonalisation
+//            with full reorthogonalisation and a Sturm-bisection of B^T B.
+// k_randblk  deterministic start block for inverse subspace iteration.
+// k_final_n  sigma (ascending) and V outputs.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace rl {
+
+constexpr int NS_THREADS = 256;
+constexpr int RR_TMAX = 32;
+constexpr int RR_BMAX = 16;
+
+__device__ inline double shfl_xor_(double v, int o) { return __shfl_xor(v, o, WAVE); }
+__device__ inline cd shfl_xor_(cd v, int o) { return cd{__shfl_xor(v.x, o, WAVE), __shfl_xor(v.y, o, WAVE)}; }
+__device__ inline double absval(double a) { return fabs(a); }
+__device__ inline double absval(cd a) { return hypot(a.x, a.y); }
+
+template <typename T, int KMAX>
+__device__ inline void nblock_sum_many(T (&vals)[KMAX], int K, T* scratch, T* out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    if (k < K) {
+      T v = wave_sum(vals[k]);
+      if (lane == 0) scratch[wid * KMAX + k] = v;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < K) {
+    T s = zero<T>();
+    for (int w = 0; w < nw; ++w) s = add(s, scratch[w * KMAX + threadIdx.x]);
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+template <typename T, int B>
+__global__ __launch_bounds__(NS_THREADS) void k_trmv(const T* __restrict__ M, int n, int lower,
+                                                     const T* __restrict__ X, T* __restrict__ Y,
+                                                     const Ctl* __restrict__ ctl, int check_done) {
+  if (check_done && ctl->done) return;
+  __shared__ T xs[256 * B];
+  const int ri = threadIdx.x >> 4, kk = threadIdx.x & 15;
+  const int i = blockIdx.x * 16 + ri;
+  const int ib0 = blockIdx.x * 16;
+  const int ib1 = (ib0 + 16 < n) ? ib0 + 16 : n;
+  const int lstart = lower ? 0 : ib0;
+  const int lend = lower ? ib1 : n;
+  T acc[B];
+#pragma unroll
+  for (int j = 0; j < B; ++j) acc[j] = zero<T>();
+  for (int l0 = lstart; l0 < lend; l0 += 256) {
+    const int cnt = (lend - l0 < 256) ? lend - l0 : 256;
+    __syncthreads();
+    for (int e = threadIdx.x; e < cnt * B; e += blockDim.x) xs[e] = X[(int64_t)l0 * B + e];
+    __syncthreads();
+    if (i < n) {
+      const int lo = lower ? l0 : (i > l0 ? i : l0);
+      const int hi = lower ? ((i + 1 < l0 + cnt) ? i + 1 : l0 + cnt) : l0 + cnt;
+      for (int l = l0 + kk; l < l0 + cnt; l += 16) {
+        if (l < lo || l >= hi) continue;
+        const T mv = M[(int64_t)i * n + l];
+#pragma unroll
+        for (int j = 0; j < B; ++j) acc[j] = fmac(mv, xs[(l - l0) * B + j], acc[j]);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) acc[j] = add(acc[j], shfl_xor_(acc[j], o));
+  }
+  if (kk == 0 && i < n) {
+#pragma unroll
+    for (int j = 0; j < B; ++j) Y[(int64_t)i * B + j] = acc[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// W (n x B, row-major) <- Orth(W - [V X]([V X]^* W)) with BCGS2; project=0 skips [V X].
+// Column j is projected on the columns of [V X W(:, 0:j)] by classical
+// Gram-Schmidt passes: two always (BCGS2 then CGS2 inside W), a third when the
+// second removed more than half of what was left (the usual "twice is enough"
+// safeguard).  A column that vanishes is completed by the first unit vector
+// that keeps norm above 1/2 after the same projections.
+template <typename T>
+__device__ void orth_project(int n, int B, int j, const T* __restrict__ V, const T* __restrict__ X, int nvx,
+                             T* __restrict__ W, T* scratch, T* h) {
+  constexpr int KM = 3 * RR_BMAX;
+  const int K = nvx + j;
+  T vals[KM];
+#pragma unroll
+  for (int k = 0; k < KM; ++k) vals[k] = zero<T>();
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    const T wr = W[(int64_t)r * B + j];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+      if (k < K) {
+        const T br = (k < nvx) ? ((k < B) ? V[(int64_t)r * B + k] : X[(int64_t)r * B + (k - B)])
+                               : W[(int64_t)r * B + (k - nvx)];
+        vals[k] = cfmac(br, wr, vals[k]);
+      }
+    }
+  }
+  nblock_sum_many<T, KM>(vals, K, scratch, h);
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    T wr = W[(int64_t)r * B + j];
+    for (int k = 0; k < K; ++k) {
+      const T br = (k < nvx) ? ((k < B) ? V[(int64_t)r * B + k] : X[(int64_t)r * B + (k - B)])
+                             : W[(int64_t)r * B + (k - nvx)];
+      wr = fnmac(br, h[k], wr);
+    }
+    W[(int64_t)r * B + j] = wr;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ double col_norm(int n, int B, int j, const T* __restrict__ W, double* red) {
+  double s = 0.0;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) s += abs2(W[(int64_t)r * B + j]);
+  return sqrt(block_sum(s, red));
+}
+
+template <typename T>
+__global__ __launch_bounds__(NS_THREADS) void k_orth(int n, int B, const T* __restrict__ V, const T* __restrict__ X,
+                                                     int project, int with_x, T* __restrict__ W, Ctl* __restrict__ ctl,
+                                                     int check_done) {
+  if (check_done && ctl->done) return;
+  constexpr int KM = 3 * RR_BMAX;
+  __shared__ T scratch[(NS_THREADS / 64) * KM];
+  __shared__ T h[KM];
+  __shared__ double red[NS_THREADS / 64];
+  const int nvx = project ? (with_x ? 2 * B : B) : 0;
+  for (int j = 0; j < B; ++j) {
+    double nrm = 0.0;
+    for (int cand = -1; cand < n; ++cand) {
+      if (cand >= 0) {
+        for (int r = threadIdx.x; r < n; r += blockDim.x) W[(int64_t)r * B + j] = from_real<T>(r == cand ? 1.0 : 0.0);
+        __syncthreads();
+      }
+      if (nvx + j > 0) {
+        orth_project<T>(n, B, j, V, X, nvx, W, scratch, h);
+        const double n1 = col_norm<T>(n, B, j, W, red);
+        orth_project<T>(n, B, j, V, X, nvx, W, scratch, h);
+        nrm = col_norm<T>(n, B, j, W, red);
+        if (nrm < 0.5 * n1) {
+          orth_project<T>(n, B, j, V, X, nvx, W, scratch, h);
+          nrm = col_norm<T>(n, B, j, W, red);
+        }
+      } else {
+        nrm = col_norm<T>(n, B, j, W, red);
+      }
+      if (cand < 0 && nrm > 0.0 && isfinite(nrm)) break;
+      if (cand >= 0 && nrm > 0.5) break;
+      if (cand < 0 && threadIdx.x == 0) ctl->degenerate = 1;
+    }
+    const double inv = 1.0 / nrm;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) W[(int64_t)r * B + j] = scal(W[(int64_t)r * B + j], inv);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+__device__ bool dev_should_stop(int i, const double* __restrict__ ht, const double* __restrict__ hr, int B,
+                                const Ctl* __restrict__ c) {
+  if (c->stop_rule == 2) return false;
+  double rmax = 0.0;
+  bool nan = false;
+  for (int j = 0; j < B; ++j) {
+    const double v = hr[(int64_t)(i + 1) * B + j];
+    if (!(v == v)) nan = true;
+    rmax = fmax(rmax, v);
+  }
+  const bool tol = !nan && (rmax <= c->sigma1 * c->sigma1 * c->tau);
+  if (c->stop_rule == 1) return tol;
+  if (i % c->check_every != 0) return false;
+  if (!tol) return false;
+  const int jn = i + 1, jm = i + 1 - 5, jo = i + 1 - 10;
+  if (jm < 0 || jo < 0) return false;
+  for (int j = 0; j < B; ++j) {
+    const double rn = hr[(int64_t)jn * B + j], rm = hr[(int64_t)jm * B + j];
+    if (!(1.1 * rn >= rm)) return false;
+    const double tn = ht[(int64_t)jn * B + j], tm = ht[(int64_t)jm * B + j], to = ht[(int64_t)jo * B + j];
+    if (tn == 0.0) continue;
+    const double lhs = 1.1 * (tm - tn) / tn;
+    const double rhs = (tm == 0.0) ? INFINITY : (to - tm) / tm;
+    if (!(lhs >= rhs)) return false;
+  }
+  return true;
+}
+
+// One-sided (Hestenes) Jacobi on the t x t matrix M (column-major, ld 32) by one
+// wave; Vj accumulates the rotations.  Lanes 0..t-1 hold one row each.
+template <typename T>
+__device__ void jacobi_wave(T* M, T* Vj, int t, int lane) {
+  const double tol = sqrt((double)t) * 2.220446049250313e-16;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    bool rotated = false;
+    for (int p = 0; p < t - 1; ++p) {
+      for (int q = p + 1; q < t; ++q) {
+        const T mp = (lane < t) ? M[p * 32 + lane] : zero<T>();
+        const T mq = (lane < t) ? M[q * 32 + lane] : zero<T>();
+        const double al = wave_sum(abs2(mp));
+        const double be = wave_sum(abs2(mq));
+        const T ga = wave_sum(cfmac(mp, mq, zero<T>()));
+        const double g = absval(ga);
+        if (!(g > tol * sqrt(al) * sqrt(be)) || g == 0.0) continue;
+        rotated = true;
+        const T eg = scal(ga, 1.0 / g);  // unit phase of gamma
+        const double zeta = (be - al) / (2.0 * g);
+        const double tn = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + tn * tn), s = c * tn;
+        if (lane < t) {
+          const T mq2 = mul(conj_(eg), mq);
+          M[p * 32 + lane] = sub(scal(mp, c), scal(mq2, s));
+          M[q * 32 + lane] = add(scal(mp, s), scal(mq2, c));
+          const T vp = Vj[p * 32 + lane];
+          const T vq2 = mul(conj_(eg), Vj[q * 32 + lane]);
+          Vj[p * 32 + lane] = sub(scal(vp, c), scal(vq2, s));
+          Vj[q * 32 + lane] = add(scal(vp, s), scal(vq2, c));
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    if (!rotated) break;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int B, int init_mode, int with_x, const T* __restrict__ Rt,
+                                                   T* __restrict__ V, T* __restrict__ X, const T* __restrict__ W,
+                                                   const T* __restrict__ G3, T* __restrict__ Vn,
+                                                   T* __restrict__ Rres, T* __restrict__ CVout, T* __restrict__ CXout,
+                                                   double* __restrict__ thb, double* __restrict__ hist_theta,
+                                                   double* __restrict__ hist_rnorm, Ctl* __restrict__ ctl) {
+  if (ctl->done) return;
+  __shared__ T M[RR_TMAX * 32];
+  __shared__ T Vj[RR_TMAX * 32];
+  __shared__ T C[RR_TMAX * 32];       // sorted right singular vectors, column-major ld 32
+  __shared__ T CV[RR_TMAX * RR_BMAX];  // t x B row-major
+  __shared__ T CX[RR_TMAX * RR_BMAX];
+  __shared__ T Qm[RR_TMAX * RR_BMAX];  // (t-B) x B row-major
+  __shared__ double th[RR_TMAX];
+  __shared__ double sig[RR_TMAX];
+  __shared__ double rn[RR_BMAX];
+  __shared__ T scratch[(NS_THREADS / 64) * RR_BMAX];
+  __shared__ T hsum[RR_BMAX];
+  __shared__ int stop_s;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int mode = init_mode ? 0 : (with_x ? 2 : 1);
+  const int t = (mode == 0) ? B : (mode == 1 ? 2 * B : 3 * B);
+  const int iter = ctl->iter;
+  for (int e = tid; e < RR_TMAX * 32; e += blockDim.x) {
+    const int c = e / 32, r = e % 32;
+    M[e] = (r < t && c < t) ? Rt[r * t + c] : zero<T>();
+    Vj[e] = from_real<T>((r == c) ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (wid == 0) {
+    jacobi_wave<T>(M, Vj, t, lane);
+    // column norms, then a descending sort (lane 0)
+    for (int c = 0; c < t; ++c) {
+      const T v = (lane < t) ? M[c * 32 + lane] : zero<T>();
+      const double s = wave_sum(abs2(v));
+      if (lane == 0) sig[c] = sqrt(s);
+    }
+    if (lane == 0) {
+      int used[RR_TMAX];
+      for (int c = 0; c < t; ++c) used[c] = 0;
+      for (int c = 0; c < t; ++c) {
+        int best = -1;
+        for (int q = 0; q < t; ++q)
+          if (!used[q] && (best < 0 || sig[q] > sig[best])) best = q;
+        used[best] = 1;
+        th[c] = sig[best];
+        for (int r = 0; r < t; ++r) C[c * 32 + r] = Vj[best * 32 + r];
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < t * B; e += blockDim.x) {
+    const int r = e / B, j = e % B;
+    CV[e] = C[(t - B + j) * 32 + r];
+  }
+  if (tid < B) thb[tid] = th[t - B + tid];
+  __syncthreads();
+  // pass 1: V_new = T C_V and the residual G_T C_V - V_new Theta_b^2, with its column norms
+  {
+    const T* GV = G3;
+    const T* GX = G3 + (int64_t)n * B;
+    const T* GW = G3 + 2 * (int64_t)n * B;
+    T vals[RR_BMAX];
+#pragma unroll
+    for (int j = 0; j < RR_BMAX; ++j) vals[j] = zero<T>();
+    for (int r = tid; r < n; r += blockDim.x) {
+      T tr[RR_TMAX], gr[RR_TMAX];
+      for (int j = 0; j < B; ++j) {
+        tr[j] = V[(int64_t)r * B + j];
+        gr[j] = GV[(int64_t)r * B + j];
+      }
+      if (mode == 2) {
+        for (int j = 0; j < B; ++j) {
+          tr[B + j] = X[(int64_t)r * B + j];
+          gr[B + j] = GX[(int64_t)r * B + j];
+          tr[2 * B + j] = W[(int64_t)r * B + j];
+          gr[2 * B + j] = GW[(int64_t)r * B + j];
+        }
+      } else if (mode == 1) {
+        for (int j = 0; j < B; ++j) {
+          tr[B + j] = W[(int64_t)r * B + j];
+          gr[B + j] = GW[(int64_t)r * B + j];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < RR_BMAX; ++j) {
+        if (j < B) {
+          T v = zero<T>(), g = zero<T>();
+          for (int c = 0; c < t; ++c) {
+            v = fmac(tr[c], CV[c * B + j], v);
+            g = fmac(gr[c], CV[c * B + j], g);
+          }
+          const double th2 = th[t - B + j] * th[t - B + j];
+          const T res = sub(g, scal(v, th2));
+          Vn[(int64_t)r * B + j] = v;
+          Rres[(int64_t)r * B + j] = res;
+          vals[j] = add(vals[j], from_real<T>(abs2(res)));
+        }
+      }
+    }
+    nblock_sum_many<T, RR_BMAX>(vals, B, scratch, hsum);
+    if (tid < B) rn[tid] = sqrt(re_(hsum[tid]));
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const int idx = init_mode ? 0 : iter + 1;
+    for (int j = 0; j < B; ++j) {
+      hist_theta[(int64_t)idx * B + j] = (init_mode && B == 1) ? INFINITY : th[t - B + j];
+      hist_rnorm[(int64_t)idx * B + j] = rn[j];
+    }
+    __threadfence_block();
+    stop_s = init_mode ? 0 : (dev_should_stop(iter, hist_theta, hist_rnorm, B, ctl) ? 1 : 0);
+    if (!init_mode && !stop_s) {
+      // Q = Orth(C(1:B, 1:t-B)^*), (t-B) x B, by modified Gram-Schmidt applied
+      // twice.  A column that vanishes (at full convergence C(1:B, 1:t-B) can be
+      // exactly 0) is completed, as Householder QR would, by the first unit
+      // vector that keeps norm above 1/2 after projection on the earlier ones.
+      const int tb = t - B;
+      for (int a = 0; a < tb; ++a)
+        for (int j = 0; j < B; ++j) Qm[a * B + j] = conj_(C[a * 32 + j]);
+      for (int j = 0; j < B; ++j) {
+        double nrm = 0.0;
+        for (int cand = -1; cand < tb; ++cand) {
+          if (cand >= 0)
+            for (int a = 0; a < tb; ++a) Qm[a * B + j] = from_real<T>(a == cand ? 1.0 : 0.0);
+          for (int pass = 0; pass < 2; ++pass) {
+            for (int q = 0; q < j; ++q) {
+              T sp = zero<T>();
+              for (int a = 0; a < tb; ++a) sp = cfmac(Qm[a * B + q], Qm[a * B + j], sp);
+              for (int a = 0; a < tb; ++a) Qm[a * B + j] = fnmac(Qm[a * B + q], sp, Qm[a * B + j]);
+            }
+          }
+          double s2 = 0.0;
+          for (int a = 0; a < tb; ++a) s2 += abs2(Qm[a * B + j]);
+          nrm = sqrt(s2);
+          if (cand < 0 && nrm > 0.0 && isfinite(nrm)) break;
+          if (cand >= 0 && nrm > 0.5) break;
+          if (cand < 0) ctl->degenerate = 1;
+        }
+        for (int a = 0; a < tb; ++a) Qm[a * B + j] = scal(Qm[a * B + j], 1.0 / nrm);
+      }
+      // C_X = C(:, 1:t-B) Q  (t x B)
+      for (int c = 0; c < t; ++c)
+        for (int j = 0; j < B; ++j) {
+          T s = zero<T>();
+          for (int a = 0; a < tb; ++a) s = fmac(C[a * 32 + c], Qm[a * B + j], s);
+          CX[c * B + j] = s;
+        }
+    }
+  }
+  __syncthreads();
+  const bool xupd = !init_mode && !stop_s;
+  // pass 2: X = T C_X from the old T, then V <- V_new
+  for (int r = tid; r < n; r += blockDim.x) {
+    if (xupd) {
+      T tr[RR_TMAX];
+      for (int j = 0; j < B; ++j) tr[j] = V[(int64_t)r * B + j];
+      if (mode == 2) {
+        for (int j = 0; j < B; ++j) {
+          tr[B + j] = X[(int64_t)r * B + j];
+          tr[2 * B + j] = W[(int64_t)r * B + j];
+        }
+      } else {
+        for (int j = 0; j < B; ++j) tr[B + j] = W[(int64_t)r * B + j];
+      }
+      for (int j = 0; j < B; ++j) {
+        T x = zero<T>();
+        for (int c = 0; c < t; ++c) x = fmac(tr[c], CX[c * B + j], x);
+        X[(int64_t)r * B + j] = x;
+      }
+    }
+    for (int j = 0; j < B; ++j) V[(int64_t)r * B + j] = Vn[(int64_t)r * B + j];
+  }
+  for (int e = tid; e < t * B; e += blockDim.x) {
+    CVout[e] = CV[e];
+    CXout[e] = xupd ? CX[e] : zero<T>();
+  }
+  __syncthreads();
+  if (tid == 0) {
+    ctl->rr_mode = mode;
+    ctl->x_update = xupd ? 1 : 0;
+    if (!init_mode) {
+      ctl->iter = iter + 1;
+      if (stop_s) {
+        ctl->done = 1;
+        ctl->status = 0;
+      } else {
+        ctl->has_x = 1;
+        if (iter + 1 >= ctl->max_iter) ctl->status = 1;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+__device__ inline uint64_t mix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ inline double unif_pm1(uint64_t h) { return (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0; }
+
+template <typename T>
+__global__ void k_randblk(T* __restrict__ Wb, int64_t count, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  T v;
+  if constexpr (sizeof(T) == sizeof(double)) {
+    v = from_real<T>(unif_pm1(mix64(seed ^ (uint64_t)(2 * i))));
+  } else {
+    cd c{unif_pm1(mix64(seed ^ (uint64_t)(2 * i))), unif_pm1(mix64(seed ^ (uint64_t)(2 * i + 1)))};
+    v = *reinterpret_cast<T*>(&c);
+  }
+  Wb[i] = v;
+}
+
+// Golub-Kahan-Lanczos on R (upper triangular, R(i,l) = Ycol[l*ld + i] = Rrow[i*n + l]).
+template <typename T>
+__global__ __launch_bounds__(NS_THREADS) void k_lanczos(int n, const T* __restrict__ Ycol, int ld,
+                                                        const T* __restrict__ Rrow, T* __restrict__ Ub,
+                                                        T* __restrict__ Vb, int KL, uint64_t seed,
+                                                        Ctl* __restrict__ ctl) {
+  extern __shared__ double smem_d[];
+  T* u = reinterpret_cast<T*>(smem_d);  // n
+  T* v = u + n;                          // n
+  __shared__ double alpha[65], beta[65];
+  __shared__ T scratch[(NS_THREADS / 64) * 32];
+  __shared__ T h[32];
+  __shared__ double red[NS_THREADS / 64];
+  __shared__ int kdone;
+  const int tid = threadIdx.x;
+  // v_0: deterministic random unit vector
+  double s = 0.0;
+  for (int i = tid; i < n; i += blockDim.x) {
+    const double x = unif_pm1(mix64(seed ^ (uint64_t)(0x5bd1e995ull + i)));
+    v[i] = from_real<T>(x);
+    s += x * x;
+  }
+  s = block_sum(s, red);
+  {
+    const double inv = 1.0 / sqrt(s);
+    for (int i = tid; i < n; i += blockDim.x) {
+      v[i] = scal(v[i], inv);
+      Vb[i] = v[i];
+    }
+  }
+  if (tid == 0) kdone = 0;
+  __syncthreads();
+  int k = 0;
+  for (int j = 0; j < KL; ++j) {
+    // u = R v_j - beta_{j-1} u_{j-1}: column form over l, rows i <= l
+    for (int i = tid; i < n; i += blockDim.x) u[i] = (j > 0) ? scal(Ub[(int64_t)(j - 1) * n + i], -beta[j - 1]) : zero<T>();
+    __syncthreads();
+    for (int l = 0; l < n; ++l) {
+      const T vl = v[l];
+      for (int i = tid; i <= l; i += blockDim.x) u[i] = fmac(Ycol[(int64_t)l * ld + i], vl, u[i]);
+    }
+    __syncthreads();
+    // reorthogonalise u against u_0..u_{j-1} (two classical passes, chunks of 32)
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int q0 = 0; q0 < j; q0 += 32) {
+        const int K = (j - q0 < 32) ? j - q0 : 32;
+        T vals[32];
+#pragma unroll
+        for (int q = 0; q < 32; ++q) vals[q] = zero<T>();
+        for (int i = tid; i < n; i += blockDim.x) {
+          const T ui = u[i];
+#pragma unroll
+          for (int q = 0; q < 32; ++q)
+            if (q < K) vals[q] = cfmac(Ub[(int64_t)(q0 + q) * n + i], ui, vals[q]);
+        }
+        nblock_sum_many<T, 32>(vals, K, scratch, h);
+        for (int i = tid; i < n; i += blockDim.x) {
+          T ui = u[i];
+          for (int q = 0; q < K; ++q) ui = fnmac(Ub[(int64_t)(q0 + q) * n + i], h[q], ui);
+          u[i] = ui;
+        }
+        __syncthreads();
+      }
+    }
+    s = 0.0;
+    for (int i = tid; i < n; i += blockDim.x) s += abs2(u[i]);
+    s = block_sum(s, red);
+    const double a = sqrt(s);
+    if (tid == 0) alpha[j] = a;
+    const double ainv = (a > 0.0) ? 1.0 / a : 0.0;
+    for (int i = tid; i < n; i += blockDim.x) {
+      u[i] = scal(u[i], ainv);
+      Ub[(int64_t)j * n + i] = u[i];
+    }
+    __syncthreads();
+    k = j + 1;
+    if (!(a > 0.0)) break;
+    // v = R^* u - alpha_j v_j: row form over i, entries l >= i
+    for (int l = tid; l < n; l += blockDim.x) v[l] = scal(v[l], -a);
+    __syncthreads();
+    for (int i = 0; i < n; ++i) {
+      const T ui = u[i];
+      for (int l = tid; l < n; l += blockDim.x)
+        if (l >= i) v[l] = cfmac(Rrow[(int64_t)i * n + l], ui, v[l]);
+    }
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int q0 = 0; q0 <= j; q0 += 32) {
+        const int K = (j + 1 - q0 < 32) ? j + 1 - q0 : 32;
+        T vals[32];
+#pragma unroll
+        for (int q = 0; q < 32; ++q) vals[q] = zero<T>();
+        for (int i = tid; i < n; i += blockDim.x) {
+          const T vi = v[i];
+#pragma unroll
+          for (int q = 0; q < 32; ++q)
+            if (q < K) vals[q] = cfmac(Vb[(int64_t)(q0 + q) * n + i], vi, vals[q]);
+        }
+        nblock_sum_many<T, 32>(vals, K, scratch, h);
+        for (int i = tid; i < n; i += blockDim.x) {
+          T vi = v[i];
+          for (int q = 0; q < K; ++q) vi = fnmac(Vb[(int64_t)(q0 + q) * n + i], h[q], vi);
+          v[i] = vi;
+        }
+        __syncthreads();
+      }
+    }
+    s = 0.0;
+    for (int i = tid; i < n; i += blockDim.x) s += abs2(v[i]);
+    s = block_sum(s, red);
+    const double bta = sqrt(s);
+    if (tid == 0) beta[j] = bta;
+    if (!(bta > 1e-15 * a) || j + 1 >= n) {
+      __syncthreads();
+      break;
+    }
+    const double binv = 1.0 / bta;
+    for (int i = tid; i < n; i += blockDim.x) {
+      v[i] = scal(v[i], binv);
+      Vb[(int64_t)(j + 1) * n + i] = v[i];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // largest eigenvalue of B^T B (symmetric tridiagonal) by Sturm bisection
+    double dg[65], of[65];
+    for (int q = 0; q < k; ++q) {
+      dg[q] = alpha[q] * alpha[q] + (q > 0 ? beta[q - 1] * beta[q - 1] : 0.0);
+      of[q] = (q + 1 < k) ? alpha[q] * beta[q] : 0.0;
+    }
+    double hi = 0.0;
+    for (int q = 0; q < k; ++q) {
+      const double rad = fabs(of[q]) + (q > 0 ? fabs(of[q - 1]) : 0.0);
+      hi = fmax(hi, dg[q] + rad);
+    }
+    double lo = 0.0;
+    for (int it = 0; it < 200 && hi - lo > 1e-17 * hi; ++it) {
+      const double x = 0.5 * (lo + hi);
+      int cnt = 0;  // eigenvalues < x
+      double qv = dg[0] - x;
+      if (qv < 0) ++cnt;
+      for (int q = 1; q < k; ++q) {
+        if (qv == 0.0) qv = 1e-300;
+        qv = (dg[q] - x) - of[q - 1] * of[q - 1] / qv;
+        if (qv < 0) ++cnt;
+      }
+      if (cnt == k) hi = x; else lo = x;
+    }
+    ctl->sigma1 = sqrt(0.5 * (lo + hi));
+  }
+}
+
+template <typename T>
+__global__ void k_final_n(int n, int B, int k, const T* __restrict__ V, const double* __restrict__ thb,
+                          double* __restrict__ sigma, T* __restrict__ Vout, int64_t ldv, Ctl* __restrict__ ctl) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < k) {
+    const double s = thb[B - 1 - idx];
+    sigma[idx] = s;
+    if (s == 0.0) ctl->zero_theta = 1;
+  }
+  if (idx < (int64_t)n * k) {
+    const int64_t r = idx / k, jo = idx % k;
+    Vout[r * ldv + jo] = V[r * B + (B - 1 - jo)];
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <typename T, int B>
+static void trmv_b(hipStream_t st, const void* M, int n, int lower, const void* X, void* Y, const Ctl* ctl, int cd_) {
+  hipLaunchKernelGGL((k_trmv<T, B>), dim3((n + 15) / 16), dim3(NS_THREADS), 0, st, (const T*)M, n, lower, (const T*)X,
+                     (T*)Y, ctl, cd_);
+}
+
+template <typename T>
+static bool trmv_t(int B, hipStream_t st, const void* M, int n, int lower, const void* X, void* Y, const Ctl* ctl,
+                   int cd_) {
+  switch (B) {
+#define RL_TB(BB) \
+  case BB: trmv_b<T, BB>(st, M, n, lower, X, Y, ctl, cd_); return true;
+    RL_TB(1) RL_TB(2) RL_TB(3) RL_TB(4) RL_TB(5) RL_TB(6) RL_TB(7) RL_TB(8) RL_TB(9) RL_TB(10)
+#undef RL_TB
+    default: return false;
+  }
+}
+
+hipError_t launch_trmv(hipStream_t st, bool cplx, int B, const void* M, int n, int lower, const void* X, void* Y,
+                       const Ctl* ctl, int check_done) {
+  const bool ok = cplx ? trmv_t<cd>(B, st, M, n, lower, X, Y, ctl, check_done)
+                       : trmv_t<double>(B, st, M, n, lower, X, Y, ctl, check_done);
+  if (!ok) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_orth(hipStream_t st, bool cplx, int n, int B, const void* V, const void* X, int project, int with_x,
+                       void* W, Ctl* ctl, int check_done) {
+  if (cplx)
+    hipLaunchKernelGGL(k_orth<cd>, dim3(1), dim3(NS_THREADS), 0, st, n, B, (const cd*)V, (const cd*)X, project,
+                       with_x, (cd*)W, ctl, check_done);
+  else
+    hipLaunchKernelGGL(k_orth<double>, dim3(1), dim3(NS_THREADS), 0, st, n, B, (const double*)V, (const double*)X,
+                       project, with_x, (double*)W, ctl, check_done);
+  return hipGetLastError();
+}
+
+hipError_t launch_rr(hipStream_t st, bool cplx, int n, int B, int init_mode, int with_x, const void* Rt, void* V,
+                     void* X, const void* W, const void* G3, void* Vn, void* Rres, void* CV, void* CX, double* thb,
+                     double* ht, double* hr, Ctl* ctl) {
+  if (cplx)
+    hipLaunchKernelGGL(k_rr<cd>, dim3(1), dim3(NS_THREADS), 0, st, n, B, init_mode, with_x, (const cd*)Rt, (cd*)V,
+                       (cd*)X, (const cd*)W, (const cd*)G3, (cd*)Vn, (cd*)Rres, (cd*)CV, (cd*)CX, thb, ht, hr, ctl);
+  else
+    hipLaunchKernelGGL(k_rr<double>, dim3(1), dim3(NS_THREADS), 0, st, n, B, init_mode, with_x, (const double*)Rt,
+                       (double*)V, (double*)X, (const double*)W, (const double*)G3, (double*)Vn, (double*)Rres,
+                       (double*)CV, (double*)CX, thb, ht, hr, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_randblk(hipStream_t st, bool cplx, void* Wb, int64_t count, uint64_t seed) {
+  const unsigned g = (unsigned)((count + 255) / 256);
+  if (cplx)
+    hipLaunchKernelGGL(k_randblk<cd>, dim3(g), dim3(256), 0, st, (cd*)Wb, count, seed);
+  else
+    hipLaunchKernelGGL(k_randblk<double>, dim3(g), dim3(256), 0, st, (double*)Wb, count, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_lanczos(hipStream_t st, bool cplx, int n, const void* Ycol, int ld, const void* Rrow, void* Ub,
+                          void* Vb, int KL, uint64_t seed, Ctl* ctl) {
+  const size_t lds = (size_t)2 * n * (cplx ? 16 : 8);
+  if (cplx) {
+    if (lds > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_lanczos<cd>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_lanczos<cd>, dim3(1), dim3(NS_THREADS), lds, st, n, (const cd*)Ycol, ld, (const cd*)Rrow,
+                       (cd*)Ub, (cd*)Vb, KL, seed, ctl);
+  } else {
+    if (lds > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute((const void*)k_lanczos<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_lanczos<double>, dim3(1), dim3(NS_THREADS), lds, st, n, (const double*)Ycol, ld,
+                       (const double*)Rrow, (double*)Ub, (double*)Vb, KL, seed, ctl);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_final_n(hipStream_t st, bool cplx, int n, int B, int k, const void* V, const double* thb,
+                          double* sigma, void* Vout, int64_t ldv, Ctl* ctl) {
+  const int64_t cnt = (int64_t)n * k > k ? (int64_t)n * k : k;
+  const unsigned g = (unsigned)((cnt + 255) / 256);
+  if (cplx)
+    hipLaunchKernelGGL(k_final_n<cd>, dim3(g), dim3(256), 0, st, n, B, k, (const cd*)V, thb, sigma, (cd*)Vout, ldv, ctl);
+  else
+    hipLaunchKernelGGL(k_final_n<double>, dim3(g), dim3(256), 0, st, n, B, k, (const double*)V, thb, sigma,
+                       (double*)Vout, ldv, ctl);
+  return hipGetLastError();
+}
+
+}  // namespace rl
+
+namespace rl {
+
+// Singular values (descending) and right singular vectors of a t x t R
+// (row-major), for the tall-SVD step entry point.
+template <typename T>
+__global__ __launch_bounds__(64) void k_rt_svd(int t, const T* __restrict__ Rt, double* __restrict__ sigma,
+                                               T* __restrict__ Cout) {
+  __shared__ T M[RR_TMAX * 32];
+  __shared__ T Vj[RR_TMAX * 32];
+  __shared__ double sig[RR_TMAX];
+  const int lane = threadIdx.x;
+  for (int e = lane; e < RR_TMAX * 32; e += 64) {
+    const int c = e / 32, r = e % 32;
+    M[e] = (r < t && c < t) ? Rt[r * t + c] : zero<T>();
+    Vj[e] = from_real<T>((r == c) ? 1.0 : 0.0);
+  }
+  __builtin_amdgcn_wave_barrier();
+  jacobi_wave<T>(M, Vj, t, lane);
+  for (int c = 0; c < t; ++c) {
+    const T v = (lane < t) ? M[c * 32 + lane] : zero<T>();
+    const double s = wave_sum(abs2(v));
+    if (lane == 0) sig[c] = sqrt(s);
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (lane == 0) {
+    int used[RR_TMAX];
+    for (int c = 0; c < t; ++c) used[c] = 0;
+    for (int c = 0; c < t; ++c) {
+      int best = -1;
+      for (int q = 0; q < t; ++q)
+        if (!used[q] && (best < 0 || sig[q] > sig[best])) best = q;
+      used[best] = 1;
+      sigma[c] = sig[best];
+      for (int r = 0; r < t; ++r) Cout[r * t + c] = Vj[best * 32 + r];
+    }
+  }
+}
+
+hipError_t launch_rt_svd(hipStream_t st, bool cplx, int t, const void* Rt, double* sigma, void* C) {
+  if (cplx)
+    hipLaunchKernelGGL(k_rt_svd<cd>, dim3(1), dim3(64), 0, st, t, (const cd*)Rt, sigma, (cd*)C);
+  else
+    hipLaunchKernelGGL(k_rt_svd<double>, dim3(1), dim3(64), 0, st, t, (const double*)Rt, sigma, (double*)C);
+  return hipGetLastError();
+}
+
+}  // namespace rl

@@ -1,0 +1,248 @@
+// Householder QR of the sketch S*A (d x n), keeping only R, and R^{-1}.
+//
+// The preconditioner of RLOBPCG only needs P with P P^* = ((S A)^* S A)^{-1}.
+// The paper builds it from the SVD of S*A (Alg. rlopcg, sketch-and-SVD); its
+// footnote to Sec. 1 step 3 names the QR route as the traditional one.  With
+// S A = Q R, P = R^{-1} gives the same operator, P P^* = (R^* R)^{-1}, so the
+// GPU path factors S*A by Householder QR and inverts the triangular R once.
+//
+// Layout: Y is column-major (ld = d), as written by the sketch reduction.
+// Blocked right-looking QR with panel width QR_NB:
+//   k_qr_panel   one workgroup factors a (d-p) x nb panel column by column
+//                (LAPACK's larfg conventions: real beta, tau = (beta-alpha)/beta,
+//                H^* = I - conj(tau) v v^*) and builds the compact-WY T factor
+//                with H_1 ... H_nb = I - V T V^* (forward, column-wise).
+//   k_qr_update  applies I - V T^* V^* to the trailing columns, CB per block.
+//   k_qr_extract writes R row-major and R^* row-major (for the products).
+//   k_trinv      R^{-1} by column-oriented back substitution, one wave per
+//                column of the identity; writes R^{-1} and R^{-*} row-major.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace rl {
+
+constexpr int QR_NB = 32;
+constexpr int QR_THREADS = 256;
+constexpr int QR_CB = 8;
+
+__device__ inline double im_(double) { return 0.0; }
+__device__ inline double im_(cd a) { return a.y; }
+
+// Sums vals[0..K) over the block; results in out[0..K).  K is block-uniform.
+template <typename T, int KMAX>
+__device__ inline void block_sum_many(T (&vals)[KMAX], int K, T* scratch, T* out) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    if (k < K) {
+      T v = wave_sum(vals[k]);
+      if (lane == 0) scratch[wid * KMAX + k] = v;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < K) {
+    T s = zero<T>();
+    for (int w = 0; w < nw; ++w) s = add(s, scratch[w * KMAX + threadIdx.x]);
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// V(r, q) of the current panel: unit lower trapezoidal, stored below the diagonal.
+template <typename T>
+__device__ inline T vpanel(const T* Y, int ld, int p, int q, int r) {
+  const int j = p + q;
+  if (r < j) return zero<T>();
+  if (r == j) return from_real<T>(1.0);
+  return Y[(int64_t)j * ld + r];
+}
+
+template <typename T>
+__global__ __launch_bounds__(QR_THREADS) void k_qr_panel(T* Y, int ld, int d, int n, int p, int nb, T* Tm) {
+  __shared__ T scratch[(QR_THREADS / 64) * QR_NB];
+  __shared__ T outs[QR_NB];
+  __shared__ T taus[QR_NB];
+  __shared__ T Tl[QR_NB * QR_NB];  // column-major nb x nb
+  __shared__ double red[QR_THREADS / 64];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < QR_NB * QR_NB; i += blockDim.x) Tl[i] = zero<T>();
+  __syncthreads();
+  for (int jj = 0; jj < nb; ++jj) {
+    const int j = p + jj;
+    T* col = Y + (int64_t)j * ld;
+    double xs = 0.0;
+    for (int r = j + 1 + tid; r < d; r += blockDim.x) xs += abs2(col[r]);
+    xs = block_sum(xs, red);
+    const T alpha = col[j];
+    const bool noref = (xs == 0.0) && (im_(alpha) == 0.0);
+    T tau = zero<T>(), sc = zero<T>();
+    double beta = re_(alpha);
+    if (!noref) {
+      const double nrm = sqrt(abs2(alpha) + xs);
+      beta = (re_(alpha) >= 0.0) ? -nrm : nrm;
+      tau = divs(sub(from_real<T>(beta), alpha), from_real<T>(beta));
+      sc = divs(from_real<T>(1.0), sub(alpha, from_real<T>(beta)));
+    }
+    __syncthreads();  // alpha read by all before it is overwritten
+    if (!noref) {
+      for (int r = j + 1 + tid; r < d; r += blockDim.x) col[r] = mul(col[r], sc);
+      if (tid == 0) col[j] = from_real<T>(beta);
+    }
+    if (tid == 0) taus[jj] = tau;
+    __syncthreads();
+    // One batched reduction over rows r >= j:
+    //   k < K1: s_k = v^* Y(:, j+1+k)           (apply H^* to the rest of the panel)
+    //   k >= K1: g_q = V(:, q)^* v, q = k - K1  (column jj of the T factor)
+    const int K1 = nb - jj - 1, K2 = jj, K = K1 + K2;
+    if (K > 0) {
+      T vals[QR_NB];
+#pragma unroll
+      for (int k = 0; k < QR_NB; ++k) vals[k] = zero<T>();
+      for (int r = j + tid; r < d; r += blockDim.x) {
+        const T vr = (r == j) ? from_real<T>(1.0) : col[r];
+#pragma unroll
+        for (int k = 0; k < QR_NB; ++k) {
+          if (k < K1) vals[k] = cfmac(vr, Y[(int64_t)(j + 1 + k) * ld + r], vals[k]);
+          else if (k < K) vals[k] = cfmac(vpanel(Y, ld, p, k - K1, r), vr, vals[k]);
+        }
+      }
+      block_sum_many<T, QR_NB>(vals, K, scratch, outs);
+      if (K1 > 0 && !noref) {
+        const T ct = conj_(tau);
+        for (int r = j + tid; r < d; r += blockDim.x) {
+          const T vr = (r == j) ? from_real<T>(1.0) : col[r];
+          for (int k = 0; k < K1; ++k) {
+            T* yk = Y + (int64_t)(j + 1 + k) * ld + r;
+            *yk = fnmac(mul(ct, outs[k]), vr, *yk);
+          }
+        }
+      }
+      if (tid == 0) {
+        // T(0:jj, jj) = -tau * T(0:jj, 0:jj) * g
+        for (int q = 0; q < jj; ++q) {
+          T s = zero<T>();
+          for (int l = q; l < jj; ++l) s = fmac(Tl[q + l * QR_NB], outs[K1 + l], s);
+          Tl[q + jj * QR_NB] = neg(mul(tau, s));
+        }
+      }
+    }
+    if (tid == 0) Tl[jj + jj * QR_NB] = tau;
+    __syncthreads();
+  }
+  for (int i = tid; i < QR_NB * QR_NB; i += blockDim.x) Tm[i] = Tl[i];
+}
+
+// C <- (I - V T V^*)^* C = C - V T^* (V^* C) on columns [p+nb, n)
+template <typename T>
+__global__ __launch_bounds__(QR_THREADS) void k_qr_update(T* Y, int ld, int d, int n, int p, int nb,
+                                                          const T* __restrict__ Tm) {
+  constexpr int RCH = 32;
+  __shared__ T Vs[RCH][QR_NB + 1];
+  __shared__ T Cs[RCH][QR_CB + 1];
+  __shared__ T Wt[QR_NB][QR_CB];
+  __shared__ T Wt2[QR_NB][QR_CB];
+  const int tid = threadIdx.x;
+  const int c0 = p + nb + blockIdx.x * QR_CB;
+  const int ncb = min(QR_CB, n - c0);
+  const int q = tid / QR_CB, cb = tid % QR_CB;  // 32 x 8 = 256
+  T acc = zero<T>();
+  for (int r0 = p; r0 < d; r0 += RCH) {
+    for (int i = tid; i < RCH * QR_NB; i += blockDim.x) {
+      const int rr = i % RCH, qq = i / RCH;
+      const int r = r0 + rr;
+      Vs[rr][qq] = (qq < nb && r < d) ? vpanel(Y, ld, p, qq, r) : zero<T>();
+    }
+    for (int i = tid; i < RCH * QR_CB; i += blockDim.x) {
+      const int rr = i % RCH, cc = i / RCH;
+      const int r = r0 + rr;
+      Cs[rr][cc] = (cc < ncb && r < d) ? Y[(int64_t)(c0 + cc) * ld + r] : zero<T>();
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int rr = 0; rr < RCH; ++rr) acc = cfmac(Vs[rr][q], Cs[rr][cb], acc);
+    __syncthreads();
+  }
+  Wt[q][cb] = acc;
+  __syncthreads();
+  {
+    T s = zero<T>();
+    for (int l = 0; l <= q && l < nb; ++l) s = cfmac(Tm[l + q * QR_NB], Wt[l][cb], s);
+    Wt2[q][cb] = (q < nb) ? s : zero<T>();
+  }
+  __syncthreads();
+  for (int r = p + tid; r < d; r += blockDim.x) {
+    for (int c = 0; c < ncb; ++c) {
+      T* y = Y + (int64_t)(c0 + c) * ld + r;
+      T v = *y;
+      for (int qq = 0; qq < nb; ++qq) v = fnmac(vpanel(Y, ld, p, qq, r), Wt2[qq][c], v);
+      *y = v;
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_qr_extract(const T* __restrict__ Y, int ld, int n, T* __restrict__ Rrow, T* __restrict__ RH) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx / n), j = (int)(idx % n);
+  Rrow[idx] = (j >= i) ? Y[(int64_t)j * ld + i] : zero<T>();
+  RH[idx] = (j <= i) ? conj_(Y[(int64_t)i * ld + j]) : zero<T>();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_trinv(const T* __restrict__ Y, int ld, int n, T* __restrict__ Rinv,
+                                               T* __restrict__ RinvH) {
+  extern __shared__ double smem_d[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T* xs = reinterpret_cast<T*>(smem_d) + (int64_t)wave * n;
+  const int k = blockIdx.x * 4 + wave;
+  if (k >= n) return;
+  for (int i = lane; i < n; i += 64) xs[i] = (i == k) ? from_real<T>(1.0) : zero<T>();
+  __builtin_amdgcn_wave_barrier();
+  for (int i = k; i >= 0; --i) {
+    const T* coli = Y + (int64_t)i * ld;
+    const T xi = divs(xs[i], coli[i]);
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) xs[i] = xi;
+    for (int l = lane; l < i; l += 64) xs[l] = fnmac(coli[l], xi, xs[l]);
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (int i = lane; i < n; i += 64) {
+    const T x = (i <= k) ? xs[i] : zero<T>();
+    Rinv[(int64_t)i * n + k] = x;
+    RinvH[(int64_t)k * n + i] = conj_(x);
+  }
+}
+
+template <typename T>
+static hipError_t qr_impl(hipStream_t st, T* Y, int d, int n, T* Tm, T* Rrow, T* RH, T* Rinv, T* RinvH) {
+  for (int p = 0; p < n; p += QR_NB) {
+    const int nb = min(QR_NB, n - p);
+    hipLaunchKernelGGL(k_qr_panel<T>, dim3(1), dim3(QR_THREADS), 0, st, Y, d, d, n, p, nb, Tm);
+    const int rest = n - p - nb;
+    if (rest > 0)
+      hipLaunchKernelGGL(k_qr_update<T>, dim3((rest + QR_CB - 1) / QR_CB), dim3(QR_THREADS), 0, st, Y, d, d, n,
+                         p, nb, (const T*)Tm);
+  }
+  const int64_t nn = (int64_t)n * n;
+  hipLaunchKernelGGL(k_qr_extract<T>, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, (const T*)Y, d, n,
+                     Rrow, RH);
+  const size_t lds = (size_t)4 * n * sizeof(T);
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_trinv<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_trinv<T>, dim3((n + 3) / 4), dim3(256), lds, st, (const T*)Y, d, n, Rinv, RinvH);
+  return hipGetLastError();
+}
+
+hipError_t launch_qr(hipStream_t st, bool cplx, void* Y, int d, int n, void* Tm, void* Rrow, void* RH, void* Rinv,
+                     void* RinvH) {
+  if (cplx)
+    return qr_impl<cd>(st, (cd*)Y, d, n, (cd*)Tm, (cd*)Rrow, (cd*)RH, (cd*)Rinv, (cd*)RinvH);
+  return qr_impl<double>(st, (double*)Y, d, n, (double*)Tm, (double*)Rrow, (double*)RH, (double*)Rinv,
+                         (double*)RinvH);
+}
+
+}  // namespace rl

@@ -1,0 +1,164 @@
+// Sketch Y = S*A for the SparseStack embedding S (paper Sec. 2.2).
+//
+// S = zeta^{-1/2} [s_1 ... s_m]; column s_i has one +-1 in each of zeta pieces.
+// Counter spec (shared in writing with the host oracle, not in code):
+//   len_j = floor(d/zeta) + (j < d mod zeta), start_j = sum_{l<j} len_l
+//   h(i,j) = splitmix64(seed ^ splitmix64(i*zeta + j))        (uint64 wrap)
+//   row = start_j + ((h & 0xffffffff) * len_j >> 32),  sign = bit63 ? -1 : +1
+// The +-1 rows are added exactly and the factor zeta^{-1/2} is applied once.
+//
+// Data layout: A is row-major with leading dimension lda (in elements); a
+// complex A is read as 2n real columns (the sketch is real-linear), so both
+// scalar types share one kernel over doubles.
+//
+// Kernel 1 (partial): grid (column tiles, row chunks).  A block owns a tile of
+// CT double-columns and a chunk of rows and keeps the whole d x CT slice of Y
+// in LDS.  Wave w owns pieces w, w+8, ..., so no two waves touch the same LDS
+// word; within a wave the 64/CT row slots of one instruction may hit the same
+// word and resolve through the LDS atomic unit.  Each lane first hashes one row
+// of the next 64 for the wave's piece, and the targets are then read with a
+// cross-lane shuffle, so every (row, piece) pair is hashed once per tile.
+// Kernel 2 (reduce): sums the chunk partials in chunk order and writes Y
+// column-major (the layout of the QR that follows), flagging NaN/Inf.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace rl {
+
+__device__ inline uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+template <int CT>
+__global__ __launch_bounds__(512) void k_sketch_partial(
+    const double* __restrict__ A, int64_t lda_d, int64_t m, int64_t ncols_d, int d, int zeta,
+    uint64_t seed, int64_t rows_per_chunk, double* __restrict__ part) {
+  extern __shared__ double acc[];  // d * CT
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  const int64_t c0 = (int64_t)blockIdx.x * CT;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_chunk;
+  const int64_t r1 = (r0 + rows_per_chunk < m) ? r0 + rows_per_chunk : m;
+  for (int i = tid; i < d * CT; i += blockDim.x) acc[i] = 0.0;
+  __syncthreads();
+  constexpr int RS = 64 / CT;   // rows per instruction
+  constexpr int NQ = 64 / RS;   // instructions per 64 rows
+  const int slot = lane / CT, col = lane % CT;
+  const bool colok = (c0 + col) < ncols_d;
+  const int base = d / zeta, extra = d % zeta;
+  for (int p = wave; p < zeta; p += nwaves) {
+    const int len = base + (p < extra ? 1 : 0);
+    const int start = p * base + (p < extra ? p : extra);
+    for (int64_t g0 = r0; g0 < r1; g0 += 64) {
+      const uint64_t i = (uint64_t)(g0 + lane);
+      const uint64_t h = splitmix64(seed ^ splitmix64(i * (uint64_t)zeta + (uint64_t)p));
+      const int tgt = start + (int)(((h & 0xFFFFFFFFull) * (uint64_t)len) >> 32);
+      const double sg = (h >> 63) ? -1.0 : 1.0;
+      double a[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int64_t row = g0 + q * RS + slot;
+        a[q] = (row < r1 && colok) ? A[row * lda_d + c0 + col] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int src = q * RS + slot;
+        const int t = __shfl(tgt, src, WAVE);
+        const double s = __shfl(sg, src, WAVE);
+        const int64_t row = g0 + src;
+        if (row < r1 && colok) atomicAdd(&acc[t * CT + col], s * a[q]);
+      }
+    }
+  }
+  __syncthreads();
+  double* out = part + (int64_t)blockIdx.y * d * ncols_d;
+  for (int i = tid; i < d * CT; i += blockDim.x) {
+    const int r = i / CT, c = i % CT;
+    if (c0 + c < ncols_d) out[(int64_t)r * ncols_d + c0 + c] = acc[i];
+  }
+}
+
+// Y (column-major, ld = d, element size es doubles) = scale * sum over chunks.
+__global__ void k_sketch_reduce(const double* __restrict__ part, int nchunk, int d, int64_t ncols_d,
+                                int es, double scale, double* __restrict__ Ycol, Ctl* ctl) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)d * ncols_d;
+  if (idx >= total) return;
+  const int64_t r = idx / ncols_d, cdb = idx % ncols_d;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * total + idx];
+  s *= scale;
+  if (!isfinite(s) && ctl) atomicOr(&ctl->nonfinite, 1);
+  const int64_t elem = cdb / es, comp = cdb % es;
+  Ycol[(elem * d + r) * es + comp] = s;
+}
+
+int sketch_plan_ct(int d, int64_t lds_budget) {
+  // widest column tile (in doubles) whose d x CT slice fits the LDS budget
+  const int cts[6] = {32, 16, 8, 4, 2, 1};
+  for (int c : cts)
+    if ((int64_t)d * c * 8 <= lds_budget) return c;
+  return 0;
+}
+
+int64_t sketch_partial_doubles(int64_t m, int64_t ncols_d, int d, int64_t lds_budget, int* nchunk_out,
+                               int64_t* rows_out) {
+  const int ct = sketch_plan_ct(d, lds_budget);
+  if (ct == 0) return -1;
+  const int64_t ntiles = (ncols_d + ct - 1) / ct;
+  int64_t nchunk = (1024 + ntiles - 1) / ntiles;
+  if (nchunk < 1) nchunk = 1;
+  int64_t rows = (m + nchunk - 1) / nchunk;
+  rows = ((rows + 63) / 64) * 64;
+  if (rows < 64) rows = 64;
+  nchunk = (m + rows - 1) / rows;
+  if (nchunk < 1) nchunk = 1;
+  *nchunk_out = (int)nchunk;
+  *rows_out = rows;
+  return nchunk * (int64_t)d * ncols_d;
+}
+
+template <int CT>
+static hipError_t launch_partial(hipStream_t st, dim3 grid, size_t lds, const double* A, int64_t lda_d,
+                                 int64_t m, int64_t ncols_d, int d, int zeta, uint64_t seed, int64_t rows,
+                                 double* part) {
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_sketch_partial<CT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_sketch_partial<CT>, grid, dim3(512), lds, st, A, lda_d, m, ncols_d, d, zeta, seed,
+                     rows, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_sketch(hipStream_t st, const double* A, int64_t lda_d, int64_t m, int64_t ncols_d,
+                         int es, int d, int zeta, uint64_t seed, double scale, double* part,
+                         double* Ycol, Ctl* ctl, int64_t lds_budget) {
+  int nchunk;
+  int64_t rows;
+  if (sketch_partial_doubles(m, ncols_d, d, lds_budget, &nchunk, &rows) < 0) return hipErrorInvalidValue;
+  const int ct = sketch_plan_ct(d, lds_budget);
+  const int64_t ntiles = (ncols_d + ct - 1) / ct;
+  dim3 grid((unsigned)ntiles, (unsigned)nchunk);
+  const size_t lds = (size_t)d * ct * sizeof(double);
+  hipError_t e;
+  switch (ct) {
+    case 32: e = launch_partial<32>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
+    case 16: e = launch_partial<16>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
+    case 8: e = launch_partial<8>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
+    case 4: e = launch_partial<4>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
+    case 2: e = launch_partial<2>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
+    default: e = launch_partial<1>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
+  }
+  if (e != hipSuccess) return e;
+  const int64_t total = (int64_t)d * ncols_d;
+  hipLaunchKernelGGL(k_sketch_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, part, nchunk,
+                     d, ncols_d, es, scale, Ycol, ctl);
+  return hipGetLastError();
+}
+
+}  // namespace rl

@@ -1,0 +1,522 @@
+// Host orchestration of RLOBPCG on one gfx950 GPU and the C-ABI of
+// include/rlobpcg.h.
+//
+// One solve (paper Sec. 1 steps 1-4; Alg. rlopcg / Alg. rlobpcg):
+//   setup  sketch S*A (one pass over A) -> Householder QR -> R, R^{-1}
+//          -> Sigma~(1,1) by Golub-Kahan-Lanczos on R
+//          -> start block: the smallest-b right singular subspace of R (= of
+//             S*A) by inverse subspace iteration with R^{-1} R^{-*}
+//          -> A_V = A V_0 and G_V = A^* A_V (one pass over A)
+//          -> Rayleigh-Ritz of A_V (b > 1 rotates V_0, A_V; b = 1 keeps v_0)
+//          -> R_0 = G_V - V_0 Theta^2
+//   loop   i = 0, 1, ...:
+//            A_V, A_X <- A_T C (coefficients of the previous Rayleigh-Ritz)
+//            W = R^{-1} (R^{-*} R_i)                       (eq:search-direction)
+//            BCGS2 of W against [V X], Orth(W)
+//            A_W = A W and G_W = A^* A_W                   (one pass over A)
+//            TSQR of A_T = [A_V A_X A_W] -> R_T; Jacobi SVD -> Theta, C
+//            V, G_V, R_{i+1}, stop rule, Q, X, G_X         (k_rr)
+//          The stop decision lives on the device (Ctl::done); every kernel of
+//          later iterations returns at once once it is set.  The host reads the
+//          flag only at iterations where the rule can fire.
+//   final  sigma ascending, V, and U = A_T C_V / theta.
+//
+// All device memory besides the caller's A and outputs is one workspace per
+// handle, grown on demand.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/rlobpcg.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace rl;
+
+struct rl_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  Ctl* host_ctl = nullptr;  // pinned
+  int64_t lds_budget = 64 * 1024;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> prof;  // pairs around A-stream launches
+};
+
+static int ensure_prof_events(rl_ctx* h, size_t pairs) {
+  while (h->prof.size() < 2 * pairs) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return RL_ERR_DEVICE;
+    h->prof.push_back(e);
+  }
+  return RL_OK;
+}
+
+static int rl_hip_fail(hipError_t, const char*) { return RL_ERR_DEVICE; }
+
+namespace {
+
+struct Arena {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    const size_t o = off;
+    off += bytes;
+    return o;
+  }
+};
+
+struct Layout {
+  size_t ctl, ht, hr, Y, part, Tm, Rrow, RH, Rinv, RinvH;
+  size_t V, X, W, Z, Vn, G3, Rres;
+  size_t AV, AX, AW, Gpart, Gtmp, tsA, tsB, CV, CX, thb, Ub, Vb;
+  size_t total;
+  int KL;
+};
+
+struct Problem {
+  int64_t m, n, d;
+  int B, k, zeta;
+  bool cplx;
+  size_t es;
+  int max_iter;
+};
+
+static Layout plan(const Problem& p, int64_t lds_budget) {
+  Layout L{};
+  Arena a;
+  const size_t es = p.es;
+  const int64_t n = p.n, m = p.m, B = p.B;
+  const int64_t ncols_d = n * (int64_t)(es / 8);
+  int nchunk;
+  int64_t rows;
+  const int64_t partd = sketch_partial_doubles(m, ncols_d, (int)p.d, lds_budget, &nchunk, &rows);
+  L.ctl = a.take(sizeof(Ctl));
+  L.ht = a.take(sizeof(double) * (size_t)(p.max_iter + 2) * B);
+  L.hr = a.take(sizeof(double) * (size_t)(p.max_iter + 2) * B);
+  L.Y = a.take(es * (size_t)p.d * n);
+  L.part = a.take(sizeof(double) * (size_t)std::max<int64_t>(partd, 1));
+  L.Tm = a.take(es * 32 * 32);
+  L.Rrow = a.take(es * (size_t)n * n);
+  L.RH = a.take(es * (size_t)n * n);
+  L.Rinv = a.take(es * (size_t)n * n);
+  L.RinvH = a.take(es * (size_t)n * n);
+  const size_t nb = es * (size_t)n * B;
+  L.V = a.take(nb);
+  L.X = a.take(nb);
+  L.W = a.take(nb);
+  L.Z = a.take(nb);
+  L.Vn = a.take(nb);
+  L.G3 = a.take(3 * nb);
+  L.Rres = a.take(nb);
+  const size_t mb = es * (size_t)m * B;
+  L.AV = a.take(mb);
+  L.AX = a.take(mb);
+  L.AW = a.take(mb);
+  const int es_d = (int)(es / 8);
+  L.Gpart = a.take(sizeof(double) * (size_t)astream_part_doubles(m, (int)n, (int)B, es_d));
+  L.Gtmp = a.take(sizeof(double) * (size_t)astream_tmp_doubles(m, (int)n, (int)B, es_d));
+  const int t = 3 * p.B;
+  const int64_t g = tsqr_groups(std::max<int64_t>(m, 1), t);
+  L.tsA = a.take(es * (size_t)g * t * t);
+  L.tsB = a.take(es * (size_t)g * t * t);
+  L.CV = a.take(es * 32 * 16);
+  L.CX = a.take(es * 32 * 16);
+  L.thb = a.take(sizeof(double) * 32);
+  L.KL = (int)std::min<int64_t>(n, 64);
+  L.Ub = a.take(es * (size_t)(L.KL + 1) * n);
+  L.Vb = a.take(es * (size_t)(L.KL + 1) * n);
+  L.total = a.off + 256;
+  return L;
+}
+
+static int ensure_ws(rl_ctx* h, size_t bytes) {
+  if (h->ws_bytes >= bytes) return RL_OK;
+  if (h->ws) {
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(h->ws);
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+  }
+  if (hipMalloc(&h->ws, bytes) != hipSuccess) {
+    h->ws = nullptr;
+    return RL_ERR_NOMEM;
+  }
+  h->ws_bytes = bytes;
+  return RL_OK;
+}
+
+template <typename P>
+static inline P* at(void* base, size_t off) {
+  return reinterpret_cast<P*>(static_cast<char*>(base) + off);
+}
+
+static int check_opts(int64_t m, int64_t n, int32_t k, const rl_opts& o) {
+  if (m < 1 || n < 1 || k < 1) return RL_ERR_ARG;
+  if (o.block < k || 3 * (int64_t)o.block > n || n > m) return RL_ERR_ARG;
+  if (o.d < n || o.zeta < 1 || o.zeta > o.d) return RL_ERR_ARG;
+  if (o.max_iter < 0 || o.check_every < 1) return RL_ERR_ARG;
+  if (o.stop_rule < 0 || o.stop_rule > 2) return RL_ERR_ARG;
+  if (o.init_iters < 0 || o.lanczos_steps < 1) return RL_ERR_ARG;
+  if (n > 1024 || o.block > 10) return RL_ERR_UNSUPPORTED;
+  if (o.d > INT32_MAX / 2) return RL_ERR_ARG;
+  return RL_OK;
+}
+
+#define CK(expr)                                 \
+  do {                                           \
+    hipError_t _e = (expr);                      \
+    if (_e != hipSuccess) return RL_ERR_DEVICE;  \
+  } while (0)
+
+static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int64_t lda, int32_t k,
+                 const rl_opts* opts_in, double* sigma, void* Vout, int64_t ldv, void* Uout, int64_t ldu,
+                 rl_info* info) {
+  if (!h || !A || !sigma || !Vout) return RL_ERR_ARG;
+  rl_opts o;
+  if (opts_in) o = *opts_in;
+  else rl_default_opts(&o, m, n, k);
+  int rc = check_opts(m, n, k, o);
+  if (rc != RL_OK) return rc;
+  if (lda < n || ldv < k || (Uout && ldu < k)) return RL_ERR_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;
+  Problem p{m, n, o.d, o.block, k, o.zeta, cplx, (size_t)(cplx ? 16 : 8), o.max_iter};
+  const Layout L = plan(p, h->lds_budget);
+  rc = ensure_ws(h, L.total);
+  if (rc != RL_OK) return rc;
+  hipStream_t st = h->stream;
+  void* ws = h->ws;
+  Ctl* ctl = at<Ctl>(ws, L.ctl);
+  const int B = o.block;
+  const bool dot2 = (o.dot2 != 0);
+  const int es_d = cplx ? 2 : 1;
+
+  // control block
+  Ctl hc;
+  memset(&hc, 0, sizeof(hc));
+  hc.stop_rule = o.stop_rule;
+  hc.check_every = o.check_every;
+  hc.max_iter = o.max_iter;
+  hc.b = B;
+  hc.tau = o.tau;
+  hc.status = 1;
+  *h->host_ctl = hc;
+  CK(hipEventRecord(h->ev[0], st));
+  CK(hipMemcpyAsync(ctl, h->host_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
+
+  // Step 1-2: sketch and QR
+  const double scale = 1.0 / sqrt((double)o.zeta);
+  CK(launch_sketch(st, (const double*)A, lda * es_d, m, n * es_d, es_d, (int)o.d, o.zeta, o.seed, scale,
+                   at<double>(ws, L.part), at<double>(ws, L.Y), ctl, h->lds_budget));
+  CK(launch_qr(st, cplx, at<void>(ws, L.Y), (int)o.d, (int)n, at<void>(ws, L.Tm), at<void>(ws, L.Rrow),
+               at<void>(ws, L.RH), at<void>(ws, L.Rinv), at<void>(ws, L.RinvH)));
+  // Sigma~(1,1)
+  const int KL = std::min<int>(L.KL, o.lanczos_steps);
+  CK(launch_lanczos(st, cplx, (int)n, at<void>(ws, L.Y), (int)o.d, at<void>(ws, L.Rrow), at<void>(ws, L.Ub),
+                    at<void>(ws, L.Vb), KL, o.seed ^ 0xA5A5A5A5ull, ctl));
+  // Step 3: start block from the smallest right singular subspace of R
+  CK(launch_randblk(st, cplx, at<void>(ws, L.W), n * B, o.seed ^ 0x3C3C3C3Cull));
+  CK(launch_orth(st, cplx, (int)n, B, nullptr, nullptr, 0, 0, at<void>(ws, L.W), ctl, 0));
+  for (int it = 0; it < o.init_iters; ++it) {
+    CK(launch_trmv(st, cplx, B, at<void>(ws, L.RinvH), (int)n, 1, at<void>(ws, L.W), at<void>(ws, L.Z), ctl, 0));
+    CK(launch_trmv(st, cplx, B, at<void>(ws, L.Rinv), (int)n, 0, at<void>(ws, L.Z), at<void>(ws, L.W), ctl, 0));
+    CK(launch_orth(st, cplx, (int)n, B, nullptr, nullptr, 0, 0, at<void>(ws, L.W), ctl, 0));
+  }
+  CK(hipMemcpyAsync(at<void>(ws, L.V), at<void>(ws, L.W), p.es * n * B, hipMemcpyDeviceToDevice, st));
+  const bool prof = o.profile != 0;
+  int nprof = 0;
+  if (prof) {
+    rc = ensure_prof_events(h, (size_t)o.max_iter + 1);
+    if (rc != RL_OK) return rc;
+    CK(hipEventRecord(h->prof[2 * nprof], st));
+  }
+  // start pass: A_V = A V_0 and A^* A_V (into the first block of G3)
+  CK(launch_astream(st, cplx, B, dot2, A, lda, m, (int)n, at<void>(ws, L.V), at<void>(ws, L.AV), nullptr, nullptr, 1,
+                    at<double>(ws, L.Gpart), at<double>(ws, L.Gtmp), at<double>(ws, L.G3), ctl));
+  if (prof) CK(hipEventRecord(h->prof[2 * nprof++ + 1], st));
+  void* Rt = nullptr;
+  CK(launch_tsqr(st, cplx, at<void>(ws, L.AV), B, nullptr, 0, nullptr, 0, m, at<void>(ws, L.tsA),
+                 at<void>(ws, L.tsB), &Rt, ctl, 0));
+  CK(launch_rr(st, cplx, (int)n, B, 1, 0, Rt, at<void>(ws, L.V), at<void>(ws, L.X), at<void>(ws, L.W),
+               at<void>(ws, L.G3), at<void>(ws, L.Vn), at<void>(ws, L.Rres), at<void>(ws, L.CV), at<void>(ws, L.CX),
+               at<double>(ws, L.thb), at<double>(ws, L.ht), at<double>(ws, L.hr), ctl));
+  CK(hipMemcpyAsync(h->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  CK(hipEventRecord(h->ev[1], st));
+  CK(hipStreamSynchronize(st));
+  if (h->host_ctl->nonfinite) return RL_ERR_NONFINITE;
+
+  // Step 4: LOBPCG
+  int it = 0;
+  for (; it < o.max_iter; ++it) {
+    CK(launch_panel(st, cplx, at<void>(ws, L.AV), at<void>(ws, L.AX), at<void>(ws, L.AW), m, B, at<void>(ws, L.CV),
+                    at<void>(ws, L.CX), ctl));
+    CK(launch_trmv(st, cplx, B, at<void>(ws, L.RinvH), (int)n, 1, at<void>(ws, L.Rres), at<void>(ws, L.Z), ctl, 1));
+    CK(launch_trmv(st, cplx, B, at<void>(ws, L.Rinv), (int)n, 0, at<void>(ws, L.Z), at<void>(ws, L.W), ctl, 1));
+    const int with_x = it > 0 ? 1 : 0;
+    CK(launch_orth(st, cplx, (int)n, B, at<void>(ws, L.V), at<void>(ws, L.X), 1, with_x, at<void>(ws, L.W), ctl, 1));
+    if (prof) CK(hipEventRecord(h->prof[2 * nprof], st));
+    CK(launch_astream(st, cplx, B, dot2, A, lda, m, (int)n, at<void>(ws, L.W), at<void>(ws, L.AW),
+                      at<void>(ws, L.AV), with_x ? at<void>(ws, L.AX) : nullptr, 0, at<double>(ws, L.Gpart),
+                      at<double>(ws, L.Gtmp), at<double>(ws, L.G3), ctl));
+    if (prof) CK(hipEventRecord(h->prof[2 * nprof++ + 1], st));
+    CK(launch_tsqr(st, cplx, at<void>(ws, L.AV), B, with_x ? at<void>(ws, L.AX) : nullptr, with_x ? B : 0,
+                   at<void>(ws, L.AW), B, m, at<void>(ws, L.tsA), at<void>(ws, L.tsB), &Rt, ctl, 1));
+    CK(launch_rr(st, cplx, (int)n, B, 0, with_x, Rt, at<void>(ws, L.V), at<void>(ws, L.X), at<void>(ws, L.W),
+                 at<void>(ws, L.G3), at<void>(ws, L.Vn), at<void>(ws, L.Rres), at<void>(ws, L.CV), at<void>(ws, L.CX),
+                 at<double>(ws, L.thb), at<double>(ws, L.ht), at<double>(ws, L.hr), ctl));
+    const bool can_stop = (o.stop_rule == RL_STOP_TOL) || (o.stop_rule == RL_STOP_PAPER && it % o.check_every == 0);
+    if (can_stop) {
+      CK(hipMemcpyAsync(h->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+      CK(hipStreamSynchronize(st));
+      if (h->host_ctl->done) {
+        ++it;
+        break;
+      }
+    }
+  }
+  CK(hipEventRecord(h->ev[2], st));
+  // outputs
+  CK(launch_final_n(st, cplx, (int)n, B, k, at<void>(ws, L.V), at<double>(ws, L.thb), sigma, Vout, ldv, ctl));
+  if (Uout)
+    CK(launch_final_u(st, cplx, at<void>(ws, L.AV), at<void>(ws, L.AX), at<void>(ws, L.AW), m, B, k,
+                      at<void>(ws, L.CV), at<double>(ws, L.thb), Uout, ldu, ctl));
+  CK(hipEventRecord(h->ev[3], st));
+  CK(hipMemcpyAsync(h->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  const Ctl& fc = *h->host_ctl;
+  const int status = fc.done ? RL_OK : RL_NOT_CONVERGED;
+  if (info) {
+    info->status = status;
+    info->iters = fc.iter;
+    info->a_passes = 2 + fc.iter;
+    info->degenerate = fc.degenerate;
+    info->zero_theta = fc.zero_theta;
+    info->block = B;
+    info->sigma1 = fc.sigma1;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, h->ev[0], h->ev[1]);
+    info->t_setup_us = 1e3 * ms;
+    (void)hipEventElapsedTime(&ms, h->ev[1], h->ev[2]);
+    info->t_iter_us = 1e3 * ms;
+    (void)hipEventElapsedTime(&ms, h->ev[2], h->ev[3]);
+    info->t_final_us = 1e3 * ms;
+    info->bytes_a = (int64_t)info->a_passes * m * n * (int64_t)p.es;
+    info->n_astream = prof ? nprof : 0;
+    info->t_astream_us = 0.0;
+    for (int q = 0; prof && q < nprof; ++q) {
+      float ka = 0.f;
+      (void)hipEventElapsedTime(&ka, h->prof[2 * q], h->prof[2 * q + 1]);
+      info->t_astream_us += 1e3 * ka;
+    }
+    if (info->hist_cap > 0) {
+      const int rowsh = std::min<int>(info->hist_cap, fc.iter + 1);
+      if (info->theta_hist)
+        CK(hipMemcpy(info->theta_hist, at<double>(ws, L.ht), sizeof(double) * rowsh * B, hipMemcpyDeviceToHost));
+      if (info->rnorm_hist)
+        CK(hipMemcpy(info->rnorm_hist, at<double>(ws, L.hr), sizeof(double) * rowsh * B, hipMemcpyDeviceToHost));
+    }
+  }
+  return status;
+}
+
+// Transpose a row-major d x n block (doubles per element es) into column-major.
+__global__ void k_rowmajor_to_col(const double* __restrict__ Y, int64_t ldy, int64_t d, int64_t n, int es,
+                                  double* __restrict__ Yc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d * n * es) return;
+  const int64_t comp = idx % es, e = idx / es;
+  const int64_t r = e / n, c = e % n;
+  Yc[(c * d + r) * es + comp] = Y[(r * ldy + c) * es + comp];
+}
+__global__ void k_col_to_rowmajor(const double* __restrict__ Yc, int64_t d, int64_t n, int es, double* __restrict__ Y,
+                                  int64_t ldy) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d * n * es) return;
+  const int64_t comp = idx % es, e = idx / es;
+  const int64_t r = e / n, c = e % n;
+  Y[(r * ldy + c) * es + comp] = Yc[(c * d + r) * es + comp];
+}
+
+}  // namespace
+
+extern "C" {
+
+int rl_create(rl_handle* out, int device, void* stream) {
+  if (!out) return RL_ERR_ARG;
+  *out = nullptr;
+  if (hipSetDevice(device) != hipSuccess) return RL_ERR_DEVICE;
+  rl_ctx* h = new (std::nothrow) rl_ctx();
+  if (!h) return RL_ERR_NOMEM;
+  h->device = device;
+  h->stream = (hipStream_t)stream;
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+    h->lds_budget = std::min<int64_t>(lds, 160 * 1024);
+  if (hipHostMalloc((void**)&h->host_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+    delete h;
+    return RL_ERR_NOMEM;
+  }
+  for (int i = 0; i < 4; ++i)
+    if (hipEventCreate(&h->ev[i]) != hipSuccess) {
+      rl_destroy(h);
+      return RL_ERR_DEVICE;
+    }
+  *out = h;
+  return RL_OK;
+}
+
+int rl_destroy(rl_handle h) {
+  if (!h) return RL_OK;
+  (void)hipSetDevice(h->device);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  if (h->ws) (void)hipFree(h->ws);
+  if (h->host_ctl) (void)hipHostFree(h->host_ctl);
+  for (int i = 0; i < 4; ++i)
+    if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
+  for (hipEvent_t e : h->prof) (void)hipEventDestroy(e);
+  delete h;
+  return RL_OK;
+}
+
+int rl_set_stream(rl_handle h, void* stream) {
+  if (!h) return RL_ERR_ARG;
+  h->stream = (hipStream_t)stream;
+  return RL_OK;
+}
+
+int rl_default_opts(rl_opts* o, int64_t m, int64_t n, int32_t k) {
+  (void)m;
+  if (!o) return RL_ERR_ARG;
+  memset(o, 0, sizeof(*o));
+  o->d = 4 * n;
+  o->zeta = 8;
+  o->block = k;
+  o->seed = 0;
+  o->tau = 2.0 * sqrt((double)n) * 2.220446049250313e-16;
+  o->max_iter = (k == 1) ? 200 : 100;
+  o->check_every = 5;
+  o->stop_rule = RL_STOP_PAPER;
+  o->dot2 = 1;
+  o->init_iters = 10;
+  o->lanczos_steps = 64;
+  return RL_OK;
+}
+
+int rl_svds_smallest_d(rl_handle h, int64_t m, int64_t n, const double* A, int64_t lda, int32_t k,
+                       const rl_opts* opts, double* sigma, double* V, int64_t ldv, double* U, int64_t ldu,
+                       rl_info* info) {
+  return solve(h, false, m, n, A, lda, k, opts, sigma, V, ldv, U, ldu, info);
+}
+
+int rl_svds_smallest_z(rl_handle h, int64_t m, int64_t n, const double* A, int64_t lda, int32_t k,
+                       const rl_opts* opts, double* sigma, double* V, int64_t ldv, double* U, int64_t ldu,
+                       rl_info* info) {
+  return solve(h, true, m, n, A, lda, k, opts, sigma, V, ldv, U, ldu, info);
+}
+
+int rl_step_sketch(rl_handle h, int is_complex, int64_t m, int64_t n, const double* A, int64_t lda, int64_t d,
+                   int32_t zeta, uint64_t seed, double* Y, int64_t ldy) {
+  if (!h || !A || !Y || m < 1 || n < 1 || lda < n || ldy < n || d < 1 || zeta < 1 || zeta > d) return RL_ERR_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;
+  const int es = is_complex ? 2 : 1;
+  int nchunk;
+  int64_t rows;
+  const int64_t partd = sketch_partial_doubles(m, n * es, (int)d, h->lds_budget, &nchunk, &rows);
+  if (partd < 0) return RL_ERR_UNSUPPORTED;
+  Arena a;
+  const size_t o_ctl = a.take(sizeof(Ctl)), o_part = a.take(sizeof(double) * partd),
+               o_yc = a.take(sizeof(double) * (size_t)d * n * es);
+  int rc = ensure_ws(h, a.off + 256);
+  if (rc != RL_OK) return rc;
+  hipStream_t st = h->stream;
+  CK(hipMemsetAsync(at<void>(h->ws, o_ctl), 0, sizeof(Ctl), st));
+  CK(launch_sketch(st, A, lda * es, m, n * es, es, (int)d, zeta, seed, 1.0 / sqrt((double)zeta),
+                   at<double>(h->ws, o_part), at<double>(h->ws, o_yc), at<Ctl>(h->ws, o_ctl), h->lds_budget));
+  const int64_t tot = d * n * es;
+  hipLaunchKernelGGL(k_col_to_rowmajor, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                     at<double>(h->ws, o_yc), d, n, es, Y, ldy);
+  CK(hipGetLastError());
+  CK(hipStreamSynchronize(st));
+  return RL_OK;
+}
+
+int rl_step_qr(rl_handle h, int is_complex, int64_t d, int64_t n, const double* Y, int64_t ldy, double* R,
+               double* Rinv) {
+  if (!h || !Y || !R || !Rinv || n < 1 || d < n || ldy < n || n > 4096) return RL_ERR_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;
+  const int es = is_complex ? 2 : 1;
+  const size_t esb = 8 * (size_t)es;
+  Arena a;
+  const size_t o_yc = a.take(esb * d * n), o_tm = a.take(esb * 32 * 32), o_rh = a.take(esb * n * n),
+               o_rih = a.take(esb * n * n);
+  int rc = ensure_ws(h, a.off + 256);
+  if (rc != RL_OK) return rc;
+  hipStream_t st = h->stream;
+  const int64_t tot = d * n * es;
+  hipLaunchKernelGGL(k_rowmajor_to_col, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Y, ldy, d, n, es,
+                     at<double>(h->ws, o_yc));
+  CK(hipGetLastError());
+  CK(launch_qr(st, is_complex != 0, at<void>(h->ws, o_yc), (int)d, (int)n, at<void>(h->ws, o_tm), R,
+               at<void>(h->ws, o_rh), Rinv, at<void>(h->ws, o_rih)));
+  CK(hipStreamSynchronize(st));
+  return RL_OK;
+}
+
+int rl_step_astream(rl_handle h, int is_complex, int64_t m, int64_t n, const double* A, int64_t lda, int32_t b,
+                    const double* W, double* AW, double* G, int32_t dot2) {
+  if (!h || !A || !W || !AW || !G || m < 1 || n < 1 || lda < n || b < 1) return RL_ERR_ARG;
+  if (n > 1024 || b > 10) return RL_ERR_UNSUPPORTED;
+  if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;
+  const int es = is_complex ? 2 : 1;
+  Arena a;
+  const size_t o_part = a.take(sizeof(double) * astream_part_doubles(m, (int)n, b, es)),
+               o_tmp = a.take(sizeof(double) * astream_tmp_doubles(m, (int)n, b, es)),
+               o_g3 = a.take(sizeof(double) * 3 * (size_t)n * b * es);
+  int rc = ensure_ws(h, a.off + 256);
+  if (rc != RL_OK) return rc;
+  hipStream_t st = h->stream;
+  CK(launch_astream(st, is_complex != 0, b, dot2 != 0, A, lda, m, (int)n, W, AW, nullptr, nullptr, 1,
+                    at<double>(h->ws, o_part), at<double>(h->ws, o_tmp), at<double>(h->ws, o_g3), nullptr));
+  CK(hipMemcpyAsync(G, at<double>(h->ws, o_g3), sizeof(double) * (size_t)n * b * es, hipMemcpyDeviceToDevice, st));
+  CK(hipStreamSynchronize(st));
+  return RL_OK;
+}
+
+int rl_step_tall_svd(rl_handle h, int is_complex, int64_t m, int32_t t, const double* P, double* sigma, double* C) {
+  if (!h || !P || !sigma || !C || m < 1 || t < 1 || t > 32) return RL_ERR_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;
+  const size_t esb = is_complex ? 16 : 8;
+  const int64_t g = tsqr_groups(m, t);
+  Arena a;
+  const size_t o_a = a.take(esb * g * t * t), o_b = a.take(esb * g * t * t), o_ctl = a.take(sizeof(Ctl));
+  int rc = ensure_ws(h, a.off + 256);
+  if (rc != RL_OK) return rc;
+  hipStream_t st = h->stream;
+  CK(hipMemsetAsync(at<void>(h->ws, o_ctl), 0, sizeof(Ctl), st));
+  void* Rt = nullptr;
+  CK(launch_tsqr(st, is_complex != 0, P, t, nullptr, 0, nullptr, 0, m, at<void>(h->ws, o_a), at<void>(h->ws, o_b),
+                 &Rt, at<Ctl>(h->ws, o_ctl), 0));
+  CK(launch_rt_svd(st, is_complex != 0, t, Rt, sigma, C));
+  CK(hipStreamSynchronize(st));
+  return RL_OK;
+}
+
+const char* rl_status_string(int code) {
+  switch (code) {
+    case RL_OK: return "ok";
+    case RL_NOT_CONVERGED: return "max_iter reached before the stopping rule held";
+    case RL_ERR_ARG: return "invalid argument";
+    case RL_ERR_DEVICE: return "HIP runtime error";
+    case RL_ERR_NOMEM: return "device allocation failed";
+    case RL_ERR_NONFINITE: return "NaN or Inf in the sketch or in R^{-1}";
+    case RL_ERR_UNSUPPORTED: return "shape outside the compiled kernels (n > 1024 or b > 10)";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

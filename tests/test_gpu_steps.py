@@ -1,0 +1,139 @@
+"""Step-level parity of the HIP kernels through the C-ABI step entry points."""
+
+import numpy as np
+import pytest
+
+from oracle import eft, sparsestack
+from workloads import integer_matrix
+
+from .gpu_util import banner, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def rl():
+    import paper_2602_16797_amd as rl
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return rl
+
+
+@pytest.mark.parametrize("m,n,d,zeta,cplx", [(10007, 37, 150, 8, False), (4096, 64, 256, 8, False),
+                                             (3001, 19, 77, 4, True), (2500, 10, 3000, 8, False),
+                                             (700, 9, 9, 9, False), (1234, 5, 40, 1, True)])
+def test_sketch_bit_exact_on_integers(rl, m, n, d, zeta, cplx):
+    banner(f"sketch integer m={m} n={n} d={d} zeta={zeta} complex={cplx}")
+    A = integer_matrix(m, n, 7 + m, is_complex=cplx)
+    Y = to_np(rl.rl_step_sketch(torch.from_numpy(A).cuda(), d, zeta, 1234 + d))
+    Yo = sparsestack.sketch(A, d, zeta, 1234 + d)
+    assert np.array_equal(Y, Yo)
+
+
+def test_sketch_float_close_and_deterministic(rl):
+    banner("sketch float 200000x120, d=480")
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((200_000, 120))
+    At = torch.from_numpy(A).cuda()
+    Y1 = to_np(rl.rl_step_sketch(At, 480, 8, 99))
+    Y2 = to_np(rl.rl_step_sketch(At, 480, 8, 99))
+    assert np.array_equal(Y1, Y2)                     # fixed reduction order
+    Yo = sparsestack.sketch(A, 480, 8, 99)
+    S = sparsestack.embedding(200_000, 480, 8, 99)
+    scale = abs(S) @ np.abs(A) / np.sqrt(8)           # sum of |terms| per entry
+    assert np.all(np.abs(Y1 - Yo) <= 2 * 200_000 * U * scale + 1e-300)
+
+
+def test_sketch_strided_lda(rl):
+    A = integer_matrix(999, 40, 5)
+    At = torch.from_numpy(A).cuda()[:, 3:33]           # lda = 40, n = 30
+    Y = to_np(rl.rl_step_sketch(At, 64, 8, 5))
+    assert np.array_equal(Y, sparsestack.sketch(A[:, 3:33], 64, 8, 5))
+
+
+@pytest.mark.parametrize("d,n,cplx", [(800, 200, False), (150, 37, False), (96, 33, True), (64, 64, False),
+                                      (3000, 70, True)])
+def test_qr_and_inverse(rl, d, n, cplx):
+    banner(f"qr d={d} n={n} complex={cplx}")
+    rng = np.random.default_rng(d + n)
+    Y = rng.standard_normal((d, n)) * np.logspace(0, -6, n)[None, :]
+    if cplx:
+        Y = Y + 1j * rng.standard_normal((d, n)) * np.logspace(0, -6, n)[None, :]
+    R, Rinv = rl.rl_step_qr(torch.from_numpy(Y).cuda())
+    R, Rinv = to_np(R), to_np(Rinv)
+    assert np.all(np.abs(np.tril(R, -1)) == 0) and np.all(np.abs(np.tril(Rinv, -1)) == 0)
+    assert np.all(np.abs(np.diag(R).imag) == 0) if cplx else True
+    Rn = np.linalg.qr(Y, mode="r")
+    ph = np.diag(Rn) / np.diag(R)
+    assert np.allclose(np.abs(ph), 1.0, rtol=1e-10)
+    Radj = ph[:, None] * R
+    # rows of R agree with LAPACK's up to a unit phase (R is unique up to phases)
+    assert np.linalg.norm(Radj - Rn) <= 1e-12 * np.linalg.norm(Rn) * np.sqrt(n)
+    # Q = Y R^{-1} is orthonormal and R^{-1} inverts R
+    Q = Y @ Rinv
+    assert np.linalg.norm(Q.conj().T @ Q - np.eye(n)) <= 1e-10
+    assert np.linalg.norm(R @ Rinv - np.eye(n)) <= 1e-10
+
+
+@pytest.mark.parametrize("m,n,b,cplx,dot2", [(5003, 37, 1, False, False), (5003, 37, 1, False, True),
+                                             (20000, 200, 1, False, True), (7777, 513, 5, False, True),
+                                             (3000, 256, 3, False, False), (2049, 65, 2, True, False),
+                                             (2049, 65, 2, True, True), (1500, 1000, 10, True, False), (999, 1024, 10, False, True)])
+def test_astream(rl, m, n, b, cplx, dot2):
+    banner(f"astream m={m} n={n} b={b} complex={cplx} dot2={dot2}")
+    rng = np.random.default_rng(m + n + b)
+    A = rng.standard_normal((m, n))
+    W = rng.standard_normal((n, b))
+    if cplx:
+        A = A + 1j * rng.standard_normal((m, n))
+        W = W + 1j * rng.standard_normal((n, b))
+    AW, G = rl.rl_step_astream(torch.from_numpy(A).cuda(), torch.from_numpy(W).cuda(), dot2=dot2)
+    AW, G = to_np(AW), to_np(G)
+    if dot2:
+        ref = eft.matmul(A, W)
+        tol = 2 * U * np.abs(ref) + 4 * (n * U) ** 2 * (np.abs(A) @ np.abs(W))
+        assert np.all(np.abs(AW - ref) <= tol)
+    else:
+        bound = 2 * n * U * (np.abs(A) @ np.abs(W))
+        assert np.all(np.abs(AW - A @ W) <= bound)
+    Gref = A.conj().T @ AW
+    gb = 2 * m * U * (np.abs(A).T @ np.abs(AW))
+    assert np.all(np.abs(G - Gref) <= gb)
+    if dot2:   # A^* AW is a Dot2-class sum too
+        G2 = eft.matmul_h(A, AW)
+        gb2 = 2 * U * np.abs(G2) + 4 * (np.log2(2 * m) * U) ** 2 * (np.abs(A).T @ np.abs(AW))
+        assert np.all(np.abs(G - G2) <= gb2)
+
+
+def test_astream_cancellation_needs_dot2(rl):
+    """On a graded A with A w tiny, Dot2 gives A w to full relative accuracy."""
+    m, n = 4000, 200
+    rng = np.random.default_rng(5)
+    Q, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    Vq, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = np.logspace(0, -12, n)
+    A = (Q * s) @ Vq.T
+    w = Vq[:, -1:].copy()
+    AW, _ = rl.rl_step_astream(torch.from_numpy(A).cuda(), torch.from_numpy(w).cuda(), dot2=True)
+    ref = eft.matmul(A, w)
+    assert np.max(np.abs(to_np(AW) - ref) / np.abs(ref)) <= 4 * U + 1e-13
+
+
+@pytest.mark.parametrize("m,t,cplx", [(100_000, 3, False), (20_000, 15, False), (5000, 30, True),
+                                      (777, 2, False), (300, 1, True), (4096, 32, False)])
+def test_tall_svd(rl, m, t, cplx):
+    banner(f"tall svd m={m} t={t} complex={cplx}")
+    rng = np.random.default_rng(m + t)
+    Qa, _ = np.linalg.qr(rng.standard_normal((m, t)) + (1j * rng.standard_normal((m, t)) if cplx else 0))
+    Qb, _ = np.linalg.qr(rng.standard_normal((t, t)) + (1j * rng.standard_normal((t, t)) if cplx else 0))
+    s = np.logspace(0, -10, t)
+    P = (Qa * s) @ Qb.conj().T
+    sg, C = rl.rl_step_tall_svd(torch.from_numpy(np.ascontiguousarray(P)).cuda())
+    sg, C = to_np(sg), to_np(C)
+    assert np.all(np.abs(sg - s) <= 1e-12 * s + 1e-15 * s[0])   # graded: relative accuracy
+    assert np.linalg.norm(C.conj().T @ C - np.eye(t)) <= 1e-12
+    # ||P c_j|| = sigma_j (normwise-accurate singular pairs)
+    assert np.all(np.abs(np.linalg.norm(P @ C, axis=0) - sg) <= 1e-14 * s[0])

@@ -160,11 +160,11 @@ def planted_torch(m: int, n: int, sigma, seed: int, *, device="cuda",
             blk = X[r0:r0 + row_chunk]
             Gm += blk.conj().T.contiguous() @ blk
         L = torch.linalg.cholesky(Gm)
-        # X <- X L^{-H}
+        # X <- X L^{-H}, with the small n x n inverse formed once
+        eye = torch.eye(n, device=device, dtype=dt)
+        Linv_h = torch.linalg.solve_triangular(L, eye, upper=False).conj().T.contiguous()
         for r0 in range(0, m, row_chunk):
-            blk = X[r0:r0 + row_chunk]
-            X[r0:r0 + row_chunk] = torch.linalg.solve_triangular(
-                L.conj(), blk.T, upper=False).T
+            X[r0:r0 + row_chunk] = X[r0:r0 + row_chunk] @ Linv_h
     H = gauss((n, n))
     V, _ = torch.linalg.qr(H)
     s = torch.as_tensor(np.asarray(sigma, dtype=np.float64), device=device)
