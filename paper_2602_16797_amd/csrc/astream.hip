@@ -26,173 +26,10 @@
 // k_panel     A_V <- A_T C_V, A_X <- A_T C_X (row-local, in place).
 // k_final_u   U(:, j) = (A_T C_V)(:, b-1-j) / theta_{b-1-j} for the outputs.
 #include "common.hpp"
+#include "astream_kernels.hpp"
 #include "kernels.hpp"
 
 namespace rl {
-
-template <int B>
-struct RowsPerBatch {
-  static constexpr int value = (B >= 8) ? 1 : (B >= 4 ? 2 : (B >= 2 ? 4 : 8));
-};
-
-// Dot2 accumulation: s + e carries the running sum to about twice the working
-// precision (TwoProduct by FMA, TwoSum by Knuth); the wave butterfly combines
-// the lanes' (s, e) pairs the same way.
-__device__ inline void dot2_add(double a, double b, double& s, double& e) {
-  double p, ep, t;
-  two_prod(a, b, p, ep);
-  two_sum(s, p, s, t);
-  e += t + ep;
-}
-__device__ inline void dot2_wave(double& s, double& e) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const double s2 = __shfl_xor(s, o, WAVE);
-    const double e2 = __shfl_xor(e, o, WAVE);
-    double t;
-    two_sum(s, s2, s, t);
-    e = e + e2 + t;
-  }
-}
-template <int NS, int B>
-__device__ inline double dot2_row(const double (&a)[NS], const double (&w)[NS][B], int j) {
-  double s = 0.0, e = 0.0;
-#pragma unroll
-  for (int k = 0; k < NS; ++k) dot2_add(a[k], w[k][j], s, e);
-  dot2_wave(s, e);
-  return s + e;
-}
-// complex: Re = sum a.x w.x - a.y w.y, Im = sum a.x w.y + a.y w.x, each a real Dot2
-template <int NS, int B>
-__device__ inline cd dot2_row(const cd (&a)[NS], const cd (&w)[NS][B], int j) {
-  double sr = 0.0, er = 0.0, si = 0.0, ei = 0.0;
-#pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    dot2_add(a[k].x, w[k][j].x, sr, er);
-    dot2_add(-a[k].y, w[k][j].y, sr, er);
-    dot2_add(a[k].x, w[k][j].y, si, ei);
-    dot2_add(a[k].y, w[k][j].x, si, ei);
-  }
-  dot2_wave(sr, er);
-  dot2_wave(si, ei);
-  return cd{sr + er, si + ei};
-}
-// (s, e) += conj(a) * v as Dot2 pairs (component-wise for complex)
-__device__ inline void dot2_cacc(double a, double v, double& s, double& e) { dot2_add(a, v, s, e); }
-__device__ inline void dot2_cacc(cd a, cd v, cd& s, cd& e) {
-  dot2_add(a.x, v.x, s.x, e.x);
-  dot2_add(a.y, v.y, s.x, e.x);
-  dot2_add(a.x, v.y, s.y, e.y);
-  dot2_add(-a.y, v.x, s.y, e.y);
-}
-
-template <typename T, int B, int NS, bool DOT2>
-__global__ __launch_bounds__(256) void k_astream(const T* __restrict__ A, int64_t lda, int64_t m, int n,
-                                                 const T* __restrict__ W, T* __restrict__ AW,
-                                                 const T* __restrict__ AVp, const T* __restrict__ AXp, int init,
-                                                 T* __restrict__ Gpart, int64_t rows_per_block,
-                                                 const Ctl* __restrict__ ctl) {
-  if (ctl != nullptr && ctl->done) return;
-  constexpr int RB = RowsPerBatch<B>::value;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const bool has_v = AVp != nullptr, has_x = AXp != nullptr;
-  T w[NS][B];
-  T g1s[NS][B], g1e[NS][B], gx[NS][B], gw[NS][B];
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const int c = lane + 64 * s;
-#pragma unroll
-    for (int j = 0; j < B; ++j) {
-      w[s][j] = (c < n) ? W[(int64_t)c * B + j] : zero<T>();
-      g1s[s][j] = zero<T>();
-      g1e[s][j] = zero<T>();
-      gx[s][j] = zero<T>();
-      gw[s][j] = zero<T>();
-    }
-  }
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
-  const int64_t r1 = (r0 + rows_per_block < m) ? r0 + rows_per_block : m;
-  for (int64_t rb = r0 + (int64_t)wave * RB; rb < r1; rb += 4 * RB) {
-    T a[RB][NS];
-#pragma unroll
-    for (int q = 0; q < RB; ++q) {
-      const int64_t row = rb + q;
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const int c = lane + 64 * s;
-        a[q][s] = (row < r1 && c < n) ? A[row * lda + c] : zero<T>();
-      }
-    }
-    T av[RB][B], ax[RB][B];
-#pragma unroll
-    for (int q = 0; q < RB; ++q) {
-      const int64_t row = rb + q;
-#pragma unroll
-      for (int j = 0; j < B; ++j) {
-        av[q][j] = (has_v && row < r1) ? AVp[row * B + j] : zero<T>();
-        ax[q][j] = (has_x && row < r1) ? AXp[row * B + j] : zero<T>();
-      }
-    }
-    T y[RB][B];
-#pragma unroll
-    for (int q = 0; q < RB; ++q) {
-#pragma unroll
-      for (int j = 0; j < B; ++j) {
-        if constexpr (DOT2) {
-          y[q][j] = dot2_row(a[q], w, j);
-        } else {
-          T acc = zero<T>();
-#pragma unroll
-          for (int s = 0; s < NS; ++s) acc = fmac(a[q][s], w[s][j], acc);
-          y[q][j] = wave_sum(acc);
-        }
-      }
-    }
-    // lane q*B + j writes y[q][j]: RB*B consecutive elements of A_W
-    T out = zero<T>();
-#pragma unroll
-    for (int q = 0; q < RB; ++q)
-#pragma unroll
-      for (int j = 0; j < B; ++j)
-        if (lane == q * B + j) out = y[q][j];
-    if (lane < RB * B) {
-      const int64_t row = rb + lane / B;
-      if (row < r1) AW[rb * B + lane] = out;
-    }
-    // column sums: group 1 (Dot2) is A^* A_V, or A^* A_W in the start pass
-#pragma unroll
-    for (int q = 0; q < RB; ++q)
-#pragma unroll
-      for (int s = 0; s < NS; ++s)
-#pragma unroll
-        for (int j = 0; j < B; ++j) {
-          const T v1 = init ? y[q][j] : av[q][j];
-          if constexpr (DOT2) dot2_cacc(a[q][s], v1, g1s[s][j], g1e[s][j]);
-          else g1s[s][j] = cfmac(a[q][s], v1, g1s[s][j]);
-          if (!init) {
-            gx[s][j] = cfmac(a[q][s], ax[q][j], gx[s][j]);
-            gw[s][j] = cfmac(a[q][s], y[q][j], gw[s][j]);
-          }
-        }
-  }
-  // per wave: sums [G1 | G_X | G_W] (3 n B) then the G1 errors (n B)
-  const int64_t plane = (int64_t)n * B;
-  T* gp = Gpart + ((int64_t)blockIdx.x * 4 + wave) * 4 * plane;
-#pragma unroll
-  for (int s = 0; s < NS; ++s) {
-    const int c = lane + 64 * s;
-    if (c < n) {
-#pragma unroll
-      for (int j = 0; j < B; ++j) {
-        const int64_t e = (int64_t)c * B + j;
-        gp[e] = g1s[s][j];
-        gp[plane + e] = gx[s][j];
-        gp[2 * plane + e] = gw[s][j];
-        gp[3 * plane + e] = g1e[s][j];
-      }
-    }
-  }
-}
 
 // Compensated, deterministic sum over parts.  Input part p has sums at
 // in_s[p*stride + e] and, for e < elen, errors at in_e[p*stride + e];
@@ -339,40 +176,6 @@ int64_t astream_tmp_doubles(int64_t m, int n, int B, int es_d) {
   return 4 * groups * 3 * (int64_t)n * B * es_d;
 }
 
-template <typename T, int B, int NS, bool DOT2>
-static void launch_as(hipStream_t st, int64_t nb, const void* A, int64_t lda, int64_t m, int n, const void* W,
-                      void* AW, const void* AVp, const void* AXp, int init, void* Gpart, const Ctl* ctl) {
-  const int64_t rows = (m + nb - 1) / nb;
-  hipLaunchKernelGGL((k_astream<T, B, NS, DOT2>), dim3((unsigned)nb), dim3(256), 0, st, (const T*)A, lda, m, n,
-                     (const T*)W, (T*)AW, (const T*)AVp, (const T*)AXp, init, (T*)Gpart, rows, ctl);
-}
-
-template <typename T, int NS, bool DOT2>
-static bool dispatch_b(int B, hipStream_t st, int64_t nb, const void* A, int64_t lda, int64_t m, int n,
-                       const void* W, void* AW, const void* AVp, const void* AXp, int init, void* Gpart,
-                       const Ctl* ctl) {
-  switch (B) {
-#define RL_CASE(BB) \
-  case BB: launch_as<T, BB, NS, DOT2>(st, nb, A, lda, m, n, W, AW, AVp, AXp, init, Gpart, ctl); return true;
-    RL_CASE(1) RL_CASE(2) RL_CASE(3) RL_CASE(4) RL_CASE(5)
-    RL_CASE(6) RL_CASE(7) RL_CASE(8) RL_CASE(9) RL_CASE(10)
-#undef RL_CASE
-    default: return false;
-  }
-}
-
-template <typename T, bool DOT2>
-static bool dispatch_ns(int ns, int B, hipStream_t st, int64_t nb, const void* A, int64_t lda, int64_t m, int n,
-                        const void* W, void* AW, const void* AVp, const void* AXp, int init, void* Gpart,
-                        const Ctl* ctl) {
-  switch (ns) {
-    case 4: return dispatch_b<T, 4, DOT2>(B, st, nb, A, lda, m, n, W, AW, AVp, AXp, init, Gpart, ctl);
-    case 8: return dispatch_b<T, 8, DOT2>(B, st, nb, A, lda, m, n, W, AW, AVp, AXp, init, Gpart, ctl);
-    case 16: return dispatch_b<T, 16, DOT2>(B, st, nb, A, lda, m, n, W, AW, AVp, AXp, init, Gpart, ctl);
-    default: return false;
-  }
-}
-
 // One pass: AW = A W and G3 = A^* [AVp AXp AW] (n x 3B, contiguous; init: G3[:, 0:B] = A^* AW).
 hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const void* A, int64_t lda, int64_t m, int n,
                           const void* W, void* AW, const void* AVp, const void* AXp, int init, double* Gpart,
@@ -381,14 +184,14 @@ hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const voi
   const int ns = astream_ns(n);
   const int64_t nb = astream_blocks(m, n, B, es_d);
   bool ok;
-  if (cplx && dot2)
-    ok = dispatch_ns<cd, true>(ns, B, st, nb, A, lda, m, n, W, AW, AVp, AXp, init, Gpart, ctl);
+  const bool aligned = (lda % 2 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  if (!cplx && n <= 256)
+    ok = dispatch_astream_r2(dot2, init, aligned ? 1 : 0, B, st, nb, (const double*)A, lda, m, n, (const double*)W,
+                             (double*)AW, (const double*)AVp, (const double*)AXp, Gpart, ctl);
   else if (cplx)
-    ok = dispatch_ns<cd, false>(ns, B, st, nb, A, lda, m, n, W, AW, AVp, AXp, init, Gpart, ctl);
-  else if (dot2)
-    ok = dispatch_ns<double, true>(ns, B, st, nb, A, lda, m, n, W, AW, AVp, AXp, init, Gpart, ctl);
+    ok = dispatch_astream_gc(dot2, ns, B, st, nb, A, lda, m, n, W, AW, AVp, AXp, init, Gpart, ctl);
   else
-    ok = dispatch_ns<double, false>(ns, B, st, nb, A, lda, m, n, W, AW, AVp, AXp, init, Gpart, ctl);
+    ok = dispatch_astream_gd(dot2, ns, B, st, nb, A, lda, m, n, W, AW, AVp, AXp, init, Gpart, ctl);
   if (!ok) return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

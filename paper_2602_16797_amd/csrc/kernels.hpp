@@ -25,6 +25,15 @@ int astream_ns(int n);
 int64_t astream_blocks(int64_t m, int n, int B, int es_d);
 int64_t astream_part_doubles(int64_t m, int n, int B, int es_d);
 int64_t astream_tmp_doubles(int64_t m, int n, int B, int es_d);
+bool dispatch_astream_r2(bool dot2, int init, int aligned, int B, hipStream_t st, int64_t nb, const double* A,
+                         int64_t lda, int64_t m, int n, const double* W, double* AW, const double* AVp,
+                         const double* AXp, double* Gpart, const Ctl* ctl);
+bool dispatch_astream_gd(bool dot2, int ns, int B, hipStream_t st, int64_t nb, const void* A, int64_t lda, int64_t m,
+                         int n, const void* W, void* AW, const void* AVp, const void* AXp, int init, double* Gpart,
+                         const Ctl* ctl);
+bool dispatch_astream_gc(bool dot2, int ns, int B, hipStream_t st, int64_t nb, const void* A, int64_t lda, int64_t m,
+                         int n, const void* W, void* AW, const void* AVp, const void* AXp, int init, double* Gpart,
+                         const Ctl* ctl);
 hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const void* A, int64_t lda, int64_t m, int n,
                           const void* W, void* AW, const void* AVp, const void* AXp, int init, double* Gpart,
                           double* tmp, double* G3, const Ctl* ctl);
