@@ -178,11 +178,6 @@ __global__ __launch_bounds__(256) void k_astream(const T* __restrict__ A, int64_
 // halves the values each lane carries at every butterfly stage, so a batch of
 // V values costs about 2V + 6 shuffles instead of 12 per value; the finished
 // sums are broadcast to every lane with scalar readlanes.
-__device__ inline double readlane_d(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
-}
 
 template <int V2, int LOG2V>
 __device__ inline void tr_reduce_dot2(double (&s)[V2], double (&e)[V2], int lane) {

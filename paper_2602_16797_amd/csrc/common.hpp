@@ -72,23 +72,48 @@ __device__ inline cd divs(cd a, cd b) {
 }
 
 // ----- wave-level reductions (64 lanes) --------------------------------------
+// Within each row of 16 lanes the sums use DPP lane permutations (pairs, quads,
+// half-row mirror, row mirror), which run at ALU latency; the four row sums are
+// then combined from scalar readlanes, so every lane gets the same value and
+// the summation order is fixed.  Callers must have the whole wave active.
+__device__ inline double readlane_d(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int DPP_QUAD_1032 = 0xB1;       // quad_perm [1,0,3,2]: partner lane ^ 1
+constexpr int DPP_QUAD_2301 = 0x4E;       // quad_perm [2,3,0,1]: partner lane ^ 2
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;  // lane 7-j within 8
+constexpr int DPP_ROW_MIRROR = 0x140;       // lane 15-j within 16
+
+// sum over the 16 lanes of each row, result in every lane of the row
+__device__ inline double row_sum16(double v) {
+  v += dpp_d<DPP_QUAD_1032>(v);
+  v += dpp_d<DPP_QUAD_2301>(v);
+  v += dpp_d<DPP_ROW_HALF_MIRROR>(v);
+  v += dpp_d<DPP_ROW_MIRROR>(v);
+  return v;
+}
+__device__ inline cd row_sum16(cd v) { return cd{row_sum16(v.x), row_sum16(v.y)}; }
+
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, WAVE);
-  return v;
+  v = row_sum16(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
-__device__ inline cd wave_sum(cd v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    v.x += __shfl_xor(v.x, o, WAVE);
-    v.y += __shfl_xor(v.y, o, WAVE);
-  }
-  return v;
-}
+__device__ inline cd wave_sum(cd v) { return cd{wave_sum(v.x), wave_sum(v.y)}; }
+__device__ inline cd readlane_d(cd v, int l) { return cd{readlane_d(v.x, l), readlane_d(v.y, l)}; }
 __device__ inline double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
-  return v;
+  v = fmax(v, dpp_d<DPP_QUAD_1032>(v));
+  v = fmax(v, dpp_d<DPP_QUAD_2301>(v));
+  v = fmax(v, dpp_d<DPP_ROW_HALF_MIRROR>(v));
+  v = fmax(v, dpp_d<DPP_ROW_MIRROR>(v));
+  return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
 }
 __device__ inline double shfl(double v, int src) { return __shfl(v, src, WAVE); }
 __device__ inline cd shfl(cd v, int src) { return cd{__shfl(v.x, src, WAVE), __shfl(v.y, src, WAVE)}; }
@@ -106,6 +131,30 @@ __device__ inline T block_sum(T v, T* red) {
   T s = zero<T>();
   for (int w = 0; w < nw; ++w) s = add(s, red[w]);
   return s;
+}
+
+// Block-wide sums of vals[0..K) (K block-uniform, K <= KMAX); out[k] gets
+// sum k.  Each value is reduced over its 16-lane row by DPP, the row sums go
+// through LDS.  `scratch` must hold (blockDim.x / 16) * KMAX values of T.
+// Contains two __syncthreads.
+template <typename T, int KMAX>
+__device__ inline void block_sum_many(T (&vals)[KMAX], int K, T* scratch, T* out) {
+  const int row = threadIdx.x >> 4;
+  const int nrows = blockDim.x >> 4;
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    if (k < K) {
+      const T v = row_sum16(vals[k]);
+      if ((threadIdx.x & 15) == 0) scratch[row * KMAX + k] = v;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < K) {
+    T s = zero<T>();
+    for (int r = 0; r < nrows; ++r) s = add(s, scratch[r * KMAX + threadIdx.x]);
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
 }
 
 // ----- error-free transformations (Knuth TwoSum, FMA TwoProduct) -------------

@@ -45,7 +45,7 @@ hipError_t launch_final_u(hipStream_t st, bool cplx, const void* AV, const void*
 // tsqr.hip
 int64_t tsqr_groups(int64_t m, int t);
 hipError_t launch_tsqr(hipStream_t st, bool cplx, const void* P0, int b0, const void* P1, int b1, const void* P2,
-                       int b2, int64_t m, void* bufA, void* bufB, void** Rfinal, const Ctl* ctl, int check_done);
+                       int b2, int64_t m, void* bufA, void* bufB, void** Rfinal, Ctl* ctl, int check_done);
 
 // nside.hip
 hipError_t launch_trmv(hipStream_t st, bool cplx, int B, const void* M, int n, int lower, const void* X, void* Y,

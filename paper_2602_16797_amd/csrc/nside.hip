@@ -33,26 +33,6 @@ __device__ inline cd shfl_xor_(cd v, int o) { return cd{__shfl_xor(v.x, o, WAVE)
 __device__ inline double absval(double a) { return fabs(a); }
 __device__ inline double absval(cd a) { return hypot(a.x, a.y); }
 
-template <typename T, int KMAX>
-__device__ inline void nblock_sum_many(T (&vals)[KMAX], int K, T* scratch, T* out) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int nw = blockDim.x >> 6;
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
-    if (k < K) {
-      T v = wave_sum(vals[k]);
-      if (lane == 0) scratch[wid * KMAX + k] = v;
-    }
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < K) {
-    T s = zero<T>();
-    for (int w = 0; w < nw; ++w) s = add(s, scratch[w * KMAX + threadIdx.x]);
-    out[threadIdx.x] = s;
-  }
-  __syncthreads();
-}
-
 // ---------------------------------------------------------------------------
 template <typename T, int B>
 __global__ __launch_bounds__(NS_THREADS) void k_trmv(const T* __restrict__ M, int n, int lower,
@@ -103,10 +83,9 @@ __global__ __launch_bounds__(NS_THREADS) void k_trmv(const T* __restrict__ M, in
 // second removed more than half of what was left (the usual "twice is enough"
 // safeguard).  A column that vanishes is completed by the first unit vector
 // that keeps norm above 1/2 after the same projections.
-template <typename T>
+template <typename T, int KM>
 __device__ void orth_project(int n, int B, int j, const T* __restrict__ V, const T* __restrict__ X, int nvx,
                              T* __restrict__ W, T* scratch, T* h) {
-  constexpr int KM = 3 * RR_BMAX;
   const int K = nvx + j;
   T vals[KM];
 #pragma unroll
@@ -122,7 +101,7 @@ __device__ void orth_project(int n, int B, int j, const T* __restrict__ V, const
       }
     }
   }
-  nblock_sum_many<T, KM>(vals, K, scratch, h);
+  block_sum_many<T, KM>(vals, K, scratch, h);
   for (int r = threadIdx.x; r < n; r += blockDim.x) {
     T wr = W[(int64_t)r * B + j];
     for (int k = 0; k < K; ++k) {
@@ -142,13 +121,13 @@ __device__ double col_norm(int n, int B, int j, const T* __restrict__ W, double*
   return sqrt(block_sum(s, red));
 }
 
-template <typename T>
+// KM bounds the number of projections of one column, 3B - 1.
+template <typename T, int KM>
 __global__ __launch_bounds__(NS_THREADS) void k_orth(int n, int B, const T* __restrict__ V, const T* __restrict__ X,
                                                      int project, int with_x, T* __restrict__ W, Ctl* __restrict__ ctl,
                                                      int check_done) {
   if (check_done && ctl->done) return;
-  constexpr int KM = 3 * RR_BMAX;
-  __shared__ T scratch[(NS_THREADS / 64) * KM];
+  __shared__ T scratch[(NS_THREADS / 16) * KM];
   __shared__ T h[KM];
   __shared__ double red[NS_THREADS / 64];
   const int nvx = project ? (with_x ? 2 * B : B) : 0;
@@ -160,12 +139,12 @@ __global__ __launch_bounds__(NS_THREADS) void k_orth(int n, int B, const T* __re
         __syncthreads();
       }
       if (nvx + j > 0) {
-        orth_project<T>(n, B, j, V, X, nvx, W, scratch, h);
+        orth_project<T, KM>(n, B, j, V, X, nvx, W, scratch, h);
         const double n1 = col_norm<T>(n, B, j, W, red);
-        orth_project<T>(n, B, j, V, X, nvx, W, scratch, h);
+        orth_project<T, KM>(n, B, j, V, X, nvx, W, scratch, h);
         nrm = col_norm<T>(n, B, j, W, red);
         if (nrm < 0.5 * n1) {
-          orth_project<T>(n, B, j, V, X, nvx, W, scratch, h);
+          orth_project<T, KM>(n, B, j, V, X, nvx, W, scratch, h);
           nrm = col_norm<T>(n, B, j, W, red);
         }
       } else {
@@ -264,7 +243,7 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int B, int init_mode, 
   __shared__ double th[RR_TMAX];
   __shared__ double sig[RR_TMAX];
   __shared__ double rn[RR_BMAX];
-  __shared__ T scratch[(NS_THREADS / 64) * RR_BMAX];
+  __shared__ T scratch[(NS_THREADS / 16) * RR_BMAX];
   __shared__ T hsum[RR_BMAX];
   __shared__ int stop_s;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -348,7 +327,7 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int B, int init_mode, 
         }
       }
     }
-    nblock_sum_many<T, RR_BMAX>(vals, B, scratch, hsum);
+    block_sum_many<T, RR_BMAX>(vals, B, scratch, hsum);
     if (tid < B) rn[tid] = sqrt(re_(hsum[tid]));
     __syncthreads();
   }
@@ -466,155 +445,177 @@ __global__ void k_randblk(T* __restrict__ Wb, int64_t count, uint64_t seed) {
 }
 
 // Golub-Kahan-Lanczos on R (upper triangular, R(i,l) = Ycol[l*ld + i] = Rrow[i*n + l]).
+// One workgroup of 1024 threads (16 waves); thread t keeps entry t of the
+// current u and v in registers (n <= 1024).  R v and R^* u are computed one
+// row (one column) of R per wave at a time, lanes running along the row
+// (column) so loads are coalesced; the operand vector is broadcast from LDS.
+// Both new vectors are reorthogonalised twice against all earlier ones.
+// The largest eigenvalue of B^T B (B the bidiagonal) is found by multisection
+// of its Sturm count over the 64 lanes of one wave.
+constexpr int LZ_THREADS = 1024;
+constexpr int LZ_WAVES = LZ_THREADS / 64;
+constexpr int LZ_MAXK = 64;
+
+// y = M x for the n x n triangular M held both ways: rows (`byrow`, row i is
+// M[i*ldr + l], l in [lo(i), hi(i))) -- the caller supplies the row access.
+template <typename T, bool CONJ>
+__device__ inline void lz_rows(int n, const T* __restrict__ M, int64_t ld, bool upper, const T* xs, T* ys) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int i0 = wid * 4; i0 < n; i0 += LZ_WAVES * 4) {
+    T acc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = zero<T>();
+    const int lo = upper ? i0 : 0;
+    const int hi = upper ? n : ((i0 + 4 < n) ? i0 + 4 : n);
+    for (int l = lo + lane; l < hi; l += 64) {
+      const T xl = xs[l];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + r;
+        if (i < n && (upper ? l >= i : l <= i)) {
+          const T m = M[(int64_t)i * ld + l];
+          acc[r] = CONJ ? cfmac(m, xl, acc[r]) : fmac(m, xl, acc[r]);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const T t = wave_sum(acc[r]);
+      if (lane == 0 && i0 + r < n) ys[i0 + r] = t;
+    }
+  }
+}
+
+// x <- x - Basis(:, 0:cnt) (Basis(:, 0:cnt)^* x), twice; x is entry tid of a
+// vector, Basis columns have stride n.  xs and hq are LDS work arrays.
 template <typename T>
-__global__ __launch_bounds__(NS_THREADS) void k_lanczos(int n, const T* __restrict__ Ycol, int ld,
+__device__ inline void lz_reorth(int n, int cnt, const T* __restrict__ Basis, T& x, T* xs, T* hq, int own) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (own) xs[threadIdx.x] = x;
+    __syncthreads();
+    for (int q = wid; q < cnt; q += LZ_WAVES) {
+      T acc = zero<T>();
+      for (int l = lane; l < n; l += 64) acc = cfmac(Basis[(int64_t)q * n + l], xs[l], acc);
+      acc = wave_sum(acc);
+      if (lane == 0) hq[q] = acc;
+    }
+    __syncthreads();
+    if (own) {
+      T a0 = zero<T>(), a1 = zero<T>();
+      int q = 0;
+      for (; q + 1 < cnt; q += 2) {
+        a0 = fmac(Basis[(int64_t)q * n + threadIdx.x], hq[q], a0);
+        a1 = fmac(Basis[(int64_t)(q + 1) * n + threadIdx.x], hq[q + 1], a1);
+      }
+      if (q < cnt) a0 = fmac(Basis[(int64_t)q * n + threadIdx.x], hq[q], a0);
+      x = sub(x, add(a0, a1));
+    }
+    __syncthreads();
+  }
+}
+
+// number of eigenvalues of the symmetric tridiagonal (dg, of) below x
+__device__ inline int sturm_count(const double* dg, const double* of, int k, double x) {
+  int cnt = 0;
+  double q = dg[0] - x;
+  if (q < 0) ++cnt;
+  for (int i = 1; i < k; ++i) {
+    if (q == 0.0) q = 1e-300;
+    q = (dg[i] - x) - of[i - 1] * of[i - 1] / q;
+    if (q < 0) ++cnt;
+  }
+  return cnt;
+}
+
+template <typename T>
+__global__ __launch_bounds__(LZ_THREADS) void k_lanczos(int n, const T* __restrict__ Ycol, int ld,
                                                         const T* __restrict__ Rrow, T* __restrict__ Ub,
                                                         T* __restrict__ Vb, int KL, uint64_t seed,
                                                         Ctl* __restrict__ ctl) {
-  extern __shared__ double smem_d[];
-  T* u = reinterpret_cast<T*>(smem_d);  // n
-  T* v = u + n;                          // n
-  __shared__ double alpha[65], beta[65];
-  __shared__ T scratch[(NS_THREADS / 64) * 32];
-  __shared__ T h[32];
-  __shared__ double red[NS_THREADS / 64];
-  __shared__ int kdone;
+  __shared__ T xs[LZ_THREADS];
+  __shared__ T ys[LZ_THREADS];
+  __shared__ T hq[LZ_MAXK + 1];
+  __shared__ double alpha[LZ_MAXK + 1], beta[LZ_MAXK + 1];
+  __shared__ double dg[LZ_MAXK + 1], of[LZ_MAXK + 1];
+  __shared__ double red[LZ_WAVES];
   const int tid = threadIdx.x;
+  const int own = tid < n;
   // v_0: deterministic random unit vector
+  T v = zero<T>();
   double s = 0.0;
-  for (int i = tid; i < n; i += blockDim.x) {
-    const double x = unif_pm1(mix64(seed ^ (uint64_t)(0x5bd1e995ull + i)));
-    v[i] = from_real<T>(x);
-    s += x * x;
+  if (own) {
+    const double x = unif_pm1(mix64(seed ^ (uint64_t)(0x5bd1e995ull + tid)));
+    v = from_real<T>(x);
+    s = x * x;
   }
   s = block_sum(s, red);
-  {
-    const double inv = 1.0 / sqrt(s);
-    for (int i = tid; i < n; i += blockDim.x) {
-      v[i] = scal(v[i], inv);
-      Vb[i] = v[i];
-    }
-  }
-  if (tid == 0) kdone = 0;
-  __syncthreads();
+  v = scal(v, 1.0 / sqrt(s));
+  if (own) Vb[tid] = v;
+  T u = zero<T>(), uprev = zero<T>();
   int k = 0;
   for (int j = 0; j < KL; ++j) {
-    // u = R v_j - beta_{j-1} u_{j-1}: column form over l, rows i <= l
-    for (int i = tid; i < n; i += blockDim.x) u[i] = (j > 0) ? scal(Ub[(int64_t)(j - 1) * n + i], -beta[j - 1]) : zero<T>();
+    // u = R v_j - beta_{j-1} u_{j-1}
+    if (own) xs[tid] = v;
     __syncthreads();
-    for (int l = 0; l < n; ++l) {
-      const T vl = v[l];
-      for (int i = tid; i <= l; i += blockDim.x) u[i] = fmac(Ycol[(int64_t)l * ld + i], vl, u[i]);
-    }
+    lz_rows<T, false>(n, Rrow, n, true, xs, ys);
     __syncthreads();
-    // reorthogonalise u against u_0..u_{j-1} (two classical passes, chunks of 32)
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int q0 = 0; q0 < j; q0 += 32) {
-        const int K = (j - q0 < 32) ? j - q0 : 32;
-        T vals[32];
-#pragma unroll
-        for (int q = 0; q < 32; ++q) vals[q] = zero<T>();
-        for (int i = tid; i < n; i += blockDim.x) {
-          const T ui = u[i];
-#pragma unroll
-          for (int q = 0; q < 32; ++q)
-            if (q < K) vals[q] = cfmac(Ub[(int64_t)(q0 + q) * n + i], ui, vals[q]);
-        }
-        nblock_sum_many<T, 32>(vals, K, scratch, h);
-        for (int i = tid; i < n; i += blockDim.x) {
-          T ui = u[i];
-          for (int q = 0; q < K; ++q) ui = fnmac(Ub[(int64_t)(q0 + q) * n + i], h[q], ui);
-          u[i] = ui;
-        }
-        __syncthreads();
-      }
-    }
-    s = 0.0;
-    for (int i = tid; i < n; i += blockDim.x) s += abs2(u[i]);
+    u = own ? ys[tid] : zero<T>();
+    if (j > 0) u = sub(u, scal(uprev, beta[j - 1]));
+    lz_reorth<T>(n, j, Ub, u, xs, hq, own);
+    s = own ? abs2(u) : 0.0;
     s = block_sum(s, red);
     const double a = sqrt(s);
     if (tid == 0) alpha[j] = a;
-    const double ainv = (a > 0.0) ? 1.0 / a : 0.0;
-    for (int i = tid; i < n; i += blockDim.x) {
-      u[i] = scal(u[i], ainv);
-      Ub[(int64_t)j * n + i] = u[i];
-    }
-    __syncthreads();
+    u = scal(u, (a > 0.0) ? 1.0 / a : 0.0);
+    if (own) Ub[(int64_t)j * n + tid] = u;
     k = j + 1;
     if (!(a > 0.0)) break;
-    // v = R^* u - alpha_j v_j: row form over i, entries l >= i
-    for (int l = tid; l < n; l += blockDim.x) v[l] = scal(v[l], -a);
+    // v = R^* u - alpha_j v_j   (column l of R is Ycol[l*ld + 0..l])
+    if (own) xs[tid] = u;
     __syncthreads();
-    for (int i = 0; i < n; ++i) {
-      const T ui = u[i];
-      for (int l = tid; l < n; l += blockDim.x)
-        if (l >= i) v[l] = cfmac(Rrow[(int64_t)i * n + l], ui, v[l]);
-    }
+    lz_rows<T, true>(n, Ycol, ld, false, xs, ys);
     __syncthreads();
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int q0 = 0; q0 <= j; q0 += 32) {
-        const int K = (j + 1 - q0 < 32) ? j + 1 - q0 : 32;
-        T vals[32];
-#pragma unroll
-        for (int q = 0; q < 32; ++q) vals[q] = zero<T>();
-        for (int i = tid; i < n; i += blockDim.x) {
-          const T vi = v[i];
-#pragma unroll
-          for (int q = 0; q < 32; ++q)
-            if (q < K) vals[q] = cfmac(Vb[(int64_t)(q0 + q) * n + i], vi, vals[q]);
-        }
-        nblock_sum_many<T, 32>(vals, K, scratch, h);
-        for (int i = tid; i < n; i += blockDim.x) {
-          T vi = v[i];
-          for (int q = 0; q < K; ++q) vi = fnmac(Vb[(int64_t)(q0 + q) * n + i], h[q], vi);
-          v[i] = vi;
-        }
-        __syncthreads();
-      }
-    }
-    s = 0.0;
-    for (int i = tid; i < n; i += blockDim.x) s += abs2(v[i]);
+    v = own ? sub(ys[tid], scal(v, a)) : zero<T>();
+    lz_reorth<T>(n, j + 1, Vb, v, xs, hq, own);
+    s = own ? abs2(v) : 0.0;
     s = block_sum(s, red);
     const double bta = sqrt(s);
     if (tid == 0) beta[j] = bta;
-    if (!(bta > 1e-15 * a) || j + 1 >= n) {
-      __syncthreads();
-      break;
-    }
-    const double binv = 1.0 / bta;
-    for (int i = tid; i < n; i += blockDim.x) {
-      v[i] = scal(v[i], binv);
-      Vb[(int64_t)(j + 1) * n + i] = v[i];
-    }
     __syncthreads();
+    if (!(bta > 1e-15 * a) || j + 1 >= n) break;
+    v = scal(v, 1.0 / bta);
+    if (own) Vb[(int64_t)(j + 1) * n + tid] = v;
+    uprev = u;
   }
   __syncthreads();
-  if (tid == 0) {
-    // largest eigenvalue of B^T B (symmetric tridiagonal) by Sturm bisection
-    double dg[65], of[65];
-    for (int q = 0; q < k; ++q) {
-      dg[q] = alpha[q] * alpha[q] + (q > 0 ? beta[q - 1] * beta[q - 1] : 0.0);
-      of[q] = (q + 1 < k) ? alpha[q] * beta[q] : 0.0;
-    }
+  // B^T B: diagonal alpha_q^2 + beta_{q-1}^2, off-diagonal alpha_q beta_q
+  if (tid < k) {
+    dg[tid] = alpha[tid] * alpha[tid] + (tid > 0 ? beta[tid - 1] * beta[tid - 1] : 0.0);
+    of[tid] = (tid + 1 < k) ? alpha[tid] * beta[tid] : 0.0;
+  }
+  __syncthreads();
+  if (tid < 64) {
     double hi = 0.0;
     for (int q = 0; q < k; ++q) {
       const double rad = fabs(of[q]) + (q > 0 ? fabs(of[q - 1]) : 0.0);
       hi = fmax(hi, dg[q] + rad);
     }
     double lo = 0.0;
-    for (int it = 0; it < 200 && hi - lo > 1e-17 * hi; ++it) {
-      const double x = 0.5 * (lo + hi);
-      int cnt = 0;  // eigenvalues < x
-      double qv = dg[0] - x;
-      if (qv < 0) ++cnt;
-      for (int q = 1; q < k; ++q) {
-        if (qv == 0.0) qv = 1e-300;
-        qv = (dg[q] - x) - of[q - 1] * of[q - 1] / qv;
-        if (qv < 0) ++cnt;
-      }
-      if (cnt == k) hi = x; else lo = x;
+    // multisection: lane l tests lo + (l+1) (hi-lo)/65; keep the sub-interval
+    // where the count of eigenvalues below reaches k
+    for (int it = 0; it < 12 && hi - lo > 1e-17 * hi; ++it) {
+      const double w = (hi - lo) / 65.0;
+      const double x = lo + (tid + 1) * w;
+      const int below = sturm_count(dg, of, k, x);
+      const uint64_t full = __ballot(below == k);
+      const int first = full ? __builtin_ctzll(full) : 64;  // first point above the top eigenvalue
+      const double nlo = lo + first * w;
+      const double nhi = (first < 64) ? lo + (first + 1) * w : hi;
+      lo = nlo;
+      hi = nhi;
     }
-    ctl->sigma1 = sqrt(0.5 * (lo + hi));
+    if (tid == 0) ctl->sigma1 = sqrt(0.5 * (lo + hi));
   }
 }
 
@@ -660,14 +661,29 @@ hipError_t launch_trmv(hipStream_t st, bool cplx, int B, const void* M, int n, i
   return hipGetLastError();
 }
 
+template <typename T, int KM>
+static void orth_go(hipStream_t st, int n, int B, const void* V, const void* X, int project, int with_x, void* W,
+                    Ctl* ctl, int check_done) {
+  hipLaunchKernelGGL((k_orth<T, KM>), dim3(1), dim3(NS_THREADS), 0, st, n, B, (const T*)V, (const T*)X, project,
+                     with_x, (T*)W, ctl, check_done);
+}
+
+template <typename T>
+static void orth_dispatch(hipStream_t st, int n, int B, const void* V, const void* X, int project, int with_x,
+                          void* W, Ctl* ctl, int check_done) {
+  const int need = 3 * B;
+  if (need <= 4) orth_go<T, 4>(st, n, B, V, X, project, with_x, W, ctl, check_done);
+  else if (need <= 8) orth_go<T, 8>(st, n, B, V, X, project, with_x, W, ctl, check_done);
+  else if (need <= 16) orth_go<T, 16>(st, n, B, V, X, project, with_x, W, ctl, check_done);
+  else if (need <= 32) orth_go<T, 32>(st, n, B, V, X, project, with_x, W, ctl, check_done);
+  else orth_go<T, 3 * RR_BMAX>(st, n, B, V, X, project, with_x, W, ctl, check_done);
+}
+
 hipError_t launch_orth(hipStream_t st, bool cplx, int n, int B, const void* V, const void* X, int project, int with_x,
                        void* W, Ctl* ctl, int check_done) {
-  if (cplx)
-    hipLaunchKernelGGL(k_orth<cd>, dim3(1), dim3(NS_THREADS), 0, st, n, B, (const cd*)V, (const cd*)X, project,
-                       with_x, (cd*)W, ctl, check_done);
-  else
-    hipLaunchKernelGGL(k_orth<double>, dim3(1), dim3(NS_THREADS), 0, st, n, B, (const double*)V, (const double*)X,
-                       project, with_x, (double*)W, ctl, check_done);
+  if (B < 1 || B > RR_BMAX) return hipErrorInvalidValue;
+  if (cplx) orth_dispatch<cd>(st, n, B, V, X, project, with_x, W, ctl, check_done);
+  else orth_dispatch<double>(st, n, B, V, X, project, with_x, W, ctl, check_done);
   return hipGetLastError();
 }
 
@@ -695,22 +711,13 @@ hipError_t launch_randblk(hipStream_t st, bool cplx, void* Wb, int64_t count, ui
 
 hipError_t launch_lanczos(hipStream_t st, bool cplx, int n, const void* Ycol, int ld, const void* Rrow, void* Ub,
                           void* Vb, int KL, uint64_t seed, Ctl* ctl) {
-  const size_t lds = (size_t)2 * n * (cplx ? 16 : 8);
-  if (cplx) {
-    if (lds > 64 * 1024) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_lanczos<cd>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_lanczos<cd>, dim3(1), dim3(NS_THREADS), lds, st, n, (const cd*)Ycol, ld, (const cd*)Rrow,
+  if (n > LZ_THREADS) return hipErrorInvalidValue;
+  if (cplx)
+    hipLaunchKernelGGL(k_lanczos<cd>, dim3(1), dim3(LZ_THREADS), 0, st, n, (const cd*)Ycol, ld, (const cd*)Rrow,
                        (cd*)Ub, (cd*)Vb, KL, seed, ctl);
-  } else {
-    if (lds > 64 * 1024) {
-      hipError_t e = hipFuncSetAttribute((const void*)k_lanczos<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k_lanczos<double>, dim3(1), dim3(NS_THREADS), lds, st, n, (const double*)Ycol, ld,
+  else
+    hipLaunchKernelGGL(k_lanczos<double>, dim3(1), dim3(LZ_THREADS), 0, st, n, (const double*)Ycol, ld,
                        (const double*)Rrow, (double*)Ub, (double*)Vb, KL, seed, ctl);
-  }
   return hipGetLastError();
 }
 

@@ -28,27 +28,6 @@ constexpr int QR_CB = 8;
 __device__ inline double im_(double) { return 0.0; }
 __device__ inline double im_(cd a) { return a.y; }
 
-// Sums vals[0..K) over the block; results in out[0..K).  K is block-uniform.
-template <typename T, int KMAX>
-__device__ inline void block_sum_many(T (&vals)[KMAX], int K, T* scratch, T* out) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int nw = blockDim.x >> 6;
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
-    if (k < K) {
-      T v = wave_sum(vals[k]);
-      if (lane == 0) scratch[wid * KMAX + k] = v;
-    }
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < K) {
-    T s = zero<T>();
-    for (int w = 0; w < nw; ++w) s = add(s, scratch[w * KMAX + threadIdx.x]);
-    out[threadIdx.x] = s;
-  }
-  __syncthreads();
-}
-
 // V(r, q) of the current panel: unit lower trapezoidal, stored below the diagonal.
 template <typename T>
 __device__ inline T vpanel(const T* Y, int ld, int p, int q, int r) {
@@ -60,7 +39,7 @@ __device__ inline T vpanel(const T* Y, int ld, int p, int q, int r) {
 
 template <typename T>
 __global__ __launch_bounds__(QR_THREADS) void k_qr_panel(T* Y, int ld, int d, int n, int p, int nb, T* Tm) {
-  __shared__ T scratch[(QR_THREADS / 64) * QR_NB];
+  __shared__ T scratch[(QR_THREADS / 16) * QR_NB];
   __shared__ T outs[QR_NB];
   __shared__ T taus[QR_NB];
   __shared__ T Tl[QR_NB * QR_NB];  // column-major nb x nb
@@ -133,6 +112,156 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr_panel(T* Y, int ld, int d, in
   for (int i = tid; i < QR_NB * QR_NB; i += blockDim.x) Tm[i] = Tl[i];
 }
 
+// Register-resident panel factorisation: 1024 threads, thread t holds rows
+// p + t + 1024 s (s < RPT) of the nb <= NBT panel columns in registers, so a
+// column step touches no memory except two block reductions.  The reduction
+// of column jj is one batched sum of NBT values: entries k > jj are v^* Y(:, k)
+// (to apply H^* to the rest of the panel), entries k < jj are V(:, k)^* v
+// (column jj of the T factor); both only involve rows >= p + jj.
+constexpr int QRP_THREADS = 1024;
+
+template <typename T, int RPT, int NBT>
+__global__ __launch_bounds__(QRP_THREADS) void k_qr_panel_reg(T* Y, int ld, int d, int p, int nb, T* Tm) {
+  __shared__ T scratch[(QRP_THREADS / 16) * NBT];
+  __shared__ T outs[NBT];
+  __shared__ T Tl[QR_NB * QR_NB];  // column-major, leading dimension QR_NB
+  __shared__ double red[QRP_THREADS / 64];
+  __shared__ T sh_alpha;
+  const int tid = threadIdx.x;
+  T P[RPT][NBT];
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) {
+    const int row = p + tid + QRP_THREADS * s;
+#pragma unroll
+    for (int q = 0; q < NBT; ++q) P[s][q] = (row < d && q < nb) ? Y[(int64_t)(p + q) * ld + row] : zero<T>();
+  }
+  for (int i = tid; i < QR_NB * QR_NB; i += QRP_THREADS) Tl[i] = zero<T>();
+  // The column loop is not unrolled: column jj of the register panel is read
+  // and written through selects over the compile-time column index.
+  for (int jj = 0; jj < nb; ++jj) {
+    T pj[RPT];
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      pj[s] = zero<T>();
+#pragma unroll
+      for (int q = 0; q < NBT; ++q)
+        if (q == jj) pj[s] = P[s][q];
+    }
+    if (tid == jj) sh_alpha = pj[0];
+    double xs = 0.0;
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      const int rel = tid + QRP_THREADS * s;
+      if (rel > jj && p + rel < d) xs += abs2(pj[s]);
+    }
+    xs = block_sum(xs, red);
+    const T alpha = sh_alpha;
+    const bool noref = (xs == 0.0) && (im_(alpha) == 0.0);
+    T tau = zero<T>(), sc = from_real<T>(1.0);
+    double beta = re_(alpha);
+    if (!noref) {
+      const double nrm = sqrt(abs2(alpha) + xs);
+      beta = (re_(alpha) >= 0.0) ? -nrm : nrm;
+      tau = divs(sub(from_real<T>(beta), alpha), from_real<T>(beta));
+      sc = divs(from_real<T>(1.0), sub(alpha, from_real<T>(beta)));
+    }
+    // v (the reflector), row by row: 1 at rel == jj, scaled entries below, 0 above
+    T v[RPT];
+#pragma unroll
+    for (int s = 0; s < RPT; ++s) {
+      const int rel = tid + QRP_THREADS * s;
+      if (rel > jj && p + rel < d) {
+        pj[s] = mul(pj[s], sc);
+        v[s] = pj[s];
+      } else if (rel == jj) {
+        v[s] = from_real<T>(1.0);
+        pj[s] = from_real<T>(beta);
+      } else {
+        v[s] = zero<T>();
+      }
+#pragma unroll
+      for (int q = 0; q < NBT; ++q)
+        if (q == jj) P[s][q] = pj[s];
+    }
+    {
+#pragma unroll
+      for (int k = 0; k < NBT; ++k) {
+        T val = zero<T>();
+#pragma unroll
+        for (int s = 0; s < RPT; ++s) {
+          if (k > jj) val = cfmac(v[s], P[s][k], val);
+          else if (k < jj) val = cfmac(P[s][k], v[s], val);
+        }
+        val = row_sum16(val);
+        if ((tid & 15) == 0) scratch[(tid >> 4) * NBT + k] = val;
+      }
+      __syncthreads();
+      if (tid < NBT) {
+        T acc = zero<T>();
+#pragma unroll 8
+        for (int r = 0; r < QRP_THREADS / 16; ++r) acc = add(acc, scratch[r * NBT + tid]);
+        outs[tid] = acc;
+      }
+      __syncthreads();
+    }
+    if (!noref) {
+      const T ct = conj_(tau);
+#pragma unroll
+      for (int k = 0; k < NBT; ++k) {
+        if (k > jj) {
+          const T f = mul(ct, outs[k]);
+#pragma unroll
+          for (int s = 0; s < RPT; ++s) P[s][k] = fnmac(f, v[s], P[s][k]);
+        }
+      }
+    }
+    // T(0:jj, jj) = -tau T(0:jj, 0:jj) g, g = V(:, 0:jj)^* v;  T(jj, jj) = tau
+    if (tid < jj) {
+      T acc = zero<T>();
+      for (int l = tid; l < jj; ++l) acc = fmac(Tl[tid + l * QR_NB], outs[l], acc);
+      Tl[tid + jj * QR_NB] = neg(mul(tau, acc));
+    } else if (tid == jj) {
+      Tl[jj + jj * QR_NB] = tau;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = 0; s < RPT; ++s) {
+    const int row = p + tid + QRP_THREADS * s;
+#pragma unroll
+    for (int q = 0; q < NBT; ++q)
+      if (row < d && q < nb) Y[(int64_t)(p + q) * ld + row] = P[s][q];
+  }
+  for (int i = tid; i < QR_NB * QR_NB; i += QRP_THREADS) Tm[i] = Tl[i];
+}
+
+// Panel width and register rows per thread for the rows [p, d): the panel
+// must fit in about 64 registers per thread.
+template <typename T>
+static int qr_pick_panel(int rows, int* rpt) {
+  const int r = (rows + QRP_THREADS - 1) / QRP_THREADS;
+  *rpt = r;
+  const int cw = (sizeof(T) == 16) ? 2 : 1;
+  if (r <= 1) return 32 / cw;
+  if (r <= 2) return 16 / cw;
+  if (r <= 4) return 8 / cw;
+  return 0;  // too tall for the register panel: generic kernel
+}
+
+template <typename T>
+static void qr_panel_launch(hipStream_t st, T* Y, int d, int p, int nb, int rpt, T* Tm) {
+  const dim3 g(1), b(QRP_THREADS);
+  if constexpr (sizeof(T) == 8) {
+    if (rpt <= 1) hipLaunchKernelGGL((k_qr_panel_reg<T, 1, 32>), g, b, 0, st, Y, d, d, p, nb, Tm);
+    else if (rpt <= 2) hipLaunchKernelGGL((k_qr_panel_reg<T, 2, 16>), g, b, 0, st, Y, d, d, p, nb, Tm);
+    else hipLaunchKernelGGL((k_qr_panel_reg<T, 4, 8>), g, b, 0, st, Y, d, d, p, nb, Tm);
+  } else {
+    if (rpt <= 1) hipLaunchKernelGGL((k_qr_panel_reg<T, 1, 16>), g, b, 0, st, Y, d, d, p, nb, Tm);
+    else if (rpt <= 2) hipLaunchKernelGGL((k_qr_panel_reg<T, 2, 8>), g, b, 0, st, Y, d, d, p, nb, Tm);
+    else hipLaunchKernelGGL((k_qr_panel_reg<T, 4, 4>), g, b, 0, st, Y, d, d, p, nb, Tm);
+  }
+}
+
 // C <- (I - V T V^*)^* C = C - V T^* (V^* C) on columns [p+nb, n)
 template <typename T>
 __global__ __launch_bounds__(QR_THREADS) void k_qr_update(T* Y, int ld, int d, int n, int p, int nb,
@@ -172,11 +301,18 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr_update(T* Y, int ld, int d, i
   }
   __syncthreads();
   for (int r = p + tid; r < d; r += blockDim.x) {
-    for (int c = 0; c < ncb; ++c) {
-      T* y = Y + (int64_t)(c0 + c) * ld + r;
-      T v = *y;
-      for (int qq = 0; qq < nb; ++qq) v = fnmac(vpanel(Y, ld, p, qq, r), Wt2[qq][c], v);
-      *y = v;
+    T vr[QR_NB];
+#pragma unroll
+    for (int qq = 0; qq < QR_NB; ++qq) vr[qq] = (qq < nb) ? vpanel(Y, ld, p, qq, r) : zero<T>();
+#pragma unroll 1
+    for (int c = 0; c < QR_CB; ++c) {
+      if (c < ncb) {
+        T* y = Y + (int64_t)(c0 + c) * ld + r;
+        T v = *y;
+#pragma unroll
+        for (int qq = 0; qq < QR_NB; ++qq) v = fnmac(vr[qq], Wt2[qq][c], v);
+        *y = v;
+      }
     }
   }
 }
@@ -217,13 +353,19 @@ __global__ __launch_bounds__(256) void k_trinv(const T* __restrict__ Y, int ld, 
 
 template <typename T>
 static hipError_t qr_impl(hipStream_t st, T* Y, int d, int n, T* Tm, T* Rrow, T* RH, T* Rinv, T* RinvH) {
-  for (int p = 0; p < n; p += QR_NB) {
-    const int nb = min(QR_NB, n - p);
-    hipLaunchKernelGGL(k_qr_panel<T>, dim3(1), dim3(QR_THREADS), 0, st, Y, d, d, n, p, nb, Tm);
+  for (int p = 0; p < n;) {
+    int rpt = 0;
+    const int nbr = qr_pick_panel<T>(d - p, &rpt);
+    const int nb = min(nbr > 0 ? nbr : QR_NB, n - p);
+    if (nbr > 0)
+      qr_panel_launch<T>(st, Y, d, p, nb, rpt, Tm);
+    else
+      hipLaunchKernelGGL(k_qr_panel<T>, dim3(1), dim3(QR_THREADS), 0, st, Y, d, d, n, p, nb, Tm);
     const int rest = n - p - nb;
     if (rest > 0)
       hipLaunchKernelGGL(k_qr_update<T>, dim3((rest + QR_CB - 1) / QR_CB), dim3(QR_THREADS), 0, st, Y, d, d, n,
                          p, nb, (const T*)Tm);
+    p += nb;
   }
   const int64_t nn = (int64_t)n * n;
   hipLaunchKernelGGL(k_qr_extract<T>, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, (const T*)Y, d, n,

@@ -23,25 +23,6 @@ namespace rl {
 constexpr int TS_TILE = 256;
 constexpr int TS_TMAX = 32;
 
-template <typename T>
-__device__ inline void ts_block_sum_many(T (&vals)[TS_TMAX], int K, T* scratch, T* out) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < TS_TMAX; ++k) {
-    if (k < K) {
-      T v = wave_sum(vals[k]);
-      if (lane == 0) scratch[wid * TS_TMAX + k] = v;
-    }
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < K) {
-    T s = zero<T>();
-    for (int w = 0; w < TS_TILE / 64; ++w) s = add(s, scratch[w * TS_TMAX + threadIdx.x]);
-    out[threadIdx.x] = s;
-  }
-  __syncthreads();
-}
-
 __device__ inline double ts_im(double) { return 0.0; }
 __device__ inline double ts_im(cd a) { return a.y; }
 
@@ -52,7 +33,7 @@ __global__ __launch_bounds__(TS_TILE) void k_tsqr(const T* __restrict__ P0, int 
   if (check_done && ctl->done) return;
   extern __shared__ double smem_d[];
   T* tile = reinterpret_cast<T*>(smem_d);  // t columns x TS_TILE rows
-  __shared__ T scratch[(TS_TILE / 64) * TS_TMAX];
+  __shared__ T scratch[(TS_TILE / 16) * TS_TMAX];
   __shared__ T outs[TS_TMAX];
   __shared__ double red[TS_TILE / 64];
   const int t = b0 + b1 + b2;
@@ -106,7 +87,7 @@ __global__ __launch_bounds__(TS_TILE) void k_tsqr(const T* __restrict__ P0, int 
           vals[k] = zero<T>();
           if (k < K) vals[k] = cfmac(vr, tile[(j + 1 + k) * TS_TILE + r], zero<T>());
         }
-        ts_block_sum_many<T>(vals, K, scratch, outs);
+        block_sum_many<T, TS_TMAX>(vals, K, scratch, outs);
         if (r >= j) {
           const T ct = conj_(tau);
           for (int k = 0; k < K; ++k) {
@@ -127,7 +108,193 @@ __global__ __launch_bounds__(TS_TILE) void k_tsqr(const T* __restrict__ P0, int 
   }
 }
 
-int64_t tsqr_groups(int64_t m, int t) {
+// ---------------------------------------------------------------------------
+// Register TSQR for t <= 16: a wave holds a 64-row tile, one row per lane
+// (t values in registers).  Lanes 0..t-1 carry the running R; the other lanes
+// take the next 64-t input rows (prefetched one tile ahead).  Householder QR
+// of the tile needs one batched wave reduction per column: with x the column
+// below the diagonal, |x|^2 and x^* a_k (k > j) are summed together, and
+// v^* a_k = a_jk + conj(1/(alpha-beta)) x^* a_k gives the reflector products
+// without a second pass.  The four waves' R factors are stacked (4t <= 64
+// rows) and factored once more by wave 0.  k_tsqr_w writes one R per
+// workgroup; k_tsqr_w_merge (one workgroup, the next launch on the stream)
+// reduces those the same way and writes R_T.
+constexpr int TW_THREADS = 256;
+constexpr int TW_TMAX = 16;
+
+template <typename T, int TT>
+__device__ inline T tw_get(const T (&x)[TT], int j) {
+  T r = zero<T>();
+#pragma unroll
+  for (int q = 0; q < TT; ++q)
+    if (q == j) r = x[q];
+  return r;
+}
+template <typename T, int TT>
+__device__ inline void tw_set(T (&x)[TT], int j, T v) {
+#pragma unroll
+  for (int q = 0; q < TT; ++q)
+    if (q == j) x[q] = v;
+}
+
+// QR of the 64 x t tile held one row per lane; on return lanes 0..t-1 hold R
+// (upper triangular) and every other entry of columns 0..t-1 is zero.
+template <typename T, int TT>
+__device__ void tw_tile_qr(T (&x)[TT], int t, int lane) {
+  for (int j = 0; j < t; ++j) {
+    const bool below = lane > j;
+    T xj = tw_get<T, TT>(x, j);
+    const double n2 = wave_sum(below ? abs2(xj) : 0.0);
+    T dk[TT];
+#pragma unroll
+    for (int k = 0; k < TT; ++k) {
+      dk[k] = zero<T>();
+      if (k > j && k < t) dk[k] = wave_sum((below ? cfmac(xj, x[k], zero<T>()) : zero<T>()));
+    }
+    const T alpha = readlane_d(xj, j);
+    const bool noref = (n2 == 0.0) && (ts_im(alpha) == 0.0);
+    if (!noref) {
+      const double nrm = sqrt(abs2(alpha) + n2);
+      const double beta = (re_(alpha) >= 0.0) ? -nrm : nrm;
+      const T tau = divs(sub(from_real<T>(beta), alpha), from_real<T>(beta));
+      const T sc = divs(from_real<T>(1.0), sub(alpha, from_real<T>(beta)));
+      const T ct = conj_(tau), csc = conj_(sc);
+      const T v = (lane == j) ? from_real<T>(1.0) : (below ? mul(sc, xj) : zero<T>());
+#pragma unroll
+      for (int k = 0; k < TT; ++k) {
+        if (k > j && k < t) {
+          const T ajk = readlane_d(x[k], j);
+          const T f = mul(ct, fmac(csc, dk[k], ajk));
+          x[k] = fnmac(f, v, x[k]);
+        }
+      }
+      if (lane == j) xj = from_real<T>(beta);
+      else if (below) xj = zero<T>();
+      tw_set<T, TT>(x, j, xj);
+    }
+  }
+}
+
+template <typename T, int TT>
+__device__ inline void tw_load(T (&x)[TT], const T* __restrict__ P0, int b0, const T* __restrict__ P1, int b1,
+                               const T* __restrict__ P2, int b2, int64_t row, bool valid) {
+#pragma unroll
+  for (int c = 0; c < TT; ++c) {
+    T v = zero<T>();
+    if (valid) {
+      if (c < b0) v = P0[row * b0 + c];
+      else if (c < b0 + b1) v = P1[row * b1 + (c - b0)];
+      else if (c < b0 + b1 + b2) v = P2[row * b2 + (c - b0 - b1)];
+    }
+    x[c] = v;
+  }
+}
+
+// Rows [g0, g1) of the stacked input, tiles of 64-t fresh rows, wave w takes
+// tiles w, w+4, ...; x ends as this wave's R.
+template <typename T, int TT>
+__device__ void tw_rows(T (&x)[TT], const T* __restrict__ P0, int b0, const T* __restrict__ P1, int b1,
+                        const T* __restrict__ P2, int b2, int64_t g0, int64_t g1, int t, int lane, int wave) {
+  const int fresh = 64 - t;
+  const int64_t step = 4 * (int64_t)fresh;
+  int64_t g = g0 + (int64_t)wave * fresh;
+  T nx[TT];
+  {
+    const int64_t row = g + lane - t;
+    tw_load<T, TT>(nx, P0, b0, P1, b1, P2, b2, row, lane >= t && row < g1);
+  }
+  for (; g < g1; g += step) {
+    if (lane >= t) {
+#pragma unroll
+      for (int c = 0; c < TT; ++c) x[c] = nx[c];
+    }
+    const int64_t row = g + step + lane - t;
+    tw_load<T, TT>(nx, P0, b0, P1, b1, P2, b2, row, lane >= t && row < g1);
+    tw_tile_qr<T, TT>(x, t, lane);
+  }
+}
+
+// Stack the four waves' R factors (through LDS) and factor them in wave 0.
+template <typename T, int TT>
+__device__ void tw_block_merge(T (&x)[TT], T* Rs, int t, int lane, int wave) {
+  if (lane < t) {
+#pragma unroll
+    for (int c = 0; c < TT; ++c)
+      if (c < t) Rs[(wave * t + lane) * t + c] = x[c];
+  }
+  __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int c = 0; c < TT; ++c) x[c] = (lane < 4 * t && c < t) ? Rs[lane * t + c] : zero<T>();
+    tw_tile_qr<T, TT>(x, t, lane);
+  }
+}
+
+template <typename T, int TT>
+__global__ __launch_bounds__(TW_THREADS) void k_tsqr_w(const T* __restrict__ P0, int b0, const T* __restrict__ P1,
+                                                       int b1, const T* __restrict__ P2, int b2, int64_t m,
+                                                       int64_t rows_per_block, T* __restrict__ Rpart,
+                                                       const Ctl* __restrict__ ctl, int check_done) {
+  if (check_done && ctl->done) return;
+  __shared__ T Rs[4 * TW_TMAX * TW_TMAX];
+  const int t = b0 + b1 + b2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T x[TT];
+#pragma unroll
+  for (int c = 0; c < TT; ++c) x[c] = zero<T>();
+  const int64_t g0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t g1 = (g0 + rows_per_block < m) ? g0 + rows_per_block : m;
+  tw_rows<T, TT>(x, P0, b0, P1, b1, P2, b2, g0, g1, t, lane, wave);
+  tw_block_merge<T, TT>(x, Rs, t, lane, wave);
+  if (wave == 0 && lane < t) {
+#pragma unroll
+    for (int c = 0; c < TT; ++c)
+      if (c < t) Rpart[((int64_t)blockIdx.x * t + lane) * t + c] = x[c];
+  }
+}
+
+// R_T of the stacked per-workgroup factors (groups*t rows), one workgroup.
+template <typename T, int TT>
+__global__ __launch_bounds__(TW_THREADS) void k_tsqr_w_merge(const T* __restrict__ Rpart, int t, int64_t rows,
+                                                             T* __restrict__ Rout, const Ctl* __restrict__ ctl,
+                                                             int check_done) {
+  if (check_done && ctl->done) return;
+  __shared__ T Rs[4 * TW_TMAX * TW_TMAX];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T x[TT];
+#pragma unroll
+  for (int c = 0; c < TT; ++c) x[c] = zero<T>();
+  tw_rows<T, TT>(x, Rpart, t, Rpart, 0, Rpart, 0, 0, rows, t, lane, wave);
+  tw_block_merge<T, TT>(x, Rs, t, lane, wave);
+  if (wave == 0 && lane < t) {
+#pragma unroll
+    for (int c = 0; c < TT; ++c)
+      if (c < t) Rout[lane * t + c] = x[c];
+  }
+}
+
+template <typename T, int TT>
+static void tsqr_w_go(hipStream_t st, const T* P0, int b0, const T* P1, int b1, const T* P2, int b2, int64_t m,
+                      int64_t g, T* bufA, T* bufB, const Ctl* ctl, int check_done) {
+  const int t = b0 + b1 + b2;
+  const int64_t rows = (m + g - 1) / g;
+  hipLaunchKernelGGL((k_tsqr_w<T, TT>), dim3((unsigned)g), dim3(TW_THREADS), 0, st, P0, b0, P1, b1, P2, b2, m, rows,
+                     bufA, ctl, check_done);
+  hipLaunchKernelGGL((k_tsqr_w_merge<T, TT>), dim3(1), dim3(TW_THREADS), 0, st, (const T*)bufA, t, g * t, bufB, ctl,
+                     check_done);
+}
+
+static int64_t tsqr_w_groups(int64_t m, int t) {
+  int64_t g = (int64_t)sqrt((double)m / (double)t);
+  const int64_t per = 4 * (int64_t)(64 - t);
+  const int64_t gmax = (m + per - 1) / per;  // at least one tile per wave
+  if (g > gmax) g = gmax;
+  if (g > 1024) g = 1024;
+  if (g < 1) g = 1;
+  return g;
+}
+
+static int64_t tsqr_lds_groups(int64_t m, int t) {
   const int64_t per = 4 * (int64_t)(TS_TILE - t);
   int64_t g = (m + per - 1) / per;
   if (g > 1024) g = 1024;
@@ -135,17 +302,31 @@ int64_t tsqr_groups(int64_t m, int t) {
   return g;
 }
 
+// Upper bound on the partial R factors of one TSQR launch (workspace sizing).
+int64_t tsqr_groups(int64_t m, int t) {
+  const int64_t a = tsqr_lds_groups(m, t), b = (t <= TW_TMAX) ? tsqr_w_groups(m, t) : 1;
+  return a > b ? a : b;
+}
+
 template <typename T>
 static hipError_t tsqr_impl(hipStream_t st, const T* P0, int b0, const T* P1, int b1, const T* P2, int b2, int64_t m,
-                            T* bufA, T* bufB, T** Rfinal, const Ctl* ctl, int check_done) {
+                            T* bufA, T* bufB, T** Rfinal, Ctl* ctl, int check_done) {
   const int t = b0 + b1 + b2;
   if (t < 1 || t > TS_TMAX) return hipErrorInvalidValue;
+  if (t <= TW_TMAX) {
+    const int64_t g = tsqr_w_groups(m, t);
+    if (t <= 4) tsqr_w_go<T, 4>(st, P0, b0, P1, b1, P2, b2, m, g, bufA, bufB, ctl, check_done);
+    else if (t <= 8) tsqr_w_go<T, 8>(st, P0, b0, P1, b1, P2, b2, m, g, bufA, bufB, ctl, check_done);
+    else tsqr_w_go<T, 16>(st, P0, b0, P1, b1, P2, b2, m, g, bufA, bufB, ctl, check_done);
+    *Rfinal = bufB;
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)t * TS_TILE * sizeof(T);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_tsqr<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  int64_t groups = tsqr_groups(m, t);
+  int64_t groups = tsqr_lds_groups(m, t);
   int64_t rows = (m + groups - 1) / groups;
   hipLaunchKernelGGL(k_tsqr<T>, dim3((unsigned)groups), dim3(TS_TILE), lds, st, P0, b0, P1, b1, P2, b2, m, rows, bufA,
                      ctl, check_done);
@@ -155,7 +336,7 @@ static hipError_t tsqr_impl(hipStream_t st, const T* P0, int b0, const T* P1, in
   T* nxt = bufB;
   while (groups > 1) {
     const int64_t mm = groups * t;
-    int64_t g2 = tsqr_groups(mm, t);
+    int64_t g2 = tsqr_lds_groups(mm, t);
     if (g2 >= groups) g2 = groups / 2 > 0 ? groups / 2 : 1;
     const int64_t rows2 = (mm + g2 - 1) / g2;
     hipLaunchKernelGGL(k_tsqr<T>, dim3((unsigned)g2), dim3(TS_TILE), lds, st, (const T*)cur, t, (const T*)nullptr, 0,
@@ -172,7 +353,7 @@ static hipError_t tsqr_impl(hipStream_t st, const T* P0, int b0, const T* P1, in
 }
 
 hipError_t launch_tsqr(hipStream_t st, bool cplx, const void* P0, int b0, const void* P1, int b1, const void* P2,
-                       int b2, int64_t m, void* bufA, void* bufB, void** Rfinal, const Ctl* ctl, int check_done) {
+                       int b2, int64_t m, void* bufA, void* bufB, void** Rfinal, Ctl* ctl, int check_done) {
   if (cplx)
     return tsqr_impl<cd>(st, (const cd*)P0, b0, (const cd*)P1, b1, (const cd*)P2, b2, m, (cd*)bufA, (cd*)bufB,
                          (cd**)Rfinal, ctl, check_done);
