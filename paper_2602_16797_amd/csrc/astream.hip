@@ -22,7 +22,8 @@
 //             stay plain FP64.  In the start pass (init) the new column is
 //             A V_0 itself, and its A^* sum is the Dot2 one.
 //             Per-wave partials: planes [G1 sum, G1 error, G_X, G_W], n x B each.
-// k_colsum2   deterministic compensated sum of the partial planes.
+// k_colsum2   deterministic compensated sum of the partial planes (the last
+//             level writes the finished sums).
 // k_panel     A_V <- A_T C_V, A_X <- A_T C_X (row-local, in place).
 // k_final_u   U(:, j) = (A_T C_V)(:, b-1-j) / theta_{b-1-j} for the outputs.
 #include "common.hpp"
@@ -38,7 +39,7 @@ namespace rl {
 __global__ __launch_bounds__(256) void k_colsum2(const double* __restrict__ in_s, const double* __restrict__ in_e,
                                                  int64_t stride, int64_t elen, int64_t nparts, int64_t len,
                                                  double* __restrict__ out_s, double* __restrict__ out_e,
-                                                 const Ctl* __restrict__ ctl) {
+                                                 double* __restrict__ fin, const Ctl* __restrict__ ctl) {
   if (ctl != nullptr && ctl->done) return;
   __shared__ double sh_s[256], sh_e[256];
   const int el = threadIdx.x & 63, g = threadIdx.x >> 6;  // 64 elements x 4 groups
@@ -64,47 +65,49 @@ __global__ __launch_bounds__(256) void k_colsum2(const double* __restrict__ in_s
       two_sum(s0, sh_s[64 * q + el], s0, t);
       e0 += t + sh_e[64 * q + el];
     }
-    out_s[(int64_t)blockIdx.y * len + e] = s0;
-    out_e[(int64_t)blockIdx.y * len + e] = e0;
+    if (fin != nullptr) {
+      fin[e] = s0 + e0;  // single group: the finished sums
+    } else {
+      out_s[(int64_t)blockIdx.y * len + e] = s0;
+      out_e[(int64_t)blockIdx.y * len + e] = e0;
+    }
   }
 }
 
-__global__ void k_pair_finish(const double* __restrict__ s, const double* __restrict__ e, int64_t len,
-                              double* __restrict__ out, const Ctl* __restrict__ ctl) {
-  if (ctl != nullptr && ctl->done) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < len) out[i] = s[i] + e[i];
-}
 
 // Row-local panel update.  mode: 0 A_T = [A_V] (t = B), 1 [A_V A_W] (t = 2B),
-// 2 [A_V A_X A_W] (t = 3B).  C_V, C_X are t x B row-major.
-template <typename T>
+// 2 [A_V A_X A_W] (t = 3B).  C_V, C_X are t x B row-major.  Each thread owns
+// rows; the row of A_T sits in registers.
+template <typename T, int B>
 __global__ __launch_bounds__(256) void k_panel(T* __restrict__ AV, T* __restrict__ AX, const T* __restrict__ AW,
-                                               int64_t m, int B, const T* __restrict__ CVg,
-                                               const T* __restrict__ CXg, const Ctl* __restrict__ ctl) {
+                                               int64_t m, const T* __restrict__ CVg, const T* __restrict__ CXg,
+                                               const Ctl* __restrict__ ctl) {
   if (ctl->done) return;
   const int mode = ctl->rr_mode;
   const int xupd = ctl->x_update;
   const int t = (mode == 0) ? B : (mode == 1 ? 2 * B : 3 * B);
-  __shared__ T CV[32 * 16];
-  __shared__ T CX[32 * 16];
-  for (int i = threadIdx.x; i < t * B; i += blockDim.x) {
-    CV[i] = CVg[i];
-    CX[i] = xupd ? CXg[i] : zero<T>();
+  __shared__ T CV[3 * B * B];
+  __shared__ T CX[3 * B * B];
+  for (int i = threadIdx.x; i < 3 * B * B; i += blockDim.x) {
+    CV[i] = (i < t * B) ? CVg[i] : zero<T>();
+    CX[i] = (xupd && i < t * B) ? CXg[i] : zero<T>();
   }
   __syncthreads();
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
-    T at[32];
-    for (int j = 0; j < B; ++j) at[j] = AV[r * B + j];
-    if (mode == 2) {
-      for (int j = 0; j < B; ++j) at[B + j] = AX[r * B + j];
-      for (int j = 0; j < B; ++j) at[2 * B + j] = AW[r * B + j];
-    } else if (mode == 1) {
-      for (int j = 0; j < B; ++j) at[B + j] = AW[r * B + j];
+    T at[3 * B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      at[j] = AV[r * B + j];
+      at[B + j] = (mode == 2) ? AX[r * B + j] : ((mode == 1) ? AW[r * B + j] : zero<T>());
+      at[2 * B + j] = (mode == 2) ? AW[r * B + j] : zero<T>();
     }
+    // the coefficient loop stays rolled for wider blocks so the t x B
+    // coefficients are read from LDS per row instead of held in registers
+#pragma unroll(B <= 2 ? B : 1)
     for (int j = 0; j < B; ++j) {
       T sv = zero<T>(), sx = zero<T>();
-      for (int c = 0; c < t; ++c) {
+#pragma unroll
+      for (int c = 0; c < 3 * B; ++c) {
         sv = fmac(at[c], CV[c * B + j], sv);
         sx = fmac(at[c], CX[c * B + j], sx);
       }
@@ -166,13 +169,20 @@ int astream_ns(int n) {
   return 0;
 }
 
+// Partial records: the r2 pass writes one per workgroup, the generic passes
+// one per wave; the workspace holds the larger of the two.
+static int64_t astream_max_parts(int64_t m, int n, int B, int es_d) {
+  const int64_t g = astream_blocks(m, n, B, es_d) * 4;
+  const int64_t r = astream_r2_blocks(m);
+  return g > r ? g : r;
+}
+
 int64_t astream_part_doubles(int64_t m, int n, int B, int es_d) {
-  return astream_blocks(m, n, B, es_d) * 4 * 4 * (int64_t)n * B * es_d;
+  return astream_max_parts(m, n, B, es_d) * 4 * (int64_t)n * B * es_d;
 }
 
 int64_t astream_tmp_doubles(int64_t m, int n, int B, int es_d) {
-  const int64_t parts = astream_blocks(m, n, B, es_d) * 4;
-  const int64_t groups = (parts + 63) / 64;
+  const int64_t groups = (astream_max_parts(m, n, B, es_d) + 63) / 64;
   return 4 * groups * 3 * (int64_t)n * B * es_d;
 }
 
@@ -182,13 +192,16 @@ hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const voi
                           double* tmp, double* G3, const Ctl* ctl) {
   const int es_d = cplx ? 2 : 1;
   const int ns = astream_ns(n);
-  const int64_t nb = astream_blocks(m, n, B, es_d);
+  int64_t nb = astream_blocks(m, n, B, es_d);
+  int64_t np = nb * 4;  // partial records
   bool ok;
   const bool aligned = (lda % 2 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
-  if (!cplx && n <= 256)
-    ok = dispatch_astream_r2(dot2, init, aligned ? 1 : 0, B, st, nb, (const double*)A, lda, m, n, (const double*)W,
-                             (double*)AW, (const double*)AVp, (const double*)AXp, Gpart, ctl);
-  else if (cplx)
+  if (!cplx && astream_r2_fits(B, n, aligned)) {
+    nb = astream_r2_blocks(m);
+    np = nb;
+    ok = dispatch_astream_r2(dot2, init, B, st, nb, (const double*)A, lda, m, n, (const double*)W, (double*)AW,
+                             (const double*)AVp, (const double*)AXp, Gpart, ctl);
+  } else if (cplx)
     ok = dispatch_astream_gc(dot2, ns, B, st, nb, A, lda, m, n, W, AW, AVp, AXp, init, Gpart, ctl);
   else
     ok = dispatch_astream_gd(dot2, ns, B, st, nb, A, lda, m, n, W, AW, AVp, AXp, init, Gpart, ctl);
@@ -198,7 +211,6 @@ hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const voi
   // compensated reduction of the per-wave partials
   const int64_t plen = (int64_t)n * B * es_d;
   const int64_t len = 3 * plen;
-  int64_t np = nb * 4;
   const int64_t g1 = (np + 63) / 64;
   const double* cur_s = Gpart;
   const double* cur_e = Gpart + len;
@@ -209,13 +221,10 @@ hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const voi
     double* ds = tmp + (int64_t)flip * 2 * g1 * len;
     double* de = ds + g1 * len;
     hipLaunchKernelGGL(k_colsum2, dim3((unsigned)((len + 63) / 64), (unsigned)groups), dim3(256), 0, st, cur_s,
-                       cur_e, stride, elen, np, len, ds, de, ctl);
+                       cur_e, stride, elen, np, len, ds, de, groups == 1 ? G3 : nullptr, ctl);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (groups == 1) {
-      hipLaunchKernelGGL(k_pair_finish, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, ds, de, len, G3, ctl);
-      return hipGetLastError();
-    }
+    if (groups == 1) return hipSuccess;
     cur_s = ds;
     cur_e = de;
     stride = len;
@@ -225,16 +234,33 @@ hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const voi
   }
 }
 
+template <typename T, int B>
+static void panel_go(hipStream_t st, int64_t nb, void* AV, void* AX, const void* AW, int64_t m, const void* CV,
+                     const void* CX, const Ctl* ctl) {
+  hipLaunchKernelGGL((k_panel<T, B>), dim3((unsigned)nb), dim3(256), 0, st, (T*)AV, (T*)AX, (const T*)AW, m,
+                     (const T*)CV, (const T*)CX, ctl);
+}
+
+template <typename T>
+static bool panel_by_b(int B, hipStream_t st, int64_t nb, void* AV, void* AX, const void* AW, int64_t m,
+                       const void* CV, const void* CX, const Ctl* ctl) {
+  switch (B) {
+#define RL_CASE(BB) \
+  case BB: panel_go<T, BB>(st, nb, AV, AX, AW, m, CV, CX, ctl); return true;
+    RL_CASE(1) RL_CASE(2) RL_CASE(3) RL_CASE(4) RL_CASE(5)
+    RL_CASE(6) RL_CASE(7) RL_CASE(8) RL_CASE(9) RL_CASE(10)
+#undef RL_CASE
+    default: return false;
+  }
+}
+
 hipError_t launch_panel(hipStream_t st, bool cplx, void* AV, void* AX, const void* AW, int64_t m, int B,
                         const void* CV, const void* CX, const Ctl* ctl) {
   int64_t nb = (m + 255) / 256;
   if (nb > 2048) nb = 2048;
-  if (cplx)
-    hipLaunchKernelGGL(k_panel<cd>, dim3((unsigned)nb), dim3(256), 0, st, (cd*)AV, (cd*)AX, (const cd*)AW, m, B,
-                       (const cd*)CV, (const cd*)CX, ctl);
-  else
-    hipLaunchKernelGGL(k_panel<double>, dim3((unsigned)nb), dim3(256), 0, st, (double*)AV, (double*)AX,
-                       (const double*)AW, m, B, (const double*)CV, (const double*)CX, ctl);
+  const bool ok = cplx ? panel_by_b<cd>(B, st, nb, AV, AX, AW, m, CV, CX, ctl)
+                       : panel_by_b<double>(B, st, nb, AV, AX, AW, m, CV, CX, ctl);
+  if (!ok) return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

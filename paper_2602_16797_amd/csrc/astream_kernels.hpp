@@ -179,6 +179,20 @@ __global__ __launch_bounds__(256) void k_astream(const T* __restrict__ A, int64_
 // V values costs about 2V + 6 shuffles instead of 12 per value; the finished
 // sums are broadcast to every lane with scalar readlanes.
 
+// Partner exchange for the butterfly stages: the stage that pairs lanes across
+// bit log2(o) reads the partner's value.  Across rows of 16 lanes (o = 16, 32)
+// this is a permute through the LDS crossbar; inside a row it is a DPP lane
+// permutation (row mirror, half-row mirror, quad permutations), whose partner
+// differs in the stage's bit and agrees in every higher bit, which is all the
+// reductions below rely on.
+__device__ inline double xor_partner(double v, int o) {
+  if (o == 8) return dpp_d<DPP_ROW_MIRROR>(v);
+  if (o == 4) return dpp_d<DPP_ROW_HALF_MIRROR>(v);
+  if (o == 2) return dpp_d<DPP_QUAD_2301>(v);
+  if (o == 1) return dpp_d<DPP_QUAD_1032>(v);
+  return __shfl_xor(v, o, WAVE);
+}
+
 template <int V2, int LOG2V>
 __device__ inline void tr_reduce_dot2(double (&s)[V2], double (&e)[V2], int lane) {
 #pragma unroll
@@ -192,8 +206,8 @@ __device__ inline void tr_reduce_dot2(double (&s)[V2], double (&e)[V2], int lane
       const double ke = hi ? e[k + half] : e[k];
       const double ss = hi ? s[k] : s[k + half];
       const double se = hi ? e[k] : e[k + half];
-      const double rs = __shfl_xor(ss, o, WAVE);
-      const double re = __shfl_xor(se, o, WAVE);
+      const double rs = xor_partner(ss, o);
+      const double re = xor_partner(se, o);
       double t;
       two_sum(ks, rs, s[k], t);
       e[k] = ke + re + t;
@@ -201,8 +215,8 @@ __device__ inline void tr_reduce_dot2(double (&s)[V2], double (&e)[V2], int lane
   }
 #pragma unroll
   for (int o = 32 >> LOG2V; o >= 1; o >>= 1) {
-    const double rs = __shfl_xor(s[0], o, WAVE);
-    const double re = __shfl_xor(e[0], o, WAVE);
+    const double rs = xor_partner(s[0], o);
+    const double re = xor_partner(e[0], o);
     double t;
     two_sum(s[0], rs, s[0], t);
     e[0] = e[0] + re + t;
@@ -220,11 +234,11 @@ __device__ inline void tr_reduce_plain(double (&s)[V2], int lane) {
     for (int k = 0; k < half; ++k) {
       const double ks = hi ? s[k + half] : s[k];
       const double ss = hi ? s[k] : s[k + half];
-      s[k] = ks + __shfl_xor(ss, o, WAVE);
+      s[k] = ks + xor_partner(ss, o);
     }
   }
 #pragma unroll
-  for (int o = 32 >> LOG2V; o >= 1; o >>= 1) s[0] += __shfl_xor(s[0], o, WAVE);
+  for (int o = 32 >> LOG2V; o >= 1; o >>= 1) s[0] += xor_partner(s[0], o);
 }
 
 // lane holding value index k after the transpose-reduction
@@ -237,27 +251,54 @@ __device__ constexpr int tr_src_lane(int k) {
 
 template <int B>
 struct BatchShape {
-  static constexpr int RB = (B >= 8) ? 2 : (B >= 4 ? 4 : (B >= 2 ? 4 : 8));
+  static constexpr int RB = 2;  // rows per wave batch
   static constexpr int V = RB * B;
   static constexpr int V2 = V <= 1 ? 1 : V <= 2 ? 2 : V <= 4 ? 4 : V <= 8 ? 8 : V <= 16 ? 16 : V <= 32 ? 32 : 64;
   static constexpr int LOG2V = V2 == 1 ? 0 : V2 == 2 ? 1 : V2 == 4 ? 2 : V2 == 8 ? 3 : V2 == 16 ? 4 : V2 == 32 ? 5 : 6;
 };
 
-template <int B, int NSP, bool DOT2>
+// rows [rb, rb+RB) of the wave's batch, columns (2 lane + 128 s, +1); zero
+// outside [.., r1) and past column n.  A must be 16-byte aligned with even lda.
+template <int RB>
+__device__ inline void r2_load(double2 (&a)[RB][2], const double* __restrict__ A, int64_t lda, int n, int64_t rb,
+                               int64_t r1, int lane) {
+#pragma unroll
+  for (int q = 0; q < RB; ++q) {
+    const int64_t row = rb + q;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int c = 2 * lane + 128 * s;
+      if (row < r1 && c + 1 < n) a[q][s] = *reinterpret_cast<const double2*>(A + row * lda + c);
+      else if (row < r1 && c < n) a[q][s] = make_double2(A[row * lda + c], 0.0);
+      else a[q][s] = make_double2(0.0, 0.0);
+    }
+  }
+}
+
+// Real data, n <= 256, b <= 2, 16-byte aligned rows: lane l owns the column
+// pairs (2l, 2l+1) and (2l+128, 2l+129).  Each wave walks batches of RB rows
+// and loads the next batch before it works on the current one.  The row sums
+// of the batch are reduced together by the compensated transpose-reduction
+// and broadcast with scalar readlanes.  The four waves' column sums are
+// combined through LDS (compensated for the A_V group) and each workgroup
+// writes one record [G_V | G_X | G_W | G_V error] of 4 n b doubles.
+// INIT: the start pass (A_V = A V_0 and A^* A_V only).
+template <int B, bool DOT2, bool INIT>
 __global__ __launch_bounds__(256) void k_astream_r2(const double* __restrict__ A, int64_t lda, int64_t m, int n,
                                                     const double* __restrict__ W, double* __restrict__ AW,
                                                     const double* __restrict__ AVp, const double* __restrict__ AXp,
-                                                    double* __restrict__ Gpart, int64_t rows_per_block, int INIT,
-                                                    int aligned, const Ctl* __restrict__ ctl) {
+                                                    double* __restrict__ Gpart, int64_t rows_per_block,
+                                                    const Ctl* __restrict__ ctl) {
   if (ctl != nullptr && ctl->done) return;
   using SH = BatchShape<B>;
   constexpr int RB = SH::RB, V = SH::V, V2 = SH::V2, LOG2V = SH::LOG2V;
+  __shared__ double red[4][2][256 * B];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool has_x = AXp != nullptr;
-  double2 w[NSP][B];
-  double2 g1s[NSP][B], g1e[NSP][B], gx[NSP][B], gw[NSP][B];
+  double2 w[2][B];
+  double2 g1s[2][B], g1e[2][B], gx[2][B], gw[2][B];
 #pragma unroll
-  for (int s = 0; s < NSP; ++s) {
+  for (int s = 0; s < 2; ++s) {
     const int c = 2 * lane + 128 * s;
 #pragma unroll
     for (int j = 0; j < B; ++j) {
@@ -271,31 +312,29 @@ __global__ __launch_bounds__(256) void k_astream_r2(const double* __restrict__ A
   }
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t r1 = (r0 + rows_per_block < m) ? r0 + rows_per_block : m;
-  for (int64_t rb = r0 + (int64_t)wave * RB; rb < r1; rb += 4 * RB) {
-    double2 a[RB][NSP];
+  int64_t rb = r0 + (int64_t)wave * RB;
+  double2 a[RB][2], an[RB][2];
+  r2_load<RB>(an, A, lda, n, rb, r1, lane);
+  double avn = 0.0, axn = 0.0;
+  if (!INIT && lane < V && rb + lane / B < r1) {
+    avn = AVp[rb * B + lane];
+    if (has_x) axn = AXp[rb * B + lane];
+  }
+  for (; rb < r1; rb += 4 * RB) {
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
-      const int64_t row = rb + q;
-#pragma unroll
-      for (int s = 0; s < NSP; ++s) {
-        const int c = 2 * lane + 128 * s;
-        if (aligned && row < r1 && c + 1 < n) {
-          a[q][s] = *reinterpret_cast<const double2*>(A + row * lda + c);
-        } else if (row < r1 && c + 1 < n) {
-          a[q][s].x = A[row * lda + c];
-          a[q][s].y = A[row * lda + c + 1];
-        } else {
-          a[q][s].x = (row < r1 && c < n) ? A[row * lda + c] : 0.0;
-          a[q][s].y = 0.0;
-        }
-      }
+      a[q][0] = an[q][0];
+      a[q][1] = an[q][1];
     }
-    // panel values of the batch: one coalesced load, then scalar broadcasts
-    double avl = 0.0, axl = 0.0;
+    const double avl = avn, axl = axn;
+    const int64_t rn = rb + 4 * RB;
+    r2_load<RB>(an, A, lda, n, rn, r1, lane);
     if (!INIT) {
-      if (lane < V && rb + lane / B < r1) {
-        avl = AVp[rb * B + lane];
-        if (has_x) axl = AXp[rb * B + lane];
+      avn = 0.0;
+      axn = 0.0;
+      if (lane < V && rn + lane / B < r1) {
+        avn = AVp[rn * B + lane];
+        if (has_x) axn = AXp[rn * B + lane];
       }
     }
     // row sums of A W for the batch
@@ -311,7 +350,7 @@ __global__ __launch_bounds__(256) void k_astream_r2(const double* __restrict__ A
       for (int j = 0; j < B; ++j) {
         const int v = q * B + j;
 #pragma unroll
-        for (int s = 0; s < NSP; ++s) {
+        for (int s = 0; s < 2; ++s) {
           if constexpr (DOT2) {
             dot2_add(a[q][s].x, w[s][j].x, ys[v], ye[v]);
             dot2_add(a[q][s].y, w[s][j].y, ys[v], ye[v]);
@@ -332,6 +371,7 @@ __global__ __launch_bounds__(256) void k_astream_r2(const double* __restrict__ A
     for (int v = 0; v < V; ++v)
       if (lane == v) out = y[v];
     if (lane < V && rb + lane / B < r1) AW[rb * B + lane] = out;
+    // column sums: A^* A_V (Dot2; A^* A_W in the start pass), A^* A_X, A^* A_W
 #pragma unroll
     for (int q = 0; q < RB; ++q)
 #pragma unroll
@@ -339,9 +379,8 @@ __global__ __launch_bounds__(256) void k_astream_r2(const double* __restrict__ A
         const int v = q * B + j;
         const double yv = y[v];
         const double av = INIT ? yv : readlane_d(avl, v);
-        const double ax = INIT ? 0.0 : readlane_d(axl, v);
 #pragma unroll
-        for (int s = 0; s < NSP; ++s) {
+        for (int s = 0; s < 2; ++s) {
           if constexpr (DOT2) {
             dot2_add(a[q][s].x, av, g1s[s][j].x, g1e[s][j].x);
             dot2_add(a[q][s].y, av, g1s[s][j].y, g1e[s][j].y);
@@ -349,7 +388,8 @@ __global__ __launch_bounds__(256) void k_astream_r2(const double* __restrict__ A
             g1s[s][j].x = fma(a[q][s].x, av, g1s[s][j].x);
             g1s[s][j].y = fma(a[q][s].y, av, g1s[s][j].y);
           }
-          if (!INIT) {
+          if constexpr (!INIT) {
+            const double ax = readlane_d(axl, v);
             gx[s][j].x = fma(a[q][s].x, ax, gx[s][j].x);
             gx[s][j].y = fma(a[q][s].y, ax, gx[s][j].y);
             gw[s][j].x = fma(a[q][s].x, yv, gw[s][j].x);
@@ -358,24 +398,47 @@ __global__ __launch_bounds__(256) void k_astream_r2(const double* __restrict__ A
         }
       }
   }
+  // combine the four waves through LDS, two planes at a time
   const int64_t plane = (int64_t)n * B;
-  double* gp = Gpart + ((int64_t)blockIdx.x * 4 + wave) * 4 * plane;
+  double* gp = Gpart + (int64_t)blockIdx.x * 4 * plane;
 #pragma unroll
-  for (int s = 0; s < NSP; ++s) {
-    const int c = 2 * lane + 128 * s;
+  for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      if (c + h < n) {
+      const int c = 2 * lane + 128 * s + h;
 #pragma unroll
-        for (int j = 0; j < B; ++j) {
-          const int64_t e = (int64_t)(c + h) * B + j;
-          gp[e] = h ? g1s[s][j].y : g1s[s][j].x;
-          gp[plane + e] = h ? gx[s][j].y : gx[s][j].x;
-          gp[2 * plane + e] = h ? gw[s][j].y : gw[s][j].x;
-          gp[3 * plane + e] = h ? g1e[s][j].y : g1e[s][j].x;
-        }
+      for (int j = 0; j < B; ++j) {
+        red[wave][0][c * B + j] = h ? g1s[s][j].y : g1s[s][j].x;
+        red[wave][1][c * B + j] = h ? g1e[s][j].y : g1e[s][j].x;
       }
     }
+  __syncthreads();
+  for (int e = threadIdx.x; e < plane; e += 256) {
+    double S = red[0][0][e], E = red[0][1][e], t;
+#pragma unroll
+    for (int q = 1; q < 4; ++q) {
+      two_sum(S, red[q][0][e], S, t);
+      E += t + red[q][1][e];
+    }
+    gp[e] = S;
+    gp[3 * plane + e] = E;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = 2 * lane + 128 * s + h;
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        red[wave][0][c * B + j] = h ? gx[s][j].y : gx[s][j].x;
+        red[wave][1][c * B + j] = h ? gw[s][j].y : gw[s][j].x;
+      }
+    }
+  __syncthreads();
+  for (int e = threadIdx.x; e < plane; e += 256) {
+    gp[plane + e] = (red[0][0][e] + red[1][0][e]) + (red[2][0][e] + red[3][0][e]);
+    gp[2 * plane + e] = (red[0][1][e] + red[1][1][e]) + (red[2][1][e] + red[3][1][e]);
   }
 }
 

@@ -1,38 +1,46 @@
-// Instantiations of the real 16-byte-load A-stream kernel (n <= 256).
+// Instantiations of the real 16-byte-load A-stream kernel (n <= 256, b <= 2).
 #include "astream_kernels.hpp"
 #include "kernels.hpp"
 
 namespace rl {
 
-template <int B, bool DOT2>
-static void launch_r2(hipStream_t st, int64_t nb, int init, int aligned, const double* A, int64_t lda, int64_t m,
-                      int n, const double* W, double* AW, const double* AVp, const double* AXp, double* Gpart,
+template <int B, bool DOT2, bool INIT>
+static void launch_r2(hipStream_t st, int64_t nb, int64_t rows, const double* A, int64_t lda, int64_t m, int n,
+                      const double* W, double* AW, const double* AVp, const double* AXp, double* Gpart,
                       const Ctl* ctl) {
-  const int64_t rows = (m + nb - 1) / nb;
-  hipLaunchKernelGGL((k_astream_r2<B, 2, DOT2>), dim3((unsigned)nb), dim3(256), 0, st, A, lda, m, n, W, AW, AVp, AXp,
-                     Gpart, rows, init, aligned, ctl);
+  hipLaunchKernelGGL((k_astream_r2<B, DOT2, INIT>), dim3((unsigned)nb), dim3(256), 0, st, A, lda, m, n, W, AW, AVp,
+                     AXp, Gpart, rows, ctl);
 }
 
-template <bool DOT2>
-static bool by_b(int B, hipStream_t st, int64_t nb, int init, int aligned, const double* A, int64_t lda, int64_t m,
-                 int n, const double* W, double* AW, const double* AVp, const double* AXp, double* Gpart,
-                 const Ctl* ctl) {
-  switch (B) {
-#define RL_CASE(BB) \
-  case BB: launch_r2<BB, DOT2>(st, nb, init, aligned, A, lda, m, n, W, AW, AVp, AXp, Gpart, ctl); return true;
-    RL_CASE(1) RL_CASE(2) RL_CASE(3) RL_CASE(4) RL_CASE(5)
-    RL_CASE(6) RL_CASE(7) RL_CASE(8) RL_CASE(9) RL_CASE(10)
-#undef RL_CASE
-    default: return false;
-  }
+template <bool DOT2, bool INIT>
+static bool by_b(int B, hipStream_t st, int64_t nb, int64_t rows, const double* A, int64_t lda, int64_t m, int n,
+                 const double* W, double* AW, const double* AVp, const double* AXp, double* Gpart, const Ctl* ctl) {
+  if (B == 1) launch_r2<1, DOT2, INIT>(st, nb, rows, A, lda, m, n, W, AW, AVp, AXp, Gpart, ctl);
+  else if (B == 2) launch_r2<2, DOT2, INIT>(st, nb, rows, A, lda, m, n, W, AW, AVp, AXp, Gpart, ctl);
+  else return false;
+  return true;
 }
 
-bool dispatch_astream_r2(bool dot2, int init, int aligned, int B, hipStream_t st, int64_t nb, const double* A,
-                         int64_t lda, int64_t m, int n, const double* W, double* AW, const double* AVp,
-                         const double* AXp, double* Gpart, const Ctl* ctl) {
+// Workgroups of the r2 pass: at most 1024 (four per compute unit, one round at
+// full occupancy), at least 64 rows each.
+int64_t astream_r2_blocks(int64_t m) {
+  int64_t rows = (m + 1023) / 1024;
+  if (rows < 64) rows = 64;
+  return (m + rows - 1) / rows;
+}
+
+bool astream_r2_fits(int B, int n, bool aligned) { return aligned && n <= 256 && B >= 1 && B <= 2; }
+
+bool dispatch_astream_r2(bool dot2, int init, int B, hipStream_t st, int64_t nb, const double* A, int64_t lda,
+                         int64_t m, int n, const double* W, double* AW, const double* AVp, const double* AXp,
+                         double* Gpart, const Ctl* ctl) {
   if (n > 256) return false;
-  if (dot2) return by_b<true>(B, st, nb, init, aligned, A, lda, m, n, W, AW, AVp, AXp, Gpart, ctl);
-  return by_b<false>(B, st, nb, init, aligned, A, lda, m, n, W, AW, AVp, AXp, Gpart, ctl);
+  const int64_t rows = (m + nb - 1) / nb;
+  if (dot2)
+    return init ? by_b<true, true>(B, st, nb, rows, A, lda, m, n, W, AW, AVp, AXp, Gpart, ctl)
+                : by_b<true, false>(B, st, nb, rows, A, lda, m, n, W, AW, AVp, AXp, Gpart, ctl);
+  return init ? by_b<false, true>(B, st, nb, rows, A, lda, m, n, W, AW, AVp, AXp, Gpart, ctl)
+              : by_b<false, false>(B, st, nb, rows, A, lda, m, n, W, AW, AVp, AXp, Gpart, ctl);
 }
 
 }  // namespace rl

@@ -25,9 +25,11 @@ int astream_ns(int n);
 int64_t astream_blocks(int64_t m, int n, int B, int es_d);
 int64_t astream_part_doubles(int64_t m, int n, int B, int es_d);
 int64_t astream_tmp_doubles(int64_t m, int n, int B, int es_d);
-bool dispatch_astream_r2(bool dot2, int init, int aligned, int B, hipStream_t st, int64_t nb, const double* A,
-                         int64_t lda, int64_t m, int n, const double* W, double* AW, const double* AVp,
-                         const double* AXp, double* Gpart, const Ctl* ctl);
+int64_t astream_r2_blocks(int64_t m);
+bool astream_r2_fits(int B, int n, bool aligned);
+bool dispatch_astream_r2(bool dot2, int init, int B, hipStream_t st, int64_t nb, const double* A, int64_t lda,
+                         int64_t m, int n, const double* W, double* AW, const double* AVp, const double* AXp,
+                         double* Gpart, const Ctl* ctl);
 bool dispatch_astream_gd(bool dot2, int ns, int B, hipStream_t st, int64_t nb, const void* A, int64_t lda, int64_t m,
                          int n, const void* W, void* AW, const void* AVp, const void* AXp, int init, double* Gpart,
                          const Ctl* ctl);
@@ -46,6 +48,10 @@ hipError_t launch_final_u(hipStream_t st, bool cplx, const void* AV, const void*
 int64_t tsqr_groups(int64_t m, int t);
 hipError_t launch_tsqr(hipStream_t st, bool cplx, const void* P0, int b0, const void* P1, int b1, const void* P2,
                        int b2, int64_t m, void* bufA, void* bufB, void** Rfinal, Ctl* ctl, int check_done);
+
+// Copies the control block between device memory and the handle's mapped
+// host block (either direction) with vector stores.
+hipError_t launch_publish(hipStream_t st, const Ctl* src, Ctl* dst);
 
 // nside.hip
 hipError_t launch_trmv(hipStream_t st, bool cplx, int B, const void* M, int n, int lower, const void* X, void* Y,

@@ -28,8 +28,6 @@ constexpr int NS_THREADS = 256;
 constexpr int RR_TMAX = 32;
 constexpr int RR_BMAX = 16;
 
-__device__ inline double shfl_xor_(double v, int o) { return __shfl_xor(v, o, WAVE); }
-__device__ inline cd shfl_xor_(cd v, int o) { return cd{__shfl_xor(v.x, o, WAVE), __shfl_xor(v.y, o, WAVE)}; }
 __device__ inline double absval(double a) { return fabs(a); }
 __device__ inline double absval(cd a) { return hypot(a.x, a.y); }
 
@@ -65,11 +63,9 @@ __global__ __launch_bounds__(NS_THREADS) void k_trmv(const T* __restrict__ M, in
       }
     }
   }
+  // the 16 threads of a row are one DPP row of the wave
 #pragma unroll
-  for (int j = 0; j < B; ++j) {
-#pragma unroll
-    for (int o = 8; o >= 1; o >>= 1) acc[j] = add(acc[j], shfl_xor_(acc[j], o));
-  }
+  for (int j = 0; j < B; ++j) acc[j] = row_sum16(acc[j]);
   if (kk == 0 && i < n) {
 #pragma unroll
     for (int j = 0; j < B; ++j) Y[(int64_t)i * B + j] = acc[j];
@@ -226,8 +222,8 @@ __device__ void jacobi_wave(T* M, T* Vj, int t, int lane) {
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int B, int init_mode, int with_x, const T* __restrict__ Rt,
+template <typename T, int B>
+__global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int with_x, const T* __restrict__ Rt,
                                                    T* __restrict__ V, T* __restrict__ X, const T* __restrict__ W,
                                                    const T* __restrict__ G3, T* __restrict__ Vn,
                                                    T* __restrict__ Rres, T* __restrict__ CVout, T* __restrict__ CXout,
@@ -293,31 +289,26 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int B, int init_mode, 
 #pragma unroll
     for (int j = 0; j < RR_BMAX; ++j) vals[j] = zero<T>();
     for (int r = tid; r < n; r += blockDim.x) {
-      T tr[RR_TMAX], gr[RR_TMAX];
+      T tr[3 * B], gr[3 * B];
+#pragma unroll
       for (int j = 0; j < B; ++j) {
         tr[j] = V[(int64_t)r * B + j];
         gr[j] = GV[(int64_t)r * B + j];
-      }
-      if (mode == 2) {
-        for (int j = 0; j < B; ++j) {
-          tr[B + j] = X[(int64_t)r * B + j];
-          gr[B + j] = GX[(int64_t)r * B + j];
-          tr[2 * B + j] = W[(int64_t)r * B + j];
-          gr[2 * B + j] = GW[(int64_t)r * B + j];
-        }
-      } else if (mode == 1) {
-        for (int j = 0; j < B; ++j) {
-          tr[B + j] = W[(int64_t)r * B + j];
-          gr[B + j] = GW[(int64_t)r * B + j];
-        }
+        tr[B + j] = (mode == 2) ? X[(int64_t)r * B + j] : ((mode == 1) ? W[(int64_t)r * B + j] : zero<T>());
+        gr[B + j] = (mode == 2) ? GX[(int64_t)r * B + j] : ((mode == 1) ? GW[(int64_t)r * B + j] : zero<T>());
+        tr[2 * B + j] = (mode == 2) ? W[(int64_t)r * B + j] : zero<T>();
+        gr[2 * B + j] = (mode == 2) ? GW[(int64_t)r * B + j] : zero<T>();
       }
 #pragma unroll
       for (int j = 0; j < RR_BMAX; ++j) {
         if (j < B) {
           T v = zero<T>(), g = zero<T>();
-          for (int c = 0; c < t; ++c) {
-            v = fmac(tr[c], CV[c * B + j], v);
-            g = fmac(gr[c], CV[c * B + j], g);
+#pragma unroll
+          for (int c = 0; c < 3 * B; ++c) {
+            if (c < t) {
+              v = fmac(tr[c], CV[c * B + j], v);
+              g = fmac(gr[c], CV[c * B + j], g);
+            }
           }
           const double th2 = th[t - B + j] * th[t - B + j];
           const T res = sub(g, scal(v, th2));
@@ -382,19 +373,19 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int B, int init_mode, 
   // pass 2: X = T C_X from the old T, then V <- V_new
   for (int r = tid; r < n; r += blockDim.x) {
     if (xupd) {
-      T tr[RR_TMAX];
-      for (int j = 0; j < B; ++j) tr[j] = V[(int64_t)r * B + j];
-      if (mode == 2) {
-        for (int j = 0; j < B; ++j) {
-          tr[B + j] = X[(int64_t)r * B + j];
-          tr[2 * B + j] = W[(int64_t)r * B + j];
-        }
-      } else {
-        for (int j = 0; j < B; ++j) tr[B + j] = W[(int64_t)r * B + j];
+      T tr[3 * B];
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        tr[j] = V[(int64_t)r * B + j];
+        tr[B + j] = (mode == 2) ? X[(int64_t)r * B + j] : W[(int64_t)r * B + j];
+        tr[2 * B + j] = (mode == 2) ? W[(int64_t)r * B + j] : zero<T>();
       }
+#pragma unroll
       for (int j = 0; j < B; ++j) {
         T x = zero<T>();
-        for (int c = 0; c < t; ++c) x = fmac(tr[c], CX[c * B + j], x);
+#pragma unroll
+        for (int c = 0; c < 3 * B; ++c)
+          if (c < t) x = fmac(tr[c], CX[c * B + j], x);
         X[(int64_t)r * B + j] = x;
       }
     }
@@ -687,16 +678,45 @@ hipError_t launch_orth(hipStream_t st, bool cplx, int n, int B, const void* V, c
   return hipGetLastError();
 }
 
+template <typename T, int B>
+static void rr_go(hipStream_t st, int n, int init_mode, int with_x, const void* Rt, void* V, void* X, const void* W,
+                  const void* G3, void* Vn, void* Rres, void* CV, void* CX, double* thb, double* ht, double* hr,
+                  Ctl* ctl) {
+  hipLaunchKernelGGL((k_rr<T, B>), dim3(1), dim3(NS_THREADS), 0, st, n, init_mode, with_x, (const T*)Rt, (T*)V,
+                     (T*)X, (const T*)W, (const T*)G3, (T*)Vn, (T*)Rres, (T*)CV, (T*)CX, thb, ht, hr, ctl);
+}
+
+template <typename T>
+static bool rr_by_b(int B, hipStream_t st, int n, int init_mode, int with_x, const void* Rt, void* V, void* X,
+                    const void* W, const void* G3, void* Vn, void* Rres, void* CV, void* CX, double* thb, double* ht,
+                    double* hr, Ctl* ctl) {
+  switch (B) {
+#define RL_CASE(BB) \
+  case BB: rr_go<T, BB>(st, n, init_mode, with_x, Rt, V, X, W, G3, Vn, Rres, CV, CX, thb, ht, hr, ctl); return true;
+    RL_CASE(1) RL_CASE(2) RL_CASE(3) RL_CASE(4) RL_CASE(5)
+    RL_CASE(6) RL_CASE(7) RL_CASE(8) RL_CASE(9) RL_CASE(10)
+#undef RL_CASE
+    default: return false;
+  }
+}
+
 hipError_t launch_rr(hipStream_t st, bool cplx, int n, int B, int init_mode, int with_x, const void* Rt, void* V,
                      void* X, const void* W, const void* G3, void* Vn, void* Rres, void* CV, void* CX, double* thb,
                      double* ht, double* hr, Ctl* ctl) {
-  if (cplx)
-    hipLaunchKernelGGL(k_rr<cd>, dim3(1), dim3(NS_THREADS), 0, st, n, B, init_mode, with_x, (const cd*)Rt, (cd*)V,
-                       (cd*)X, (const cd*)W, (const cd*)G3, (cd*)Vn, (cd*)Rres, (cd*)CV, (cd*)CX, thb, ht, hr, ctl);
-  else
-    hipLaunchKernelGGL(k_rr<double>, dim3(1), dim3(NS_THREADS), 0, st, n, B, init_mode, with_x, (const double*)Rt,
-                       (double*)V, (double*)X, (const double*)W, (const double*)G3, (double*)Vn, (double*)Rres,
-                       (double*)CV, (double*)CX, thb, ht, hr, ctl);
+  const bool ok = cplx ? rr_by_b<cd>(B, st, n, init_mode, with_x, Rt, V, X, W, G3, Vn, Rres, CV, CX, thb, ht, hr, ctl)
+                       : rr_by_b<double>(B, st, n, init_mode, with_x, Rt, V, X, W, G3, Vn, Rres, CV, CX, thb, ht, hr,
+                                         ctl);
+  if (!ok) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+__global__ void k_publish(const int32_t* __restrict__ src, int32_t* __restrict__ dst, int words) {
+  for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+}
+
+hipError_t launch_publish(hipStream_t st, const Ctl* src, Ctl* dst) {
+  static_assert(sizeof(Ctl) % 4 == 0, "Ctl is copied in 32-bit words");
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, st, (const int32_t*)src, (int32_t*)dst, (int)(sizeof(Ctl) / 4));
   return hipGetLastError();
 }
 

@@ -41,7 +41,8 @@ struct rl_ctx {
   hipStream_t stream = nullptr;
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  Ctl* host_ctl = nullptr;  // pinned
+  Ctl* host_ctl = nullptr;      // pinned, mapped host memory
+  Ctl* host_ctl_dev = nullptr;  // its device address
   int64_t lds_budget = 64 * 1024;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> prof;  // pairs around A-stream launches
@@ -206,7 +207,7 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   hc.status = 1;
   *h->host_ctl = hc;
   CK(hipEventRecord(h->ev[0], st));
-  CK(hipMemcpyAsync(ctl, h->host_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
+  CK(launch_publish(st, h->host_ctl_dev, ctl));
 
   // Step 1-2: sketch and QR
   const double scale = 1.0 / sqrt((double)o.zeta);
@@ -244,7 +245,7 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   CK(launch_rr(st, cplx, (int)n, B, 1, 0, Rt, at<void>(ws, L.V), at<void>(ws, L.X), at<void>(ws, L.W),
                at<void>(ws, L.G3), at<void>(ws, L.Vn), at<void>(ws, L.Rres), at<void>(ws, L.CV), at<void>(ws, L.CX),
                at<double>(ws, L.thb), at<double>(ws, L.ht), at<double>(ws, L.hr), ctl));
-  CK(hipMemcpyAsync(h->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  CK(launch_publish(st, ctl, h->host_ctl_dev));
   CK(hipEventRecord(h->ev[1], st));
   CK(hipStreamSynchronize(st));
   if (h->host_ctl->nonfinite) return RL_ERR_NONFINITE;
@@ -270,7 +271,7 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
                  at<double>(ws, L.thb), at<double>(ws, L.ht), at<double>(ws, L.hr), ctl));
     const bool can_stop = (o.stop_rule == RL_STOP_TOL) || (o.stop_rule == RL_STOP_PAPER && it % o.check_every == 0);
     if (can_stop) {
-      CK(hipMemcpyAsync(h->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+      CK(launch_publish(st, ctl, h->host_ctl_dev));
       CK(hipStreamSynchronize(st));
       if (h->host_ctl->done) {
         ++it;
@@ -285,7 +286,7 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
     CK(launch_final_u(st, cplx, at<void>(ws, L.AV), at<void>(ws, L.AX), at<void>(ws, L.AW), m, B, k,
                       at<void>(ws, L.CV), at<double>(ws, L.thb), Uout, ldu, ctl));
   CK(hipEventRecord(h->ev[3], st));
-  CK(hipMemcpyAsync(h->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  CK(launch_publish(st, ctl, h->host_ctl_dev));
   CK(hipStreamSynchronize(st));
   const Ctl& fc = *h->host_ctl;
   const int status = fc.done ? RL_OK : RL_NOT_CONVERGED;
@@ -356,9 +357,14 @@ int rl_create(rl_handle* out, int device, void* stream) {
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
     h->lds_budget = std::min<int64_t>(lds, 160 * 1024);
-  if (hipHostMalloc((void**)&h->host_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&h->host_ctl, sizeof(Ctl), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
     delete h;
     return RL_ERR_NOMEM;
+  }
+  if (hipHostGetDevicePointer((void**)&h->host_ctl_dev, h->host_ctl, 0) != hipSuccess) {
+    (void)hipHostFree(h->host_ctl);
+    delete h;
+    return RL_ERR_DEVICE;
   }
   for (int i = 0; i < 4; ++i)
     if (hipEventCreate(&h->ev[i]) != hipSuccess) {

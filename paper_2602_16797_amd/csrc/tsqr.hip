@@ -109,16 +109,17 @@ __global__ __launch_bounds__(TS_TILE) void k_tsqr(const T* __restrict__ P0, int 
 }
 
 // ---------------------------------------------------------------------------
-// Register TSQR for t <= 16: a wave holds a 64-row tile, one row per lane
-// (t values in registers).  Lanes 0..t-1 carry the running R; the other lanes
-// take the next 64-t input rows (prefetched one tile ahead).  Householder QR
-// of the tile needs one batched wave reduction per column: with x the column
-// below the diagonal, |x|^2 and x^* a_k (k > j) are summed together, and
+// Register TSQR for t <= 16: a wave holds a tile of 64*RPL rows, RPL rows per
+// lane (t values each in registers).  Rows 0..t-1 of the tile (lanes 0..t-1,
+// first register row) carry the running R; the other rows take the next
+// 64*RPL-t input rows, loaded one tile ahead.  Householder QR of the tile
+// needs one batched wave reduction per column: with x the column below the
+// diagonal, |x|^2 and x^* a_k (k > j) are summed together, and
 // v^* a_k = a_jk + conj(1/(alpha-beta)) x^* a_k gives the reflector products
-// without a second pass.  The four waves' R factors are stacked (4t <= 64
-// rows) and factored once more by wave 0.  k_tsqr_w writes one R per
-// workgroup; k_tsqr_w_merge (one workgroup, the next launch on the stream)
-// reduces those the same way and writes R_T.
+// without a second pass.  The waves' R factors are stacked in LDS and
+// factored again by wave 0.  k_tsqr_w writes one R per workgroup;
+// k_tsqr_w_merge (one workgroup of 16 waves, 8 for complex data or t > 8, the
+// next launch on the stream) reduces those the same way and writes R_T.
 constexpr int TW_THREADS = 256;
 constexpr int TW_TMAX = 16;
 
@@ -137,21 +138,34 @@ __device__ inline void tw_set(T (&x)[TT], int j, T v) {
     if (q == j) x[q] = v;
 }
 
-// QR of the 64 x t tile held one row per lane; on return lanes 0..t-1 hold R
-// (upper triangular) and every other entry of columns 0..t-1 is zero.
-template <typename T, int TT>
-__device__ void tw_tile_qr(T (&x)[TT], int t, int lane) {
+// QR of the tile; on return tile rows 0..t-1 hold R (upper triangular) and
+// every other entry of columns 0..t-1 is zero.
+template <typename T, int TT, int RPL>
+__device__ void tw_tile_qr(T (&x)[RPL][TT], int t, int lane) {
   for (int j = 0; j < t; ++j) {
-    const bool below = lane > j;
-    T xj = tw_get<T, TT>(x, j);
-    const double n2 = wave_sum(below ? abs2(xj) : 0.0);
+    T xj[RPL];
+    bool below[RPL];
+    double n2p = 0.0;
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+      xj[s] = tw_get<T, TT>(x[s], j);
+      below[s] = (s > 0) || (lane > j);
+      if (below[s]) n2p += abs2(xj[s]);
+    }
+    const double n2 = wave_sum(n2p);
     T dk[TT];
 #pragma unroll
     for (int k = 0; k < TT; ++k) {
       dk[k] = zero<T>();
-      if (k > j && k < t) dk[k] = wave_sum((below ? cfmac(xj, x[k], zero<T>()) : zero<T>()));
+      if (k > j && k < t) {
+        T acc = zero<T>();
+#pragma unroll
+        for (int s = 0; s < RPL; ++s)
+          if (below[s]) acc = cfmac(xj[s], x[s][k], acc);
+        dk[k] = wave_sum(acc);
+      }
     }
-    const T alpha = readlane_d(xj, j);
+    const T alpha = readlane_d(xj[0], j);
     const bool noref = (n2 == 0.0) && (ts_im(alpha) == 0.0);
     if (!noref) {
       const double nrm = sqrt(abs2(alpha) + n2);
@@ -159,139 +173,194 @@ __device__ void tw_tile_qr(T (&x)[TT], int t, int lane) {
       const T tau = divs(sub(from_real<T>(beta), alpha), from_real<T>(beta));
       const T sc = divs(from_real<T>(1.0), sub(alpha, from_real<T>(beta)));
       const T ct = conj_(tau), csc = conj_(sc);
-      const T v = (lane == j) ? from_real<T>(1.0) : (below ? mul(sc, xj) : zero<T>());
+      T v[RPL];
+#pragma unroll
+      for (int s = 0; s < RPL; ++s)
+        v[s] = (s == 0 && lane == j) ? from_real<T>(1.0) : (below[s] ? mul(sc, xj[s]) : zero<T>());
 #pragma unroll
       for (int k = 0; k < TT; ++k) {
         if (k > j && k < t) {
-          const T ajk = readlane_d(x[k], j);
+          const T ajk = readlane_d(x[0][k], j);
           const T f = mul(ct, fmac(csc, dk[k], ajk));
-          x[k] = fnmac(f, v, x[k]);
+#pragma unroll
+          for (int s = 0; s < RPL; ++s) x[s][k] = fnmac(f, v[s], x[s][k]);
         }
       }
-      if (lane == j) xj = from_real<T>(beta);
-      else if (below) xj = zero<T>();
-      tw_set<T, TT>(x, j, xj);
-    }
-  }
-}
-
-template <typename T, int TT>
-__device__ inline void tw_load(T (&x)[TT], const T* __restrict__ P0, int b0, const T* __restrict__ P1, int b1,
-                               const T* __restrict__ P2, int b2, int64_t row, bool valid) {
 #pragma unroll
-  for (int c = 0; c < TT; ++c) {
-    T v = zero<T>();
-    if (valid) {
-      if (c < b0) v = P0[row * b0 + c];
-      else if (c < b0 + b1) v = P1[row * b1 + (c - b0)];
-      else if (c < b0 + b1 + b2) v = P2[row * b2 + (c - b0 - b1)];
+      for (int s = 0; s < RPL; ++s) {
+        T nx = xj[s];
+        if (s == 0 && lane == j) nx = from_real<T>(beta);
+        else if (below[s]) nx = zero<T>();
+        tw_set<T, TT>(x[s], j, nx);
+      }
     }
-    x[c] = v;
   }
 }
 
-// Rows [g0, g1) of the stacked input, tiles of 64-t fresh rows, wave w takes
-// tiles w, w+4, ...; x ends as this wave's R.
-template <typename T, int TT>
-__device__ void tw_rows(T (&x)[TT], const T* __restrict__ P0, int b0, const T* __restrict__ P1, int b1,
-                        const T* __restrict__ P2, int b2, int64_t g0, int64_t g1, int t, int lane, int wave) {
-  const int fresh = 64 - t;
-  const int64_t step = 4 * (int64_t)fresh;
+// Input rows: the row-major panels [P0 | P1 | P2] (b0 + b1 + b2 = t columns).
+template <typename T>
+struct TwPanels {
+  const T* P0;
+  const T* P1;
+  const T* P2;
+  int b0, b1, b2;
+  __device__ T get(int64_t row, int c) const {
+    if (c < b0) return P0[row * b0 + c];
+    if (c < b0 + b1) return P1[row * b1 + (c - b0)];
+    return P2[row * b2 + (c - b0 - b1)];
+  }
+};
+
+// Tile rows t..64*RPL-1 of x <- input rows g + (tile row - t), zero past g1.
+template <typename T, int TT, int RPL, typename Src>
+__device__ inline void tw_load(T (&x)[RPL][TT], const Src& src, int64_t g, int64_t g1, int t, int lane) {
+#pragma unroll
+  for (int s = 0; s < RPL; ++s) {
+    const int tr = lane + 64 * s;
+    const int64_t row = g + tr - t;
+    const bool valid = tr >= t && row < g1;
+#pragma unroll
+    for (int c = 0; c < TT; ++c) x[s][c] = (valid && c < t) ? src.get(row, c) : zero<T>();
+  }
+}
+
+// Rows [g0, g1) of the input, tiles of 64*RPL-t fresh rows, wave w of nw
+// takes tiles w, w+nw, ...; x ends as this wave's R.
+template <typename T, int TT, int RPL, typename Src>
+__device__ void tw_rows(T (&x)[RPL][TT], const Src& src, int64_t g0, int64_t g1, int t, int lane, int wave, int nw) {
+  const int fresh = 64 * RPL - t;
+  const int64_t step = (int64_t)nw * fresh;
   int64_t g = g0 + (int64_t)wave * fresh;
-  T nx[TT];
-  {
-    const int64_t row = g + lane - t;
-    tw_load<T, TT>(nx, P0, b0, P1, b1, P2, b2, row, lane >= t && row < g1);
-  }
+  T nx[RPL][TT];
+  tw_load<T, TT, RPL>(nx, src, g, g1, t, lane);
   for (; g < g1; g += step) {
-    if (lane >= t) {
 #pragma unroll
-      for (int c = 0; c < TT; ++c) x[c] = nx[c];
+    for (int s = 0; s < RPL; ++s) {
+      if (lane + 64 * s >= t) {
+#pragma unroll
+        for (int c = 0; c < TT; ++c) x[s][c] = nx[s][c];
+      }
     }
-    const int64_t row = g + step + lane - t;
-    tw_load<T, TT>(nx, P0, b0, P1, b1, P2, b2, row, lane >= t && row < g1);
-    tw_tile_qr<T, TT>(x, t, lane);
+    tw_load<T, TT, RPL>(nx, src, g + step, g1, t, lane);
+    tw_tile_qr<T, TT, RPL>(x, t, lane);
   }
 }
 
-// Stack the four waves' R factors (through LDS) and factor them in wave 0.
-template <typename T, int TT>
-__device__ void tw_block_merge(T (&x)[TT], T* Rs, int t, int lane, int wave) {
+template <typename T>
+struct TwRows {  // rows of a row-major n x t array (global or LDS)
+  const T* P;
+  int t;
+  __device__ T get(int64_t row, int c) const { return P[row * t + c]; }
+};
+
+// Stack the NW waves' R factors in LDS and factor them in wave 0.
+template <typename T, int TT, int RPL, int NW>
+__device__ void tw_block_merge(T (&x)[RPL][TT], T* Rs, int t, int lane, int wave) {
   if (lane < t) {
 #pragma unroll
     for (int c = 0; c < TT; ++c)
-      if (c < t) Rs[(wave * t + lane) * t + c] = x[c];
+      if (c < t) Rs[(wave * t + lane) * t + c] = x[0][c];
   }
   __syncthreads();
   if (wave == 0) {
 #pragma unroll
-    for (int c = 0; c < TT; ++c) x[c] = (lane < 4 * t && c < t) ? Rs[lane * t + c] : zero<T>();
-    tw_tile_qr<T, TT>(x, t, lane);
+    for (int s = 0; s < RPL; ++s)
+#pragma unroll
+      for (int c = 0; c < TT; ++c) x[s][c] = zero<T>();
+    const TwRows<T> src{Rs, t};
+    tw_rows<T, TT, RPL>(x, src, 0, (int64_t)NW * t, t, lane, 0, 1);
   }
 }
 
-template <typename T, int TT>
+template <typename T, int TT, int RPL>
 __global__ __launch_bounds__(TW_THREADS) void k_tsqr_w(const T* __restrict__ P0, int b0, const T* __restrict__ P1,
                                                        int b1, const T* __restrict__ P2, int b2, int64_t m,
                                                        int64_t rows_per_block, T* __restrict__ Rpart,
                                                        const Ctl* __restrict__ ctl, int check_done) {
   if (check_done && ctl->done) return;
-  __shared__ T Rs[4 * TW_TMAX * TW_TMAX];
+  constexpr int NW = TW_THREADS / 64;
+  __shared__ T Rs[NW * TT * TT];
   const int t = b0 + b1 + b2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  T x[TT];
+  T x[RPL][TT];
 #pragma unroll
-  for (int c = 0; c < TT; ++c) x[c] = zero<T>();
+  for (int s = 0; s < RPL; ++s)
+#pragma unroll
+    for (int c = 0; c < TT; ++c) x[s][c] = zero<T>();
   const int64_t g0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t g1 = (g0 + rows_per_block < m) ? g0 + rows_per_block : m;
-  tw_rows<T, TT>(x, P0, b0, P1, b1, P2, b2, g0, g1, t, lane, wave);
-  tw_block_merge<T, TT>(x, Rs, t, lane, wave);
+  const TwPanels<T> src{P0, P1, P2, b0, b1, b2};
+  tw_rows<T, TT, RPL>(x, src, g0, g1, t, lane, wave, NW);
+  tw_block_merge<T, TT, RPL, NW>(x, Rs, t, lane, wave);
   if (wave == 0 && lane < t) {
 #pragma unroll
     for (int c = 0; c < TT; ++c)
-      if (c < t) Rpart[((int64_t)blockIdx.x * t + lane) * t + c] = x[c];
+      if (c < t) Rpart[((int64_t)blockIdx.x * t + lane) * t + c] = x[0][c];
   }
 }
 
-// R_T of the stacked per-workgroup factors (groups*t rows), one workgroup.
-template <typename T, int TT>
-__global__ __launch_bounds__(TW_THREADS) void k_tsqr_w_merge(const T* __restrict__ Rpart, int t, int64_t rows,
-                                                             T* __restrict__ Rout, const Ctl* __restrict__ ctl,
-                                                             int check_done) {
+// R_T of the stacked per-workgroup factors (rows = groups * t), one workgroup.
+template <typename T, int TT, int RPL, int NW>
+__global__ __launch_bounds__(NW * 64) void k_tsqr_w_merge(const T* __restrict__ Rpart, int t, int64_t rows,
+                                                          T* __restrict__ Rout, const Ctl* __restrict__ ctl,
+                                                          int check_done) {
   if (check_done && ctl->done) return;
-  __shared__ T Rs[4 * TW_TMAX * TW_TMAX];
+  __shared__ T Rs[NW * TT * TT];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  T x[TT];
+  T x[RPL][TT];
 #pragma unroll
-  for (int c = 0; c < TT; ++c) x[c] = zero<T>();
-  tw_rows<T, TT>(x, Rpart, t, Rpart, 0, Rpart, 0, 0, rows, t, lane, wave);
-  tw_block_merge<T, TT>(x, Rs, t, lane, wave);
+  for (int s = 0; s < RPL; ++s)
+#pragma unroll
+    for (int c = 0; c < TT; ++c) x[s][c] = zero<T>();
+  const TwRows<T> src{Rpart, t};
+  tw_rows<T, TT, RPL>(x, src, 0, rows, t, lane, wave, NW);
+  tw_block_merge<T, TT, RPL, NW>(x, Rs, t, lane, wave);
   if (wave == 0 && lane < t) {
 #pragma unroll
     for (int c = 0; c < TT; ++c)
-      if (c < t) Rout[lane * t + c] = x[c];
+      if (c < t) Rout[lane * t + c] = x[0][c];
   }
+}
+
+// rows per lane: the tile (RPL x TT values, twice with the prefetch) stays
+// within the register budget
+template <typename T, int TT>
+struct TwRpl {
+  static constexpr int real = TT <= 4 ? 4 : (TT <= 8 ? 2 : 1);
+  static constexpr int value = sizeof(T) == 16 ? (real > 1 ? real / 2 : 1) : real;
+};
+template <typename T, int TT>
+struct TwMergeWaves {
+  static constexpr int value = (sizeof(T) == 16 || TT > 8) ? 8 : 16;
+};
+
+static int64_t tsqr_w_groups(int64_t m, int t, bool cplx) {
+  const int tt = t <= 4 ? 4 : (t <= 8 ? 8 : 16);
+  int rpl = tt <= 4 ? 4 : (tt <= 8 ? 2 : 1);
+  if (cplx) rpl = rpl > 1 ? rpl / 2 : 1;
+  const int64_t fresh = 64 * rpl - t;
+  int64_t g = (int64_t)sqrt(4.0 * (double)m / (double)t);
+  const int64_t gmax = (m + 4 * fresh - 1) / (4 * fresh);  // at least one tile per wave
+  if (g > gmax) g = gmax;
+  if (g > 1024) g = 1024;
+  if (g < 1) g = 1;
+  return g;
 }
 
 template <typename T, int TT>
 static void tsqr_w_go(hipStream_t st, const T* P0, int b0, const T* P1, int b1, const T* P2, int b2, int64_t m,
                       int64_t g, T* bufA, T* bufB, const Ctl* ctl, int check_done) {
+  constexpr int RPL = TwRpl<T, TT>::value;
+  constexpr int NWM = TwMergeWaves<T, TT>::value;
   const int t = b0 + b1 + b2;
   const int64_t rows = (m + g - 1) / g;
-  hipLaunchKernelGGL((k_tsqr_w<T, TT>), dim3((unsigned)g), dim3(TW_THREADS), 0, st, P0, b0, P1, b1, P2, b2, m, rows,
-                     bufA, ctl, check_done);
-  hipLaunchKernelGGL((k_tsqr_w_merge<T, TT>), dim3(1), dim3(TW_THREADS), 0, st, (const T*)bufA, t, g * t, bufB, ctl,
-                     check_done);
-}
-
-static int64_t tsqr_w_groups(int64_t m, int t) {
-  int64_t g = (int64_t)sqrt((double)m / (double)t);
-  const int64_t per = 4 * (int64_t)(64 - t);
-  const int64_t gmax = (m + per - 1) / per;  // at least one tile per wave
-  if (g > gmax) g = gmax;
-  if (g > 1024) g = 1024;
-  if (g < 1) g = 1;
-  return g;
+  // never-read panels still get a valid pointer
+  if (P1 == nullptr) P1 = P0;
+  if (P2 == nullptr) P2 = P0;
+  hipLaunchKernelGGL((k_tsqr_w<T, TT, RPL>), dim3((unsigned)g), dim3(TW_THREADS), 0, st, P0, b0, P1, b1, P2, b2, m,
+                     rows, bufA, ctl, check_done);
+  hipLaunchKernelGGL((k_tsqr_w_merge<T, TT, RPL, NWM>), dim3(1), dim3(NWM * 64), 0, st, (const T*)bufA, t, g * t,
+                     bufB, ctl, check_done);
 }
 
 static int64_t tsqr_lds_groups(int64_t m, int t) {
@@ -304,7 +373,7 @@ static int64_t tsqr_lds_groups(int64_t m, int t) {
 
 // Upper bound on the partial R factors of one TSQR launch (workspace sizing).
 int64_t tsqr_groups(int64_t m, int t) {
-  const int64_t a = tsqr_lds_groups(m, t), b = (t <= TW_TMAX) ? tsqr_w_groups(m, t) : 1;
+  const int64_t a = tsqr_lds_groups(m, t), b = (t <= TW_TMAX) ? tsqr_w_groups(m, t, true) : 1;
   return a > b ? a : b;
 }
 
@@ -314,7 +383,7 @@ static hipError_t tsqr_impl(hipStream_t st, const T* P0, int b0, const T* P1, in
   const int t = b0 + b1 + b2;
   if (t < 1 || t > TS_TMAX) return hipErrorInvalidValue;
   if (t <= TW_TMAX) {
-    const int64_t g = tsqr_w_groups(m, t);
+    const int64_t g = tsqr_w_groups(m, t, sizeof(T) == 16);
     if (t <= 4) tsqr_w_go<T, 4>(st, P0, b0, P1, b1, P2, b2, m, g, bufA, bufB, ctl, check_done);
     else if (t <= 8) tsqr_w_go<T, 8>(st, P0, b0, P1, b1, P2, b2, m, g, bufA, bufB, ctl, check_done);
     else tsqr_w_go<T, 16>(st, P0, b0, P1, b1, P2, b2, m, g, bufA, bufB, ctl, check_done);
