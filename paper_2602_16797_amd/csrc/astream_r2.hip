@@ -21,10 +21,10 @@ static bool by_b(int B, hipStream_t st, int64_t nb, int64_t rows, const double* 
   return true;
 }
 
-// Workgroups of the r2 pass: at most 1024 (four per compute unit, one round at
-// full occupancy), at least 64 rows each.
+// Workgroups of the r2 pass: about 2048 (two rounds of four per compute unit,
+// which balances better than one), at least 64 rows each.
 int64_t astream_r2_blocks(int64_t m) {
-  int64_t rows = (m + 1023) / 1024;
+  int64_t rows = (m + 2047) / 2048;
   if (rows < 64) rows = 64;
   return (m + rows - 1) / rows;
 }

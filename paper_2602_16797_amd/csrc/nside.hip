@@ -487,24 +487,35 @@ __device__ inline void lz_reorth(int n, int cnt, const T* __restrict__ Basis, T&
     __syncthreads();
     for (int q = wid; q < cnt; q += LZ_WAVES) {
       T acc = zero<T>();
+#pragma unroll 4
       for (int l = lane; l < n; l += 64) acc = cfmac(Basis[(int64_t)q * n + l], xs[l], acc);
       acc = wave_sum(acc);
       if (lane == 0) hq[q] = acc;
     }
     __syncthreads();
     if (own) {
-      T a0 = zero<T>(), a1 = zero<T>();
+      // eight independent loads in flight per step of the loop
+      T acc[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = zero<T>();
       int q = 0;
-      for (; q + 1 < cnt; q += 2) {
-        a0 = fmac(Basis[(int64_t)q * n + threadIdx.x], hq[q], a0);
-        a1 = fmac(Basis[(int64_t)(q + 1) * n + threadIdx.x], hq[q + 1], a1);
+      for (; q + 8 <= cnt; q += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] = fmac(Basis[(int64_t)(q + u) * n + threadIdx.x], hq[q + u], acc[u]);
       }
-      if (q < cnt) a0 = fmac(Basis[(int64_t)q * n + threadIdx.x], hq[q], a0);
-      x = sub(x, add(a0, a1));
+      for (; q < cnt; ++q) acc[0] = fmac(Basis[(int64_t)q * n + threadIdx.x], hq[q], acc[0]);
+      T tot = zero<T>();
+#pragma unroll
+      for (int u = 0; u < 8; ++u) tot = add(tot, acc[u]);
+      x = sub(x, tot);
     }
     __syncthreads();
   }
 }
+
+// Largest eigenvalue of the k x k symmetric tridiagonal (dg, of) by
+// multisection of its Sturm count over the 64 lanes of the calling wave.
+__device__ double tridiag_top(const double* dg, const double* of, int k);
 
 // number of eigenvalues of the symmetric tridiagonal (dg, of) below x
 __device__ inline int sturm_count(const double* dg, const double* of, int k, double x) {
@@ -519,6 +530,39 @@ __device__ inline int sturm_count(const double* dg, const double* of, int k, dou
   return cnt;
 }
 
+__device__ double tridiag_top(const double* dg, const double* of, int k) {
+  const int lane = threadIdx.x & 63;
+  double hi = 0.0;
+  for (int q = 0; q < k; ++q) {
+    const double rad = fabs(of[q]) + (q > 0 ? fabs(of[q - 1]) : 0.0);
+    hi = fmax(hi, dg[q] + rad);
+  }
+  double lo = 0.0;
+  // lane l tests lo + (l+1) (hi-lo)/65; keep the sub-interval where the count
+  // of eigenvalues below reaches k
+  for (int it = 0; it < 12 && hi - lo > 1e-17 * hi; ++it) {
+    const double w = (hi - lo) / 65.0;
+    const double x = lo + (lane + 1) * w;
+    const int below = sturm_count(dg, of, k, x);
+    const uint64_t full = __ballot(below == k);
+    const int first = full ? __builtin_ctzll(full) : 64;
+    const double nlo = lo + first * w;
+    const double nhi = (first < 64) ? lo + (first + 1) * w : hi;
+    lo = nlo;
+    hi = nhi;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// B^T B of the first k Lanczos steps: diagonal alpha_q^2 + beta_{q-1}^2,
+// off-diagonal alpha_q beta_q.
+__device__ inline void lz_tridiag(const double* alpha, const double* beta, int k, double* dg, double* of) {
+  for (int q = threadIdx.x; q < k; q += blockDim.x) {
+    dg[q] = alpha[q] * alpha[q] + (q > 0 ? beta[q - 1] * beta[q - 1] : 0.0);
+    of[q] = (q + 1 < k) ? alpha[q] * beta[q] : 0.0;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(LZ_THREADS) void k_lanczos(int n, const T* __restrict__ Ycol, int ld,
                                                         const T* __restrict__ Rrow, T* __restrict__ Ub,
@@ -530,8 +574,13 @@ __global__ __launch_bounds__(LZ_THREADS) void k_lanczos(int n, const T* __restri
   __shared__ double alpha[LZ_MAXK + 1], beta[LZ_MAXK + 1];
   __shared__ double dg[LZ_MAXK + 1], of[LZ_MAXK + 1];
   __shared__ double red[LZ_WAVES];
+  __shared__ double est[2];  // previous top Ritz value, converged flag
   const int tid = threadIdx.x;
   const int own = tid < n;
+  if (tid == 0) {
+    est[0] = -1.0;
+    est[1] = 0.0;
+  }
   // v_0: deterministic random unit vector
   T v = zero<T>();
   double s = 0.0;
@@ -578,35 +627,28 @@ __global__ __launch_bounds__(LZ_THREADS) void k_lanczos(int n, const T* __restri
     v = scal(v, 1.0 / bta);
     if (own) Vb[(int64_t)(j + 1) * n + tid] = v;
     uprev = u;
+    // every 8 steps from step 16: stop once the top Ritz value of B^T B has
+    // settled to 1e-15 relative (k = j + 1 steps so far)
+    if (j + 1 >= 16 && (j + 1) % 8 == 0 && j + 1 < KL) {
+      lz_tridiag(alpha, beta, j + 1, dg, of);
+      __syncthreads();
+      if (tid < 64) {
+        const double top = tridiag_top(dg, of, j + 1);
+        if (tid == 0) {
+          est[1] = (fabs(top - est[0]) <= 1e-15 * top) ? 1.0 : 0.0;
+          est[0] = top;
+        }
+      }
+      __syncthreads();
+      if (est[1] != 0.0) break;
+    }
   }
   __syncthreads();
-  // B^T B: diagonal alpha_q^2 + beta_{q-1}^2, off-diagonal alpha_q beta_q
-  if (tid < k) {
-    dg[tid] = alpha[tid] * alpha[tid] + (tid > 0 ? beta[tid - 1] * beta[tid - 1] : 0.0);
-    of[tid] = (tid + 1 < k) ? alpha[tid] * beta[tid] : 0.0;
-  }
+  lz_tridiag(alpha, beta, k, dg, of);
   __syncthreads();
   if (tid < 64) {
-    double hi = 0.0;
-    for (int q = 0; q < k; ++q) {
-      const double rad = fabs(of[q]) + (q > 0 ? fabs(of[q - 1]) : 0.0);
-      hi = fmax(hi, dg[q] + rad);
-    }
-    double lo = 0.0;
-    // multisection: lane l tests lo + (l+1) (hi-lo)/65; keep the sub-interval
-    // where the count of eigenvalues below reaches k
-    for (int it = 0; it < 12 && hi - lo > 1e-17 * hi; ++it) {
-      const double w = (hi - lo) / 65.0;
-      const double x = lo + (tid + 1) * w;
-      const int below = sturm_count(dg, of, k, x);
-      const uint64_t full = __ballot(below == k);
-      const int first = full ? __builtin_ctzll(full) : 64;  // first point above the top eigenvalue
-      const double nlo = lo + first * w;
-      const double nhi = (first < 64) ? lo + (first + 1) * w : hi;
-      lo = nlo;
-      hi = nhi;
-    }
-    if (tid == 0) ctl->sigma1 = sqrt(0.5 * (lo + hi));
+    const double top = tridiag_top(dg, of, k);
+    if (tid == 0) ctl->sigma1 = sqrt(top);
   }
 }
 

@@ -122,12 +122,16 @@ constexpr int QRP_THREADS = 1024;
 
 template <typename T, int RPT, int NBT>
 __global__ __launch_bounds__(QRP_THREADS) void k_qr_panel_reg(T* Y, int ld, int d, int p, int nb, T* Tm) {
-  __shared__ T scratch[(QRP_THREADS / 16) * NBT];
+  constexpr int NROW = QRP_THREADS / 16;  // DPP rows of the workgroup
+  constexpr int NW = QRP_THREADS / 64;
+  __shared__ T scratch[NROW * NBT];
   __shared__ T outs[NBT];
+  __shared__ T Gm[QR_NB * QR_NB];  // Gm[l * QR_NB + jj] = V(:, l)^* v_jj, l < jj
+  __shared__ T taus[QR_NB];
   __shared__ T Tl[QR_NB * QR_NB];  // column-major, leading dimension QR_NB
-  __shared__ double red[QRP_THREADS / 64];
+  __shared__ double red[NW];
   __shared__ T sh_alpha;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   T P[RPT][NBT];
 #pragma unroll
   for (int s = 0; s < RPT; ++s) {
@@ -135,7 +139,6 @@ __global__ __launch_bounds__(QRP_THREADS) void k_qr_panel_reg(T* Y, int ld, int 
 #pragma unroll
     for (int q = 0; q < NBT; ++q) P[s][q] = (row < d && q < nb) ? Y[(int64_t)(p + q) * ld + row] : zero<T>();
   }
-  for (int i = tid; i < QR_NB * QR_NB; i += QRP_THREADS) Tl[i] = zero<T>();
   // The column loop is not unrolled: column jj of the register panel is read
   // and written through selects over the compile-time column index.
   for (int jj = 0; jj < nb; ++jj) {
@@ -183,27 +186,27 @@ __global__ __launch_bounds__(QRP_THREADS) void k_qr_panel_reg(T* Y, int ld, int 
       for (int q = 0; q < NBT; ++q)
         if (q == jj) P[s][q] = pj[s];
     }
-    {
+    // one batched sum: k > jj: v^* Y(:, k);  k < jj: V(:, k)^* v
 #pragma unroll
-      for (int k = 0; k < NBT; ++k) {
-        T val = zero<T>();
+    for (int k = 0; k < NBT; ++k) {
+      T val = zero<T>();
 #pragma unroll
-        for (int s = 0; s < RPT; ++s) {
-          if (k > jj) val = cfmac(v[s], P[s][k], val);
-          else if (k < jj) val = cfmac(P[s][k], v[s], val);
-        }
-        val = row_sum16(val);
-        if ((tid & 15) == 0) scratch[(tid >> 4) * NBT + k] = val;
+      for (int s = 0; s < RPT; ++s) {
+        if (k > jj) val = cfmac(v[s], P[s][k], val);
+        else if (k < jj) val = cfmac(P[s][k], v[s], val);
       }
-      __syncthreads();
-      if (tid < NBT) {
-        T acc = zero<T>();
-#pragma unroll 8
-        for (int r = 0; r < QRP_THREADS / 16; ++r) acc = add(acc, scratch[r * NBT + tid]);
-        outs[tid] = acc;
-      }
-      __syncthreads();
+      val = row_sum16(val);
+      if ((tid & 15) == 0) scratch[(tid >> 4) * NBT + k] = val;
     }
+    __syncthreads();
+    // wave w finishes sums w, w + NW, ... over the NROW row partials
+    for (int k = wid; k < NBT; k += NW) {
+      T acc = zero<T>();
+      for (int r = lane; r < NROW; r += 64) acc = add(acc, scratch[r * NBT + k]);
+      acc = wave_sum(acc);
+      if (lane == 0) outs[k] = acc;
+    }
+    __syncthreads();
     if (!noref) {
       const T ct = conj_(tau);
 #pragma unroll
@@ -215,15 +218,27 @@ __global__ __launch_bounds__(QRP_THREADS) void k_qr_panel_reg(T* Y, int ld, int 
         }
       }
     }
-    // T(0:jj, jj) = -tau T(0:jj, 0:jj) g, g = V(:, 0:jj)^* v;  T(jj, jj) = tau
-    if (tid < jj) {
-      T acc = zero<T>();
-      for (int l = tid; l < jj; ++l) acc = fmac(Tl[tid + l * QR_NB], outs[l], acc);
-      Tl[tid + jj * QR_NB] = neg(mul(tau, acc));
-    } else if (tid == jj) {
-      Tl[jj + jj * QR_NB] = tau;
+    if (tid < jj) Gm[tid * QR_NB + jj] = outs[tid];
+    if (tid == jj) taus[jj] = tau;
+  }
+  __syncthreads();
+  // T factor, row q by thread q: T(q, q) = tau_q,
+  // T(q, jj) = -tau_jj sum_{l = q}^{jj-1} T(q, l) (V(:, l)^* v_jj)
+  if (tid < QR_NB) {
+    const int q = tid;
+    for (int jj = 0; jj < QR_NB; ++jj) {
+      T val = zero<T>();
+      if (jj < nb) {
+        if (jj == q) {
+          val = taus[q];
+        } else if (jj > q) {
+          T acc = zero<T>();
+          for (int l = q; l < jj; ++l) acc = fmac(Tl[q + l * QR_NB], Gm[l * QR_NB + jj], acc);
+          val = neg(mul(taus[jj], acc));
+        }
+      }
+      Tl[q + jj * QR_NB] = val;
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int s = 0; s < RPT; ++s) {
@@ -232,6 +247,7 @@ __global__ __launch_bounds__(QRP_THREADS) void k_qr_panel_reg(T* Y, int ld, int 
     for (int q = 0; q < NBT; ++q)
       if (row < d && q < nb) Y[(int64_t)(p + q) * ld + row] = P[s][q];
   }
+  __syncthreads();
   for (int i = tid; i < QR_NB * QR_NB; i += QRP_THREADS) Tm[i] = Tl[i];
 }
 
