@@ -44,6 +44,15 @@ extern "C" {
 #define RL_STOP_TOL 1   /* the tolerance alone, every iteration (Alg. rlobpcg as typeset) */
 #define RL_STOP_NONE 2  /* run max_iter iterations */
 
+/* Precision of the sketch and of its QR factorization.  Everything after
+ * them (R^{-1}, the A products, residuals, Rayleigh-Ritz, orthonormalisation)
+ * is FP64; the preconditioner only needs to be approximate (Sec. 2.2), but a
+ * reduced-precision R loses the directions of A below about u_low ||A||, so
+ * the number of iterations can grow when cond(A) u_low is not small. */
+#define RL_SKETCH_F64 0  /* FP64 sketch and Householder QR */
+#define RL_SKETCH_F32 1  /* FP32 sketch (A rounded once per entry) and FP32 QR; R promoted to FP64 */
+#define RL_SKETCH_BF16 2 /* FP32 sketch; QR trailing updates with bfloat16 inputs and FP32 accumulation */
+
 typedef struct rl_ctx* rl_handle;
 
 /* Options.  rl_default_opts fills the paper's defaults. */
@@ -60,7 +69,8 @@ typedef struct {
   int32_t init_iters; /* inverse-subspace-iteration steps for the start block; default 10 */
   int32_t lanczos_steps; /* Golub-Kahan steps for Sigma~(1,1); default min(n, 64) */
   int32_t profile;    /* 1: time every A-stream launch with HIP events (rl_info.t_astream_us) */
-  int32_t reserved[5];
+  int32_t sketch_prec; /* RL_SKETCH_*: precision of the sketch S*A and its QR (real A only); default FP64 */
+  int32_t reserved[4];
 } rl_opts;
 
 /* Per-solve report (host).  theta_hist / rnorm_hist are optional host arrays
@@ -123,6 +133,21 @@ int rl_step_sketch(rl_handle h, int is_complex, int64_t m, int64_t n, const doub
  * (upper triangular; R has a real diagonal). */
 int rl_step_qr(rl_handle h, int is_complex, int64_t d, int64_t n, const double* Y, int64_t ldy, double* R,
                double* Rinv);
+
+/* The reduced-precision sketch (RL_SKETCH_F32 and RL_SKETCH_BF16 use it):
+ * Y = S*A accumulated in FP32, each entry of A rounded to FP32 once (Sec. 2.2
+ * embedding, real A).  A device m x n FP64 (lda); Y device d x n FP32
+ * row-major (ldy >= n). */
+int rl_step_sketch_f32(rl_handle h, int64_t m, int64_t n, const double* A, int64_t lda, int64_t d, int32_t zeta,
+                       uint64_t seed, float* Y, int64_t ldy);
+
+/* R from the reduced-precision QR of the FP32 sketch Y (d x n row-major,
+ * ldy): sketch_prec RL_SKETCH_F32 (FP32 Householder QR) or RL_SKETCH_BF16
+ * (trailing updates with bfloat16 inputs, FP32 accumulation).  R is promoted
+ * to FP64; R and R^{-1} (computed in FP64 from the promoted R) are device
+ * n x n FP64 row-major.  RL_ERR_ARG for another sketch_prec. */
+int rl_step_qr_lowp(rl_handle h, int64_t d, int64_t n, const float* Y, int64_t ldy, int32_t sketch_prec, double* R,
+                    double* Rinv);
 
 /* One pass over A (Alg. rlopcg, the product with the trial space, and the
  * residual's A^*): AW = A W and G = A^* AW.  W device n x b, AW device m x b,

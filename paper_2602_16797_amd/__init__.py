@@ -25,13 +25,18 @@ RL_ERR_DEVICE = -2
 RL_ERR_NOMEM = -3
 RL_ERR_NONFINITE = -4
 RL_ERR_UNSUPPORTED = -7
+
+RL_SKETCH_F64 = 0
+RL_SKETCH_F32 = 1
+RL_SKETCH_BF16 = 2
+SKETCH_PRECS = {"f64": RL_SKETCH_F64, "f32": RL_SKETCH_F32, "bf16": RL_SKETCH_BF16}
 STOP_RULES = {"paper": 0, "tol": 1, "none": 2}
 
 EXPORTED = (
     "rl_create", "rl_destroy", "rl_set_stream", "rl_default_opts",
     "rl_svds_smallest_d", "rl_svds_smallest_z",
     "rl_step_sketch", "rl_step_qr", "rl_step_astream", "rl_step_tall_svd",
-    "rl_status_string",
+    "rl_step_sketch_f32", "rl_step_qr_lowp", "rl_status_string",
 )
 
 
@@ -49,7 +54,8 @@ class RlOpts(ctypes.Structure):
         ("init_iters", ctypes.c_int32),
         ("lanczos_steps", ctypes.c_int32),
         ("profile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("sketch_prec", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -102,6 +108,8 @@ def load_library() -> ctypes.CDLL:
                                        ctypes.POINTER(RlInfo)]
     lib.rl_step_sketch.argtypes = [P, ctypes.c_int, I64, I64, P, I64, I64, I32, U64, P, I64]
     lib.rl_step_qr.argtypes = [P, ctypes.c_int, I64, I64, P, I64, P, P]
+    lib.rl_step_sketch_f32.argtypes = [P, I64, I64, P, I64, I64, I32, U64, P, I64]
+    lib.rl_step_qr_lowp.argtypes = [P, I64, I64, P, I64, I32, P, P]
     lib.rl_step_astream.argtypes = [P, ctypes.c_int, I64, I64, P, I64, I32, P, P, P, I32]
     lib.rl_step_tall_svd.argtypes = [P, ctypes.c_int, I64, I32, P, P, P]
     lib.rl_status_string.argtypes = [ctypes.c_int]
@@ -215,7 +223,7 @@ class SolveResult:
 
 def make_opts(m: int, n: int, k: int, *, block=None, d=None, zeta=None, seed=0, tau=None, max_iter=None,
               check_every=None, rule="paper", dot2=None, init_iters=None, lanczos_steps=None,
-              profile=False) -> RlOpts:
+              profile=False, sketch_prec="f64") -> RlOpts:
     o = default_opts(m, n, k if block is None else block)
     o.block = k if block is None else block
     if block is not None:
@@ -239,6 +247,7 @@ def make_opts(m: int, n: int, k: int, *, block=None, d=None, zeta=None, seed=0, 
     if lanczos_steps is not None:
         o.lanczos_steps = lanczos_steps
     o.profile = int(bool(profile))
+    o.sketch_prec = SKETCH_PRECS[sketch_prec]
     return o
 
 
@@ -299,6 +308,37 @@ def rl_step_qr(Y):
     rc = h.lib.rl_step_qr(h.h, int(Y.is_complex()), d, n, _ptr(Y), Y.stride(0), _ptr(R), _ptr(Rinv))
     if rc != RL_OK:
         raise RlError(rc, "rl_step_qr")
+    return R, Rinv
+
+
+def rl_step_sketch_f32(A, d: int, zeta: int, seed: int):
+    """FP32 sketch of the real FP64 device matrix A (C-ABI rl_step_sketch_f32)."""
+    torch = _torch()
+    _check_matrix(A, torch)
+    if A.is_complex():
+        raise ValueError("the reduced-precision sketch takes real A")
+    m, n = A.shape
+    h = handle(A.device.index or 0)
+    Y = torch.empty((d, n), dtype=torch.float32, device=A.device)
+    rc = h.lib.rl_step_sketch_f32(h.h, m, n, _ptr(A), A.stride(0), d, zeta, ctypes.c_uint64(seed), _ptr(Y), n)
+    if rc != RL_OK:
+        raise RlError(rc, "rl_step_sketch_f32")
+    return Y
+
+
+def rl_step_qr_lowp(Y, sketch_prec: str = "f32"):
+    """R (FP64, promoted) and R^{-1} of the FP32 sketch Y (C-ABI rl_step_qr_lowp)."""
+    torch = _torch()
+    if not (isinstance(Y, torch.Tensor) and Y.is_cuda and Y.dtype == torch.float32 and Y.dim() == 2):
+        raise TypeError("Y must be a 2-D float32 tensor on a GPU")
+    Y = Y.contiguous()
+    d, n = Y.shape
+    h = handle(Y.device.index or 0)
+    R = torch.empty((n, n), dtype=torch.float64, device=Y.device)
+    Rinv = torch.empty((n, n), dtype=torch.float64, device=Y.device)
+    rc = h.lib.rl_step_qr_lowp(h.h, d, n, _ptr(Y), n, SKETCH_PRECS[sketch_prec], _ptr(R), _ptr(Rinv))
+    if rc != RL_OK:
+        raise RlError(rc, "rl_step_qr_lowp")
     return R, Rinv
 
 

@@ -59,6 +59,23 @@ __device__ inline double fnmac(double a, double b, double c) { return fma(-a, b,
 __device__ inline cd fnmac(cd a, cd b, cd c) {
   return cd{fma(-a.x, b.x, fma(a.y, b.y, c.x)), fma(-a.x, b.y, fma(-a.y, b.x, c.y))};
 }
+// float (the reduced-precision sketch and QR): the same operations in FP32;
+// abs2 widens to double so norms are accumulated in FP64.
+template <> __device__ __host__ inline float zero<float>() { return 0.0f; }
+template <> __device__ __host__ inline float from_real<float>(double a) { return (float)a; }
+__device__ __host__ inline float conj_(float a) { return a; }
+__device__ __host__ inline double re_(float a) { return a; }
+__device__ __host__ inline double abs2(float a) { return (double)a * (double)a; }
+__device__ __host__ inline float add(float a, float b) { return a + b; }
+__device__ __host__ inline float sub(float a, float b) { return a - b; }
+__device__ __host__ inline float neg(float a) { return -a; }
+__device__ __host__ inline float mul(float a, float b) { return a * b; }
+__device__ __host__ inline float scal(float a, double s) { return a * (float)s; }
+__device__ inline float fmac(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ inline float cfmac(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ inline float fnmac(float a, float b, float c) { return fmaf(-a, b, c); }
+__device__ inline float divs(float a, float b) { return a / b; }
+
 // a / b for cd via Smith's algorithm
 __device__ inline double divs(double a, double b) { return a / b; }
 __device__ inline cd divs(cd a, cd b) {
@@ -101,12 +118,28 @@ __device__ inline double row_sum16(double v) {
   return v;
 }
 __device__ inline cd row_sum16(cd v) { return cd{row_sum16(v.x), row_sum16(v.y)}; }
+template <int CTRL>
+__device__ inline float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ inline float row_sum16(float v) {
+  v += dpp_f<DPP_QUAD_1032>(v);
+  v += dpp_f<DPP_QUAD_2301>(v);
+  v += dpp_f<DPP_ROW_HALF_MIRROR>(v);
+  v += dpp_f<DPP_ROW_MIRROR>(v);
+  return v;
+}
+__device__ inline float readlane_f(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
 
 __device__ inline double wave_sum(double v) {
   v = row_sum16(v);
   return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 __device__ inline cd wave_sum(cd v) { return cd{wave_sum(v.x), wave_sum(v.y)}; }
+__device__ inline float wave_sum(float v) {
+  v = row_sum16(v);
+  return (readlane_f(v, 0) + readlane_f(v, 16)) + (readlane_f(v, 32) + readlane_f(v, 48));
+}
 __device__ inline cd readlane_d(cd v, int l) { return cd{readlane_d(v.x, l), readlane_d(v.y, l)}; }
 __device__ inline double wave_max(double v) {
   v = fmax(v, dpp_d<DPP_QUAD_1032>(v));

@@ -9,14 +9,16 @@
 namespace rl {
 
 // sketch.hip
-int sketch_plan_ct(int d, int64_t lds_budget);
+int sketch_plan_ct(int d, int64_t lds_budget, int acc_bytes);
 int64_t sketch_partial_doubles(int64_t m, int64_t ncols_d, int d, int64_t lds_budget, int* nchunk_out,
-                               int64_t* rows_out);
+                               int64_t* rows_out, int acc_bytes);
 hipError_t launch_sketch(hipStream_t st, const double* A, int64_t lda_d, int64_t m, int64_t ncols_d, int es, int d,
-                         int zeta, uint64_t seed, double scale, double* part, double* Ycol, Ctl* ctl,
-                         int64_t lds_budget);
+                         int zeta, uint64_t seed, double scale, void* part, void* Ycol, Ctl* ctl,
+                         int64_t lds_budget, bool fp32);
 
 // qr.hip
+hipError_t launch_qr_lowp(hipStream_t st, float* Yf, int d, int n, float* Tmf, double* Y, double* Rrow, double* RH,
+                          double* Rinv, double* RinvH, bool bf16);
 hipError_t launch_qr(hipStream_t st, bool cplx, void* Y, int d, int n, void* Tm, void* Rrow, void* RH, void* Rinv,
                      void* RinvH);
 

@@ -27,6 +27,16 @@ constexpr int QR_CB = 8;
 
 __device__ inline double im_(double) { return 0.0; }
 __device__ inline double im_(cd a) { return a.y; }
+__device__ inline double im_(float) { return 0.0; }
+
+// Round a float to the nearest bfloat16 (ties to even), kept in a float: the
+// inputs of the BF16 trailing update.
+__device__ inline float bf16_round(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7F800000u) == 0x7F800000u) return x;  // Inf / NaN unchanged
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xFFFF0000u);
+}
 
 // V(r, q) of the current panel: unit lower trapezoidal, stored below the diagonal.
 template <typename T>
@@ -257,7 +267,7 @@ template <typename T>
 static int qr_pick_panel(int rows, int* rpt) {
   const int r = (rows + QRP_THREADS - 1) / QRP_THREADS;
   *rpt = r;
-  const int cw = (sizeof(T) == 16) ? 2 : 1;
+  const int cw = (sizeof(T) == 16) ? 2 : 1;  // FP32 panels use the FP64 shapes
   if (r <= 1) return 32 / cw;
   if (r <= 2) return 16 / cw;
   if (r <= 4) return 8 / cw;
@@ -267,7 +277,7 @@ static int qr_pick_panel(int rows, int* rpt) {
 template <typename T>
 static void qr_panel_launch(hipStream_t st, T* Y, int d, int p, int nb, int rpt, T* Tm) {
   const dim3 g(1), b(QRP_THREADS);
-  if constexpr (sizeof(T) == 8) {
+  if constexpr (sizeof(T) <= 8) {
     if (rpt <= 1) hipLaunchKernelGGL((k_qr_panel_reg<T, 1, 32>), g, b, 0, st, Y, d, d, p, nb, Tm);
     else if (rpt <= 2) hipLaunchKernelGGL((k_qr_panel_reg<T, 2, 16>), g, b, 0, st, Y, d, d, p, nb, Tm);
     else hipLaunchKernelGGL((k_qr_panel_reg<T, 4, 8>), g, b, 0, st, Y, d, d, p, nb, Tm);
@@ -279,7 +289,9 @@ static void qr_panel_launch(hipStream_t st, T* Y, int d, int p, int nb, int rpt,
 }
 
 // C <- (I - V T V^*)^* C = C - V T^* (V^* C) on columns [p+nb, n)
-template <typename T>
+// BF16IN (float only): the panel V and the trailing columns enter both
+// products rounded to bfloat16; products and sums stay in FP32.
+template <typename T, bool BF16IN = false>
 __global__ __launch_bounds__(QR_THREADS) void k_qr_update(T* Y, int ld, int d, int n, int p, int nb,
                                                           const T* __restrict__ Tm) {
   constexpr int RCH = 32;
@@ -297,11 +309,13 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr_update(T* Y, int ld, int d, i
       const int rr = i % RCH, qq = i / RCH;
       const int r = r0 + rr;
       Vs[rr][qq] = (qq < nb && r < d) ? vpanel(Y, ld, p, qq, r) : zero<T>();
+      if constexpr (BF16IN) Vs[rr][qq] = bf16_round(Vs[rr][qq]);
     }
     for (int i = tid; i < RCH * QR_CB; i += blockDim.x) {
       const int rr = i % RCH, cc = i / RCH;
       const int r = r0 + rr;
       Cs[rr][cc] = (cc < ncb && r < d) ? Y[(int64_t)(c0 + cc) * ld + r] : zero<T>();
+      if constexpr (BF16IN) Cs[rr][cc] = bf16_round(Cs[rr][cc]);
     }
     __syncthreads();
 #pragma unroll 8
@@ -319,14 +333,20 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr_update(T* Y, int ld, int d, i
   for (int r = p + tid; r < d; r += blockDim.x) {
     T vr[QR_NB];
 #pragma unroll
-    for (int qq = 0; qq < QR_NB; ++qq) vr[qq] = (qq < nb) ? vpanel(Y, ld, p, qq, r) : zero<T>();
+    for (int qq = 0; qq < QR_NB; ++qq) {
+      vr[qq] = (qq < nb) ? vpanel(Y, ld, p, qq, r) : zero<T>();
+      if constexpr (BF16IN) vr[qq] = bf16_round(vr[qq]);
+    }
 #pragma unroll 1
     for (int c = 0; c < QR_CB; ++c) {
       if (c < ncb) {
         T* y = Y + (int64_t)(c0 + c) * ld + r;
         T v = *y;
 #pragma unroll
-        for (int qq = 0; qq < QR_NB; ++qq) v = fnmac(vr[qq], Wt2[qq][c], v);
+        for (int qq = 0; qq < QR_NB; ++qq) {
+          if constexpr (BF16IN) v = fnmac(vr[qq], bf16_round(Wt2[qq][c]), v);
+          else v = fnmac(vr[qq], Wt2[qq][c], v);
+        }
         *y = v;
       }
     }
@@ -367,8 +387,9 @@ __global__ __launch_bounds__(256) void k_trinv(const T* __restrict__ Y, int ld, 
   }
 }
 
-template <typename T>
-static hipError_t qr_impl(hipStream_t st, T* Y, int d, int n, T* Tm, T* Rrow, T* RH, T* Rinv, T* RinvH) {
+// Blocked Householder factorization of the d x n column-major Y in place.
+template <typename T, bool BF16IN = false>
+static void qr_factor(hipStream_t st, T* Y, int d, int n, T* Tm) {
   for (int p = 0; p < n;) {
     int rpt = 0;
     const int nbr = qr_pick_panel<T>(d - p, &rpt);
@@ -379,20 +400,38 @@ static hipError_t qr_impl(hipStream_t st, T* Y, int d, int n, T* Tm, T* Rrow, T*
       hipLaunchKernelGGL(k_qr_panel<T>, dim3(1), dim3(QR_THREADS), 0, st, Y, d, d, n, p, nb, Tm);
     const int rest = n - p - nb;
     if (rest > 0)
-      hipLaunchKernelGGL(k_qr_update<T>, dim3((rest + QR_CB - 1) / QR_CB), dim3(QR_THREADS), 0, st, Y, d, d, n,
-                         p, nb, (const T*)Tm);
+      hipLaunchKernelGGL((k_qr_update<T, BF16IN>), dim3((rest + QR_CB - 1) / QR_CB), dim3(QR_THREADS), 0, st, Y, d,
+                         d, n, p, nb, (const T*)Tm);
     p += nb;
   }
+}
+
+// R (upper triangle of Y) in row-major form and R^{-1}, R^{-*}.
+template <typename T>
+static hipError_t qr_finish(hipStream_t st, const T* Y, int d, int n, T* Rrow, T* RH, T* Rinv, T* RinvH) {
   const int64_t nn = (int64_t)n * n;
-  hipLaunchKernelGGL(k_qr_extract<T>, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, (const T*)Y, d, n,
-                     Rrow, RH);
+  hipLaunchKernelGGL(k_qr_extract<T>, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, Y, d, n, Rrow, RH);
   const size_t lds = (size_t)4 * n * sizeof(T);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_trinv<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_trinv<T>, dim3((n + 3) / 4), dim3(256), lds, st, (const T*)Y, d, n, Rinv, RinvH);
+  hipLaunchKernelGGL(k_trinv<T>, dim3((n + 3) / 4), dim3(256), lds, st, Y, d, n, Rinv, RinvH);
   return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t qr_impl(hipStream_t st, T* Y, int d, int n, T* Tm, T* Rrow, T* RH, T* Rinv, T* RinvH) {
+  qr_factor<T>(st, Y, d, n, Tm);
+  return qr_finish<T>(st, Y, d, n, Rrow, RH, Rinv, RinvH);
+}
+
+// Upper triangle (rows 0..n-1) of the FP32 factor into the FP64 Y (ld d).
+__global__ void k_promote_upper(const float* __restrict__ Yf, int d, int n, double* __restrict__ Y) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int j = (int)(idx / n), i = (int)(idx % n);  // column j, row i
+  Y[(int64_t)j * d + i] = (i <= j) ? (double)Yf[(int64_t)j * d + i] : 0.0;
 }
 
 hipError_t launch_qr(hipStream_t st, bool cplx, void* Y, int d, int n, void* Tm, void* Rrow, void* RH, void* Rinv,
@@ -401,6 +440,21 @@ hipError_t launch_qr(hipStream_t st, bool cplx, void* Y, int d, int n, void* Tm,
     return qr_impl<cd>(st, (cd*)Y, d, n, (cd*)Tm, (cd*)Rrow, (cd*)RH, (cd*)Rinv, (cd*)RinvH);
   return qr_impl<double>(st, (double*)Y, d, n, (double*)Tm, (double*)Rrow, (double*)RH, (double*)Rinv,
                          (double*)RinvH);
+}
+
+// Reduced-precision QR of a real sketch: factor the FP32 Yf (trailing updates
+// in FP32, or with bfloat16 inputs and FP32 accumulation), promote R to FP64
+// into Y, then R^{-1} and the row-major copies in FP64.
+hipError_t launch_qr_lowp(hipStream_t st, float* Yf, int d, int n, float* Tmf, double* Y, double* Rrow, double* RH,
+                          double* Rinv, double* RinvH, bool bf16) {
+  if (bf16) qr_factor<float, true>(st, Yf, d, n, Tmf);
+  else qr_factor<float, false>(st, Yf, d, n, Tmf);
+  const int64_t nn = (int64_t)n * n;
+  hipLaunchKernelGGL(k_promote_upper, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, (const float*)Yf, d, n,
+                     Y);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return qr_finish<double>(st, Y, d, n, Rrow, RH, Rinv, RinvH);
 }
 
 }  // namespace rl

@@ -20,6 +20,8 @@
 // cross-lane shuffle, so every (row, piece) pair is hashed once per tile.
 // Kernel 2 (reduce): sums the chunk partials in chunk order and writes Y
 // column-major (the layout of the QR that follows), flagging NaN/Inf.
+// Both kernels take the accumulator type: FP64, or FP32 for the
+// reduced-precision sketch (A is read in FP64 and rounded once per entry).
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -32,17 +34,18 @@ __device__ inline uint64_t splitmix64(uint64_t x) {
   return z ^ (z >> 31);
 }
 
-template <int CT>
+template <int CT, typename Acc>
 __global__ __launch_bounds__(512) void k_sketch_partial(
     const double* __restrict__ A, int64_t lda_d, int64_t m, int64_t ncols_d, int d, int zeta,
-    uint64_t seed, int64_t rows_per_chunk, double* __restrict__ part) {
-  extern __shared__ double acc[];  // d * CT
+    uint64_t seed, int64_t rows_per_chunk, Acc* __restrict__ part) {
+  extern __shared__ double acc_raw[];
+  Acc* acc = reinterpret_cast<Acc*>(acc_raw);  // d * CT
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
   const int64_t c0 = (int64_t)blockIdx.x * CT;
   const int64_t r0 = (int64_t)blockIdx.y * rows_per_chunk;
   const int64_t r1 = (r0 + rows_per_chunk < m) ? r0 + rows_per_chunk : m;
-  for (int i = tid; i < d * CT; i += blockDim.x) acc[i] = 0.0;
+  for (int i = tid; i < d * CT; i += blockDim.x) acc[i] = (Acc)0;
   __syncthreads();
   constexpr int RS = 64 / CT;   // rows per instruction
   constexpr int NQ = 64 / RS;   // instructions per 64 rows
@@ -57,11 +60,11 @@ __global__ __launch_bounds__(512) void k_sketch_partial(
       const uint64_t h = splitmix64(seed ^ splitmix64(i * (uint64_t)zeta + (uint64_t)p));
       const int tgt = start + (int)(((h & 0xFFFFFFFFull) * (uint64_t)len) >> 32);
       const double sg = (h >> 63) ? -1.0 : 1.0;
-      double a[NQ];
+      Acc a[NQ];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int64_t row = g0 + q * RS + slot;
-        a[q] = (row < r1 && colok) ? A[row * lda_d + c0 + col] : 0.0;
+        a[q] = (Acc)((row < r1 && colok) ? A[row * lda_d + c0 + col] : 0.0);
       }
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
@@ -69,44 +72,48 @@ __global__ __launch_bounds__(512) void k_sketch_partial(
         const int t = __shfl(tgt, src, WAVE);
         const double s = __shfl(sg, src, WAVE);
         const int64_t row = g0 + src;
-        if (row < r1 && colok) atomicAdd(&acc[t * CT + col], s * a[q]);
+        if (row < r1 && colok) atomicAdd(&acc[t * CT + col], (Acc)s * a[q]);
       }
     }
   }
   __syncthreads();
-  double* out = part + (int64_t)blockIdx.y * d * ncols_d;
+  Acc* out = part + (int64_t)blockIdx.y * d * ncols_d;
   for (int i = tid; i < d * CT; i += blockDim.x) {
     const int r = i / CT, c = i % CT;
     if (c0 + c < ncols_d) out[(int64_t)r * ncols_d + c0 + c] = acc[i];
   }
 }
 
-// Y (column-major, ld = d, element size es doubles) = scale * sum over chunks.
-__global__ void k_sketch_reduce(const double* __restrict__ part, int nchunk, int d, int64_t ncols_d,
-                                int es, double scale, double* __restrict__ Ycol, Ctl* ctl) {
+// Y (column-major, ld = d, element size es scalars) = scale * sum over chunks.
+template <typename Acc>
+__global__ void k_sketch_reduce(const Acc* __restrict__ part, int nchunk, int d, int64_t ncols_d, int es,
+                                double scale, Acc* __restrict__ Ycol, Ctl* ctl) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = (int64_t)d * ncols_d;
   if (idx >= total) return;
   const int64_t r = idx / ncols_d, cdb = idx % ncols_d;
-  double s = 0.0;
+  Acc s = (Acc)0;
   for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * total + idx];
-  s *= scale;
-  if (!isfinite(s) && ctl) atomicOr(&ctl->nonfinite, 1);
+  s *= (Acc)scale;
+  if (!isfinite((double)s) && ctl) atomicOr(&ctl->nonfinite, 1);
   const int64_t elem = cdb / es, comp = cdb % es;
   Ycol[(elem * d + r) * es + comp] = s;
 }
 
-int sketch_plan_ct(int d, int64_t lds_budget) {
-  // widest column tile (in doubles) whose d x CT slice fits the LDS budget
+// widest column tile (in scalars) whose d x CT slice of accumulators fits the
+// LDS budget
+int sketch_plan_ct(int d, int64_t lds_budget, int acc_bytes) {
   const int cts[6] = {32, 16, 8, 4, 2, 1};
   for (int c : cts)
-    if ((int64_t)d * c * 8 <= lds_budget) return c;
+    if ((int64_t)d * c * acc_bytes <= lds_budget) return c;
   return 0;
 }
 
+// Accumulator elements of the chunk partials (the buffer holds doubles; FP32
+// accumulators use the first half).
 int64_t sketch_partial_doubles(int64_t m, int64_t ncols_d, int d, int64_t lds_budget, int* nchunk_out,
-                               int64_t* rows_out) {
-  const int ct = sketch_plan_ct(d, lds_budget);
+                               int64_t* rows_out, int acc_bytes) {
+  const int ct = sketch_plan_ct(d, lds_budget, acc_bytes);
   if (ct == 0) return -1;
   const int64_t ntiles = (ncols_d + ct - 1) / ct;
   int64_t nchunk = (1024 + ntiles - 1) / ntiles;
@@ -121,44 +128,56 @@ int64_t sketch_partial_doubles(int64_t m, int64_t ncols_d, int d, int64_t lds_bu
   return nchunk * (int64_t)d * ncols_d;
 }
 
-template <int CT>
+template <int CT, typename Acc>
 static hipError_t launch_partial(hipStream_t st, dim3 grid, size_t lds, const double* A, int64_t lda_d,
                                  int64_t m, int64_t ncols_d, int d, int zeta, uint64_t seed, int64_t rows,
-                                 double* part) {
+                                 Acc* part) {
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_sketch_partial<CT>,
+    hipError_t e = hipFuncSetAttribute((const void*)k_sketch_partial<CT, Acc>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_sketch_partial<CT>, grid, dim3(512), lds, st, A, lda_d, m, ncols_d, d, zeta, seed,
+  hipLaunchKernelGGL((k_sketch_partial<CT, Acc>), grid, dim3(512), lds, st, A, lda_d, m, ncols_d, d, zeta, seed,
                      rows, part);
   return hipGetLastError();
 }
 
-hipError_t launch_sketch(hipStream_t st, const double* A, int64_t lda_d, int64_t m, int64_t ncols_d,
-                         int es, int d, int zeta, uint64_t seed, double scale, double* part,
-                         double* Ycol, Ctl* ctl, int64_t lds_budget) {
+template <typename Acc>
+static hipError_t sketch_impl(hipStream_t st, const double* A, int64_t lda_d, int64_t m, int64_t ncols_d, int es,
+                              int d, int zeta, uint64_t seed, double scale, Acc* part, Acc* Ycol, Ctl* ctl,
+                              int64_t lds_budget) {
   int nchunk;
   int64_t rows;
-  if (sketch_partial_doubles(m, ncols_d, d, lds_budget, &nchunk, &rows) < 0) return hipErrorInvalidValue;
-  const int ct = sketch_plan_ct(d, lds_budget);
+  const int ab = (int)sizeof(Acc);
+  if (sketch_partial_doubles(m, ncols_d, d, lds_budget, &nchunk, &rows, ab) < 0) return hipErrorInvalidValue;
+  const int ct = sketch_plan_ct(d, lds_budget, ab);
   const int64_t ntiles = (ncols_d + ct - 1) / ct;
   dim3 grid((unsigned)ntiles, (unsigned)nchunk);
-  const size_t lds = (size_t)d * ct * sizeof(double);
+  const size_t lds = (size_t)d * ct * sizeof(Acc);
   hipError_t e;
   switch (ct) {
-    case 32: e = launch_partial<32>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
-    case 16: e = launch_partial<16>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
-    case 8: e = launch_partial<8>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
-    case 4: e = launch_partial<4>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
-    case 2: e = launch_partial<2>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
-    default: e = launch_partial<1>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
+    case 32: e = launch_partial<32, Acc>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
+    case 16: e = launch_partial<16, Acc>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
+    case 8: e = launch_partial<8, Acc>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
+    case 4: e = launch_partial<4, Acc>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
+    case 2: e = launch_partial<2, Acc>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
+    default: e = launch_partial<1, Acc>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
   }
   if (e != hipSuccess) return e;
   const int64_t total = (int64_t)d * ncols_d;
-  hipLaunchKernelGGL(k_sketch_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, part, nchunk,
+  hipLaunchKernelGGL(k_sketch_reduce<Acc>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, part, nchunk,
                      d, ncols_d, es, scale, Ycol, ctl);
   return hipGetLastError();
+}
+
+hipError_t launch_sketch(hipStream_t st, const double* A, int64_t lda_d, int64_t m, int64_t ncols_d, int es, int d,
+                         int zeta, uint64_t seed, double scale, void* part, void* Ycol, Ctl* ctl,
+                         int64_t lds_budget, bool fp32) {
+  if (fp32)
+    return sketch_impl<float>(st, A, lda_d, m, ncols_d, es, d, zeta, seed, scale, (float*)part, (float*)Ycol, ctl,
+                              lds_budget);
+  return sketch_impl<double>(st, A, lda_d, m, ncols_d, es, d, zeta, seed, scale, (double*)part, (double*)Ycol, ctl,
+                             lds_budget);
 }
 
 }  // namespace rl

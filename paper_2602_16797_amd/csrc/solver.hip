@@ -72,7 +72,7 @@ struct Arena {
 };
 
 struct Layout {
-  size_t ctl, ht, hr, Y, part, Tm, Rrow, RH, Rinv, RinvH;
+  size_t ctl, ht, hr, Y, Yf, Tmf, part, Tm, Rrow, RH, Rinv, RinvH;
   size_t V, X, W, Z, Vn, G3, Rres;
   size_t AV, AX, AW, Gpart, Gtmp, tsA, tsB, CV, CX, thb, Ub, Vb;
   size_t total;
@@ -85,6 +85,7 @@ struct Problem {
   bool cplx;
   size_t es;
   int max_iter;
+  int sketch_prec;
 };
 
 static Layout plan(const Problem& p, int64_t lds_budget) {
@@ -95,11 +96,19 @@ static Layout plan(const Problem& p, int64_t lds_budget) {
   const int64_t ncols_d = n * (int64_t)(es / 8);
   int nchunk;
   int64_t rows;
-  const int64_t partd = sketch_partial_doubles(m, ncols_d, (int)p.d, lds_budget, &nchunk, &rows);
+  int64_t partd = sketch_partial_doubles(m, ncols_d, (int)p.d, lds_budget, &nchunk, &rows, 8);
+  if (p.sketch_prec != RL_SKETCH_F64) {
+    const int64_t pf = sketch_partial_doubles(m, ncols_d, (int)p.d, lds_budget, &nchunk, &rows, 4);
+    partd = std::max<int64_t>(partd, (pf + 1) / 2);
+  }
   L.ctl = a.take(sizeof(Ctl));
   L.ht = a.take(sizeof(double) * (size_t)(p.max_iter + 2) * B);
   L.hr = a.take(sizeof(double) * (size_t)(p.max_iter + 2) * B);
   L.Y = a.take(es * (size_t)p.d * n);
+  if (p.sketch_prec != RL_SKETCH_F64) {
+    L.Yf = a.take(sizeof(float) * (size_t)p.d * n);
+    L.Tmf = a.take(sizeof(float) * 32 * 32);
+  }
   L.part = a.take(sizeof(double) * (size_t)std::max<int64_t>(partd, 1));
   L.Tm = a.take(es * 32 * 32);
   L.Rrow = a.take(es * (size_t)n * n);
@@ -163,6 +172,7 @@ static int check_opts(int64_t m, int64_t n, int32_t k, const rl_opts& o) {
   if (o.max_iter < 0 || o.check_every < 1) return RL_ERR_ARG;
   if (o.stop_rule < 0 || o.stop_rule > 2) return RL_ERR_ARG;
   if (o.init_iters < 0 || o.lanczos_steps < 1) return RL_ERR_ARG;
+  if (o.sketch_prec < RL_SKETCH_F64 || o.sketch_prec > RL_SKETCH_BF16) return RL_ERR_ARG;
   if (n > 1024 || o.block > 10) return RL_ERR_UNSUPPORTED;
   if (o.d > INT32_MAX / 2) return RL_ERR_ARG;
   return RL_OK;
@@ -184,8 +194,9 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   int rc = check_opts(m, n, k, o);
   if (rc != RL_OK) return rc;
   if (lda < n || ldv < k || (Uout && ldu < k)) return RL_ERR_ARG;
+  if (cplx && o.sketch_prec != RL_SKETCH_F64) return RL_ERR_UNSUPPORTED;
   if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;
-  Problem p{m, n, o.d, o.block, k, o.zeta, cplx, (size_t)(cplx ? 16 : 8), o.max_iter};
+  Problem p{m, n, o.d, o.block, k, o.zeta, cplx, (size_t)(cplx ? 16 : 8), o.max_iter, o.sketch_prec};
   const Layout L = plan(p, h->lds_budget);
   rc = ensure_ws(h, L.total);
   if (rc != RL_OK) return rc;
@@ -211,10 +222,19 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
 
   // Step 1-2: sketch and QR
   const double scale = 1.0 / sqrt((double)o.zeta);
-  CK(launch_sketch(st, (const double*)A, lda * es_d, m, n * es_d, es_d, (int)o.d, o.zeta, o.seed, scale,
-                   at<double>(ws, L.part), at<double>(ws, L.Y), ctl, h->lds_budget));
-  CK(launch_qr(st, cplx, at<void>(ws, L.Y), (int)o.d, (int)n, at<void>(ws, L.Tm), at<void>(ws, L.Rrow),
-               at<void>(ws, L.RH), at<void>(ws, L.Rinv), at<void>(ws, L.RinvH)));
+  if (o.sketch_prec == RL_SKETCH_F64) {
+    CK(launch_sketch(st, (const double*)A, lda * es_d, m, n * es_d, es_d, (int)o.d, o.zeta, o.seed, scale,
+                     at<void>(ws, L.part), at<void>(ws, L.Y), ctl, h->lds_budget, false));
+    CK(launch_qr(st, cplx, at<void>(ws, L.Y), (int)o.d, (int)n, at<void>(ws, L.Tm), at<void>(ws, L.Rrow),
+                 at<void>(ws, L.RH), at<void>(ws, L.Rinv), at<void>(ws, L.RinvH)));
+  } else {
+    // reduced-precision sketch and QR; R is promoted to FP64 for everything after
+    CK(launch_sketch(st, (const double*)A, lda, m, n, 1, (int)o.d, o.zeta, o.seed, scale, at<void>(ws, L.part),
+                     at<void>(ws, L.Yf), ctl, h->lds_budget, true));
+    CK(launch_qr_lowp(st, at<float>(ws, L.Yf), (int)o.d, (int)n, at<float>(ws, L.Tmf), at<double>(ws, L.Y),
+                      at<double>(ws, L.Rrow), at<double>(ws, L.RH), at<double>(ws, L.Rinv), at<double>(ws, L.RinvH),
+                      o.sketch_prec == RL_SKETCH_BF16));
+  }
   // Sigma~(1,1)
   const int KL = std::min<int>(L.KL, o.lanczos_steps);
   CK(launch_lanczos(st, cplx, (int)n, at<void>(ws, L.Y), (int)o.d, at<void>(ws, L.Rrow), at<void>(ws, L.Ub),
@@ -325,6 +345,20 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
 }
 
 // Transpose a row-major d x n block (doubles per element es) into column-major.
+__global__ void k_rowmajor_to_col_f(const float* __restrict__ Y, int64_t ldy, int64_t d, int64_t n,
+                                    float* __restrict__ Yc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d * n) return;
+  const int64_t r = idx / n, c = idx % n;
+  Yc[c * d + r] = Y[r * ldy + c];
+}
+__global__ void k_col_to_rowmajor_f(const float* __restrict__ Yc, int64_t d, int64_t n, float* __restrict__ Y,
+                                    int64_t ldy) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d * n) return;
+  const int64_t r = idx / n, c = idx % n;
+  Y[r * ldy + c] = Yc[c * d + r];
+}
 __global__ void k_rowmajor_to_col(const double* __restrict__ Y, int64_t ldy, int64_t d, int64_t n, int es,
                                   double* __restrict__ Yc) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -432,7 +466,7 @@ int rl_step_sketch(rl_handle h, int is_complex, int64_t m, int64_t n, const doub
   const int es = is_complex ? 2 : 1;
   int nchunk;
   int64_t rows;
-  const int64_t partd = sketch_partial_doubles(m, n * es, (int)d, h->lds_budget, &nchunk, &rows);
+  const int64_t partd = sketch_partial_doubles(m, n * es, (int)d, h->lds_budget, &nchunk, &rows, 8);
   if (partd < 0) return RL_ERR_UNSUPPORTED;
   Arena a;
   const size_t o_ctl = a.take(sizeof(Ctl)), o_part = a.take(sizeof(double) * partd),
@@ -442,7 +476,7 @@ int rl_step_sketch(rl_handle h, int is_complex, int64_t m, int64_t n, const doub
   hipStream_t st = h->stream;
   CK(hipMemsetAsync(at<void>(h->ws, o_ctl), 0, sizeof(Ctl), st));
   CK(launch_sketch(st, A, lda * es, m, n * es, es, (int)d, zeta, seed, 1.0 / sqrt((double)zeta),
-                   at<double>(h->ws, o_part), at<double>(h->ws, o_yc), at<Ctl>(h->ws, o_ctl), h->lds_budget));
+                   at<void>(h->ws, o_part), at<void>(h->ws, o_yc), at<Ctl>(h->ws, o_ctl), h->lds_budget, false));
   const int64_t tot = d * n * es;
   hipLaunchKernelGGL(k_col_to_rowmajor, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
                      at<double>(h->ws, o_yc), d, n, es, Y, ldy);
@@ -469,6 +503,53 @@ int rl_step_qr(rl_handle h, int is_complex, int64_t d, int64_t n, const double* 
   CK(hipGetLastError());
   CK(launch_qr(st, is_complex != 0, at<void>(h->ws, o_yc), (int)d, (int)n, at<void>(h->ws, o_tm), R,
                at<void>(h->ws, o_rh), Rinv, at<void>(h->ws, o_rih)));
+  CK(hipStreamSynchronize(st));
+  return RL_OK;
+}
+
+int rl_step_sketch_f32(rl_handle h, int64_t m, int64_t n, const double* A, int64_t lda, int64_t d, int32_t zeta,
+                       uint64_t seed, float* Y, int64_t ldy) {
+  if (!h || !A || !Y || m < 1 || n < 1 || lda < n || ldy < n || d < 1 || zeta < 1 || zeta > d) return RL_ERR_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;
+  int nchunk;
+  int64_t rows;
+  const int64_t partf = sketch_partial_doubles(m, n, (int)d, h->lds_budget, &nchunk, &rows, 4);
+  if (partf < 0) return RL_ERR_UNSUPPORTED;
+  Arena a;
+  const size_t o_ctl = a.take(sizeof(Ctl)), o_part = a.take(sizeof(float) * partf),
+               o_yc = a.take(sizeof(float) * (size_t)d * n);
+  int rc = ensure_ws(h, a.off + 256);
+  if (rc != RL_OK) return rc;
+  hipStream_t st = h->stream;
+  CK(hipMemsetAsync(at<void>(h->ws, o_ctl), 0, sizeof(Ctl), st));
+  CK(launch_sketch(st, A, lda, m, n, 1, (int)d, zeta, seed, 1.0 / sqrt((double)zeta), at<void>(h->ws, o_part),
+                   at<void>(h->ws, o_yc), at<Ctl>(h->ws, o_ctl), h->lds_budget, true));
+  const int64_t tot = d * n;
+  hipLaunchKernelGGL(k_col_to_rowmajor_f, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                     at<float>(h->ws, o_yc), d, n, Y, ldy);
+  CK(hipGetLastError());
+  CK(hipStreamSynchronize(st));
+  return RL_OK;
+}
+
+int rl_step_qr_lowp(rl_handle h, int64_t d, int64_t n, const float* Y, int64_t ldy, int32_t sketch_prec, double* R,
+                    double* Rinv) {
+  if (!h || !Y || !R || !Rinv || n < 1 || d < n || ldy < n || n > 4096) return RL_ERR_ARG;
+  if (sketch_prec != RL_SKETCH_F32 && sketch_prec != RL_SKETCH_BF16) return RL_ERR_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;
+  Arena a;
+  const size_t o_yf = a.take(sizeof(float) * d * n), o_tm = a.take(sizeof(float) * 32 * 32),
+               o_y = a.take(sizeof(double) * d * n), o_rh = a.take(sizeof(double) * n * n),
+               o_rih = a.take(sizeof(double) * n * n);
+  int rc = ensure_ws(h, a.off + 256);
+  if (rc != RL_OK) return rc;
+  hipStream_t st = h->stream;
+  const int64_t tot = d * n;
+  hipLaunchKernelGGL(k_rowmajor_to_col_f, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Y, ldy, d, n,
+                     at<float>(h->ws, o_yf));
+  CK(hipGetLastError());
+  CK(launch_qr_lowp(st, at<float>(h->ws, o_yf), (int)d, (int)n, at<float>(h->ws, o_tm), at<double>(h->ws, o_y), R,
+                    at<double>(h->ws, o_rh), Rinv, at<double>(h->ws, o_rih), sketch_prec == RL_SKETCH_BF16));
   CK(hipStreamSynchronize(st));
   return RL_OK;
 }

@@ -1,0 +1,122 @@
+"""Reduced-precision sketch and QR (FP32, and bfloat16-input trailing updates
+with FP32 accumulation) against the FP64 oracle.
+
+The sketch in FP32 is pinned exactly on integer data (sums of small integers
+are exact in FP32, so only the final scaling rounds, once, in FP32); on
+Gaussian data it is held to the FP32 rounding bound.  The QR is held to the
+backward-error level of its precision.  The full solves keep every step after
+R in FP64, so where they stop by the rule they must meet the same gates as the
+FP64 path; the iteration counts are reported.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import rlobpcg, sparsestack
+from workloads import integer_matrix, planted_numpy, spectrum_gap, spectrum_logspace_tail
+
+from .gpu_util import banner, sin_angle, to_np
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+UBF16 = 2.0 ** -9
+
+
+@pytest.fixture(scope="module")
+def rl():
+    import paper_2602_16797_amd as rl
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return rl
+
+
+@pytest.mark.parametrize("m,n,d,zeta", [(20011, 37, 150, 8), (4096, 64, 256, 8), (3000, 200, 800, 8),
+                                        (700, 9, 9, 9)])
+def test_sketch_f32_exact_on_integers(rl, m, n, d, zeta):
+    banner(f"f32 sketch integer m={m} n={n} d={d} zeta={zeta}")
+    A = integer_matrix(m, n, 11 + m)
+    Y = to_np(rl.rl_step_sketch_f32(torch.from_numpy(A).cuda(), d, zeta, 4321 + d))
+    S = sparsestack.embedding(m, d, zeta, 4321 + d)
+    unscaled = np.asarray(S @ A)                       # exact integers, |.| < 2^24
+    assert np.abs(unscaled).max() < 2 ** 24
+    expect = (unscaled.astype(np.float32) * np.float32(sparsestack.scale_factor(zeta))).astype(np.float32)
+    assert Y.dtype == np.float32
+    assert np.array_equal(Y, expect)
+
+
+def test_sketch_f32_rounding_bound(rl):
+    banner("f32 sketch gaussian 100000x80, d=320")
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((100_000, 80))
+    Y = to_np(rl.rl_step_sketch_f32(torch.from_numpy(A).cuda(), 320, 8, 77)).astype(np.float64)
+    Yo = sparsestack.sketch(A, 320, 8, 77)
+    S = sparsestack.embedding(100_000, 320, 8, 77)
+    absum = abs(S) @ np.abs(A) / np.sqrt(8)            # sum of |terms| per entry
+    cnt = np.asarray(abs(S).sum(axis=1)).ravel()[:, None]  # terms per row of Y
+    assert np.all(np.abs(Y - Yo) <= (cnt + 2) * U32 * absum * 1.01)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("d,n", [(800, 200), (150, 37), (2000, 120)])
+def test_qr_lowp_backward_error(rl, prec, d, n):
+    banner(f"qr {prec} d={d} n={n}")
+    rng = np.random.default_rng(d + n)
+    Y = rng.standard_normal((d, n)).astype(np.float32)
+    R, Rinv = rl.rl_step_qr_lowp(torch.from_numpy(Y).cuda(), prec)
+    R, Rinv = to_np(R), to_np(Rinv)
+    Y64 = Y.astype(np.float64)
+    assert np.allclose(np.tril(R, -1), 0.0)
+    # R^T R = Y^T Y up to the backward error of the precision
+    u = U32 if prec == "f32" else UBF16
+    err = np.linalg.norm(R.T @ R - Y64.T @ Y64) / np.linalg.norm(Y64) ** 2
+    banner(f"  ||R^T R - Y^T Y|| / ||Y||^2 = {err:.3e}")
+    assert err <= 4 * np.sqrt(n) * u
+    # R^{-1} is computed in FP64 from the promoted R
+    assert np.linalg.norm(R @ Rinv - np.eye(n)) <= 1e-12 * np.linalg.cond(R)
+
+
+def _solve_vs_oracle(rl, A, k, seed, prec, normA, block=None, allow_max_iter=False):
+    At = torch.from_numpy(A).cuda()
+    kw = dict(seed=seed, sketch_prec=prec)
+    if block is not None:
+        kw["block"] = block
+    r = rl.rl_svds_smallest(At, k, **kw)
+    o = rlobpcg(A, k, seed=seed, block=block)
+    f = rl.rl_svds_smallest(At, k, seed=seed, block=block) if block else rl.rl_svds_smallest(At, k, seed=seed)
+    sg, Vg, Ug = to_np(r.sigma), to_np(r.V), to_np(r.U)
+    banner(f"  {prec}: iters {r.iters} status {r.status}; fp64 iters {f.iters}; oracle iters {o.iters}")
+    # a bfloat16 preconditioner can slow the iteration past max_iter; the last
+    # iterate is returned then and must still meet the accuracy gates
+    assert r.status == rl.RL_OK or (allow_max_iter and r.status == rl.RL_NOT_CONVERGED)
+    assert np.max(np.abs(sg - o.sigma)) <= 1e-12 * normA
+    res = A @ Vg - Ug * sg[None, :]
+    assert np.linalg.norm(res, axis=0).max() <= 1e-12 * normA
+    ang = sin_angle(Vg, o.V)
+    banner(f"  sin angle to the FP64 oracle {ang:.3e}")
+    assert ang <= 1e-10
+    return r.iters, f.iters
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_solve_single_vector_lowp(rl, prec):
+    banner(f"solve 4000x50 k=1 sketch {prec}")
+    sig = spectrum_logspace_tail(50, 1e-3, 1e-6)
+    A, _, _ = planted_numpy(4000, 50, sig, 1001)
+    _solve_vs_oracle(rl, A, 1, 2001, prec, 1.0)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_solve_block_lowp(rl, prec):
+    banner(f"solve 30000x90 k=3 sketch {prec}")
+    sig = spectrum_gap(90, 3, 1e-6, 100.0)
+    A, _, _ = planted_numpy(30_000, 90, sig, 17)
+    _solve_vs_oracle(rl, A, 3, 23, prec, 1.0, allow_max_iter=(prec == "bf16"))
+
+
+def test_lowp_rejects_complex(rl):
+    A = torch.zeros((300, 30), dtype=torch.complex128, device="cuda")
+    with pytest.raises(rl.RlError) as e:
+        rl.rl_svds_smallest(A, 1, sketch_prec="f32")
+    assert e.value.code == rl.RL_ERR_UNSUPPORTED

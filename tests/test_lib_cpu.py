@@ -29,7 +29,8 @@ def _declared():
 def test_header_declares_the_boundary():
     names = _declared()
     for must in ("rl_create", "rl_destroy", "rl_default_opts", "rl_svds_smallest_d", "rl_svds_smallest_z",
-                 "rl_step_sketch", "rl_step_qr", "rl_step_astream", "rl_step_tall_svd", "rl_status_string"):
+                 "rl_step_sketch", "rl_step_qr", "rl_step_astream", "rl_step_tall_svd", "rl_status_string",
+                 "rl_step_sketch_f32", "rl_step_qr_lowp"):
         assert must in names
 
 
@@ -50,13 +51,14 @@ def test_struct_layout_matches_ctypes(tmp_path):
         '#include <stdio.h>\n#include <stddef.h>\n#include "rlobpcg.h"\n'
         "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(rl_opts), sizeof(rl_info),"
         " offsetof(rl_opts, tau), offsetof(rl_opts, lanczos_steps), offsetof(rl_info, sigma1),"
-        " offsetof(rl_info, hist_cap), offsetof(rl_info, rnorm_hist));return 0;}\n")
+        " offsetof(rl_info, hist_cap), offsetof(rl_info, rnorm_hist));"
+        "printf(\"%zu\\n\", offsetof(rl_opts, sketch_prec));return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     O, I = rl.RlOpts, rl.RlInfo
     assert vals == [ctypes.sizeof(O), ctypes.sizeof(I), O.tau.offset, O.lanczos_steps.offset, I.sigma1.offset,
-                    I.hist_cap.offset, I.rnorm_hist.offset]
+                    I.hist_cap.offset, I.rnorm_hist.offset, O.sketch_prec.offset]
 
 
 def test_host_only_calls():
@@ -64,6 +66,7 @@ def test_host_only_calls():
     o = rl.default_opts(10_000, 200, 1)
     assert o.d == 800 and o.zeta == 8 and o.block == 1 and o.max_iter == 200 and o.check_every == 5
     assert o.tau == 2.0 * 200 ** 0.5 * 2.0 ** -52
+    assert o.sketch_prec == rl.RL_SKETCH_F64
     assert rl.default_opts(10_000, 200, 3).max_iter == 100
     assert rl.status_string(rl.RL_ERR_ARG) == "invalid argument"
     assert lib.rl_default_opts(None, 1, 1, 1) == rl.RL_ERR_ARG
