@@ -90,6 +90,12 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="tall-1e6x200-k1", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sketch-prec", default="f64", choices=["f64", "f32", "bf16"],
+                    help="precision of the sketch and its QR (the rest stays FP64)")
+    ap.add_argument("--no-dot2", action="store_true", help="plain FP64 products of A (no compensation)")
+    ap.add_argument("--vs-fp64", action="store_true",
+                    help="after timing, solve once with the FP64 sketch and Dot2 products and report the "
+                         "difference of the timed variant's sigma and subspace from it")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
@@ -108,7 +114,7 @@ def main(argv=None):
     A, Vp, s = planted_torch(m, n, sig, dseed, device="cuda", is_complex=cplx)
     torch.cuda.synchronize()
     es = 16 if cplx else 8
-    kw = dict(seed=sseed, d=d, zeta=zeta)
+    kw = dict(seed=sseed, d=d, zeta=zeta, sketch_prec=args.sketch_prec, dot2=not args.no_dot2)
 
     for w in range(args.warmup):
         r = rl.rl_svds_smallest(A, k, **kw)
@@ -135,6 +141,16 @@ def main(argv=None):
     gates = {"resid_max": res, "resid_gate": 1e-12 * float(sig[0]), "sigma_err_vs_planted": sig_err,
              "passed": bool(res <= 1e-12 * sig[0] and sig_err <= 1e-12 * sig[0])}
     log(f"gates: {gates}")
+    if args.vs_fp64:
+        ref = rl.rl_svds_smallest(A, k, seed=sseed, d=d, zeta=zeta)
+        with torch.no_grad():
+            Qa, _ = torch.linalg.qr(last.V)
+            Qb, _ = torch.linalg.qr(ref.V)
+            sin = torch.linalg.matrix_norm(Qb - Qa @ (Qa.conj().T @ Qb), ord=2).item()
+        gates["vs_fp64_dot2"] = {"sin_angle": sin,
+                                 "sigma_diff": float((last.sigma - ref.sigma).abs().max().item()),
+                                 "fp64_iters": ref.iters}
+        log(f"vs FP64 Dot2 solve: {gates['vs_fp64_dot2']}")
 
     # dominant kernel: the fused A-stream pass, timed per launch with HIP events
     # Algorithmic bytes of each launch: A once, W, the A_W write, and the
@@ -175,7 +191,8 @@ def main(argv=None):
         "dtype": "c128" if cplx else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "k": k, "d": d, "zeta": zeta,
-                   "spectrum": list(spec), "stop_rule": "paper", "dot2": True},
+                   "spectrum": list(spec), "stop_rule": "paper", "dot2": not args.no_dot2,
+                   "sketch_prec": args.sketch_prec},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail": {"iters": last.iters, "a_passes": last.a_passes, "status": last.status,

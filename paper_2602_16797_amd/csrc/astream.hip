@@ -26,6 +26,8 @@
 //             level writes the finished sums).
 // k_panel     A_V <- A_T C_V, A_X <- A_T C_X (row-local, in place).
 // k_final_u   U(:, j) = (A_T C_V)(:, b-1-j) / theta_{b-1-j} for the outputs.
+#include <algorithm>
+
 #include "common.hpp"
 #include "astream_kernels.hpp"
 #include "kernels.hpp"
@@ -174,7 +176,8 @@ int astream_ns(int n) {
 static int64_t astream_max_parts(int64_t m, int n, int B, int es_d) {
   const int64_t g = astream_blocks(m, n, B, es_d) * 4;
   const int64_t r = astream_r2_blocks(m);
-  return g > r ? g : r;
+  const int64_t c = astream_cs_blocks(m, n);
+  return std::max(g, std::max(r, c));
 }
 
 int64_t astream_part_doubles(int64_t m, int n, int B, int es_d) {
@@ -200,6 +203,11 @@ hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const voi
     nb = astream_r2_blocks(m);
     np = nb;
     ok = dispatch_astream_r2(dot2, init, B, st, nb, (const double*)A, lda, m, n, (const double*)W, (double*)AW,
+                             (const double*)AVp, (const double*)AXp, Gpart, ctl);
+  } else if (!cplx && astream_cs_fits(B, n, aligned)) {
+    nb = astream_cs_blocks(m, n);
+    np = nb;
+    ok = dispatch_astream_cs(dot2, init, B, st, nb, (const double*)A, lda, m, n, (const double*)W, (double*)AW,
                              (const double*)AVp, (const double*)AXp, Gpart, ctl);
   } else if (cplx)
     ok = dispatch_astream_gc(dot2, ns, B, st, nb, A, lda, m, n, W, AW, AVp, AXp, init, Gpart, ctl);

@@ -179,66 +179,146 @@ __global__ __launch_bounds__(256) void k_astream(const T* __restrict__ A, int64_
 // V values costs about 2V + 6 shuffles instead of 12 per value; the finished
 // sums are broadcast to every lane with scalar readlanes.
 
-// Partner exchange for the butterfly stages: the stage that pairs lanes across
-// bit log2(o) reads the partner's value.  Across rows of 16 lanes (o = 16, 32)
-// this is a permute through the LDS crossbar; inside a row it is a DPP lane
-// permutation (row mirror, half-row mirror, quad permutations), whose partner
-// differs in the stage's bit and agrees in every higher bit, which is all the
-// reductions below rely on.
-__device__ inline double xor_partner(double v, int o) {
-  if (o == 8) return dpp_d<DPP_ROW_MIRROR>(v);
-  if (o == 4) return dpp_d<DPP_ROW_HALF_MIRROR>(v);
-  if (o == 2) return dpp_d<DPP_QUAD_2301>(v);
-  if (o == 1) return dpp_d<DPP_QUAD_1032>(v);
-  return __shfl_xor(v, o, WAVE);
+// Butterfly stages of the reductions below.  Across rows of 16 lanes (o = 32,
+// 16) the exchange uses the gfx950 lane swaps: permlane32_swap(x, y) leaves
+// x = [x(0:31), y(0:31)] and y = [x(32:63), y(32:63)], and permlane16_swap does
+// the same with 16-lane groups inside each half, so with x the lower-half
+// values and y the upper-half values of a stage, x + y is in every lane the
+// sum that lane keeps, with no selects and no LDS traffic.  Inside a row
+// (o = 8, 4, 2, 1) the partner is read with a DPP lane permutation (row
+// mirror, half-row mirror, quad permutations); its partner differs in the
+// stage's bit and agrees in every higher bit, which is all the reductions rely
+// on.
+template <int O>
+__device__ inline void lane_swap(double& x, double& y) {
+  static_assert(O == 32 || O == 16, "lane swaps exist for 32 and 16");
+  if constexpr (O == 32) {
+    auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(y), false, false);
+    auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(y), false, false);
+    x = __hiloint2double((int)hi[0], (int)lo[0]);
+    y = __hiloint2double((int)hi[1], (int)lo[1]);
+  } else {
+    auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(y), false, false);
+    auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(y), false, false);
+    x = __hiloint2double((int)hi[0], (int)lo[0]);
+    y = __hiloint2double((int)hi[1], (int)lo[1]);
+  }
 }
 
-template <int V2, int LOG2V>
-__device__ inline void tr_reduce_dot2(double (&s)[V2], double (&e)[V2], int lane) {
+template <int O>
+__device__ inline double dpp_partner(double v) {
+  if constexpr (O == 8) return dpp_d<DPP_ROW_MIRROR>(v);
+  else if constexpr (O == 4) return dpp_d<DPP_ROW_HALF_MIRROR>(v);
+  else if constexpr (O == 2) return dpp_d<DPP_QUAD_2301>(v);
+  else return dpp_d<DPP_QUAD_1032>(v);
+}
+
+// one transposed stage: values k < H pair with k + H; lanes with bit log2(O)
+// clear keep the lower half
+template <int O, int H, int V2>
+__device__ inline void tr_stage_dot2(double (&s)[V2], double (&e)[V2], int lane) {
 #pragma unroll
-  for (int st = 0; st < LOG2V; ++st) {
-    const int half = V2 >> (st + 1);
-    const int o = 32 >> st;
-    const bool hi = (lane & o) != 0;
-#pragma unroll
-    for (int k = 0; k < half; ++k) {
-      const double ks = hi ? s[k + half] : s[k];
-      const double ke = hi ? e[k + half] : e[k];
-      const double ss = hi ? s[k] : s[k + half];
-      const double se = hi ? e[k] : e[k + half];
-      const double rs = xor_partner(ss, o);
-      const double re = xor_partner(se, o);
-      double t;
+  for (int k = 0; k < H; ++k) {
+    double t;
+    if constexpr (O >= 16) {
+      double xs = s[k], ys = s[k + H], xe = e[k], ye = e[k + H];
+      lane_swap<O>(xs, ys);
+      lane_swap<O>(xe, ye);
+      two_sum(xs, ys, s[k], t);
+      e[k] = (xe + ye) + t;
+    } else {
+      const bool hi = (lane & O) != 0;
+      const double ks = hi ? s[k + H] : s[k];
+      const double ke = hi ? e[k + H] : e[k];
+      const double rs = dpp_partner<O>(hi ? s[k] : s[k + H]);
+      const double re = dpp_partner<O>(hi ? e[k] : e[k + H]);
       two_sum(ks, rs, s[k], t);
-      e[k] = ke + re + t;
+      e[k] = (ke + re) + t;
     }
   }
-#pragma unroll
-  for (int o = 32 >> LOG2V; o >= 1; o >>= 1) {
-    const double rs = xor_partner(s[0], o);
-    const double re = xor_partner(e[0], o);
+}
+
+// all-reduce stage of one (sum, error) pair
+template <int O>
+__device__ inline void ar_stage_dot2(double& s, double& e) {
+  double rs, re;
+  if constexpr (O >= 16) {
+    double xs = s, ys = s, xe = e, ye = e;
+    lane_swap<O>(xs, ys);
+    lane_swap<O>(xe, ye);
     double t;
-    two_sum(s[0], rs, s[0], t);
-    e[0] = e[0] + re + t;
+    two_sum(xs, ys, s, t);
+    e = (xe + ye) + t;
+  } else {
+    rs = dpp_partner<O>(s);
+    re = dpp_partner<O>(e);
+    double t;
+    two_sum(s, rs, s, t);
+    e = (e + re) + t;
   }
+}
+
+template <int O>
+__device__ inline double ar_stage_plain(double v) {
+  if constexpr (O >= 16) {
+    double x = v, y = v;
+    lane_swap<O>(x, y);
+    return x + y;
+  } else {
+    return v + dpp_partner<O>(v);
+  }
+}
+
+template <int O, int H, int V2>
+__device__ inline void tr_stage_plain(double (&s)[V2], int lane) {
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    if constexpr (O >= 16) {
+      double x = s[k], y = s[k + H];
+      lane_swap<O>(x, y);
+      s[k] = x + y;
+    } else {
+      const bool hi = (lane & O) != 0;
+      const double ks = hi ? s[k + H] : s[k];
+      s[k] = ks + dpp_partner<O>(hi ? s[k] : s[k + H]);
+    }
+  }
+}
+
+// Compensated transpose-reduction of V2 = 2^LOG2V (sum, error) pairs over the
+// wave: stage st halves the values each lane carries (bit 5 - st of the lane
+// picks the half); the remaining stages all-reduce one pair.  On return lane l
+// holds in (s[0], e[0]) the wave sum of value tr_src_lane^-1(l).
+template <int V2, int LOG2V>
+__device__ inline void tr_reduce_dot2(double (&s)[V2], double (&e)[V2], int lane) {
+  if constexpr (LOG2V >= 1) tr_stage_dot2<32, V2 / 2, V2>(s, e, lane);
+  if constexpr (LOG2V >= 2) tr_stage_dot2<16, V2 / 4, V2>(s, e, lane);
+  if constexpr (LOG2V >= 3) tr_stage_dot2<8, V2 / 8, V2>(s, e, lane);
+  if constexpr (LOG2V >= 4) tr_stage_dot2<4, V2 / 16, V2>(s, e, lane);
+  if constexpr (LOG2V >= 5) tr_stage_dot2<2, V2 / 32, V2>(s, e, lane);
+  if constexpr (LOG2V >= 6) tr_stage_dot2<1, V2 / 64, V2>(s, e, lane);
+  if constexpr (LOG2V < 1) ar_stage_dot2<32>(s[0], e[0]);
+  if constexpr (LOG2V < 2) ar_stage_dot2<16>(s[0], e[0]);
+  if constexpr (LOG2V < 3) ar_stage_dot2<8>(s[0], e[0]);
+  if constexpr (LOG2V < 4) ar_stage_dot2<4>(s[0], e[0]);
+  if constexpr (LOG2V < 5) ar_stage_dot2<2>(s[0], e[0]);
+  if constexpr (LOG2V < 6) ar_stage_dot2<1>(s[0], e[0]);
 }
 
 template <int V2, int LOG2V>
 __device__ inline void tr_reduce_plain(double (&s)[V2], int lane) {
-#pragma unroll
-  for (int st = 0; st < LOG2V; ++st) {
-    const int half = V2 >> (st + 1);
-    const int o = 32 >> st;
-    const bool hi = (lane & o) != 0;
-#pragma unroll
-    for (int k = 0; k < half; ++k) {
-      const double ks = hi ? s[k + half] : s[k];
-      const double ss = hi ? s[k] : s[k + half];
-      s[k] = ks + xor_partner(ss, o);
-    }
-  }
-#pragma unroll
-  for (int o = 32 >> LOG2V; o >= 1; o >>= 1) s[0] += xor_partner(s[0], o);
+  if constexpr (LOG2V >= 1) tr_stage_plain<32, V2 / 2, V2>(s, lane);
+  if constexpr (LOG2V >= 2) tr_stage_plain<16, V2 / 4, V2>(s, lane);
+  if constexpr (LOG2V >= 3) tr_stage_plain<8, V2 / 8, V2>(s, lane);
+  if constexpr (LOG2V >= 4) tr_stage_plain<4, V2 / 16, V2>(s, lane);
+  if constexpr (LOG2V >= 5) tr_stage_plain<2, V2 / 32, V2>(s, lane);
+  if constexpr (LOG2V >= 6) tr_stage_plain<1, V2 / 64, V2>(s, lane);
+  if constexpr (LOG2V < 1) s[0] = ar_stage_plain<32>(s[0]);
+  if constexpr (LOG2V < 2) s[0] = ar_stage_plain<16>(s[0]);
+  if constexpr (LOG2V < 3) s[0] = ar_stage_plain<8>(s[0]);
+  if constexpr (LOG2V < 4) s[0] = ar_stage_plain<4>(s[0]);
+  if constexpr (LOG2V < 5) s[0] = ar_stage_plain<2>(s[0]);
+  if constexpr (LOG2V < 6) s[0] = ar_stage_plain<1>(s[0]);
 }
 
 // lane holding value index k after the transpose-reduction
@@ -439,6 +519,171 @@ __global__ __launch_bounds__(256) void k_astream_r2(const double* __restrict__ A
   for (int e = threadIdx.x; e < plane; e += 256) {
     gp[plane + e] = (red[0][0][e] + red[1][0][e]) + (red[2][0][e] + red[3][0][e]);
     gp[2 * plane + e] = (red[0][1][e] + red[1][1][e]) + (red[2][1][e] + red[3][1][e]);
+  }
+}
+
+// Real data, n <= 1024, any b <= 10, 16-byte aligned rows: the column-split
+// pass.  A workgroup of nw waves (blockDim.x = 64 nw) walks its rows in
+// batches of RB rows; wave w owns the column pairs 2 lane + 128 w, so each
+// column belongs to exactly one wave and the waves read disjoint parts of
+// every row.  Each wave reduces its partial row sums row by row (compensated
+// transpose-reduction over the b values of a row) into LDS; after one barrier
+// per batch, lane v of every wave combines the nw partials of value v in wave
+// order and the finished sums are broadcast with scalar readlanes.  Every wave
+// then accumulates the column sums of its own columns, so the per-workgroup
+// record needs no cross-wave step.  init (the start pass) is a run-time flag.
+template <int B>
+struct CsShape {
+  static constexpr int RB = (B >= 6) ? 2 : 4;  // rows per batch (one barrier each)
+  static constexpr int V = RB * B;             // row sums per batch (<= 20)
+  static constexpr int B2 = B <= 1 ? 1 : B <= 2 ? 2 : B <= 4 ? 4 : B <= 8 ? 8 : 16;
+  static constexpr int LOG2B = B2 == 1 ? 0 : B2 == 2 ? 1 : B2 == 4 ? 2 : B2 == 8 ? 3 : 4;
+};
+constexpr int CS_MAXW = 8;
+
+template <int B, bool DOT2>
+__global__ __launch_bounds__(512) void k_astream_cs(const double* __restrict__ A, int64_t lda, int64_t m, int n,
+                                                    const double* __restrict__ W, double* __restrict__ AW,
+                                                    const double* __restrict__ AVp, const double* __restrict__ AXp,
+                                                    double* __restrict__ Gpart, int64_t rows_per_block, int init,
+                                                    const Ctl* __restrict__ ctl) {
+  if (ctl != nullptr && ctl->done) return;
+  using SH = CsShape<B>;
+  constexpr int RB = SH::RB, V = SH::V, B2 = SH::B2, LOG2B = SH::LOG2B;
+  __shared__ double sp[2][CS_MAXW][V], ep[2][CS_MAXW][V];
+  const int nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool has_x = AXp != nullptr;
+  const int c = 2 * lane + 128 * wave;
+  // value index held by this lane after tr_reduce over B2 values: the top
+  // LOG2B lane bits, most significant first; lanes whose lower bits are zero
+  // represent their group
+  int my_idx = 0;
+#pragma unroll
+  for (int st = 0; st < LOG2B; ++st) my_idx |= ((lane >> (5 - st)) & 1) << (LOG2B - 1 - st);
+  const bool my_rep = (lane & ((1 << (6 - LOG2B)) - 1)) == 0;
+  double2 w[B], g1s[B], g1e[B], gx[B], gw[B];
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    w[j].x = (c < n) ? W[(int64_t)c * B + j] : 0.0;
+    w[j].y = (c + 1 < n) ? W[(int64_t)(c + 1) * B + j] : 0.0;
+    g1s[j] = make_double2(0.0, 0.0);
+    g1e[j] = make_double2(0.0, 0.0);
+    gx[j] = make_double2(0.0, 0.0);
+    gw[j] = make_double2(0.0, 0.0);
+  }
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = (r0 + rows_per_block < m) ? r0 + rows_per_block : m;
+  auto load = [&](double2 (&a)[RB], int64_t rb) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      const int64_t row = rb + q;
+      if (row < r1 && c + 1 < n) a[q] = *reinterpret_cast<const double2*>(A + row * lda + c);
+      else if (row < r1 && c < n) a[q] = make_double2(A[row * lda + c], 0.0);
+      else a[q] = make_double2(0.0, 0.0);
+    }
+  };
+  int64_t rb = r0;
+  double2 a[RB], an[RB];
+  load(an, rb);
+  double avn = 0.0, axn = 0.0;
+  if (!init && lane < V && rb + lane / B < r1) {
+    avn = AVp[rb * B + lane];
+    if (has_x) axn = AXp[rb * B + lane];
+  }
+  int buf = 0;
+  for (; rb < r1; rb += RB) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) a[q] = an[q];
+    const double avl = avn, axl = axn;
+    const int64_t rn = rb + RB;
+    load(an, rn);
+    if (!init) {
+      avn = 0.0;
+      axn = 0.0;
+      if (lane < V && rn + lane / B < r1) {
+        avn = AVp[rn * B + lane];
+        if (has_x) axn = AXp[rn * B + lane];
+      }
+    }
+    // this wave's partial row sums, one row at a time
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      double ys[B2], ye[B2];
+#pragma unroll
+      for (int j = 0; j < B2; ++j) {
+        ys[j] = 0.0;
+        ye[j] = 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        if constexpr (DOT2) {
+          dot2_add(a[q].x, w[j].x, ys[j], ye[j]);
+          dot2_add(a[q].y, w[j].y, ys[j], ye[j]);
+        } else {
+          ys[j] = fma(a[q].x, w[j].x, ys[j]);
+          ys[j] = fma(a[q].y, w[j].y, ys[j]);
+        }
+      }
+      if constexpr (DOT2) tr_reduce_dot2<B2, LOG2B>(ys, ye, lane);
+      else tr_reduce_plain<B2, LOG2B>(ys, lane);
+      // after the reduction every lane holds the finished sum of value
+      // my_idx; one lane per value writes it
+      if (my_rep && my_idx < B) {
+        sp[buf][wave][q * B + my_idx] = ys[0];
+        ep[buf][wave][q * B + my_idx] = DOT2 ? ye[0] : 0.0;
+      }
+    }
+    __syncthreads();
+    // lane v < V combines value v over the waves, in wave order
+    double comb = 0.0;
+    if (lane < V) {
+      double S = sp[buf][0][lane], E = ep[buf][0][lane], t;
+      for (int q = 1; q < nw; ++q) {
+        two_sum(S, sp[buf][q][lane], S, t);
+        E += t + ep[buf][q][lane];
+      }
+      comb = S + E;
+    }
+    buf ^= 1;
+    if (wave == 0 && lane < V && rb + lane / B < r1) AW[rb * B + lane] = comb;
+#pragma unroll
+    for (int q = 0; q < RB; ++q)
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        const int v = q * B + j;
+        const double yv = readlane_d(comb, v);
+        const double av = init ? yv : readlane_d(avl, v);
+        if constexpr (DOT2) {
+          dot2_add(a[q].x, av, g1s[j].x, g1e[j].x);
+          dot2_add(a[q].y, av, g1s[j].y, g1e[j].y);
+        } else {
+          g1s[j].x = fma(a[q].x, av, g1s[j].x);
+          g1s[j].y = fma(a[q].y, av, g1s[j].y);
+        }
+        if (!init) {
+          const double ax = readlane_d(axl, v);
+          gx[j].x = fma(a[q].x, ax, gx[j].x);
+          gx[j].y = fma(a[q].y, ax, gx[j].y);
+          gw[j].x = fma(a[q].x, yv, gw[j].x);
+          gw[j].y = fma(a[q].y, yv, gw[j].y);
+        }
+      }
+  }
+  const int64_t plane = (int64_t)n * B;
+  double* gp = Gpart + (int64_t)blockIdx.x * 4 * plane;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (c + h < n) {
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        const int64_t e = (int64_t)(c + h) * B + j;
+        gp[e] = h ? g1s[j].y : g1s[j].x;
+        gp[plane + e] = h ? gx[j].y : gx[j].x;
+        gp[2 * plane + e] = h ? gw[j].y : gw[j].x;
+        gp[3 * plane + e] = h ? g1e[j].y : g1e[j].x;
+      }
+    }
   }
 }
 

@@ -28,6 +28,12 @@ int64_t astream_blocks(int64_t m, int n, int B, int es_d);
 int64_t astream_part_doubles(int64_t m, int n, int B, int es_d);
 int64_t astream_tmp_doubles(int64_t m, int n, int B, int es_d);
 int64_t astream_r2_blocks(int64_t m);
+int astream_cs_waves(int n);
+bool astream_cs_fits(int B, int n, bool aligned);
+int64_t astream_cs_blocks(int64_t m, int n);
+bool dispatch_astream_cs(bool dot2, int init, int B, hipStream_t st, int64_t nb, const double* A, int64_t lda,
+                         int64_t m, int n, const double* W, double* AW, const double* AVp, const double* AXp,
+                         double* Gpart, const Ctl* ctl);
 bool astream_r2_fits(int B, int n, bool aligned);
 bool dispatch_astream_r2(bool dot2, int init, int B, hipStream_t st, int64_t nb, const double* A, int64_t lda,
                          int64_t m, int n, const double* W, double* AW, const double* AVp, const double* AXp,

@@ -81,7 +81,9 @@ def test_qr_and_inverse(rl, d, n, cplx):
 @pytest.mark.parametrize("m,n,b,cplx,dot2", [(5003, 37, 1, False, False), (5003, 37, 1, False, True),
                                              (20000, 200, 1, False, True), (7777, 513, 5, False, True),
                                              (3000, 256, 3, False, False), (2049, 65, 2, True, False),
-                                             (2049, 65, 2, True, True), (1500, 1000, 10, True, False), (999, 1024, 10, False, True)])
+                                             (2049, 65, 2, True, True), (1500, 1000, 10, True, False), (999, 1024, 10, False, True),
+                                             (17, 130, 3, False, True), (40_000, 300, 4, False, True),
+                                             (30_000, 500, 5, False, False)])
 def test_astream(rl, m, n, b, cplx, dot2):
     banner(f"astream m={m} n={n} b={b} complex={cplx} dot2={dot2}")
     rng = np.random.default_rng(m + n + b)
