@@ -38,6 +38,9 @@ extern "C" {
 #define RL_ERR_NOMEM (-3)     /* device workspace allocation failed */
 #define RL_ERR_NONFINITE (-4) /* NaN/Inf in S*A or in R^{-1} (S*A numerically rank deficient) */
 #define RL_ERR_UNSUPPORTED (-7) /* a shape outside the compiled kernels (n > 1024 or b > 10) */
+#define RL_PENDING 2             /* served job not finished (rl_server_poll / rl_server_wait time-out) */
+#define RL_ERR_ADMISSION (-5)    /* a served request whose workspace can never fit the server's budget */
+#define RL_ERR_CANCELLED (-6)    /* a request submitted to a server that is shutting down */
 
 /* Stopping rules (oracle.termination documents the same three). */
 #define RL_STOP_PAPER 0 /* at i = 0 mod check_every: tolerance and both stagnation checks, every column */
@@ -161,6 +164,59 @@ int rl_step_astream(rl_handle h, int is_complex, int64_t m, int64_t n, const dou
  * C (device t x t row-major, column j <-> sigma[j]) via TSQR + one-sided Jacobi
  * (Alg. rlopcg, svd of A_T). */
 int rl_step_tall_svd(rl_handle h, int is_complex, int64_t m, int32_t t, const double* P, double* sigma, double* C);
+
+/* ---- Served form: continuous batching of solves of different shapes.
+ *
+ * Callers that stream many solves (different m, n, k) hand them to a server
+ * instead of solving one at a time.  Each request is queued; a request is
+ * admitted as soon as a slot is free and the workspaces of the solves in
+ * flight plus its own fit hbm_budget_bytes (the caller's A and outputs are not
+ * counted).  Admitted solves run concurrently, one stream per slot, so their
+ * kernels overlap on the device.  A solve's results are the same as when it
+ * runs alone (same kernels, same launch configuration).
+ *
+ * Ownership: A and the outputs are the caller's device memory and must stay
+ * valid and untouched until rl_server_poll or rl_server_wait reports the job
+ * done.  The server copies *req and *req->opts at submit.  A finished job is
+ * reported once; afterwards its ticket is unknown (RL_ERR_ARG). */
+typedef struct rl_server* rl_server_h;
+
+typedef struct {
+  int32_t is_complex; /* 0: FP64 A, V, U; 1: interleaved complex FP64 */
+  int32_t k;          /* number of smallest triplets */
+  int64_t m, n;
+  const double* A;    /* device, m x n row-major, leading dimension lda */
+  int64_t lda;
+  const rl_opts* opts;/* host, may be NULL (defaults); copied at submit */
+  double* sigma;      /* device, k doubles (ascending) */
+  double* V;          /* device, n x k row-major (ldv) */
+  int64_t ldv;
+  double* U;          /* device, m x k row-major (ldu), or NULL */
+  int64_t ldu;
+} rl_request;
+
+typedef struct {
+  double queued_us;        /* submit -> admitted */
+  double run_us;           /* admitted -> results in the caller's buffers */
+  double latency_us;       /* submit -> results in the caller's buffers */
+  int64_t workspace_bytes; /* device workspace the solve was admitted with */
+} rl_job_times;
+
+/* max_inflight slots (1..64), each with its own stream and worker thread. */
+int rl_server_create(rl_server_h* s, int device, size_t hbm_budget_bytes, int32_t max_inflight);
+/* Queue a solve; *ticket identifies it.  Argument errors as rl_svds_smallest_*,
+ * RL_ERR_ADMISSION if its workspace exceeds the budget, RL_ERR_CANCELLED while
+ * the server shuts down.  Never blocks on device work. */
+int rl_server_submit(rl_server_h s, const rl_request* req, uint64_t* ticket);
+/* *done = 0 and RL_PENDING while the job runs or waits; otherwise *done = 1
+ * and the job's status (as rl_svds_smallest_*), with info (scalar fields; the
+ * history arrays are not filled) and times when non-NULL. */
+int rl_server_poll(rl_server_h s, uint64_t ticket, int32_t* done, rl_info* info, rl_job_times* times);
+/* Block until the job is done (timeout_us < 0: no limit); RL_PENDING if the
+ * time-out expires first, else as rl_server_poll with done = 1. */
+int rl_server_wait(rl_server_h s, uint64_t ticket, int64_t timeout_us, rl_info* info, rl_job_times* times);
+/* Stop accepting, run every queued job to the end, release the slots. */
+int rl_server_destroy(rl_server_h s);
 
 const char* rl_status_string(int code);
 

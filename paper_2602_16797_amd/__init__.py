@@ -25,6 +25,9 @@ RL_ERR_DEVICE = -2
 RL_ERR_NOMEM = -3
 RL_ERR_NONFINITE = -4
 RL_ERR_UNSUPPORTED = -7
+RL_PENDING = 2
+RL_ERR_ADMISSION = -5
+RL_ERR_CANCELLED = -6
 
 RL_SKETCH_F64 = 0
 RL_SKETCH_F32 = 1
@@ -37,6 +40,7 @@ EXPORTED = (
     "rl_svds_smallest_d", "rl_svds_smallest_z",
     "rl_step_sketch", "rl_step_qr", "rl_step_astream", "rl_step_tall_svd",
     "rl_step_sketch_f32", "rl_step_qr_lowp", "rl_status_string",
+    "rl_server_create", "rl_server_submit", "rl_server_poll", "rl_server_wait", "rl_server_destroy",
 )
 
 
@@ -80,6 +84,34 @@ class RlInfo(ctypes.Structure):
     ]
 
 
+class RlRequest(ctypes.Structure):
+    """Mirror of rl_request (include/rlobpcg.h)."""
+    _fields_ = [
+        ("is_complex", ctypes.c_int32),
+        ("k", ctypes.c_int32),
+        ("m", ctypes.c_int64),
+        ("n", ctypes.c_int64),
+        ("A", ctypes.c_void_p),
+        ("lda", ctypes.c_int64),
+        ("opts", ctypes.POINTER(RlOpts)),
+        ("sigma", ctypes.c_void_p),
+        ("V", ctypes.c_void_p),
+        ("ldv", ctypes.c_int64),
+        ("U", ctypes.c_void_p),
+        ("ldu", ctypes.c_int64),
+    ]
+
+
+class RlJobTimes(ctypes.Structure):
+    """Mirror of rl_job_times (include/rlobpcg.h)."""
+    _fields_ = [
+        ("queued_us", ctypes.c_double),
+        ("run_us", ctypes.c_double),
+        ("latency_us", ctypes.c_double),
+        ("workspace_bytes", ctypes.c_int64),
+    ]
+
+
 class RlError(RuntimeError):
     def __init__(self, code: int, what: str):
         self.code = code
@@ -113,6 +145,11 @@ def load_library() -> ctypes.CDLL:
     lib.rl_step_astream.argtypes = [P, ctypes.c_int, I64, I64, P, I64, I32, P, P, P, I32]
     lib.rl_step_tall_svd.argtypes = [P, ctypes.c_int, I64, I32, P, P, P]
     lib.rl_status_string.argtypes = [ctypes.c_int]
+    lib.rl_server_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.c_size_t, I32]
+    lib.rl_server_submit.argtypes = [P, ctypes.POINTER(RlRequest), ctypes.POINTER(U64)]
+    lib.rl_server_poll.argtypes = [P, U64, ctypes.POINTER(I32), ctypes.POINTER(RlInfo), ctypes.POINTER(RlJobTimes)]
+    lib.rl_server_wait.argtypes = [P, U64, I64, ctypes.POINTER(RlInfo), ctypes.POINTER(RlJobTimes)]
+    lib.rl_server_destroy.argtypes = [P]
     lib.rl_status_string.restype = ctypes.c_char_p
     for name in EXPORTED:
         if name != "rl_status_string":
@@ -369,3 +406,86 @@ def rl_step_tall_svd(P):
     if rc != RL_OK:
         raise RlError(rc, "rl_step_tall_svd")
     return sigma, C
+
+
+@dataclass
+class ServedResult:
+    sigma: object
+    V: object
+    U: object
+    status: int
+    iters: int
+    queued_us: float
+    run_us: float
+    latency_us: float
+    workspace_bytes: int
+
+
+class Server:
+    """Continuous-batching server of the C-ABI (rl_server_*): submit solves of
+    different shapes, each admitted when a slot is free and its workspace fits
+    the HBM budget; results come back per ticket."""
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 8, device: int = 0):
+        self.lib = load_library()
+        self.h = ctypes.c_void_p()
+        rc = self.lib.rl_server_create(ctypes.byref(self.h), device, hbm_budget_bytes, max_inflight)
+        if rc != RL_OK:
+            raise RlError(rc, "rl_server_create")
+        self.device = device
+        self._live = {}
+
+    def submit(self, A, k: int, *, want_u: bool = True, **kw) -> int:
+        torch = _torch()
+        _check_matrix(A, torch)
+        m, n = A.shape
+        o = make_opts(m, n, k, **kw)
+        sigma = torch.empty(k, dtype=torch.float64, device=A.device)
+        V = torch.empty((n, k), dtype=A.dtype, device=A.device)
+        U = torch.empty((m, k), dtype=A.dtype, device=A.device) if want_u else None
+        req = RlRequest(is_complex=int(A.dtype == torch.complex128), k=k, m=m, n=n, A=_ptr(A), lda=A.stride(0),
+                        opts=ctypes.pointer(o), sigma=_ptr(sigma), V=_ptr(V), ldv=k,
+                        U=_ptr(U) if U is not None else None, ldu=k)
+        t = ctypes.c_uint64()
+        # the inputs were produced on torch's stream; the server's slots use their own
+        torch.cuda.current_stream(A.device).synchronize()
+        rc = self.lib.rl_server_submit(self.h, ctypes.byref(req), ctypes.byref(t))
+        if rc != RL_OK:
+            raise RlError(rc, "rl_server_submit")
+        self._live[t.value] = (A, sigma, V, U, o)
+        return t.value
+
+    def _result(self, ticket, rc, info, times):
+        A, sigma, V, U, _ = self._live.pop(ticket)
+        if rc not in (RL_OK, RL_NOT_CONVERGED):
+            raise RlError(rc, "served solve")
+        return ServedResult(sigma=sigma, V=V, U=U, status=rc, iters=info.iters, queued_us=times.queued_us,
+                            run_us=times.run_us, latency_us=times.latency_us,
+                            workspace_bytes=times.workspace_bytes)
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        info, times = RlInfo(), RlJobTimes()
+        rc = self.lib.rl_server_wait(self.h, ticket, timeout_us, ctypes.byref(info), ctypes.byref(times))
+        if rc == RL_PENDING:
+            return None
+        return self._result(ticket, rc, info, times)
+
+    def poll(self, ticket: int):
+        done = ctypes.c_int32()
+        info, times = RlInfo(), RlJobTimes()
+        rc = self.lib.rl_server_poll(self.h, ticket, ctypes.byref(done), ctypes.byref(info), ctypes.byref(times))
+        if not done.value:
+            return None
+        return self._result(ticket, rc, info, times)
+
+    def close(self):
+        if self.h:
+            self.lib.rl_server_destroy(self.h)
+            self.h = ctypes.c_void_p()
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -27,7 +27,13 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
 #include <new>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/rlobpcg.h"
@@ -46,6 +52,7 @@ struct rl_ctx {
   int64_t lds_budget = 64 * 1024;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> prof;  // pairs around A-stream launches
+  bool ws_async = false;         // workspace from the stream-ordered allocator (server slots)
 };
 
 static int ensure_prof_events(rl_ctx* h, size_t pairs) {
@@ -146,6 +153,18 @@ static Layout plan(const Problem& p, int64_t lds_budget) {
 
 static int ensure_ws(rl_ctx* h, size_t bytes) {
   if (h->ws_bytes >= bytes) return RL_OK;
+  if (h->ws_async) {
+    // server slots: stream-ordered, so other slots' work is never waited on
+    if (h->ws) (void)hipFreeAsync(h->ws, h->stream);
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+    if (hipMallocAsync(&h->ws, bytes, h->stream) != hipSuccess) {
+      h->ws = nullptr;
+      return RL_ERR_NOMEM;
+    }
+    h->ws_bytes = bytes;
+    return RL_OK;
+  }
   if (h->ws) {
     (void)hipStreamSynchronize(h->stream);
     (void)hipFree(h->ws);
@@ -158,6 +177,14 @@ static int ensure_ws(rl_ctx* h, size_t bytes) {
   }
   h->ws_bytes = bytes;
   return RL_OK;
+}
+
+static void release_ws(rl_ctx* h) {
+  if (!h->ws) return;
+  if (h->ws_async) (void)hipFreeAsync(h->ws, h->stream);
+  else (void)hipFree(h->ws);
+  h->ws = nullptr;
+  h->ws_bytes = 0;
 }
 
 template <typename P>
@@ -183,6 +210,15 @@ static int check_opts(int64_t m, int64_t n, int32_t k, const rl_opts& o) {
     hipError_t _e = (expr);                      \
     if (_e != hipSuccess) return RL_ERR_DEVICE;  \
   } while (0)
+
+// Flags NaN/Inf among n doubles (R^{-1} of a numerically singular sketch).
+__global__ void k_flag_nonfinite(const double* __restrict__ x, int64_t n, Ctl* __restrict__ ctl) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (!isfinite(x[i])) {
+      atomicOr(&ctl->nonfinite, 1);
+      return;
+    }
+}
 
 static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int64_t lda, int32_t k,
                  const rl_opts* opts_in, double* sigma, void* Vout, int64_t ldv, void* Uout, int64_t ldu,
@@ -234,6 +270,12 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
     CK(launch_qr_lowp(st, at<float>(ws, L.Yf), (int)o.d, (int)n, at<float>(ws, L.Tmf), at<double>(ws, L.Y),
                       at<double>(ws, L.Rrow), at<double>(ws, L.RH), at<double>(ws, L.Rinv), at<double>(ws, L.RinvH),
                       o.sketch_prec == RL_SKETCH_BF16));
+  }
+  {
+    const int64_t cnt = n * n * es_d;
+    hipLaunchKernelGGL(k_flag_nonfinite, dim3((unsigned)std::min<int64_t>((cnt + 255) / 256, 1024)), dim3(256), 0,
+                       st, at<double>(ws, L.Rinv), cnt, ctl);
+    CK(hipGetLastError());
   }
   // Sigma~(1,1)
   const int KL = std::min<int>(L.KL, o.lanczos_steps);
@@ -344,6 +386,13 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   return status;
 }
 
+// Workspace bytes one solve of this shape and these options needs (the
+// server's admission unit).
+static int64_t planned_bytes(bool cplx, int64_t m, int64_t n, int32_t k, const rl_opts& o, int64_t lds_budget) {
+  Problem p{m, n, o.d, o.block, k, o.zeta, cplx, (size_t)(cplx ? 16 : 8), o.max_iter, o.sketch_prec};
+  return (int64_t)plan(p, lds_budget).total;
+}
+
 // Transpose a row-major d x n block (doubles per element es) into column-major.
 __global__ void k_rowmajor_to_col_f(const float* __restrict__ Y, int64_t ldy, int64_t d, int64_t n,
                                     float* __restrict__ Yc) {
@@ -377,6 +426,98 @@ __global__ void k_col_to_rowmajor(const double* __restrict__ Yc, int64_t d, int6
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Served form: continuous admission of solves of different shapes.
+//
+// A server owns `slots` worker threads; each has its own stream (default
+// priority) and handle, so the solves in flight overlap on the device: the
+// small latency-bound kernels of one solve run beside the A passes of
+// another.  A submitted request waits in a FIFO queue; a free slot takes the
+// head of the queue as soon as the planned workspaces of the solves in flight
+// plus the head's fit the HBM budget.  Workspaces come from the
+// stream-ordered allocator and are returned when the solve ends, so memory
+// freed by one solve admits the next without a device-wide synchronisation.
+// Every solve runs the same kernels in the same configuration as alone, so its
+// results do not depend on what else is in flight.
+struct rl_job {
+  uint64_t ticket = 0;
+  bool cplx = false;
+  int64_t m = 0, n = 0, lda = 0, ldv = 0, ldu = 0;
+  int32_t k = 0;
+  const void* A = nullptr;
+  double* sigma = nullptr;
+  void* V = nullptr;
+  void* U = nullptr;
+  rl_opts opts{};
+  int64_t bytes = 0;
+  int status = RL_PENDING;
+  bool done = false;
+  rl_info info{};
+  std::chrono::steady_clock::time_point t_submit, t_start, t_end;
+};
+
+struct rl_server {
+  int device = 0;
+  int64_t budget = 0;
+  int64_t in_use = 0;
+  int64_t lds_budget = 64 * 1024;
+  bool stopping = false;
+  uint64_t next_ticket = 1;
+  std::mutex mu;
+  std::condition_variable cv_work;  // workers: a job may be admissible
+  std::condition_variable cv_done;  // waiters: a job finished
+  std::deque<rl_job*> queue;
+  std::unordered_map<uint64_t, rl_job*> jobs;
+  std::vector<std::thread> workers;
+  std::vector<rl_ctx*> ctxs;
+  std::vector<hipStream_t> streams;
+};
+
+static void server_worker(rl_server* s, int slot) {
+  (void)hipSetDevice(s->device);
+  rl_ctx* h = s->ctxs[slot];
+  for (;;) {
+    rl_job* job = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_work.wait(lk, [&] {
+        if (s->queue.empty()) return s->stopping;
+        return s->in_use + s->queue.front()->bytes <= s->budget;
+      });
+      if (s->queue.empty()) return;  // stopping and drained
+      job = s->queue.front();
+      s->queue.pop_front();
+      s->in_use += job->bytes;
+      job->t_start = std::chrono::steady_clock::now();
+    }
+    s->cv_work.notify_all();  // the next head may fit too
+    rl_info info{};
+    const int rc = solve(h, job->cplx, job->m, job->n, job->A, job->lda, job->k, &job->opts, job->sigma, job->V,
+                         job->ldv, job->U, job->ldu, &info);
+    release_ws(h);
+    (void)hipStreamSynchronize(h->stream);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      job->info = info;
+      job->status = rc;
+      job->done = true;
+      job->t_end = std::chrono::steady_clock::now();
+      s->in_use -= job->bytes;
+    }
+    s->cv_work.notify_all();
+    s->cv_done.notify_all();
+  }
+}
+
+static void fill_times(const rl_job* j, rl_job_times* t) {
+  if (!t) return;
+  using us = std::chrono::duration<double, std::micro>;
+  t->queued_us = us(j->t_start - j->t_submit).count();
+  t->run_us = us(j->t_end - j->t_start).count();
+  t->latency_us = us(j->t_end - j->t_submit).count();
+  t->workspace_bytes = j->bytes;
+}
 
 extern "C" {
 
@@ -593,6 +734,144 @@ int rl_step_tall_svd(rl_handle h, int is_complex, int64_t m, int32_t t, const do
   return RL_OK;
 }
 
+int rl_server_create(rl_server_h* out, int device, size_t hbm_budget_bytes, int32_t max_inflight) {
+  if (!out || max_inflight < 1 || max_inflight > 64 || hbm_budget_bytes == 0) return RL_ERR_ARG;
+  *out = nullptr;
+  if (hipSetDevice(device) != hipSuccess) return RL_ERR_DEVICE;
+  rl_server* s = new (std::nothrow) rl_server();
+  if (!s) return RL_ERR_NOMEM;
+  s->device = device;
+  s->budget = (int64_t)hbm_budget_bytes;
+  for (int i = 0; i < max_inflight; ++i) {
+    hipStream_t st = nullptr;
+    rl_handle h = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess || rl_create(&h, device, st) != RL_OK) {
+      if (st) (void)hipStreamDestroy(st);
+      s->stopping = true;
+      rl_server_destroy(s);
+      return RL_ERR_DEVICE;
+    }
+    h->ws_async = true;
+    s->lds_budget = h->lds_budget;
+    s->streams.push_back(st);
+    s->ctxs.push_back(h);
+  }
+  for (int i = 0; i < max_inflight; ++i) s->workers.emplace_back(server_worker, s, i);
+  *out = s;
+  return RL_OK;
+}
+
+int rl_server_submit(rl_server_h s, const rl_request* req, uint64_t* ticket) {
+  if (!s || !req || !ticket) return RL_ERR_ARG;
+  if (!req->A || !req->sigma || !req->V) return RL_ERR_ARG;
+  const bool cplx = req->is_complex != 0;
+  rl_opts o;
+  if (req->opts) o = *req->opts;
+  else rl_default_opts(&o, req->m, req->n, req->k);
+  int rc = check_opts(req->m, req->n, req->k, o);
+  if (rc != RL_OK) return rc;
+  if (req->lda < req->n || req->ldv < req->k || (req->U && req->ldu < req->k)) return RL_ERR_ARG;
+  if (cplx && o.sketch_prec != RL_SKETCH_F64) return RL_ERR_UNSUPPORTED;
+  rl_job* j = new (std::nothrow) rl_job();
+  if (!j) return RL_ERR_NOMEM;
+  j->cplx = cplx;
+  j->m = req->m;
+  j->n = req->n;
+  j->k = req->k;
+  j->A = req->A;
+  j->lda = req->lda;
+  j->sigma = req->sigma;
+  j->V = req->V;
+  j->ldv = req->ldv;
+  j->U = req->U;
+  j->ldu = req->ldu;
+  j->opts = o;
+  j->opts.profile = 0;
+  j->bytes = planned_bytes(cplx, req->m, req->n, req->k, o, s->lds_budget);
+  if (j->bytes > s->budget) {
+    delete j;
+    return RL_ERR_ADMISSION;
+  }
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stopping) {
+      delete j;
+      return RL_ERR_CANCELLED;
+    }
+    j->ticket = s->next_ticket++;
+    j->t_submit = std::chrono::steady_clock::now();
+    s->jobs[j->ticket] = j;
+    s->queue.push_back(j);
+    *ticket = j->ticket;
+  }
+  s->cv_work.notify_all();
+  return RL_OK;
+}
+
+// A finished job is reported once and then forgotten.
+static int take_result(rl_server* s, std::unique_lock<std::mutex>& lk, rl_job* j, rl_info* info,
+                       rl_job_times* times) {
+  (void)lk;
+  const int st = j->status;
+  if (info) {
+    // copy the scalar fields; the server does not fill caller history arrays
+    double* th = info->theta_hist;
+    double* rn = info->rnorm_hist;
+    const int32_t cap = info->hist_cap;
+    *info = j->info;
+    info->theta_hist = th;
+    info->rnorm_hist = rn;
+    info->hist_cap = cap;
+  }
+  fill_times(j, times);
+  s->jobs.erase(j->ticket);
+  delete j;
+  return st;
+}
+
+int rl_server_poll(rl_server_h s, uint64_t ticket, int32_t* done, rl_info* info, rl_job_times* times) {
+  if (!s || !done) return RL_ERR_ARG;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->jobs.find(ticket);
+  if (it == s->jobs.end()) return RL_ERR_ARG;
+  if (!it->second->done) {
+    *done = 0;
+    return RL_PENDING;
+  }
+  *done = 1;
+  return take_result(s, lk, it->second, info, times);
+}
+
+int rl_server_wait(rl_server_h s, uint64_t ticket, int64_t timeout_us, rl_info* info, rl_job_times* times) {
+  if (!s) return RL_ERR_ARG;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->jobs.find(ticket);
+  if (it == s->jobs.end()) return RL_ERR_ARG;
+  rl_job* j = it->second;
+  if (timeout_us < 0) {
+    s->cv_done.wait(lk, [&] { return j->done; });
+  } else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), [&] { return j->done; })) {
+    return RL_PENDING;
+  }
+  return take_result(s, lk, j, info, times);
+}
+
+int rl_server_destroy(rl_server_h s) {
+  if (!s) return RL_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stopping = true;  // queued jobs still run: destroy drains
+  }
+  s->cv_work.notify_all();
+  for (auto& t : s->workers)
+    if (t.joinable()) t.join();
+  for (rl_ctx* h : s->ctxs) rl_destroy(h);
+  for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+  for (auto& kv : s->jobs) delete kv.second;
+  delete s;
+  return RL_OK;
+}
+
 const char* rl_status_string(int code) {
   switch (code) {
     case RL_OK: return "ok";
@@ -602,6 +881,9 @@ const char* rl_status_string(int code) {
     case RL_ERR_NOMEM: return "device allocation failed";
     case RL_ERR_NONFINITE: return "NaN or Inf in the sketch or in R^{-1}";
     case RL_ERR_UNSUPPORTED: return "shape outside the compiled kernels (n > 1024 or b > 10)";
+    case RL_PENDING: return "the served job has not finished";
+    case RL_ERR_ADMISSION: return "the request can never fit the server's HBM budget";
+    case RL_ERR_CANCELLED: return "the server is shutting down";
     default: return "unknown status";
   }
 }

@@ -30,7 +30,8 @@ def test_header_declares_the_boundary():
     names = _declared()
     for must in ("rl_create", "rl_destroy", "rl_default_opts", "rl_svds_smallest_d", "rl_svds_smallest_z",
                  "rl_step_sketch", "rl_step_qr", "rl_step_astream", "rl_step_tall_svd", "rl_status_string",
-                 "rl_step_sketch_f32", "rl_step_qr_lowp"):
+                 "rl_step_sketch_f32", "rl_step_qr_lowp", "rl_server_create", "rl_server_submit",
+                 "rl_server_poll", "rl_server_wait", "rl_server_destroy"):
         assert must in names
 
 
@@ -52,13 +53,17 @@ def test_struct_layout_matches_ctypes(tmp_path):
         "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(rl_opts), sizeof(rl_info),"
         " offsetof(rl_opts, tau), offsetof(rl_opts, lanczos_steps), offsetof(rl_info, sigma1),"
         " offsetof(rl_info, hist_cap), offsetof(rl_info, rnorm_hist));"
-        "printf(\"%zu\\n\", offsetof(rl_opts, sketch_prec));return 0;}\n")
+        "printf(\"%zu\\n\", offsetof(rl_opts, sketch_prec));"
+        "printf(\"%zu %zu %zu %zu\\n\", sizeof(rl_request), offsetof(rl_request, opts), offsetof(rl_request, ldu),"
+        " sizeof(rl_job_times));return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     O, I = rl.RlOpts, rl.RlInfo
     assert vals == [ctypes.sizeof(O), ctypes.sizeof(I), O.tau.offset, O.lanczos_steps.offset, I.sigma1.offset,
-                    I.hist_cap.offset, I.rnorm_hist.offset, O.sketch_prec.offset]
+                    I.hist_cap.offset, I.rnorm_hist.offset, O.sketch_prec.offset,
+                    ctypes.sizeof(rl.RlRequest), rl.RlRequest.opts.offset, rl.RlRequest.ldu.offset,
+                    ctypes.sizeof(rl.RlJobTimes)]
 
 
 def test_host_only_calls():

@@ -17,4 +17,6 @@ from .planted import (  # noqa: F401
     planted_torch,
     integer_matrix,
     served_requests,
+    request_spectrum,
+    config_spectrum,
 )
