@@ -48,6 +48,28 @@ def spectrum(n, k, spec):
     return spectrum_logspace_tail(n, spec[1], spec[2])
 
 
+def measured_traffic(workload: str):
+    """HBM bytes per A-stream launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel of known size),
+    or None when there is none for this workload or the kernel sources have
+    changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"astream_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\s*(\{.*?\})\s*```", open(path).read(), re.S)
+    if not m:
+        return None
+    data = json.loads(m.group(1))
+    h = hashlib.sha256()
+    for f in data["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != data["source_sha256"]:
+        return None
+    return int(data["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(A_dev, k, seed, d, zeta, gpu_iters, budget_s=25.0):
     """The oracle timed on this host: its setup (sketch, SVD, start) plus a few
     LOBPCG iterations on the full input, scaled to the GPU's iteration count."""
@@ -179,6 +201,9 @@ def main(argv=None):
     ap.add_argument("--vs-fp64", action="store_true",
                     help="after timing, solve once with the FP64 sketch and Dot2 products and report the "
                          "difference of the timed variant's sigma and subspace from it")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the solves, copy a 1.6 GB device buffer three times (a plain copy kernel of "
+                         "known size, the reference for the HBM byte counters)")
     ap.add_argument("--served", action="store_true",
                     help="run the served stream (continuous batching) instead of the single-solve workload")
     ap.add_argument("--served-count", type=int, default=256)
@@ -257,10 +282,21 @@ def main(argv=None):
         tot_bytes += (1 + it) * base + it * m * k * es + max(it - 1, 0) * m * k * es
     bytes_launch = tot_bytes / max(n_as, 1)
     achieved = bytes_launch / (avg_us * 1e-6) / 1e9
+    traffic = measured_traffic(args.workload) if (args.sketch_prec == "f64" and not args.no_dot2) else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_astream (A W and A^* A W in one pass)", "avg_launch_us": round(avg_us, 2),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_astream_r2 (A W and A^* [A_V A_X A_W] in one pass)", "avg_launch_us": round(avg_us, 2),
                 "launches": n_as, "algorithmic_bytes_per_launch": round(bytes_launch)}
+
+    if args.copy_calibration:
+        src = torch.empty(200_000_000, dtype=torch.float64, device="cuda")
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 copies of 1.6e9 bytes")
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(TS_TILE) void k_tsqr(const T* __restrict__ P0, int 
 // k_tsqr_w_merge (one workgroup of 16 waves, 8 for complex data or t > 8, the
 // next launch on the stream) reduces those the same way and writes R_T.
 constexpr int TW_THREADS = 256;
-constexpr int TW_TMAX = 16;
+constexpr int TW_TMAX = 32;
 
 template <typename T, int TT>
 __device__ inline T tw_get(const T (&x)[TT], int j) {
@@ -139,9 +139,11 @@ __device__ inline void tw_set(T (&x)[TT], int j, T v) {
 }
 
 // QR of the tile; on return tile rows 0..t-1 hold R (upper triangular) and
-// every other entry of columns 0..t-1 is zero.
+// every other entry of columns 0..t-1 is zero.  For column j the reflector
+// products v^* a_k are formed column by column (x^* a_k is summed over the
+// wave just before a_k is updated), so no array of them is kept.
 template <typename T, int TT, int RPL>
-__device__ void tw_tile_qr(T (&x)[RPL][TT], int t, int lane) {
+__device__ __forceinline__ void tw_tile_qr(T (&x)[RPL][TT], int t, int lane) {
   for (int j = 0; j < t; ++j) {
     T xj[RPL];
     bool below[RPL];
@@ -153,46 +155,38 @@ __device__ void tw_tile_qr(T (&x)[RPL][TT], int t, int lane) {
       if (below[s]) n2p += abs2(xj[s]);
     }
     const double n2 = wave_sum(n2p);
-    T dk[TT];
+    const T alpha = readlane_d(xj[0], j);
+    const bool noref = (n2 == 0.0) && (ts_im(alpha) == 0.0);
+    if (noref) continue;  // the column is already zero below the diagonal
+    const double nrm = sqrt(abs2(alpha) + n2);
+    const double beta = (re_(alpha) >= 0.0) ? -nrm : nrm;
+    const T tau = divs(sub(from_real<T>(beta), alpha), from_real<T>(beta));
+    const T sc = divs(from_real<T>(1.0), sub(alpha, from_real<T>(beta)));
+    const T ct = conj_(tau), csc = conj_(sc);
+    T v[RPL];
+#pragma unroll
+    for (int s = 0; s < RPL; ++s)
+      v[s] = (s == 0 && lane == j) ? from_real<T>(1.0) : (below[s] ? mul(sc, xj[s]) : zero<T>());
 #pragma unroll
     for (int k = 0; k < TT; ++k) {
-      dk[k] = zero<T>();
       if (k > j && k < t) {
         T acc = zero<T>();
 #pragma unroll
         for (int s = 0; s < RPL; ++s)
           if (below[s]) acc = cfmac(xj[s], x[s][k], acc);
-        dk[k] = wave_sum(acc);
+        const T dk = wave_sum(acc);
+        const T ajk = readlane_d(x[0][k], j);
+        const T f = mul(ct, fmac(csc, dk, ajk));
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) x[s][k] = fnmac(f, v[s], x[s][k]);
       }
     }
-    const T alpha = readlane_d(xj[0], j);
-    const bool noref = (n2 == 0.0) && (ts_im(alpha) == 0.0);
-    if (!noref) {
-      const double nrm = sqrt(abs2(alpha) + n2);
-      const double beta = (re_(alpha) >= 0.0) ? -nrm : nrm;
-      const T tau = divs(sub(from_real<T>(beta), alpha), from_real<T>(beta));
-      const T sc = divs(from_real<T>(1.0), sub(alpha, from_real<T>(beta)));
-      const T ct = conj_(tau), csc = conj_(sc);
-      T v[RPL];
 #pragma unroll
-      for (int s = 0; s < RPL; ++s)
-        v[s] = (s == 0 && lane == j) ? from_real<T>(1.0) : (below[s] ? mul(sc, xj[s]) : zero<T>());
-#pragma unroll
-      for (int k = 0; k < TT; ++k) {
-        if (k > j && k < t) {
-          const T ajk = readlane_d(x[0][k], j);
-          const T f = mul(ct, fmac(csc, dk[k], ajk));
-#pragma unroll
-          for (int s = 0; s < RPL; ++s) x[s][k] = fnmac(f, v[s], x[s][k]);
-        }
-      }
-#pragma unroll
-      for (int s = 0; s < RPL; ++s) {
-        T nx = xj[s];
-        if (s == 0 && lane == j) nx = from_real<T>(beta);
-        else if (below[s]) nx = zero<T>();
-        tw_set<T, TT>(x[s], j, nx);
-      }
+    for (int s = 0; s < RPL; ++s) {
+      T nx = xj[s];
+      if (s == 0 && lane == j) nx = from_real<T>(beta);
+      else if (below[s]) nx = zero<T>();
+      tw_set<T, TT>(x[s], j, nx);
     }
   }
 }
@@ -227,22 +221,39 @@ __device__ inline void tw_load(T (&x)[RPL][TT], const Src& src, int64_t g, int64
 // Rows [g0, g1) of the input, tiles of 64*RPL-t fresh rows, wave w of nw
 // takes tiles w, w+nw, ...; x ends as this wave's R.
 template <typename T, int TT, int RPL, typename Src>
-__device__ void tw_rows(T (&x)[RPL][TT], const Src& src, int64_t g0, int64_t g1, int t, int lane, int wave, int nw) {
+__device__ __forceinline__ void tw_rows(T (&x)[RPL][TT], const Src& src, int64_t g0, int64_t g1, int t, int lane, int wave, int nw) {
   const int fresh = 64 * RPL - t;
   const int64_t step = (int64_t)nw * fresh;
   int64_t g = g0 + (int64_t)wave * fresh;
-  T nx[RPL][TT];
-  tw_load<T, TT, RPL>(nx, src, g, g1, t, lane);
-  for (; g < g1; g += step) {
+  // the next tile is loaded ahead when the copy fits the register budget
+  constexpr bool PF = RPL * TT * (int)(sizeof(T) / 8) <= 32;
+  if constexpr (PF) {
+    T nx[RPL][TT];
+    tw_load<T, TT, RPL>(nx, src, g, g1, t, lane);
+    for (; g < g1; g += step) {
 #pragma unroll
-    for (int s = 0; s < RPL; ++s) {
-      if (lane + 64 * s >= t) {
+      for (int s = 0; s < RPL; ++s) {
+        if (lane + 64 * s >= t) {
 #pragma unroll
-        for (int c = 0; c < TT; ++c) x[s][c] = nx[s][c];
+          for (int c = 0; c < TT; ++c) x[s][c] = nx[s][c];
+        }
       }
+      tw_load<T, TT, RPL>(nx, src, g + step, g1, t, lane);
+      tw_tile_qr<T, TT, RPL>(x, t, lane);
     }
-    tw_load<T, TT, RPL>(nx, src, g + step, g1, t, lane);
-    tw_tile_qr<T, TT, RPL>(x, t, lane);
+  } else {
+    for (; g < g1; g += step) {
+      T nx[RPL][TT];
+      tw_load<T, TT, RPL>(nx, src, g, g1, t, lane);
+#pragma unroll
+      for (int s = 0; s < RPL; ++s) {
+        if (lane + 64 * s >= t) {
+#pragma unroll
+          for (int c = 0; c < TT; ++c) x[s][c] = nx[s][c];
+        }
+      }
+      tw_tile_qr<T, TT, RPL>(x, t, lane);
+    }
   }
 }
 
@@ -255,7 +266,7 @@ struct TwRows {  // rows of a row-major n x t array (global or LDS)
 
 // Stack the NW waves' R factors in LDS and factor them in wave 0.
 template <typename T, int TT, int RPL, int NW>
-__device__ void tw_block_merge(T (&x)[RPL][TT], T* Rs, int t, int lane, int wave) {
+__device__ __forceinline__ void tw_block_merge(T (&x)[RPL][TT], T* Rs, int t, int lane, int wave) {
   if (lane < t) {
 #pragma unroll
     for (int c = 0; c < TT; ++c)
@@ -331,11 +342,11 @@ struct TwRpl {
 };
 template <typename T, int TT>
 struct TwMergeWaves {
-  static constexpr int value = (sizeof(T) == 16 || TT > 8) ? 8 : 16;
+  static constexpr int value = TT > 16 ? 4 : ((sizeof(T) == 16 || TT > 8) ? 8 : 16);
 };
 
 static int64_t tsqr_w_groups(int64_t m, int t, bool cplx) {
-  const int tt = t <= 4 ? 4 : (t <= 8 ? 8 : 16);
+  const int tt = t <= 4 ? 4 : (t <= 8 ? 8 : (t <= 16 ? 16 : 32));
   int rpl = tt <= 4 ? 4 : (tt <= 8 ? 2 : 1);
   if (cplx) rpl = rpl > 1 ? rpl / 2 : 1;
   const int64_t fresh = 64 * rpl - t;
@@ -386,7 +397,8 @@ static hipError_t tsqr_impl(hipStream_t st, const T* P0, int b0, const T* P1, in
     const int64_t g = tsqr_w_groups(m, t, sizeof(T) == 16);
     if (t <= 4) tsqr_w_go<T, 4>(st, P0, b0, P1, b1, P2, b2, m, g, bufA, bufB, ctl, check_done);
     else if (t <= 8) tsqr_w_go<T, 8>(st, P0, b0, P1, b1, P2, b2, m, g, bufA, bufB, ctl, check_done);
-    else tsqr_w_go<T, 16>(st, P0, b0, P1, b1, P2, b2, m, g, bufA, bufB, ctl, check_done);
+    else if (t <= 16) tsqr_w_go<T, 16>(st, P0, b0, P1, b1, P2, b2, m, g, bufA, bufB, ctl, check_done);
+    else tsqr_w_go<T, 32>(st, P0, b0, P1, b1, P2, b2, m, g, bufA, bufB, ctl, check_done);
     *Rfinal = bufB;
     return hipGetLastError();
   }
