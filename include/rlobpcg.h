@@ -159,6 +159,18 @@ int rl_step_qr_lowp(rl_handle h, int64_t d, int64_t n, const float* Y, int64_t l
 int rl_step_astream(rl_handle h, int is_complex, int64_t m, int64_t n, const double* A, int64_t lda, int32_t b,
                     const double* W, double* AW, double* G, int32_t dot2);
 
+/* The same pass in the form every LOBPCG iteration after the first uses
+ * (Alg. rlopcg, Sec. 3.3: one read of A gives A W and the Gram data
+ * A^* [A_V A_X A_W] of the Rayleigh-Ritz step): AW = A W and
+ * G3 = [A^* AV | A^* AX | A^* AW].  W device n x b; AV, AX, AW device m x b;
+ * G3 device 3 x n x b, the three n x b blocks one after the other (all
+ * row-major, dense).  AX may be NULL (no previous direction yet): then the
+ * middle block is zero.  dot2 = 1 accumulates A W and A^* AV as Dot2 sums.
+ * RL_ERR_ARG on a NULL required pointer or bad size, RL_ERR_UNSUPPORTED for
+ * n > 1024 or b > 10. */
+int rl_step_astream_iter(rl_handle h, int is_complex, int64_t m, int64_t n, const double* A, int64_t lda, int32_t b,
+                         const double* W, const double* AV, const double* AX, double* AW, double* G3, int32_t dot2);
+
 /* Rayleigh-Ritz data of a tall m x t block P (row-major, dense, t <= 32):
  * singular values (descending, device t doubles) and right singular vectors
  * C (device t x t row-major, column j <-> sigma[j]) via TSQR + one-sided Jacobi

@@ -38,7 +38,7 @@ STOP_RULES = {"paper": 0, "tol": 1, "none": 2}
 EXPORTED = (
     "rl_create", "rl_destroy", "rl_set_stream", "rl_default_opts",
     "rl_svds_smallest_d", "rl_svds_smallest_z",
-    "rl_step_sketch", "rl_step_qr", "rl_step_astream", "rl_step_tall_svd",
+    "rl_step_sketch", "rl_step_qr", "rl_step_astream", "rl_step_astream_iter", "rl_step_tall_svd",
     "rl_step_sketch_f32", "rl_step_qr_lowp", "rl_status_string",
     "rl_server_create", "rl_server_submit", "rl_server_poll", "rl_server_wait", "rl_server_destroy",
 )
@@ -143,6 +143,7 @@ def load_library() -> ctypes.CDLL:
     lib.rl_step_sketch_f32.argtypes = [P, I64, I64, P, I64, I64, I32, U64, P, I64]
     lib.rl_step_qr_lowp.argtypes = [P, I64, I64, P, I64, I32, P, P]
     lib.rl_step_astream.argtypes = [P, ctypes.c_int, I64, I64, P, I64, I32, P, P, P, I32]
+    lib.rl_step_astream_iter.argtypes = [P, ctypes.c_int, I64, I64, P, I64, I32, P, P, P, P, P, I32]
     lib.rl_step_tall_svd.argtypes = [P, ctypes.c_int, I64, I32, P, P, P]
     lib.rl_status_string.argtypes = [ctypes.c_int]
     lib.rl_server_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.c_size_t, I32]
@@ -393,6 +394,27 @@ def rl_step_astream(A, W, dot2: bool = False):
     if rc != RL_OK:
         raise RlError(rc, "rl_step_astream")
     return AW, G
+
+
+def rl_step_astream_iter(A, W, AV, AX=None, dot2: bool = False):
+    """AW = A W and G3 = [A^* AV | A^* AX | A^* AW] (3 x n x b) in one pass."""
+    torch = _torch()
+    _check_matrix(A, torch)
+    m, n = A.shape
+    W, AV = W.contiguous(), AV.contiguous()
+    b = W.shape[1]
+    if AV.shape != (m, b) or (AX is not None and AX.shape != (m, b)) or W.shape != (n, b):
+        raise ValueError("rl_step_astream_iter: W must be n x b, AV and AX m x b")
+    if AX is not None:
+        AX = AX.contiguous()
+    h = handle(A.device.index or 0)
+    AW = torch.empty((m, b), dtype=A.dtype, device=A.device)
+    G3 = torch.empty((3, n, b), dtype=A.dtype, device=A.device)
+    rc = h.lib.rl_step_astream_iter(h.h, int(A.is_complex()), m, n, _ptr(A), A.stride(0), b, _ptr(W), _ptr(AV),
+                                    _ptr(AX) if AX is not None else None, _ptr(AW), _ptr(G3), int(bool(dot2)))
+    if rc != RL_OK:
+        raise RlError(rc, "rl_step_astream_iter")
+    return AW, G3
 
 
 def rl_step_tall_svd(P):

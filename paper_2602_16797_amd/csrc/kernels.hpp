@@ -28,6 +28,13 @@ int64_t astream_blocks(int64_t m, int n, int B, int es_d);
 int64_t astream_part_doubles(int64_t m, int n, int B, int es_d);
 int64_t astream_tmp_doubles(int64_t m, int n, int B, int es_d);
 int64_t astream_r2_blocks(int64_t m);
+int astream_ccs_waves(int n);
+bool astream_ccs_fits(int B, int n, bool aligned);
+void astream_ccs_groups(int B, bool dot2, int* ng, int* bs);
+int64_t astream_ccs_ranges(int64_t m, int n, int B, bool dot2);
+bool dispatch_astream_ccs(bool dot2, int init, int B, hipStream_t st, int64_t nrb, const void* A, int64_t lda,
+                          int64_t m, int n, const void* W, void* AW, const void* AVp, const void* AXp,
+                          double* Gpart, const Ctl* ctl);
 int astream_cs_waves(int n);
 bool astream_cs_fits(int B, int n, bool aligned);
 int64_t astream_cs_blocks(int64_t m, int n);

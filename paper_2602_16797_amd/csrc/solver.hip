@@ -715,6 +715,24 @@ int rl_step_astream(rl_handle h, int is_complex, int64_t m, int64_t n, const dou
   return RL_OK;
 }
 
+int rl_step_astream_iter(rl_handle h, int is_complex, int64_t m, int64_t n, const double* A, int64_t lda, int32_t b,
+                         const double* W, const double* AV, const double* AX, double* AW, double* G3, int32_t dot2) {
+  if (!h || !A || !W || !AV || !AW || !G3 || m < 1 || n < 1 || lda < n || b < 1) return RL_ERR_ARG;
+  if (n > 1024 || b > 10) return RL_ERR_UNSUPPORTED;
+  if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;
+  const int es = is_complex ? 2 : 1;
+  Arena a;
+  const size_t o_part = a.take(sizeof(double) * astream_part_doubles(m, (int)n, b, es)),
+               o_tmp = a.take(sizeof(double) * astream_tmp_doubles(m, (int)n, b, es));
+  int rc = ensure_ws(h, a.off + 256);
+  if (rc != RL_OK) return rc;
+  hipStream_t st = h->stream;
+  CK(launch_astream(st, is_complex != 0, b, dot2 != 0, A, lda, m, (int)n, W, AW, AV, AX, 0,
+                    at<double>(h->ws, o_part), at<double>(h->ws, o_tmp), G3, nullptr));
+  CK(hipStreamSynchronize(st));
+  return RL_OK;
+}
+
 int rl_step_tall_svd(rl_handle h, int is_complex, int64_t m, int32_t t, const double* P, double* sigma, double* C) {
   if (!h || !P || !sigma || !C || m < 1 || t < 1 || t > 32) return RL_ERR_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;

@@ -17,6 +17,7 @@
 // same kernel reduces again until one R_T remains.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "tr_reduce.hpp"
 
 namespace rl {
 
@@ -374,6 +375,218 @@ static void tsqr_w_go(hipStream_t st, const T* P0, int b0, const T* P1, int b1, 
                      bufB, ctl, check_done);
 }
 
+// ---------------------------------------------------------------------------
+// Column-wave TSQR for 16 < t <= 32: one tile of 64*RPL rows per workgroup of
+// NW waves, held in registers with the columns dealt out over the waves (wave
+// w owns columns w, w+NW, ...; lane l holds tile rows l + 64 s, s < RPL).  The
+// tile is NW times taller than a one-wave tile, so the t rows of running R
+// take a small share of it, and no wave holds more than TT/NW columns.
+//
+// Column j is factored by its owner wave (one wave reduction for |x|^2), which
+// publishes the Householder vector and conj(tau) in LDS; after one barrier
+// every wave applies the reflector to its own columns k > j: the products
+// v^* a_k of all its columns are summed in one transpose-reduction, broadcast
+// with readlanes and used for the rank-one update.  The owner of column j+1
+// factors it right after applying reflector j, so one barrier per column
+// suffices (the vector buffer alternates between two slots).
+//
+// The first tile of a row range fills all 64*RPL rows; later tiles keep R in
+// rows 0..t-1 and take 64*RPL-t fresh rows.  One R per workgroup is written;
+// the stacked R factors are reduced by the same kernel in further launches
+// until one remains.
+template <typename T, int TT, int NW, int RPL>
+struct CwShape {
+  static constexpr int CPW = TT / NW;                       // columns per wave
+  static constexpr int RT = 64 * RPL;                       // tile rows
+  static constexpr int NV = CPW * (int)(sizeof(T) / 8);     // reals reduced per column
+  static constexpr int LOG2NV = NV <= 1 ? 0 : NV <= 2 ? 1 : NV <= 4 ? 2 : NV <= 8 ? 3 : NV <= 16 ? 4 : 5;
+};
+
+template <typename T, int TT, int NW, int RPL>
+__global__ __launch_bounds__(NW * 64) void k_tsqr_cw(const T* __restrict__ P0, int b0, const T* __restrict__ P1,
+                                                     int b1, const T* __restrict__ P2, int b2, int64_t m,
+                                                     int64_t rows_per_block, T* __restrict__ Rout,
+                                                     const Ctl* __restrict__ ctl, int check_done) {
+  if (check_done && ctl->done) return;
+  using SH = CwShape<T, TT, NW, RPL>;
+  constexpr int CPW = SH::CPW, RT = SH::RT, NV = SH::NV, LOG2NV = SH::LOG2NV;
+  constexpr int ES = (int)(sizeof(T) / 8);
+  __shared__ T vbuf[2][RT];
+  __shared__ T tbuf[2];
+  const int t = b0 + b1 + b2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t g0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t g1 = (g0 + rows_per_block < m) ? g0 + rows_per_block : m;
+  const TwPanels<T> src{P0, P1, P2, b0, b1, b2};
+  T x[CPW][RPL];
+#pragma unroll
+  for (int kc = 0; kc < CPW; ++kc)
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) x[kc][s] = zero<T>();
+
+  // owner of column j factors it (its slot kc holds column j)
+  auto factor = [&](T (&col)[RPL], int j, int slot) {
+    double n2p = 0.0;
+#pragma unroll
+    for (int s = 0; s < RPL; ++s)
+      if (lane + 64 * s > j) n2p += abs2(col[s]);
+    const double n2 = wave_sum(n2p);
+    const T alpha = readlane_d(col[0], j);
+    if (n2 == 0.0 && ts_im(alpha) == 0.0) {  // already zero below the diagonal
+      if (lane == 0) tbuf[slot] = zero<T>();
+      return;
+    }
+    const double nrm = sqrt(abs2(alpha) + n2);
+    const double beta = (re_(alpha) >= 0.0) ? -nrm : nrm;
+    const T tau = divs(sub(from_real<T>(beta), alpha), from_real<T>(beta));
+    const T sc = divs(from_real<T>(1.0), sub(alpha, from_real<T>(beta)));
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+      const int r = lane + 64 * s;
+      const T vs = (r > j) ? mul(sc, col[s]) : (r == j ? from_real<T>(1.0) : zero<T>());
+      vbuf[slot][r] = vs;
+      if (r > j) col[s] = zero<T>();
+      else if (r == j) col[s] = from_real<T>(beta);
+    }
+    if (lane == 0) tbuf[slot] = conj_(tau);
+  };
+
+  bool first = true;
+  for (int64_t g = g0; g < g1;) {
+    // load the tile: all rows the first time, rows t.. afterwards
+    const int r0 = first ? 0 : t;
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+      const int r = lane + 64 * s;
+      const int64_t row = g + (r - r0);
+      const bool valid = r >= r0 && row < g1;
+#pragma unroll
+      for (int kc = 0; kc < CPW; ++kc) {
+        const int c = wave + NW * kc;
+        if (r >= r0) x[kc][s] = (valid && c < t) ? src.get(row, c) : zero<T>();
+      }
+    }
+    g += RT - r0;
+    first = false;
+    // column 0 belongs to wave 0, slot 0
+    if (wave == 0) factor(x[0], 0, 0);
+#pragma unroll
+    for (int jc = 0; jc < CPW; ++jc) {
+      for (int ow = 0; ow < NW; ++ow) {
+        const int j = NW * jc + ow;
+        if (j >= t) break;
+        __syncthreads();
+        const T ct = tbuf[j & 1];
+        if (!(re_(ct) == 0.0 && ts_im(ct) == 0.0)) {
+          T v[RPL];
+#pragma unroll
+          for (int s = 0; s < RPL; ++s) v[s] = vbuf[j & 1][lane + 64 * s];
+          double ys[NV];
+#pragma unroll
+          for (int q = 0; q < NV; ++q) ys[q] = 0.0;
+#pragma unroll
+          for (int kc = 0; kc < CPW; ++kc) {
+            const int k = wave + NW * kc;
+            if (k > j && k < t) {
+              T acc = zero<T>();
+#pragma unroll
+              for (int s = 0; s < RPL; ++s) acc = cfmac(v[s], x[kc][s], acc);
+              if constexpr (ES == 2) {
+                ys[2 * kc] = re_(acc);
+                ys[2 * kc + 1] = ts_im(acc);
+              } else {
+                ys[kc] = re_(acc);
+              }
+            }
+          }
+          tr_reduce_plain<NV, LOG2NV>(ys, lane);
+#pragma unroll
+          for (int kc = 0; kc < CPW; ++kc) {
+            const int k = wave + NW * kc;
+            if (k > j && k < t) {
+              T d;
+              if constexpr (ES == 2) {
+                d = T{readlane_d(ys[0], tr_src_lane<LOG2NV>(2 * kc)), readlane_d(ys[0], tr_src_lane<LOG2NV>(2 * kc + 1))};
+              } else {
+                d = readlane_d(ys[0], tr_src_lane<LOG2NV>(kc));
+              }
+              const T f = mul(ct, d);
+#pragma unroll
+              for (int s = 0; s < RPL; ++s) x[kc][s] = fnmac(f, v[s], x[kc][s]);
+            }
+          }
+        }
+        // the owner of column j + 1 factors it
+        const int j1 = j + 1;
+        if (j1 < t && wave == (ow + 1) % NW) {
+          if (ow + 1 < NW) factor(x[jc], j1, j1 & 1);
+          else if (jc + 1 < CPW) factor(x[jc + 1 < CPW ? jc + 1 : jc], j1, j1 & 1);
+        }
+      }
+    }
+    __syncthreads();  // the vector buffer is rewritten by the next tile
+  }
+  // R: rows 0..t-1 (lanes 0..t-1 of the first register row)
+  if (lane < t) {
+#pragma unroll
+    for (int kc = 0; kc < CPW; ++kc) {
+      const int c = wave + NW * kc;
+      if (c < t) Rout[((int64_t)blockIdx.x * t + lane) * t + c] = x[kc][0];
+    }
+  }
+}
+
+template <typename T>
+struct CwCfg {  // waves, rows per lane of the column-wave TSQR
+  static constexpr int NW = 4;
+  static constexpr int RPL = sizeof(T) == 16 ? 4 : 8;
+};
+
+static int64_t tsqr_cw_fresh(int t, bool cplx) { return 64 * (cplx ? CwCfg<cd>::RPL : CwCfg<double>::RPL) - t; }
+
+// row ranges of the first launch: two tiles or more each, at most 512
+static int64_t tsqr_cw_groups(int64_t m, int t, bool cplx) {
+  const int64_t fresh = tsqr_cw_fresh(t, cplx);
+  int64_t g = (m + 2 * fresh - 1) / (2 * fresh);
+  if (g > 512) g = 512;
+  return g < 1 ? 1 : g;
+}
+
+template <typename T>
+static hipError_t tsqr_cw_impl(hipStream_t st, const T* P0, int b0, const T* P1, int b1, const T* P2, int b2,
+                               int64_t m, T* bufA, T* bufB, T** Rfinal, const Ctl* ctl, int check_done) {
+  constexpr int NW = CwCfg<T>::NW, RPL = CwCfg<T>::RPL;
+  const int t = b0 + b1 + b2;
+  const bool cplx = sizeof(T) == 16;
+  if (P1 == nullptr) P1 = P0;
+  if (P2 == nullptr) P2 = P0;
+  int64_t g = tsqr_cw_groups(m, t, cplx);
+  int64_t rows = (m + g - 1) / g;
+  hipLaunchKernelGGL((k_tsqr_cw<T, 32, NW, RPL>), dim3((unsigned)g), dim3(NW * 64), 0, st, P0, b0, P1, b1, P2, b2, m,
+                     rows, bufA, ctl, check_done);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  T* cur = bufA;
+  T* nxt = bufB;
+  // reduce the stacked factors until one remains
+  while (g > 1) {
+    const int64_t mm = g * t;
+    int64_t g2 = tsqr_cw_groups(mm, t, cplx);
+    if (g2 >= g) g2 = g / 2 > 0 ? g / 2 : 1;
+    rows = (mm + g2 - 1) / g2;
+    hipLaunchKernelGGL((k_tsqr_cw<T, 32, NW, RPL>), dim3((unsigned)g2), dim3(NW * 64), 0, st, (const T*)cur, t,
+                       (const T*)cur, 0, (const T*)cur, 0, mm, rows, nxt, ctl, check_done);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    T* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+    g = g2;
+  }
+  *Rfinal = cur;
+  return hipSuccess;
+}
+
 static int64_t tsqr_lds_groups(int64_t m, int t) {
   const int64_t per = 4 * (int64_t)(TS_TILE - t);
   int64_t g = (m + per - 1) / per;
@@ -385,7 +598,8 @@ static int64_t tsqr_lds_groups(int64_t m, int t) {
 // Upper bound on the partial R factors of one TSQR launch (workspace sizing).
 int64_t tsqr_groups(int64_t m, int t) {
   const int64_t a = tsqr_lds_groups(m, t), b = (t <= TW_TMAX) ? tsqr_w_groups(m, t, true) : 1;
-  return a > b ? a : b;
+  const int64_t c = std::max(tsqr_cw_groups(m, t, true), tsqr_cw_groups(m, t, false));
+  return std::max(a, std::max(b, c));
 }
 
 template <typename T>
@@ -393,6 +607,7 @@ static hipError_t tsqr_impl(hipStream_t st, const T* P0, int b0, const T* P1, in
                             T* bufA, T* bufB, T** Rfinal, Ctl* ctl, int check_done) {
   const int t = b0 + b1 + b2;
   if (t < 1 || t > TS_TMAX) return hipErrorInvalidValue;
+  if (t > 16 && t <= 32) return tsqr_cw_impl<T>(st, P0, b0, P1, b1, P2, b2, m, bufA, bufB, Rfinal, ctl, check_done);
   if (t <= TW_TMAX) {
     const int64_t g = tsqr_w_groups(m, t, sizeof(T) == 16);
     if (t <= 4) tsqr_w_go<T, 4>(st, P0, b0, P1, b1, P2, b2, m, g, bufA, bufB, ctl, check_done);

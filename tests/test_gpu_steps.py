@@ -110,6 +110,81 @@ def test_astream(rl, m, n, b, cplx, dot2):
         assert np.all(np.abs(G - G2) <= gb2)
 
 
+def _rand(rng, shape, cplx):
+    x = rng.standard_normal(shape)
+    return x + 1j * rng.standard_normal(shape) if cplx else x
+
+
+# one case per kernel family: real column-pair rows (n <= 256, b <= 2, even
+# lda), real column split, complex column split (b split into vector groups,
+# remainders of 1, 2 and 3), real generic (odd lda)
+@pytest.mark.parametrize("m,n,b,cplx,dot2,with_x", [
+    (5003, 37, 1, False, True, True), (20000, 200, 2, False, False, True),
+    (4001, 700, 7, False, True, True), (3000, 1024, 10, False, False, False),
+    (2049, 65, 2, True, True, True), (3001, 1000, 10, True, True, True), (3001, 1000, 10, True, False, True),
+    (5000, 777, 7, True, False, False), (1234, 1024, 5, True, True, True), (40, 64, 3, True, False, True),
+    (7777, 513, 5, False, True, True)])
+def test_astream_iter(rl, m, n, b, cplx, dot2, with_x):
+    """Iteration form of the pass: A W and A^* [A_V A_X A_W] from one read of A."""
+    banner(f"astream_iter m={m} n={n} b={b} complex={cplx} dot2={dot2} AX={with_x}")
+    rng = np.random.default_rng(7 * m + n + b)
+    A, W = _rand(rng, (m, n), cplx), _rand(rng, (n, b), cplx)
+    AV, AX = _rand(rng, (m, b), cplx), _rand(rng, (m, b), cplx)
+    dev = lambda x: torch.from_numpy(x).cuda()
+    AW, G3 = rl.rl_step_astream_iter(dev(A), dev(W), dev(AV), dev(AX) if with_x else None, dot2=dot2)
+    AW, G3 = to_np(AW), to_np(G3)
+    absA = np.abs(A)
+    if dot2:
+        ref = eft.matmul(A, W)
+        assert np.all(np.abs(AW - ref) <= 2 * U * np.abs(ref) + 4 * (n * U) ** 2 * (absA @ np.abs(W)))
+    else:
+        assert np.all(np.abs(AW - A @ W) <= 2 * n * U * (absA @ np.abs(W)))
+    # block 0: A^* A_V (Dot2-class with dot2), block 1: A^* A_X or zero,
+    # block 2: A^* A_W of the returned A_W
+    if dot2:
+        G1 = eft.matmul_h(A, AV)
+        assert np.all(np.abs(G3[0] - G1) <= 2 * U * np.abs(G1)
+                      + 4 * (np.log2(2 * m) * U) ** 2 * (absA.T @ np.abs(AV)))
+    else:
+        assert np.all(np.abs(G3[0] - A.conj().T @ AV) <= 2 * m * U * (absA.T @ np.abs(AV)))
+    if with_x:
+        assert np.all(np.abs(G3[1] - A.conj().T @ AX) <= 2 * m * U * (absA.T @ np.abs(AX)))
+    else:
+        assert np.all(G3[1] == 0)
+    assert np.all(np.abs(G3[2] - A.conj().T @ AW) <= 2 * m * U * (absA.T @ np.abs(AW)))
+
+
+def test_astream_misaligned_complex(rl):
+    """A complex A whose base address is 8 bytes off a 16-byte boundary takes
+    the generic complex kernel; same results as the aligned copy."""
+    m, n, b = 3001, 300, 3
+    rng = np.random.default_rng(99)
+    A, W = _rand(rng, (m, n), True), _rand(rng, (n, b), True)
+    AV = _rand(rng, (m, b), True)
+    buf = torch.zeros(2 * m * n + 1, dtype=torch.float64, device="cuda")
+    view = buf[1:].view(m, n, 2)
+    view.copy_(torch.from_numpy(np.stack([A.real, A.imag], axis=-1)).cuda())
+    Wd, AVd = torch.from_numpy(W).cuda(), torch.from_numpy(AV).cuda()
+    AW = torch.empty((m, b), dtype=torch.complex128, device="cuda")
+    G3 = torch.empty((3, n, b), dtype=torch.complex128, device="cuda")
+    h = rl.handle(0)
+    ptr = buf.data_ptr() + 8
+    assert ptr % 16 == 8
+    import ctypes
+    rc = h.lib.rl_step_astream_iter(h.h, 1, m, n, ctypes.c_void_p(ptr), n, b, ctypes.c_void_p(Wd.data_ptr()),
+                                    ctypes.c_void_p(AVd.data_ptr()), None, ctypes.c_void_p(AW.data_ptr()),
+                                    ctypes.c_void_p(G3.data_ptr()), 0)
+    assert rc == rl.RL_OK
+    torch.cuda.synchronize()
+    AW2, G32 = rl.rl_step_astream_iter(torch.from_numpy(A).cuda(), Wd, AVd, None, dot2=False)
+    AW, G3, AW2, G32 = to_np(AW), to_np(G3), to_np(AW2), to_np(G32)
+    absA = np.abs(A)
+    bound = 2 * n * U * (absA @ np.abs(W))
+    assert np.all(np.abs(AW - A @ W) <= bound) and np.all(np.abs(AW2 - A @ W) <= bound)
+    assert np.all(np.abs(G3[0] - A.conj().T @ AV) <= 2 * m * U * (absA.T @ np.abs(AV)))
+    assert np.all(G3[1] == 0)
+
+
 def test_astream_cancellation_needs_dot2(rl):
     """On a graded A with A w tiny, Dot2 gives A w to full relative accuracy."""
     m, n = 4000, 200
@@ -127,7 +202,12 @@ def test_astream_cancellation_needs_dot2(rl):
 @pytest.mark.parametrize("m,t,cplx", [(100_000, 3, False), (20_000, 15, False), (5000, 30, True),
                                       (777, 2, False), (300, 1, True), (4096, 32, False),
                                       (1_000_000, 3, False), (20, 16, False), (64, 16, True), (65, 8, False),
-                                      (123_457, 6, True), (40_000, 16, False)])
+                                      (123_457, 6, True), (40_000, 16, False),
+                                      # column-wave kernel (16 < t <= 32): one tile, several tiles,
+                                      # several levels of stacked factors
+                                      (17, 17, True), (31, 31, False), (129, 18, False), (1000, 20, True),
+                                      (50_000, 32, True), (300_000, 24, False), (200_000, 30, True),
+                                      (1_000_000, 30, False)])
 def test_tall_svd(rl, m, t, cplx):
     banner(f"tall svd m={m} t={t} complex={cplx}")
     rng = np.random.default_rng(m + t)
