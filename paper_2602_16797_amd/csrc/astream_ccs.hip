@@ -66,7 +66,7 @@ __global__ __launch_bounds__(1024) void k_astream_ccs(const cd* __restrict__ A, 
   __shared__ double sp[2][CCS_MAXW][V];
   __shared__ double ep[DOT2 ? 2 : 1][DOT2 ? CCS_MAXW : 1][DOT2 ? V : 1];
   const int nw = blockDim.x >> 6;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_index();
   const bool has_x = AXp != nullptr;
   const int c = lane + 64 * wave;
   int my_idx = 0;

@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void k_astream(const T* __restrict__ A, int64_
                                                  const Ctl* __restrict__ ctl) {
   if (ctl != nullptr && ctl->done) return;
   constexpr int RB = RowsPerBatch<B>::value;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_index();
   const bool has_v = AVp != nullptr, has_x = AXp != nullptr;
   T w[NS][B];
   T g1s[NS][B], g1e[NS][B], gx[NS][B], gw[NS][B];
@@ -183,31 +183,38 @@ __global__ __launch_bounds__(256) void k_astream(const T* __restrict__ A, int64_
 
 template <int B>
 struct BatchShape {
-  static constexpr int RB = 2;  // rows per wave batch
+  // rows per wave batch: the transpose-reduction of a batch costs about one
+  // butterfly stage per value plus log2(64 / values) stages, so more rows per
+  // batch amortise the all-reduce stages
+  static constexpr int RB = 4;
   static constexpr int V = RB * B;
   static constexpr int V2 = V <= 1 ? 1 : V <= 2 ? 2 : V <= 4 ? 4 : V <= 8 ? 8 : V <= 16 ? 16 : V <= 32 ? 32 : 64;
   static constexpr int LOG2V = V2 == 1 ? 0 : V2 == 2 ? 1 : V2 == 4 ? 2 : V2 == 8 ? 3 : V2 == 16 ? 4 : V2 == 32 ? 5 : 6;
 };
 
 // rows [rb, rb+RB) of the wave's batch, columns (2 lane + 128 s, +1); zero
-// outside [.., r1) and past column n.  A must be 16-byte aligned with even lda.
+// for rows at or past r1.  n is even, A 16-byte aligned with even lda.  A lane
+// whose column pair lies past n reads pair 0 of the same row instead (cl[s]);
+// its W entries are zero, so it adds nothing to the row sums, and its column
+// sums are never written.  Row validity is wave-uniform, so the only branch
+// is a scalar one.
 template <int RB>
-__device__ inline void r2_load(double2 (&a)[RB][2], const double* __restrict__ A, int64_t lda, int n, int64_t rb,
-                               int64_t r1, int lane) {
+__device__ inline void r2_load(double2 (&a)[RB][2], const double* __restrict__ A, int64_t lda, const int (&cl)[2],
+                               int64_t rb, int64_t r1) {
 #pragma unroll
   for (int q = 0; q < RB; ++q) {
     const int64_t row = rb + q;
+    if (row < r1) {
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const int c = 2 * lane + 128 * s;
-      if (row < r1 && c + 1 < n) a[q][s] = *reinterpret_cast<const double2*>(A + row * lda + c);
-      else if (row < r1 && c < n) a[q][s] = make_double2(A[row * lda + c], 0.0);
-      else a[q][s] = make_double2(0.0, 0.0);
+      for (int s = 0; s < 2; ++s) a[q][s] = *reinterpret_cast<const double2*>(A + row * lda + cl[s]);
+    } else {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) a[q][s] = make_double2(0.0, 0.0);
     }
   }
 }
 
-// Real data, n <= 256, b <= 2, 16-byte aligned rows: lane l owns the column
+// Real data, even n <= 256, b <= 2, 16-byte aligned rows: lane l owns the column
 // pairs (2l, 2l+1) and (2l+128, 2l+129).  Each wave walks batches of RB rows
 // and loads the next batch before it works on the current one.  The row sums
 // of the batch are reduced together by the compensated transpose-reduction
@@ -225,7 +232,7 @@ __global__ __launch_bounds__(256) void k_astream_r2(const double* __restrict__ A
   using SH = BatchShape<B>;
   constexpr int RB = SH::RB, V = SH::V, V2 = SH::V2, LOG2V = SH::LOG2V;
   __shared__ double red[4][2][256 * B];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_index();
   const bool has_x = AXp != nullptr;
   double2 w[2][B];
   double2 g1s[2][B], g1e[2][B], gx[2][B], gw[2][B];
@@ -245,8 +252,11 @@ __global__ __launch_bounds__(256) void k_astream_r2(const double* __restrict__ A
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t r1 = (r0 + rows_per_block < m) ? r0 + rows_per_block : m;
   int64_t rb = r0 + (int64_t)wave * RB;
+  int cl[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) cl[s] = (2 * lane + 128 * s < n) ? 2 * lane + 128 * s : 0;
   double2 a[RB][2], an[RB][2];
-  r2_load<RB>(an, A, lda, n, rb, r1, lane);
+  r2_load<RB>(an, A, lda, cl, rb, r1);
   double avn = 0.0, axn = 0.0;
   if (!INIT && lane < V && rb + lane / B < r1) {
     avn = AVp[rb * B + lane];
@@ -260,7 +270,7 @@ __global__ __launch_bounds__(256) void k_astream_r2(const double* __restrict__ A
     }
     const double avl = avn, axl = axn;
     const int64_t rn = rb + 4 * RB;
-    r2_load<RB>(an, A, lda, n, rn, r1, lane);
+    r2_load<RB>(an, A, lda, cl, rn, r1);
     if (!INIT) {
       avn = 0.0;
       axn = 0.0;
@@ -284,7 +294,9 @@ __global__ __launch_bounds__(256) void k_astream_r2(const double* __restrict__ A
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
           if constexpr (DOT2) {
-            dot2_add(a[q][s].x, w[s][j].x, ys[v], ye[v]);
+            // the first product starts the pair exactly
+            if (s == 0) two_prod(a[q][s].x, w[s][j].x, ys[v], ye[v]);
+            else dot2_add(a[q][s].x, w[s][j].x, ys[v], ye[v]);
             dot2_add(a[q][s].y, w[s][j].y, ys[v], ye[v]);
           } else {
             ys[v] = fma(a[q][s].x, w[s][j].x, ys[v]);
@@ -404,7 +416,7 @@ __global__ __launch_bounds__(512) void k_astream_cs(const double* __restrict__ A
   constexpr int RB = SH::RB, V = SH::V, B2 = SH::B2, LOG2B = SH::LOG2B;
   __shared__ double sp[2][CS_MAXW][V], ep[2][CS_MAXW][V];
   const int nw = blockDim.x >> 6;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_index();
   const bool has_x = AXp != nullptr;
   const int c = 2 * lane + 128 * wave;
   // value index held by this lane after tr_reduce over B2 values: the top

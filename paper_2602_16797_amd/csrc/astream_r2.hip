@@ -29,7 +29,7 @@ int64_t astream_r2_blocks(int64_t m) {
   return (m + rows - 1) / rows;
 }
 
-bool astream_r2_fits(int B, int n, bool aligned) { return aligned && n <= 256 && B >= 1 && B <= 2; }
+bool astream_r2_fits(int B, int n, bool aligned) { return aligned && n % 2 == 0 && n <= 256 && B >= 1 && B <= 2; }
 
 bool dispatch_astream_r2(bool dot2, int init, int B, hipStream_t st, int64_t nb, const double* A, int64_t lda,
                          int64_t m, int n, const double* W, double* AW, const double* AVp, const double* AXp,

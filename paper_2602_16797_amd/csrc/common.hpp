@@ -93,6 +93,10 @@ __device__ inline cd divs(cd a, cd b) {
 // half-row mirror, row mirror), which run at ALU latency; the four row sums are
 // then combined from scalar readlanes, so every lane gets the same value and
 // the summation order is fixed.  Callers must have the whole wave active.
+// Index of the calling wave in its workgroup, known to the compiler to be
+// wave-uniform (scalar register), so branches on it are scalar branches.
+__device__ inline int wave_index() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
 __device__ inline double readlane_d(double v, int l) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);

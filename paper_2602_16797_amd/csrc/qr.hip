@@ -18,6 +18,7 @@
 //                column of the identity; writes R^{-1} and R^{-*} row-major.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "tr_reduce.hpp"
 
 namespace rl {
 
@@ -261,6 +262,193 @@ __global__ __launch_bounds__(QRP_THREADS) void k_qr_panel_reg(T* Y, int ld, int 
   for (int i = tid; i < QR_NB * QR_NB; i += QRP_THREADS) Tm[i] = Tl[i];
 }
 
+// Column-wave panel factorisation (FP64 up to 1024 rows [p, d), complex up
+// to 512): the nb <= 32 panel columns are dealt out over NW waves (wave w owns
+// columns w, w+NW, ...) and lane l holds rows p + l + 64 s of them, so every
+// column lives in one wave.  Column jj is factored by its owner alone (one
+// wave reduction for the norm), which publishes the reflector and conj(tau)
+// in LDS; after one barrier each wave, in one batched transpose-reduction,
+// forms v^* Y(:, k) for its columns k > jj (then applies H^*) and
+// V(:, k)^* v for its columns k < jj (column jj of the T factor).  The owner
+// of column jj+1 factors it right after, so a column costs one barrier.
+template <typename T, int NW, int RPL>
+__global__ __launch_bounds__(NW * 64) void k_qr_panel_cw(T* Y, int ld, int d, int p, int nb, T* Tm) {
+  constexpr int CPW = QR_NB / NW;
+  constexpr int ES = (int)(sizeof(T) / 8);
+  constexpr int NV = CPW * ES;  // reals reduced per column step
+  constexpr int LOG2NV = NV <= 2 ? 1 : NV <= 4 ? 2 : NV <= 8 ? 3 : 4;
+  static_assert(NV >= 2 && NV <= 16, "batched reduction of 2..16 reals");
+  __shared__ T vbuf[2][64 * RPL];
+  __shared__ T tbuf[2];
+  __shared__ T taus[QR_NB];
+  __shared__ T Gm[QR_NB * QR_NB];  // Gm[l * QR_NB + jj] = V(:, l)^* v_jj, l < jj
+  __shared__ T Tl[QR_NB * QR_NB];  // column-major, leading dimension QR_NB
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = wave_index();
+  T x[CPW][RPL];
+#pragma unroll
+  for (int kc = 0; kc < CPW; ++kc) {
+    const int col = wave + NW * kc;
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+      const int row = p + lane + 64 * s;
+      x[kc][s] = (col < nb && row < d) ? Y[(int64_t)(p + col) * ld + row] : zero<T>();
+    }
+  }
+  // column jj by its owner: Householder vector below the diagonal, beta on it
+  auto factor = [&](T (&c)[RPL], int jj, int slot) {
+    double n2p = 0.0;
+#pragma unroll
+    for (int s = 0; s < RPL; ++s)
+      if (lane + 64 * s > jj) n2p += abs2(c[s]);
+    const double n2 = wave_sum(n2p);
+    const T alpha = readlane_d(c[0], jj);
+    const bool noref = (n2 == 0.0) && (im_(alpha) == 0.0);
+    T tau = zero<T>(), sc = from_real<T>(1.0);
+    double beta = re_(alpha);
+    if (!noref) {
+      const double nrm = sqrt(abs2(alpha) + n2);
+      beta = (re_(alpha) >= 0.0) ? -nrm : nrm;
+      tau = divs(sub(from_real<T>(beta), alpha), from_real<T>(beta));
+      sc = divs(from_real<T>(1.0), sub(alpha, from_real<T>(beta)));
+    }
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+      const int rel = lane + 64 * s;
+      T vs = zero<T>();
+      if (rel > jj) {
+        if (!noref) c[s] = mul(c[s], sc);
+        vs = c[s];
+      } else if (rel == jj) {
+        vs = from_real<T>(1.0);
+        if (!noref) c[s] = from_real<T>(beta);
+      }
+      vbuf[slot][rel] = vs;
+    }
+    if (lane == 0) {
+      tbuf[slot] = conj_(tau);
+      taus[jj] = tau;
+    }
+  };
+  if (wave == 0) factor(x[0], 0, 0);
+#pragma unroll
+  for (int jc = 0; jc < CPW; ++jc) {
+    for (int ow = 0; ow < NW; ++ow) {
+      const int jj = NW * jc + ow;
+      if (jj >= nb) break;
+      __syncthreads();
+      const T ct = tbuf[jj & 1];
+      T v[RPL];
+#pragma unroll
+      for (int s = 0; s < RPL; ++s) v[s] = vbuf[jj & 1][lane + 64 * s];
+      double ys[NV];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) ys[q] = 0.0;
+#pragma unroll
+      for (int kc = 0; kc < CPW; ++kc) {
+        const int k = wave + NW * kc;
+        if (k < nb && k != jj) {
+          T acc = zero<T>();
+          if (k > jj) {
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) acc = cfmac(v[s], x[kc][s], acc);
+          } else {
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) acc = cfmac(x[kc][s], v[s], acc);
+          }
+          if constexpr (ES == 2) {
+            ys[2 * kc] = re_(acc);
+            ys[2 * kc + 1] = im_(acc);
+          } else {
+            ys[kc] = re_(acc);
+          }
+        }
+      }
+      tr_reduce_plain<NV, LOG2NV>(ys, lane);
+#pragma unroll
+      for (int kc = 0; kc < CPW; ++kc) {
+        const int k = wave + NW * kc;
+        if (k < nb && k != jj) {
+          T dk;
+          if constexpr (ES == 2) {
+            dk = T{readlane_d(ys[0], tr_src_lane<LOG2NV>(2 * kc)), readlane_d(ys[0], tr_src_lane<LOG2NV>(2 * kc + 1))};
+          } else {
+            dk = readlane_d(ys[0], tr_src_lane<LOG2NV>(kc));
+          }
+          if (k > jj) {
+            const T f = mul(ct, dk);
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) x[kc][s] = fnmac(f, v[s], x[kc][s]);
+          } else if (lane == 0) {
+            Gm[k * QR_NB + jj] = dk;
+          }
+        }
+      }
+      const int j1 = jj + 1;
+      if (j1 < nb && wave == (ow + 1) % NW) {
+        if (ow + 1 < NW) factor(x[jc], j1, j1 & 1);
+        else if (jc + 1 < CPW) factor(x[jc + 1 < CPW ? jc + 1 : jc], j1, j1 & 1);
+      }
+    }
+  }
+  __syncthreads();
+  // T factor, row q by thread q: T(q, q) = tau_q,
+  // T(q, jj) = -tau_jj sum_{l = q}^{jj-1} T(q, l) (V(:, l)^* v_jj)
+  if (tid < QR_NB) {
+    const int q = tid;
+    for (int jj = 0; jj < QR_NB; ++jj) {
+      T val = zero<T>();
+      if (jj < nb) {
+        if (jj == q) {
+          val = taus[q];
+        } else if (jj > q) {
+          T acc = zero<T>();
+          for (int l = q; l < jj; ++l) acc = fmac(Tl[q + l * QR_NB], Gm[l * QR_NB + jj], acc);
+          val = neg(mul(taus[jj], acc));
+        }
+      }
+      Tl[q + jj * QR_NB] = val;
+    }
+  }
+#pragma unroll
+  for (int kc = 0; kc < CPW; ++kc) {
+    const int col = wave + NW * kc;
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+      const int row = p + lane + 64 * s;
+      if (col < nb && row < d) Y[(int64_t)(p + col) * ld + row] = x[kc][s];
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < QR_NB * QR_NB; i += NW * 64) Tm[i] = Tl[i];
+}
+
+// rows per lane of the column-wave panel for `rows` rows, or 0 when the panel
+// is too tall for it
+template <typename T>
+static int qr_cw_rpl(int rows) {
+  if constexpr (sizeof(T) == 4) return 0;  // FP32 panels keep their own kernels
+  // the panel stays in registers: 4 x 16 doubles or 2 x 8 complex per lane
+  const int r = (rows + 63) / 64;
+  const int rmax = sizeof(T) == 16 ? 8 : 16;
+  if (r > rmax) return 0;
+  return r <= 4 ? 4 : r <= 8 ? 8 : 16;
+}
+
+template <typename T>
+static void qr_panel_cw_launch(hipStream_t st, T* Y, int d, int p, int nb, int rpl, T* Tm) {
+  if constexpr (sizeof(T) == 8) {
+    const dim3 g(1);
+    if (rpl == 4) hipLaunchKernelGGL((k_qr_panel_cw<T, 8, 4>), g, dim3(512), 0, st, Y, d, d, p, nb, Tm);
+    else if (rpl == 8) hipLaunchKernelGGL((k_qr_panel_cw<T, 8, 8>), g, dim3(512), 0, st, Y, d, d, p, nb, Tm);
+    else hipLaunchKernelGGL((k_qr_panel_cw<T, 8, 16>), g, dim3(512), 0, st, Y, d, d, p, nb, Tm);
+  } else if constexpr (sizeof(T) == 16) {
+    const dim3 g(1), b(1024);
+    if (rpl == 4) hipLaunchKernelGGL((k_qr_panel_cw<T, 16, 4>), g, b, 0, st, Y, d, d, p, nb, Tm);
+    else hipLaunchKernelGGL((k_qr_panel_cw<T, 16, 8>), g, b, 0, st, Y, d, d, p, nb, Tm);
+  }
+}
+
 // Panel width and register rows per thread for the rows [p, d): the panel
 // must fit in about 64 registers per thread.
 template <typename T>
@@ -366,7 +554,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_trinv(const T* __restrict__ Y, int ld, int n, T* __restrict__ Rinv,
                                                T* __restrict__ RinvH) {
   extern __shared__ double smem_d[];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_index();
   T* xs = reinterpret_cast<T*>(smem_d) + (int64_t)wave * n;
   const int k = blockIdx.x * 4 + wave;
   if (k >= n) return;
@@ -391,13 +579,19 @@ __global__ __launch_bounds__(256) void k_trinv(const T* __restrict__ Y, int ld, 
 template <typename T, bool BF16IN = false>
 static void qr_factor(hipStream_t st, T* Y, int d, int n, T* Tm) {
   for (int p = 0; p < n;) {
-    int rpt = 0;
-    const int nbr = qr_pick_panel<T>(d - p, &rpt);
-    const int nb = min(nbr > 0 ? nbr : QR_NB, n - p);
-    if (nbr > 0)
-      qr_panel_launch<T>(st, Y, d, p, nb, rpt, Tm);
-    else
-      hipLaunchKernelGGL(k_qr_panel<T>, dim3(1), dim3(QR_THREADS), 0, st, Y, d, d, n, p, nb, Tm);
+    int rpt = 0, nb;
+    const int rpl = qr_cw_rpl<T>(d - p);
+    if (rpl > 0) {
+      nb = min(QR_NB, n - p);
+      qr_panel_cw_launch<T>(st, Y, d, p, nb, rpl, Tm);
+    } else {
+      const int nbr = qr_pick_panel<T>(d - p, &rpt);
+      nb = min(nbr > 0 ? nbr : QR_NB, n - p);
+      if (nbr > 0)
+        qr_panel_launch<T>(st, Y, d, p, nb, rpt, Tm);
+      else
+        hipLaunchKernelGGL(k_qr_panel<T>, dim3(1), dim3(QR_THREADS), 0, st, Y, d, d, n, p, nb, Tm);
+    }
     const int rest = n - p - nb;
     if (rest > 0)
       hipLaunchKernelGGL((k_qr_update<T, BF16IN>), dim3((rest + QR_CB - 1) / QR_CB), dim3(QR_THREADS), 0, st, Y, d,

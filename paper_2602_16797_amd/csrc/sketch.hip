@@ -13,11 +13,13 @@
 //
 // Kernel 1 (partial): grid (column tiles, row chunks).  A block owns a tile of
 // CT double-columns and a chunk of rows and keeps the whole d x CT slice of Y
-// in LDS.  Wave w owns pieces w, w+8, ..., so no two waves touch the same LDS
-// word; within a wave the 64/CT row slots of one instruction may hit the same
-// word and resolve through the LDS atomic unit.  Each lane first hashes one row
-// of the next 64 for the wave's piece, and the targets are then read with a
-// cross-lane shuffle, so every (row, piece) pair is hashed once per tile.
+// in LDS (row stride CT + 1, so the 64/CT row slots of one instruction fall
+// on different banks).  Wave w owns pieces w, w+8, ..., whose rows of Y no
+// other wave touches; within a wave the row slots of one instruction may hit
+// the same word, so the adds are LDS atomics (issued without waiting, unlike a
+// read-modify-write).  Each lane hashes one row of the next 64 for the wave's
+// piece while those rows load, and the targets are read with a cross-lane
+// shuffle, so every (row, piece) pair is hashed once per tile.
 // Kernel 2 (reduce): sums the chunk partials in chunk order and writes Y
 // column-major (the layout of the QR that follows), flagging NaN/Inf.
 // Both kernels take the accumulator type: FP64, or FP32 for the
@@ -39,13 +41,16 @@ __global__ __launch_bounds__(512) void k_sketch_partial(
     const double* __restrict__ A, int64_t lda_d, int64_t m, int64_t ncols_d, int d, int zeta,
     uint64_t seed, int64_t rows_per_chunk, Acc* __restrict__ part) {
   extern __shared__ double acc_raw[];
-  Acc* acc = reinterpret_cast<Acc*>(acc_raw);  // d * CT
+  // d x CT accumulators with a row stride of CT + 1, so the target rows of
+  // the RS row slots of one instruction fall on different LDS banks
+  constexpr int CTP = CT + 1;
+  Acc* acc = reinterpret_cast<Acc*>(acc_raw);
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  const int lane = tid & 63, wave = wave_index(), nwaves = blockDim.x >> 6;
   const int64_t c0 = (int64_t)blockIdx.x * CT;
   const int64_t r0 = (int64_t)blockIdx.y * rows_per_chunk;
   const int64_t r1 = (r0 + rows_per_chunk < m) ? r0 + rows_per_chunk : m;
-  for (int i = tid; i < d * CT; i += blockDim.x) acc[i] = (Acc)0;
+  for (int i = tid; i < d * CTP; i += blockDim.x) acc[i] = (Acc)0;
   __syncthreads();
   constexpr int RS = 64 / CT;   // rows per instruction
   constexpr int NQ = 64 / RS;   // instructions per 64 rows
@@ -55,24 +60,40 @@ __global__ __launch_bounds__(512) void k_sketch_partial(
   for (int p = wave; p < zeta; p += nwaves) {
     const int len = base + (p < extra ? 1 : 0);
     const int start = p * base + (p < extra ? p : extra);
-    for (int64_t g0 = r0; g0 < r1; g0 += 64) {
-      const uint64_t i = (uint64_t)(g0 + lane);
+    // lane l hashes row g + l for piece p; target row and sign travel as one
+    // word (sign in the top bit)
+    auto target = [&](int64_t g) {
+      const uint64_t i = (uint64_t)(g + lane);
       const uint64_t h = splitmix64(seed ^ splitmix64(i * (uint64_t)zeta + (uint64_t)p));
       const int tgt = start + (int)(((h & 0xFFFFFFFFull) * (uint64_t)len) >> 32);
-      const double sg = (h >> 63) ? -1.0 : 1.0;
-      Acc a[NQ];
+      return (h >> 63) ? (tgt | (int)0x80000000) : tgt;
+    };
+    auto load = [&](Acc (&a)[NQ], int64_t g) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const int64_t row = g0 + q * RS + slot;
+        const int64_t row = g + q * RS + slot;
         a[q] = (Acc)((row < r1 && colok) ? A[row * lda_d + c0 + col] : 0.0);
+      }
+    };
+    // the next 64 rows are loaded and hashed while the current ones are added
+    Acc an[NQ];
+    load(an, r0);
+    int pn = target(r0);
+    for (int64_t g0 = r0; g0 < r1; g0 += 64) {
+      Acc a[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) a[q] = an[q];
+      const int packed = pn;
+      if (g0 + 64 < r1) {
+        load(an, g0 + 64);
+        pn = target(g0 + 64);
       }
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const int src = q * RS + slot;
-        const int t = __shfl(tgt, src, WAVE);
-        const double s = __shfl(sg, src, WAVE);
-        const int64_t row = g0 + src;
-        if (row < r1 && colok) atomicAdd(&acc[t * CT + col], (Acc)s * a[q]);
+        const int pk = __shfl(packed, q * RS + slot, WAVE);
+        const int t = pk & 0x7FFFFFFF;
+        const Acc v = (pk < 0) ? -a[q] : a[q];
+        if ((g0 + q * RS + slot < r1) && colok) atomicAdd(&acc[t * CTP + col], v);
       }
     }
   }
@@ -80,7 +101,7 @@ __global__ __launch_bounds__(512) void k_sketch_partial(
   Acc* out = part + (int64_t)blockIdx.y * d * ncols_d;
   for (int i = tid; i < d * CT; i += blockDim.x) {
     const int r = i / CT, c = i % CT;
-    if (c0 + c < ncols_d) out[(int64_t)r * ncols_d + c0 + c] = acc[i];
+    if (c0 + c < ncols_d) out[(int64_t)r * ncols_d + c0 + c] = acc[r * CTP + c];
   }
 }
 
@@ -100,12 +121,12 @@ __global__ void k_sketch_reduce(const Acc* __restrict__ part, int nchunk, int d,
   Ycol[(elem * d + r) * es + comp] = s;
 }
 
-// widest column tile (in scalars) whose d x CT slice of accumulators fits the
-// LDS budget
+// widest column tile (in scalars) whose d x (CT + 1) slice of accumulators
+// fits the LDS budget
 int sketch_plan_ct(int d, int64_t lds_budget, int acc_bytes) {
-  const int cts[6] = {32, 16, 8, 4, 2, 1};
+  const int cts[5] = {16, 8, 4, 2, 1};  // 32 would spill the prefetched rows
   for (int c : cts)
-    if ((int64_t)d * c * acc_bytes <= lds_budget) return c;
+    if ((int64_t)d * (c + 1) * acc_bytes <= lds_budget) return c;
   return 0;
 }
 
@@ -153,10 +174,9 @@ static hipError_t sketch_impl(hipStream_t st, const double* A, int64_t lda_d, in
   const int ct = sketch_plan_ct(d, lds_budget, ab);
   const int64_t ntiles = (ncols_d + ct - 1) / ct;
   dim3 grid((unsigned)ntiles, (unsigned)nchunk);
-  const size_t lds = (size_t)d * ct * sizeof(Acc);
+  const size_t lds = (size_t)d * (ct + 1) * sizeof(Acc);
   hipError_t e;
   switch (ct) {
-    case 32: e = launch_partial<32, Acc>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
     case 16: e = launch_partial<16, Acc>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
     case 8: e = launch_partial<8, Acc>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
     case 4: e = launch_partial<4, Acc>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;

@@ -293,7 +293,7 @@ __global__ __launch_bounds__(TW_THREADS) void k_tsqr_w(const T* __restrict__ P0,
   constexpr int NW = TW_THREADS / 64;
   __shared__ T Rs[NW * TT * TT];
   const int t = b0 + b1 + b2;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_index();
   T x[RPL][TT];
 #pragma unroll
   for (int s = 0; s < RPL; ++s)
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(NW * 64) void k_tsqr_w_merge(const T* __restrict__ 
                                                           int check_done) {
   if (check_done && ctl->done) return;
   __shared__ T Rs[NW * TT * TT];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_index();
   T x[RPL][TT];
 #pragma unroll
   for (int s = 0; s < RPL; ++s)
@@ -414,7 +414,7 @@ __global__ __launch_bounds__(NW * 64) void k_tsqr_cw(const T* __restrict__ P0, i
   __shared__ T vbuf[2][RT];
   __shared__ T tbuf[2];
   const int t = b0 + b1 + b2;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_index();
   const int64_t g0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t g1 = (g0 + rows_per_block < m) ? g0 + rows_per_block : m;
   const TwPanels<T> src{P0, P1, P2, b0, b1, b2};
