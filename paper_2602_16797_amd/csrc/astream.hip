@@ -177,7 +177,8 @@ static int64_t astream_max_parts(int64_t m, int n, int B, int es_d) {
   const int64_t g = astream_blocks(m, n, B, es_d) * 4;
   const int64_t r = astream_r2_blocks(m);
   const int64_t c = astream_cs_blocks(m, n);
-  const int64_t cc = std::max(astream_ccs_ranges(m, n, B, true), astream_ccs_ranges(m, n, B, false));
+  const int64_t cc = std::max(std::max(astream_ccs_ranges(m, n, B, true), astream_ccs_ranges(m, n, B, false)),
+                              astream_c2_ranges(m, n, B));
   return std::max(std::max(g, cc), std::max(r, c));
 }
 
@@ -210,6 +211,10 @@ hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const voi
     np = nb;
     ok = dispatch_astream_cs(dot2, init, B, st, nb, (const double*)A, lda, m, n, (const double*)W, (double*)AW,
                              (const double*)AVp, (const double*)AXp, Gpart, ctl);
+  } else if (cplx && astream_c2_fits(B, n, ((reinterpret_cast<uintptr_t>(A) & 15) == 0))) {
+    nb = astream_c2_ranges(m, n, B);
+    np = nb;
+    ok = dispatch_astream_c2(dot2, init, B, st, nb, A, lda, m, n, W, AW, AVp, AXp, Gpart, ctl);
   } else if (cplx && astream_ccs_fits(B, n, ((reinterpret_cast<uintptr_t>(A) & 15) == 0))) {
     nb = astream_ccs_ranges(m, n, B, dot2);
     np = nb;

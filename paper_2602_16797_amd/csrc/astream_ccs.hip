@@ -12,10 +12,11 @@
 // by that XCD's L2 while the first is still streaming them.
 //
 // Per batch of RB rows each wave reduces its partial sums of the 2 BS real
-// components (re, im per vector) with the transpose-reduction, writes them to
-// LDS, and after one barrier lane v of every wave combines component v over the
-// waves in wave order (compensated); the finished row sums are broadcast with
-// readlanes and used at once for the column sums.
+// components (re, im per vector) with the transpose-reduction and writes them
+// to LDS; after one barrier every wave combines the waves' partials
+// (compensated), its 64 lanes splitting the work over components and waves,
+// and the finished row sums are broadcast with readlanes and used at once for
+// the column sums.
 #include "astream_kernels.hpp"
 #include "kernels.hpp"
 
@@ -54,6 +55,8 @@ __global__ __launch_bounds__(1024) void k_astream_ccs(const cd* __restrict__ A, 
   if (ctl != nullptr && ctl->done) return;
   using SH = CcsShape<BS, DOT2>;
   constexpr int RB = SH::RB, T = SH::T, V = SH::V, T2 = SH::T2, LOG2T = SH::LOG2T;
+  constexpr int VP = V <= 2 ? 2 : V <= 4 ? 4 : V <= 8 ? 8 : V <= 16 ? 16 : 32;
+  constexpr int CQ = 64 / VP;  // lanes per component in the cross-wave combine
   // block -> (row range, vector group): the ng groups of a row range are
   // consecutive blocks of one XCD
   const int64_t bid = blockIdx.x;
@@ -95,6 +98,7 @@ __global__ __launch_bounds__(1024) void k_astream_ccs(const cd* __restrict__ A, 
   // v mod T (2 j + 0 for Re, 2 j + 1 for Im of vector j0 + j)
   const int vq = lane / T, vt = lane - (lane / T) * T;
   const bool vlane = lane < V && vt < 2 * bsr;
+  const int ccv = lane / CQ, ccq = lane - (lane / CQ) * CQ;
   const double* AVd = reinterpret_cast<const double*>(AVp);
   const double* AXd = reinterpret_cast<const double*>(AXp);
   double* AWd = reinterpret_cast<double*>(AW);
@@ -155,26 +159,36 @@ __global__ __launch_bounds__(1024) void k_astream_ccs(const cd* __restrict__ A, 
       }
     }
     __syncthreads();
-    // lane v < V combines component v over the waves, in wave order
-    double comb = 0.0;
-    if (lane < V) {
-      double S = sp[buf][0][lane], E = DOT2 ? ep[buf][0][lane] : 0.0, t;
-      for (int q = 1; q < nw; ++q) {
-        two_sum(S, sp[buf][q][lane], S, t);
+    // the wave partials are combined by all 64 lanes: lane l takes component
+    // l / CQ and the waves congruent to l mod CQ, then the CQ lanes of a
+    // component finish the sum with compensated butterfly stages
+    double S = 0.0, E = 0.0;
+    if (ccv < V) {
+      for (int q = ccq; q < nw; q += CQ) {
+        double t;
+        two_sum(S, sp[buf][q][ccv], S, t);
         E += t;
-        if constexpr (DOT2) E += ep[buf][q][lane];
+        if constexpr (DOT2) E += ep[buf][q][ccv];
       }
-      comb = S + E;
     }
+    if constexpr (CQ > 16) ar_stage_dot2<16>(S, E);
+    if constexpr (CQ > 8) ar_stage_dot2<8>(S, E);
+    if constexpr (CQ > 4) ar_stage_dot2<4>(S, E);
+    if constexpr (CQ > 2) ar_stage_dot2<2>(S, E);
+    if constexpr (CQ > 1) ar_stage_dot2<1>(S, E);
+    const double comb = S + E;  // component lane / CQ
     buf ^= 1;
-    if (wave == 0 && vlane && rb + vq < r1) AWd[(rb + vq) * ldv + 2 * j0 + vt] = comb;
+    if (wave == 0 && ccq == 0 && ccv < V) {
+      const int wq = ccv / T, wt = ccv - (ccv / T) * T;
+      if (wt < 2 * bsr && rb + wq < r1) AWd[(rb + wq) * ldv + 2 * j0 + wt] = comb;
+    }
 #pragma unroll
     for (int q = 0; q < RB; ++q)
 #pragma unroll
       for (int j = 0; j < BS; ++j) {
         if (j < bsr) {
           const int v = q * T + 2 * j;
-          const double yr = readlane_d(comb, v), yi = readlane_d(comb, v + 1);
+          const double yr = readlane_d(comb, v * CQ), yi = readlane_d(comb, (v + 1) * CQ);
           const double vr = init ? yr : readlane_d(avl, v), vi = init ? yi : readlane_d(avl, v + 1);
           if constexpr (DOT2) ccs_dot2_cacc(a[q], vr, vi, g1s[j], g1e[j]);
           else ccs_cacc(a[q], vr, vi, g1s[j]);
@@ -224,10 +238,18 @@ static bool ccs_by_bs(int BS, hipStream_t st, int64_t nblk, int nw, int64_t rows
   case S:                                                                                                  \
     launch_ccs<S, DOT2>(st, nblk, nw, rows, nrb, ng, A, lda, m, n, B, W, AW, AVp, AXp, Gpart, init, ctl); \
     return true;
-    RL_CASE(1) RL_CASE(2) RL_CASE(3) RL_CASE(4)
+    RL_CASE(1) RL_CASE(2)
 #undef RL_CASE
-    default: return false;
+    default: break;
   }
+  if constexpr (!DOT2) {  // Dot2 groups hold at most two vectors
+    switch (BS) {
+      case 3: launch_ccs<3, DOT2>(st, nblk, nw, rows, nrb, ng, A, lda, m, n, B, W, AW, AVp, AXp, Gpart, init, ctl); return true;
+      case 4: launch_ccs<4, DOT2>(st, nblk, nw, rows, nrb, ng, A, lda, m, n, B, W, AW, AVp, AXp, Gpart, init, ctl); return true;
+      default: break;
+    }
+  }
+  return false;
 }
 
 int astream_ccs_waves(int n) { return (n + 63) / 64; }
