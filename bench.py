@@ -52,6 +52,22 @@ def spectrum(n, k, spec):
     return spectrum_logspace_tail(n, spec[1], spec[2])
 
 
+def astream_kernel(cplx: bool, n: int, b: int) -> str:
+    """The pass kernel(s) the library launches for this shape (the dispatch
+    rule of launch_astream, for a dense A with 16-byte aligned rows)."""
+    if cplx:
+        if 256 < n <= 1024:
+            return "k_c2_rows + k_c2_cols (A W, then A^* [A_V A_X A_W]: two reads of A)"
+        if n <= 1024:
+            return "k_astream_ccs (A W and A^* [A_V A_X A_W] in one read of A)"
+        return "k_astream<cd> (A W and A^* [A_V A_X A_W] in one read of A)"
+    if n % 2 == 0 and n <= 256 and b <= 2:
+        return "k_astream_r2 (A W and A^* [A_V A_X A_W] in one read of A)"
+    if n <= 1024 and b <= 10:
+        return "k_astream_cs (A W and A^* [A_V A_X A_W] in one read of A)"
+    return "k_astream<double> (A W and A^* [A_V A_X A_W] in one read of A)"
+
+
 def measured_traffic(workload: str):
     """HBM bytes per A-stream launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a copy kernel of known size),
@@ -276,7 +292,8 @@ def main(argv=None):
                                  "fp64_iters": ref.iters}
         log(f"vs FP64 Dot2 solve: {gates['vs_fp64_dot2']}")
 
-    # dominant kernel: the fused A-stream pass, timed per launch with HIP events
+    # dominant kernel: the A-stream pass, its kernels timed per launch with HIP
+    # events (the reduction of the per-workgroup partial sums is excluded)
     # Algorithmic bytes of each launch: A once, W, the A_W write, and the
     # panel reads the fused form needs (A_V from the first loop pass on, A_X
     # from the second); the start pass reads neither.
@@ -293,7 +310,7 @@ def main(argv=None):
     traffic = measured_traffic(args.workload) if (args.sketch_prec == "f64" and not args.no_dot2) else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_astream_r2 (A W and A^* [A_V A_X A_W] in one pass)", "avg_launch_us": round(avg_us, 2),
+                "kernel": astream_kernel(cplx, n, last.block), "avg_launch_us": round(avg_us, 2),
                 "launches": n_as, "algorithmic_bytes_per_launch": round(bytes_launch)}
 
     if args.copy_calibration:

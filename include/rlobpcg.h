@@ -71,7 +71,7 @@ typedef struct {
   int32_t dot2;       /* 1: row products of A accumulated as Dot2 (real and complex); default 1 */
   int32_t init_iters; /* inverse-subspace-iteration steps for the start block; default 10 */
   int32_t lanczos_steps; /* Golub-Kahan steps for Sigma~(1,1); default min(n, 64) */
-  int32_t profile;    /* 1: time every A-stream launch with HIP events (rl_info.t_astream_us) */
+  int32_t profile;    /* 1: time the pass kernels of every A-stream launch with HIP events (rl_info.t_astream_us) */
   int32_t sketch_prec; /* RL_SKETCH_*: precision of the sketch S*A and its QR (real A only); default FP64 */
   int32_t reserved[4];
 } rl_opts;
@@ -93,7 +93,7 @@ typedef struct {
   int64_t bytes_a;     /* bytes of A read by the solve (a_passes * m * n * element size) */
   int32_t hist_cap;    /* capacity (rows) of the history arrays below; 0 = none */
   int32_t n_astream;   /* A-stream launches timed (opts.profile) */
-  double t_astream_us; /* summed duration of those launches */
+  double t_astream_us; /* summed duration of their pass kernels (the reduction of the partial sums excluded) */
   double* theta_hist;  /* host, may be NULL */
   double* rnorm_hist;  /* host, may be NULL */
 } rl_info;

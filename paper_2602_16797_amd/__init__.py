@@ -255,6 +255,7 @@ class SolveResult:
     bytes_a: int
     n_astream: int = 0
     t_astream_us: float = 0.0
+    block: int = 0
     theta_hist: np.ndarray = field(default=None)
     rnorm_hist: np.ndarray = field(default=None)
 
@@ -319,7 +320,7 @@ def rl_svds_smallest(A, k: int, *, want_u: bool = True, history: bool = True, **
                        degenerate=bool(info.degenerate), zero_theta=bool(info.zero_theta),
                        t_setup_us=info.t_setup_us, t_iter_us=info.t_iter_us, t_final_us=info.t_final_us,
                        bytes_a=info.bytes_a, n_astream=info.n_astream, t_astream_us=info.t_astream_us,
-                       theta_hist=th[: it + 1].copy() if history else None,
+                       block=info.block, theta_hist=th[: it + 1].copy() if history else None,
                        rnorm_hist=rn[: it + 1].copy() if history else None)
 
 

@@ -194,7 +194,7 @@ int64_t astream_tmp_doubles(int64_t m, int n, int B, int es_d) {
 // One pass: AW = A W and G3 = A^* [AVp AXp AW] (n x 3B, contiguous; init: G3[:, 0:B] = A^* AW).
 hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const void* A, int64_t lda, int64_t m, int n,
                           const void* W, void* AW, const void* AVp, const void* AXp, int init, double* Gpart,
-                          double* tmp, double* G3, const Ctl* ctl) {
+                          double* tmp, double* G3, const Ctl* ctl, hipEvent_t pass_done) {
   const int es_d = cplx ? 2 : 1;
   const int ns = astream_ns(n);
   int64_t nb = astream_blocks(m, n, B, es_d);
@@ -226,6 +226,11 @@ hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const voi
   if (!ok) return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  // the pass itself ends here (timing of the pass kernels alone)
+  if (pass_done != nullptr) {
+    e = hipEventRecord(pass_done, st);
+    if (e != hipSuccess) return e;
+  }
   // compensated reduction of the per-wave partials
   const int64_t plen = (int64_t)n * B * es_d;
   const int64_t len = 3 * plen;

@@ -58,7 +58,7 @@ bool dispatch_astream_gc(bool dot2, int ns, int B, hipStream_t st, int64_t nb, c
                          const Ctl* ctl);
 hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const void* A, int64_t lda, int64_t m, int n,
                           const void* W, void* AW, const void* AVp, const void* AXp, int init, double* Gpart,
-                          double* tmp, double* G3, const Ctl* ctl);
+                          double* tmp, double* G3, const Ctl* ctl, hipEvent_t pass_done = nullptr);
 hipError_t launch_panel(hipStream_t st, bool cplx, void* AV, void* AX, const void* AW, int64_t m, int B,
                         const void* CV, const void* CX, const Ctl* ctl);
 hipError_t launch_final_u(hipStream_t st, bool cplx, const void* AV, const void* AX, const void* AW, int64_t m, int B,

@@ -299,8 +299,9 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   }
   // start pass: A_V = A V_0 and A^* A_V (into the first block of G3)
   CK(launch_astream(st, cplx, B, dot2, A, lda, m, (int)n, at<void>(ws, L.V), at<void>(ws, L.AV), nullptr, nullptr, 1,
-                    at<double>(ws, L.Gpart), at<double>(ws, L.Gtmp), at<double>(ws, L.G3), ctl));
-  if (prof) CK(hipEventRecord(h->prof[2 * nprof++ + 1], st));
+                    at<double>(ws, L.Gpart), at<double>(ws, L.Gtmp), at<double>(ws, L.G3), ctl,
+                    prof ? h->prof[2 * nprof + 1] : nullptr));
+  if (prof) ++nprof;
   void* Rt = nullptr;
   CK(launch_tsqr(st, cplx, at<void>(ws, L.AV), B, nullptr, 0, nullptr, 0, m, at<void>(ws, L.tsA),
                  at<void>(ws, L.tsB), &Rt, ctl, 0));
@@ -324,8 +325,8 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
     if (prof) CK(hipEventRecord(h->prof[2 * nprof], st));
     CK(launch_astream(st, cplx, B, dot2, A, lda, m, (int)n, at<void>(ws, L.W), at<void>(ws, L.AW),
                       at<void>(ws, L.AV), with_x ? at<void>(ws, L.AX) : nullptr, 0, at<double>(ws, L.Gpart),
-                      at<double>(ws, L.Gtmp), at<double>(ws, L.G3), ctl));
-    if (prof) CK(hipEventRecord(h->prof[2 * nprof++ + 1], st));
+                      at<double>(ws, L.Gtmp), at<double>(ws, L.G3), ctl, prof ? h->prof[2 * nprof + 1] : nullptr));
+    if (prof) ++nprof;
     CK(launch_tsqr(st, cplx, at<void>(ws, L.AV), B, with_x ? at<void>(ws, L.AX) : nullptr, with_x ? B : 0,
                    at<void>(ws, L.AW), B, m, at<void>(ws, L.tsA), at<void>(ws, L.tsB), &Rt, ctl, 1));
     CK(launch_rr(st, cplx, (int)n, B, 0, with_x, Rt, at<void>(ws, L.V), at<void>(ws, L.X), at<void>(ws, L.W),
