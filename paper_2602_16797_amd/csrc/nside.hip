@@ -185,42 +185,68 @@ __device__ bool dev_should_stop(int i, const double* __restrict__ ht, const doub
   return true;
 }
 
-// One-sided (Hestenes) Jacobi on the t x t matrix M (column-major, ld 32) by one
-// wave; Vj accumulates the rotations.  Lanes 0..t-1 hold one row each.
+// One-sided (Hestenes) Jacobi on the t x t matrix M (column-major, ld 32) by a
+// workgroup of 256 threads, in parallel (round-robin) order: the columns,
+// padded to an even count tp, meet in tp - 1 rounds of tp/2 disjoint pairs
+// per sweep, and the 16 lanes of one DPP row take one pair (lane i holds rows
+// i and i + 16), so a round is three 16-lane sums and one rotation per pair
+// with one barrier.  Vj accumulates the rotations.  Same rotation formulas as
+// the cyclic order; the sweep stops when no pair was rotated.
 template <typename T>
-__device__ void jacobi_wave(T* M, T* Vj, int t, int lane) {
+__device__ void jacobi_block(T* M, T* Vj, int t) {
   const double tol = sqrt((double)t) * 2.220446049250313e-16;
+  const int grp = threadIdx.x >> 4, li = threadIdx.x & 15;
+  const int tp = t + (t & 1);
   for (int sweep = 0; sweep < 60; ++sweep) {
-    bool rotated = false;
-    for (int p = 0; p < t - 1; ++p) {
-      for (int q = p + 1; q < t; ++q) {
-        const T mp = (lane < t) ? M[p * 32 + lane] : zero<T>();
-        const T mq = (lane < t) ? M[q * 32 + lane] : zero<T>();
-        const double al = wave_sum(abs2(mp));
-        const double be = wave_sum(abs2(mq));
-        const T ga = wave_sum(cfmac(mp, mq, zero<T>()));
-        const double g = absval(ga);
-        if (!(g > tol * sqrt(al) * sqrt(be)) || g == 0.0) continue;
-        rotated = true;
-        const T eg = scal(ga, 1.0 / g);  // unit phase of gamma
-        const double zeta = (be - al) / (2.0 * g);
-        const double tn = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + tn * tn), s = c * tn;
-        if (lane < t) {
-          const T mq2 = mul(conj_(eg), mq);
-          M[p * 32 + lane] = sub(scal(mp, c), scal(mq2, s));
-          M[q * 32 + lane] = add(scal(mp, s), scal(mq2, c));
-          const T vp = Vj[p * 32 + lane];
-          const T vq2 = mul(conj_(eg), Vj[q * 32 + lane]);
-          Vj[p * 32 + lane] = sub(scal(vp, c), scal(vq2, s));
-          Vj[q * 32 + lane] = add(scal(vp, s), scal(vq2, c));
+    int rotated = 0;
+    for (int r = 0; r < tp - 1; ++r) {
+      if (grp < tp / 2) {
+        int a, b;
+        if (grp == 0) {
+          a = r;
+          b = tp - 1;
+        } else {
+          a = (r + grp) % (tp - 1);
+          b = (r - grp + tp - 1) % (tp - 1);
         }
-        __builtin_amdgcn_wave_barrier();
+        const int p = a < b ? a : b, q = a < b ? b : a;
+        if (q < t) {
+          const bool r0 = li < t, r1 = li + 16 < t;
+          const T mp0 = r0 ? M[p * 32 + li] : zero<T>(), mp1 = r1 ? M[p * 32 + li + 16] : zero<T>();
+          const T mq0 = r0 ? M[q * 32 + li] : zero<T>(), mq1 = r1 ? M[q * 32 + li + 16] : zero<T>();
+          const double al = row_sum16(abs2(mp0) + abs2(mp1));
+          const double be = row_sum16(abs2(mq0) + abs2(mq1));
+          const T ga = row_sum16(cfmac(mp1, mq1, cfmac(mp0, mq0, zero<T>())));
+          const double g = absval(ga);
+          if (g > tol * sqrt(al) * sqrt(be) && g != 0.0) {
+            rotated = 1;
+            const T eg = scal(ga, 1.0 / g);  // unit phase of gamma
+            const double zeta = (be - al) / (2.0 * g);
+            const double tn = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double c = 1.0 / sqrt(1.0 + tn * tn), s = c * tn;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const int row = li + 16 * h;
+              if (row < t) {
+                const T mp = h ? mp1 : mp0;
+                const T mq2 = mul(conj_(eg), h ? mq1 : mq0);
+                M[p * 32 + row] = sub(scal(mp, c), scal(mq2, s));
+                M[q * 32 + row] = add(scal(mp, s), scal(mq2, c));
+                const T vp = Vj[p * 32 + row];
+                const T vq2 = mul(conj_(eg), Vj[q * 32 + row]);
+                Vj[p * 32 + row] = sub(scal(vp, c), scal(vq2, s));
+                Vj[q * 32 + row] = add(scal(vp, s), scal(vq2, c));
+              }
+            }
+          }
+        }
       }
+      __syncthreads();
     }
-    if (!rotated) break;
+    if (!__syncthreads_or(rotated)) break;
   }
 }
+
 
 template <typename T, int B>
 __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int with_x, const T* __restrict__ Rt,
@@ -252,8 +278,8 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
     Vj[e] = from_real<T>((r == c) ? 1.0 : 0.0);
   }
   __syncthreads();
+  jacobi_block<T>(M, Vj, t);
   if (wid == 0) {
-    jacobi_wave<T>(M, Vj, t, lane);
     // column norms, then a descending sort (lane 0)
     for (int c = 0; c < t; ++c) {
       const T v = (lane < t) ? M[c * 32 + lane] : zero<T>();
@@ -802,19 +828,20 @@ namespace rl {
 // Singular values (descending) and right singular vectors of a t x t R
 // (row-major), for the tall-SVD step entry point.
 template <typename T>
-__global__ __launch_bounds__(64) void k_rt_svd(int t, const T* __restrict__ Rt, double* __restrict__ sigma,
-                                               T* __restrict__ Cout) {
+__global__ __launch_bounds__(NS_THREADS) void k_rt_svd(int t, const T* __restrict__ Rt, double* __restrict__ sigma,
+                                                       T* __restrict__ Cout) {
   __shared__ T M[RR_TMAX * 32];
   __shared__ T Vj[RR_TMAX * 32];
   __shared__ double sig[RR_TMAX];
   const int lane = threadIdx.x;
-  for (int e = lane; e < RR_TMAX * 32; e += 64) {
+  for (int e = lane; e < RR_TMAX * 32; e += blockDim.x) {
     const int c = e / 32, r = e % 32;
     M[e] = (r < t && c < t) ? Rt[r * t + c] : zero<T>();
     Vj[e] = from_real<T>((r == c) ? 1.0 : 0.0);
   }
-  __builtin_amdgcn_wave_barrier();
-  jacobi_wave<T>(M, Vj, t, lane);
+  __syncthreads();
+  jacobi_block<T>(M, Vj, t);
+  if (threadIdx.x >= 64) return;
   for (int c = 0; c < t; ++c) {
     const T v = (lane < t) ? M[c * 32 + lane] : zero<T>();
     const double s = wave_sum(abs2(v));
@@ -837,9 +864,9 @@ __global__ __launch_bounds__(64) void k_rt_svd(int t, const T* __restrict__ Rt, 
 
 hipError_t launch_rt_svd(hipStream_t st, bool cplx, int t, const void* Rt, double* sigma, void* C) {
   if (cplx)
-    hipLaunchKernelGGL(k_rt_svd<cd>, dim3(1), dim3(64), 0, st, t, (const cd*)Rt, sigma, (cd*)C);
+    hipLaunchKernelGGL(k_rt_svd<cd>, dim3(1), dim3(NS_THREADS), 0, st, t, (const cd*)Rt, sigma, (cd*)C);
   else
-    hipLaunchKernelGGL(k_rt_svd<double>, dim3(1), dim3(64), 0, st, t, (const double*)Rt, sigma, (double*)C);
+    hipLaunchKernelGGL(k_rt_svd<double>, dim3(1), dim3(NS_THREADS), 0, st, t, (const double*)Rt, sigma, (double*)C);
   return hipGetLastError();
 }
 

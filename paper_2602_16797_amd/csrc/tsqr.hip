@@ -110,7 +110,7 @@ __global__ __launch_bounds__(TS_TILE) void k_tsqr(const T* __restrict__ P0, int 
 }
 
 // ---------------------------------------------------------------------------
-// Register TSQR for t <= 16: a wave holds a tile of 64*RPL rows, RPL rows per
+// Register TSQR for t <= 8: a wave holds a tile of 64*RPL rows, RPL rows per
 // lane (t values each in registers).  Rows 0..t-1 of the tile (lanes 0..t-1,
 // first register row) carry the running R; the other rows take the next
 // 64*RPL-t input rows, loaded one tile ahead.  Householder QR of the tile
@@ -376,7 +376,7 @@ static void tsqr_w_go(hipStream_t st, const T* P0, int b0, const T* P1, int b1, 
 }
 
 // ---------------------------------------------------------------------------
-// Column-wave TSQR for 16 < t <= 32: one tile of 64*RPL rows per workgroup of
+// Column-wave TSQR for 8 < t <= 32: one tile of 64*RPL rows per workgroup of
 // NW waves, held in registers with the columns dealt out over the waves (wave
 // w owns columns w, w+NW, ...; lane l holds tile rows l + 64 s, s < RPL).  The
 // tile is NW times taller than a one-wave tile, so the t rows of running R
@@ -536,13 +536,17 @@ __global__ __launch_bounds__(NW * 64) void k_tsqr_cw(const T* __restrict__ P0, i
   }
 }
 
-template <typename T>
-struct CwCfg {  // waves, rows per lane of the column-wave TSQR
+template <typename T, int TT>
+struct CwCfg {  // waves, rows per lane of the column-wave TSQR (64 register values per lane)
   static constexpr int NW = 4;
-  static constexpr int RPL = sizeof(T) == 16 ? 4 : 8;
+  static constexpr int RPL = (TT == 32 ? 8 : 16) / (sizeof(T) == 16 ? 2 : 1);
 };
 
-static int64_t tsqr_cw_fresh(int t, bool cplx) { return 64 * (cplx ? CwCfg<cd>::RPL : CwCfg<double>::RPL) - t; }
+static int64_t tsqr_cw_fresh(int t, bool cplx) {
+  const int rpl = t > 16 ? (cplx ? CwCfg<cd, 32>::RPL : CwCfg<double, 32>::RPL)
+                         : (cplx ? CwCfg<cd, 16>::RPL : CwCfg<double, 16>::RPL);
+  return 64 * rpl - t;
+}
 
 // row ranges of the first launch: two tiles or more each, at most 512
 static int64_t tsqr_cw_groups(int64_t m, int t, bool cplx) {
@@ -552,17 +556,17 @@ static int64_t tsqr_cw_groups(int64_t m, int t, bool cplx) {
   return g < 1 ? 1 : g;
 }
 
-template <typename T>
+template <typename T, int TT>
 static hipError_t tsqr_cw_impl(hipStream_t st, const T* P0, int b0, const T* P1, int b1, const T* P2, int b2,
                                int64_t m, T* bufA, T* bufB, T** Rfinal, const Ctl* ctl, int check_done) {
-  constexpr int NW = CwCfg<T>::NW, RPL = CwCfg<T>::RPL;
+  constexpr int NW = CwCfg<T, TT>::NW, RPL = CwCfg<T, TT>::RPL;
   const int t = b0 + b1 + b2;
   const bool cplx = sizeof(T) == 16;
   if (P1 == nullptr) P1 = P0;
   if (P2 == nullptr) P2 = P0;
   int64_t g = tsqr_cw_groups(m, t, cplx);
   int64_t rows = (m + g - 1) / g;
-  hipLaunchKernelGGL((k_tsqr_cw<T, 32, NW, RPL>), dim3((unsigned)g), dim3(NW * 64), 0, st, P0, b0, P1, b1, P2, b2, m,
+  hipLaunchKernelGGL((k_tsqr_cw<T, TT, NW, RPL>), dim3((unsigned)g), dim3(NW * 64), 0, st, P0, b0, P1, b1, P2, b2, m,
                      rows, bufA, ctl, check_done);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -574,7 +578,7 @@ static hipError_t tsqr_cw_impl(hipStream_t st, const T* P0, int b0, const T* P1,
     int64_t g2 = tsqr_cw_groups(mm, t, cplx);
     if (g2 >= g) g2 = g / 2 > 0 ? g / 2 : 1;
     rows = (mm + g2 - 1) / g2;
-    hipLaunchKernelGGL((k_tsqr_cw<T, 32, NW, RPL>), dim3((unsigned)g2), dim3(NW * 64), 0, st, (const T*)cur, t,
+    hipLaunchKernelGGL((k_tsqr_cw<T, TT, NW, RPL>), dim3((unsigned)g2), dim3(NW * 64), 0, st, (const T*)cur, t,
                        (const T*)cur, 0, (const T*)cur, 0, mm, rows, nxt, ctl, check_done);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -607,7 +611,8 @@ static hipError_t tsqr_impl(hipStream_t st, const T* P0, int b0, const T* P1, in
                             T* bufA, T* bufB, T** Rfinal, Ctl* ctl, int check_done) {
   const int t = b0 + b1 + b2;
   if (t < 1 || t > TS_TMAX) return hipErrorInvalidValue;
-  if (t > 16 && t <= 32) return tsqr_cw_impl<T>(st, P0, b0, P1, b1, P2, b2, m, bufA, bufB, Rfinal, ctl, check_done);
+  if (t > 16 && t <= 32) return tsqr_cw_impl<T, 32>(st, P0, b0, P1, b1, P2, b2, m, bufA, bufB, Rfinal, ctl, check_done);
+  if (t > 8 && t <= 16) return tsqr_cw_impl<T, 16>(st, P0, b0, P1, b1, P2, b2, m, bufA, bufB, Rfinal, ctl, check_done);
   if (t <= TW_TMAX) {
     const int64_t g = tsqr_w_groups(m, t, sizeof(T) == 16);
     if (t <= 4) tsqr_w_go<T, 4>(st, P0, b0, P1, b1, P2, b2, m, g, bufA, bufB, ctl, check_done);
