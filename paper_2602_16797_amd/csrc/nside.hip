@@ -27,6 +27,7 @@ namespace rl {
 constexpr int NS_THREADS = 256;
 constexpr int RR_TMAX = 32;
 constexpr int RR_BMAX = 16;
+constexpr int ORTH_KC = 8;  // projections summed per block reduction
 
 __device__ inline double absval(double a) { return fabs(a); }
 __device__ inline double absval(cd a) { return hypot(a.x, a.y); }
@@ -83,21 +84,26 @@ template <typename T, int KM>
 __device__ void orth_project(int n, int B, int j, const T* __restrict__ V, const T* __restrict__ X, int nvx,
                              T* __restrict__ W, T* scratch, T* h) {
   const int K = nvx + j;
-  T vals[KM];
+  // the K projections are summed in chunks of ORTH_KC, so the per-thread
+  // partial sums stay in registers for any b
+  for (int k0 = 0; k0 < K; k0 += ORTH_KC) {
+    T vals[ORTH_KC];
 #pragma unroll
-  for (int k = 0; k < KM; ++k) vals[k] = zero<T>();
-  for (int r = threadIdx.x; r < n; r += blockDim.x) {
-    const T wr = W[(int64_t)r * B + j];
+    for (int kk = 0; kk < ORTH_KC; ++kk) vals[kk] = zero<T>();
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+      const T wr = W[(int64_t)r * B + j];
 #pragma unroll
-    for (int k = 0; k < KM; ++k) {
-      if (k < K) {
-        const T br = (k < nvx) ? ((k < B) ? V[(int64_t)r * B + k] : X[(int64_t)r * B + (k - B)])
-                               : W[(int64_t)r * B + (k - nvx)];
-        vals[k] = cfmac(br, wr, vals[k]);
+      for (int kk = 0; kk < ORTH_KC; ++kk) {
+        const int k = k0 + kk;
+        if (k < K) {
+          const T br = (k < nvx) ? ((k < B) ? V[(int64_t)r * B + k] : X[(int64_t)r * B + (k - B)])
+                                 : W[(int64_t)r * B + (k - nvx)];
+          vals[kk] = cfmac(br, wr, vals[kk]);
+        }
       }
     }
+    block_sum_many<T, ORTH_KC>(vals, (K - k0 < ORTH_KC) ? K - k0 : ORTH_KC, scratch, h + k0);
   }
-  block_sum_many<T, KM>(vals, K, scratch, h);
   for (int r = threadIdx.x; r < n; r += blockDim.x) {
     T wr = W[(int64_t)r * B + j];
     for (int k = 0; k < K; ++k) {
@@ -119,11 +125,9 @@ __device__ double col_norm(int n, int B, int j, const T* __restrict__ W, double*
 
 // KM bounds the number of projections of one column, 3B - 1.
 template <typename T, int KM>
-__global__ __launch_bounds__(NS_THREADS) void k_orth(int n, int B, const T* __restrict__ V, const T* __restrict__ X,
-                                                     int project, int with_x, T* __restrict__ W, Ctl* __restrict__ ctl,
-                                                     int check_done) {
-  if (check_done && ctl->done) return;
-  __shared__ T scratch[(NS_THREADS / 16) * KM];
+__device__ void orth_block(int n, int B, const T* __restrict__ V, const T* __restrict__ X, int project, int with_x,
+                           T* __restrict__ W, Ctl* __restrict__ ctl) {
+  __shared__ T scratch[(NS_THREADS / 16) * ORTH_KC];
   __shared__ T h[KM];
   __shared__ double red[NS_THREADS / 64];
   const int nvx = project ? (with_x ? 2 * B : B) : 0;
@@ -155,6 +159,15 @@ __global__ __launch_bounds__(NS_THREADS) void k_orth(int n, int B, const T* __re
     __syncthreads();
   }
 }
+
+template <typename T, int KM>
+__global__ __launch_bounds__(NS_THREADS) void k_orth(int n, int B, const T* __restrict__ V, const T* __restrict__ X,
+                                                     int project, int with_x, T* __restrict__ W, Ctl* __restrict__ ctl,
+                                                     int check_done) {
+  if (check_done && ctl->done) return;
+  orth_block<T, KM>(n, B, V, X, project, with_x, W, ctl);
+}
+
 
 // ---------------------------------------------------------------------------
 __device__ bool dev_should_stop(int i, const double* __restrict__ ht, const double* __restrict__ hr, int B,
@@ -315,33 +328,40 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
 #pragma unroll
     for (int j = 0; j < RR_BMAX; ++j) vals[j] = zero<T>();
     for (int r = tid; r < n; r += blockDim.x) {
-      T tr[3 * B], gr[3 * B];
+      // [V X W](r, :) C_V and G_T(r, :) C_V, one trial-space column at a time
+      T v[B], g[B];
 #pragma unroll
       for (int j = 0; j < B; ++j) {
-        tr[j] = V[(int64_t)r * B + j];
-        gr[j] = GV[(int64_t)r * B + j];
-        tr[B + j] = (mode == 2) ? X[(int64_t)r * B + j] : ((mode == 1) ? W[(int64_t)r * B + j] : zero<T>());
-        gr[B + j] = (mode == 2) ? GX[(int64_t)r * B + j] : ((mode == 1) ? GW[(int64_t)r * B + j] : zero<T>());
-        tr[2 * B + j] = (mode == 2) ? W[(int64_t)r * B + j] : zero<T>();
-        gr[2 * B + j] = (mode == 2) ? GW[(int64_t)r * B + j] : zero<T>();
+        v[j] = zero<T>();
+        g[j] = zero<T>();
+      }
+      for (int c = 0; c < t; ++c) {
+        const int blk = c / B, jc = c - (c / B) * B;
+        const int64_t e = (int64_t)r * B + jc;
+        T trc, grc;
+        if (blk == 0) {
+          trc = V[e];
+          grc = GV[e];
+        } else if (blk == 1) {
+          trc = (mode == 2) ? X[e] : W[e];
+          grc = (mode == 2) ? GX[e] : GW[e];
+        } else {
+          trc = W[e];
+          grc = GW[e];
+        }
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+          v[j] = fmac(trc, CV[c * B + j], v[j]);
+          g[j] = fmac(grc, CV[c * B + j], g[j]);
+        }
       }
 #pragma unroll
-      for (int j = 0; j < RR_BMAX; ++j) {
-        if (j < B) {
-          T v = zero<T>(), g = zero<T>();
-#pragma unroll
-          for (int c = 0; c < 3 * B; ++c) {
-            if (c < t) {
-              v = fmac(tr[c], CV[c * B + j], v);
-              g = fmac(gr[c], CV[c * B + j], g);
-            }
-          }
-          const double th2 = th[t - B + j] * th[t - B + j];
-          const T res = sub(g, scal(v, th2));
-          Vn[(int64_t)r * B + j] = v;
-          Rres[(int64_t)r * B + j] = res;
-          vals[j] = add(vals[j], from_real<T>(abs2(res)));
-        }
+      for (int j = 0; j < B; ++j) {
+        const double th2 = th[t - B + j] * th[t - B + j];
+        const T res = sub(g[j], scal(v[j], th2));
+        Vn[(int64_t)r * B + j] = v[j];
+        Rres[(int64_t)r * B + j] = res;
+        vals[j] = add(vals[j], from_real<T>(abs2(res)));
       }
     }
     block_sum_many<T, RR_BMAX>(vals, B, scratch, hsum);
@@ -399,21 +419,18 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
   // pass 2: X = T C_X from the old T, then V <- V_new
   for (int r = tid; r < n; r += blockDim.x) {
     if (xupd) {
-      T tr[3 * B];
+      T x[B];
 #pragma unroll
-      for (int j = 0; j < B; ++j) {
-        tr[j] = V[(int64_t)r * B + j];
-        tr[B + j] = (mode == 2) ? X[(int64_t)r * B + j] : W[(int64_t)r * B + j];
-        tr[2 * B + j] = (mode == 2) ? W[(int64_t)r * B + j] : zero<T>();
+      for (int j = 0; j < B; ++j) x[j] = zero<T>();
+      for (int c = 0; c < t; ++c) {
+        const int blk = c / B, jc = c - (c / B) * B;
+        const int64_t e = (int64_t)r * B + jc;
+        const T trc = (blk == 0) ? V[e] : ((blk == 1) ? ((mode == 2) ? X[e] : W[e]) : W[e]);
+#pragma unroll
+        for (int j = 0; j < B; ++j) x[j] = fmac(trc, CX[c * B + j], x[j]);
       }
 #pragma unroll
-      for (int j = 0; j < B; ++j) {
-        T x = zero<T>();
-#pragma unroll
-        for (int c = 0; c < 3 * B; ++c)
-          if (c < t) x = fmac(tr[c], CX[c * B + j], x);
-        X[(int64_t)r * B + j] = x;
-      }
+      for (int j = 0; j < B; ++j) X[(int64_t)r * B + j] = x[j];
     }
     for (int j = 0; j < B; ++j) V[(int64_t)r * B + j] = Vn[(int64_t)r * B + j];
   }

@@ -346,15 +346,17 @@ struct TwMergeWaves {
   static constexpr int value = TT > 16 ? 4 : ((sizeof(T) == 16 || TT > 8) ? 8 : 16);
 };
 
+// Workgroups of the first launch: enough for every SIMD (256 workgroups of
+// four waves), no more: the first launch's time is set by its total tile count
+// over the whole chip, the single-workgroup merge's by the number of stacked
+// factors.
 static int64_t tsqr_w_groups(int64_t m, int t, bool cplx) {
   const int tt = t <= 4 ? 4 : (t <= 8 ? 8 : (t <= 16 ? 16 : 32));
   int rpl = tt <= 4 ? 4 : (tt <= 8 ? 2 : 1);
   if (cplx) rpl = rpl > 1 ? rpl / 2 : 1;
   const int64_t fresh = 64 * rpl - t;
-  int64_t g = (int64_t)sqrt(4.0 * (double)m / (double)t);
-  const int64_t gmax = (m + 4 * fresh - 1) / (4 * fresh);  // at least one tile per wave
-  if (g > gmax) g = gmax;
-  if (g > 1024) g = 1024;
+  int64_t g = (m + 4 * fresh - 1) / (4 * fresh);  // at least one tile per wave
+  if (g > 256) g = 256;
   if (g < 1) g = 1;
   return g;
 }
