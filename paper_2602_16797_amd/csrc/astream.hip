@@ -192,9 +192,12 @@ int64_t astream_tmp_doubles(int64_t m, int n, int B, int es_d) {
 }
 
 // One pass: AW = A W and G3 = A^* [AVp AXp AW] (n x 3B, contiguous; init: G3[:, 0:B] = A^* AW).
-hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const void* A, int64_t lda, int64_t m, int n,
-                          const void* W, void* AW, const void* AVp, const void* AXp, int init, double* Gpart,
-                          double* tmp, double* G3, const Ctl* ctl, hipEvent_t pass_done) {
+// The pass kernels: AW = A W and the per-workgroup partial column sums of
+// A^* [AVp AXp AW] (init: A^* AW); *np_out receives the number of partial
+// records for launch_astream_reduce.
+hipError_t launch_astream_pass(hipStream_t st, bool cplx, int B, bool dot2, const void* A, int64_t lda, int64_t m,
+                               int n, const void* W, void* AW, const void* AVp, const void* AXp, int init,
+                               double* Gpart, const Ctl* ctl, int64_t* np_out) {
   const int es_d = cplx ? 2 : 1;
   const int ns = astream_ns(n);
   int64_t nb = astream_blocks(m, n, B, es_d);
@@ -224,14 +227,14 @@ hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const voi
   else
     ok = dispatch_astream_gd(dot2, ns, B, st, nb, A, lda, m, n, W, AW, AVp, AXp, init, Gpart, ctl);
   if (!ok) return hipErrorInvalidValue;
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  // the pass itself ends here (timing of the pass kernels alone)
-  if (pass_done != nullptr) {
-    e = hipEventRecord(pass_done, st);
-    if (e != hipSuccess) return e;
-  }
-  // compensated reduction of the per-wave partials
+  *np_out = np;
+  return hipGetLastError();
+}
+
+// Compensated reduction of the np partial records into G3 (n x 3B).
+hipError_t launch_astream_reduce(hipStream_t st, bool cplx, int B, int n, int64_t np, const double* Gpart,
+                                 double* tmp, double* G3, const Ctl* ctl) {
+  const int es_d = cplx ? 2 : 1;
   const int64_t plen = (int64_t)n * B * es_d;
   const int64_t len = 3 * plen;
   const int64_t g1 = (np + 63) / 64;
@@ -245,7 +248,7 @@ hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const voi
     double* de = ds + g1 * len;
     hipLaunchKernelGGL(k_colsum2, dim3((unsigned)((len + 63) / 64), (unsigned)groups), dim3(256), 0, st, cur_s,
                        cur_e, stride, elen, np, len, ds, de, groups == 1 ? G3 : nullptr, ctl);
-    e = hipGetLastError();
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (groups == 1) return hipSuccess;
     cur_s = ds;
@@ -255,6 +258,20 @@ hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const voi
     np = groups;
     flip ^= 1;
   }
+}
+
+hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const void* A, int64_t lda, int64_t m, int n,
+                          const void* W, void* AW, const void* AVp, const void* AXp, int init, double* Gpart,
+                          double* tmp, double* G3, const Ctl* ctl, hipEvent_t pass_done) {
+  int64_t np = 0;
+  hipError_t e = launch_astream_pass(st, cplx, B, dot2, A, lda, m, n, W, AW, AVp, AXp, init, Gpart, ctl, &np);
+  if (e != hipSuccess) return e;
+  // the pass itself ends here (timing of the pass kernels alone)
+  if (pass_done != nullptr) {
+    e = hipEventRecord(pass_done, st);
+    if (e != hipSuccess) return e;
+  }
+  return launch_astream_reduce(st, cplx, B, n, np, Gpart, tmp, G3, ctl);
 }
 
 template <typename T, int B>

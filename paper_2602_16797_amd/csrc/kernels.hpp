@@ -56,6 +56,11 @@ bool dispatch_astream_gd(bool dot2, int ns, int B, hipStream_t st, int64_t nb, c
 bool dispatch_astream_gc(bool dot2, int ns, int B, hipStream_t st, int64_t nb, const void* A, int64_t lda, int64_t m,
                          int n, const void* W, void* AW, const void* AVp, const void* AXp, int init, double* Gpart,
                          const Ctl* ctl);
+hipError_t launch_astream_pass(hipStream_t st, bool cplx, int B, bool dot2, const void* A, int64_t lda, int64_t m,
+                               int n, const void* W, void* AW, const void* AVp, const void* AXp, int init,
+                               double* Gpart, const Ctl* ctl, int64_t* np_out);
+hipError_t launch_astream_reduce(hipStream_t st, bool cplx, int B, int n, int64_t np, const double* Gpart,
+                                 double* tmp, double* G3, const Ctl* ctl);
 hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const void* A, int64_t lda, int64_t m, int n,
                           const void* W, void* AW, const void* AVp, const void* AXp, int init, double* Gpart,
                           double* tmp, double* G3, const Ctl* ctl, hipEvent_t pass_done = nullptr);
