@@ -206,7 +206,7 @@ __device__ inline void r2_load(double2 (&a)[RB][2], const double* __restrict__ A
     const int64_t row = rb + q;
     if (row < r1) {
 #pragma unroll
-      for (int s = 0; s < 2; ++s) a[q][s] = *reinterpret_cast<const double2*>(A + row * lda + cl[s]);
+      for (int s = 0; s < 2; ++s) a[q][s] = ld_stream2(A + row * lda + cl[s]);
     } else {
 #pragma unroll
       for (int s = 0; s < 2; ++s) a[q][s] = make_double2(0.0, 0.0);
@@ -442,7 +442,7 @@ __global__ __launch_bounds__(512) void k_astream_cs(const double* __restrict__ A
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
       const int64_t row = rb + q;
-      if (row < r1 && c + 1 < n) a[q] = *reinterpret_cast<const double2*>(A + row * lda + c);
+      if (row < r1 && c + 1 < n) a[q] = ld_stream2(A + row * lda + c);
       else if (row < r1 && c < n) a[q] = make_double2(A[row * lda + c], 0.0);
       else a[q] = make_double2(0.0, 0.0);
     }

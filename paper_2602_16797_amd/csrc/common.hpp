@@ -93,6 +93,16 @@ __device__ inline cd divs(cd a, cd b) {
 // half-row mirror, row mirror), which run at ALU latency; the four row sums are
 // then combined from scalar readlanes, so every lane gets the same value and
 // the summation order is fixed.  Callers must have the whole wave active.
+// 16-byte streaming loads of A by the kernels that read each element once:
+// non-temporal, so the stream does not displace the reused vectors from the
+// caches.  (The complex kernels whose vector groups re-read A rely on L2 and
+// use ordinary loads.)
+typedef double rl_dv2 __attribute__((ext_vector_type(2)));
+__device__ inline double2 ld_stream2(const double* p) {
+  const rl_dv2 v = __builtin_nontemporal_load(reinterpret_cast<const rl_dv2*>(p));
+  return make_double2(v.x, v.y);
+}
+
 // Index of the calling wave in its workgroup, known to the compiler to be
 // wave-uniform (scalar register), so branches on it are scalar branches.
 __device__ inline int wave_index() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
