@@ -124,7 +124,10 @@ __global__ void k_sketch_reduce(const Acc* __restrict__ part, int nchunk, int d,
 // widest column tile (in scalars) whose d x (CT + 1) slice of accumulators
 // fits the LDS budget
 int sketch_plan_ct(int d, int64_t lds_budget, int acc_bytes) {
-  const int cts[5] = {16, 8, 4, 2, 1};  // 32 would spill the prefetched rows
+  // at most 8 columns: at d = 800 two workgroups then share a CU (58 KB of LDS
+  // each), which measured 7 % faster than one workgroup of 16 columns; 4
+  // columns per tile re-read each 128-byte line of A four times
+  const int cts[4] = {8, 4, 2, 1};
   for (int c : cts)
     if ((int64_t)d * (c + 1) * acc_bytes <= lds_budget) return c;
   return 0;
@@ -177,7 +180,6 @@ static hipError_t sketch_impl(hipStream_t st, const double* A, int64_t lda_d, in
   const size_t lds = (size_t)d * (ct + 1) * sizeof(Acc);
   hipError_t e;
   switch (ct) {
-    case 16: e = launch_partial<16, Acc>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
     case 8: e = launch_partial<8, Acc>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
     case 4: e = launch_partial<4, Acc>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
     case 2: e = launch_partial<2, Acc>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
