@@ -53,7 +53,22 @@ struct rl_ctx {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> prof;  // pairs around A-stream launches
   bool ws_async = false;         // workspace from the stream-ordered allocator (server slots)
+  hipStream_t aux = nullptr;     // second stream: Sigma~(1,1) beside the start block
+  hipEvent_t fork = nullptr, join = nullptr;
 };
+
+// The second stream and its fork/join events, created on first use.
+static int ensure_aux(rl_ctx* h) {
+  if (h->aux) return RL_OK;
+  if (hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->join, hipEventDisableTiming) != hipSuccess)
+    return RL_ERR_DEVICE;
+  if (hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) {
+    h->aux = nullptr;
+    return RL_ERR_DEVICE;
+  }
+  return RL_OK;
+}
 
 static int ensure_prof_events(rl_ctx* h, size_t pairs) {
   while (h->prof.size() < 2 * pairs) {
@@ -181,8 +196,14 @@ static int ensure_ws(rl_ctx* h, size_t bytes) {
 
 static void release_ws(rl_ctx* h) {
   if (!h->ws) return;
-  if (h->ws_async) (void)hipFreeAsync(h->ws, h->stream);
-  else (void)hipFree(h->ws);
+  // work left on the second stream (a solve that returned early) finishes first
+  if (h->aux) (void)hipStreamWaitEvent(h->stream, h->join, 0);
+  if (h->ws_async) {
+    (void)hipFreeAsync(h->ws, h->stream);
+  } else {
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(h->ws);
+  }
   h->ws = nullptr;
   h->ws_bytes = 0;
 }
@@ -234,6 +255,8 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;
   Problem p{m, n, o.d, o.block, k, o.zeta, cplx, (size_t)(cplx ? 16 : 8), o.max_iter, o.sketch_prec};
   const Layout L = plan(p, h->lds_budget);
+  // a previous solve that returned early may have left work on the second stream
+  if (h->aux) CK(hipStreamWaitEvent(h->stream, h->join, 0));
   rc = ensure_ws(h, L.total);
   if (rc != RL_OK) return rc;
   hipStream_t st = h->stream;
@@ -277,10 +300,16 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
                        st, at<double>(ws, L.Rinv), cnt, ctl);
     CK(hipGetLastError());
   }
-  // Sigma~(1,1)
+  // Sigma~(1,1) on the second stream: it only reads R and writes sigma1, which
+  // the first stopping test needs; the start block proceeds meanwhile
+  rc = ensure_aux(h);
+  if (rc != RL_OK) return rc;
+  CK(hipEventRecord(h->fork, st));
+  CK(hipStreamWaitEvent(h->aux, h->fork, 0));
   const int KL = std::min<int>(L.KL, o.lanczos_steps);
-  CK(launch_lanczos(st, cplx, (int)n, at<void>(ws, L.Y), (int)o.d, at<void>(ws, L.Rrow), at<void>(ws, L.Ub),
+  CK(launch_lanczos(h->aux, cplx, (int)n, at<void>(ws, L.Y), (int)o.d, at<void>(ws, L.Rrow), at<void>(ws, L.Ub),
                     at<void>(ws, L.Vb), KL, o.seed ^ 0xA5A5A5A5ull, ctl));
+  CK(hipEventRecord(h->join, h->aux));
   // Step 3: start block from the smallest right singular subspace of R
   CK(launch_randblk(st, cplx, at<void>(ws, L.W), n * B, o.seed ^ 0x3C3C3C3Cull));
   CK(launch_orth(st, cplx, (int)n, B, nullptr, nullptr, 0, 0, at<void>(ws, L.W), ctl, 0));
@@ -308,6 +337,7 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   CK(launch_rr(st, cplx, (int)n, B, 1, 0, Rt, at<void>(ws, L.V), at<void>(ws, L.X), at<void>(ws, L.W),
                at<void>(ws, L.G3), at<void>(ws, L.Vn), at<void>(ws, L.Rres), at<void>(ws, L.CV), at<void>(ws, L.CX),
                at<double>(ws, L.thb), at<double>(ws, L.ht), at<double>(ws, L.hr), ctl));
+  CK(hipStreamWaitEvent(st, h->join, 0));
   CK(launch_publish(st, ctl, h->host_ctl_dev));
   CK(hipEventRecord(h->ev[1], st));
   CK(hipStreamSynchronize(st));
@@ -554,6 +584,7 @@ int rl_create(rl_handle* out, int device, void* stream) {
 int rl_destroy(rl_handle h) {
   if (!h) return RL_OK;
   (void)hipSetDevice(h->device);
+  if (h->aux) (void)hipStreamSynchronize(h->aux);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   else (void)hipDeviceSynchronize();
   if (h->ws) (void)hipFree(h->ws);
@@ -561,6 +592,9 @@ int rl_destroy(rl_handle h) {
   for (int i = 0; i < 4; ++i)
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
   for (hipEvent_t e : h->prof) (void)hipEventDestroy(e);
+  if (h->aux) (void)hipStreamDestroy(h->aux);
+  if (h->fork) (void)hipEventDestroy(h->fork);
+  if (h->join) (void)hipEventDestroy(h->join);
   delete h;
   return RL_OK;
 }
