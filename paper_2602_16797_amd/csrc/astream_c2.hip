@@ -103,9 +103,15 @@ __global__ __launch_bounds__(C2_THREADS, 2) void k_c2_rows(const cd* __restrict_
         if (j < bsr) {
           const cd w = Ws[j * NC + lane + 64 * s];
           if constexpr (DOT2) {
-            dot2_add(a[s].x, w.x, ys[2 * j], ye[2 * j]);
+            // the first product of each component starts its pair exactly
+            if (s == 0) {
+              two_prod(a[s].x, w.x, ys[2 * j], ye[2 * j]);
+              two_prod(a[s].x, w.y, ys[2 * j + 1], ye[2 * j + 1]);
+            } else {
+              dot2_add(a[s].x, w.x, ys[2 * j], ye[2 * j]);
+              dot2_add(a[s].x, w.y, ys[2 * j + 1], ye[2 * j + 1]);
+            }
             dot2_add(-a[s].y, w.y, ys[2 * j], ye[2 * j]);
-            dot2_add(a[s].x, w.y, ys[2 * j + 1], ye[2 * j + 1]);
             dot2_add(a[s].y, w.x, ys[2 * j + 1], ye[2 * j + 1]);
           } else {
             ys[2 * j] = fma(a[s].x, w.x, ys[2 * j]);

@@ -139,9 +139,10 @@ __global__ __launch_bounds__(1024) void k_astream_ccs(const cd* __restrict__ A, 
       for (int j = 0; j < BS; ++j) {
         if (j < bsr) {
           if constexpr (DOT2) {
-            dot2_add(a[q].x, w[j].x, ys[2 * j], ye[2 * j]);
+            // the first product of each component starts its pair exactly
+            two_prod(a[q].x, w[j].x, ys[2 * j], ye[2 * j]);
             dot2_add(-a[q].y, w[j].y, ys[2 * j], ye[2 * j]);
-            dot2_add(a[q].x, w[j].y, ys[2 * j + 1], ye[2 * j + 1]);
+            two_prod(a[q].x, w[j].y, ys[2 * j + 1], ye[2 * j + 1]);
             dot2_add(a[q].y, w[j].x, ys[2 * j + 1], ye[2 * j + 1]);
           } else {
             ys[2 * j] = fma(a[q].x, w[j].x, ys[2 * j]);

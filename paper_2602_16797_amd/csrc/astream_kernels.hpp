@@ -482,7 +482,8 @@ __global__ __launch_bounds__(512) void k_astream_cs(const double* __restrict__ A
 #pragma unroll
       for (int j = 0; j < B; ++j) {
         if constexpr (DOT2) {
-          dot2_add(a[q].x, w[j].x, ys[j], ye[j]);
+          // the first product starts the pair exactly
+          two_prod(a[q].x, w[j].x, ys[j], ye[j]);
           dot2_add(a[q].y, w[j].y, ys[j], ye[j]);
         } else {
           ys[j] = fma(a[q].x, w[j].x, ys[j]);
