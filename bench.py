@@ -227,7 +227,7 @@ def main(argv=None):
     ap.add_argument("--served", action="store_true",
                     help="run the served stream (continuous batching) instead of the single-solve workload")
     ap.add_argument("--served-count", type=int, default=256)
-    ap.add_argument("--served-slots", type=int, default=16)
+    ap.add_argument("--served-slots", type=int, default=8)
     ap.add_argument("--served-budget-gb", type=float, default=16.0)
     args = ap.parse_args(argv)
     if args.gpus != 1:
