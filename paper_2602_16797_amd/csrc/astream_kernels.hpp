@@ -1,6 +1,6 @@
 // Device code of the A-stream pass, shared by the instantiation units
-// (astream_r2.hip, astream_gd.hip, astream_gc.hip).  See astream.hip for the
-// algorithm.
+// (astream_r2.hip, astream_cs.hip, astream_ccs.hip, astream_c2.hip,
+// astream_gd.hip, astream_gc.hip).  See astream.hip for the algorithm.
 #pragma once
 
 #include "common.hpp"
