@@ -47,16 +47,23 @@ __global__ __launch_bounds__(256) void k_colsum2(const double* __restrict__ in_s
   const int el = threadIdx.x & 63, g = threadIdx.x >> 6;  // 64 elements x 4 groups
   const int64_t e = (int64_t)blockIdx.x * 64 + el;
   const int64_t p0 = (int64_t)blockIdx.y * 64;
+  // the thread's 16 records are loaded together (one memory latency instead
+  // of one per record); records past the end are zeros, which change neither
+  // the sum nor its error
+  double vs[16], ve[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int64_t p = p0 + g + 4 * u;
+    const bool ok = (e < len) && (p < nparts);
+    vs[u] = ok ? in_s[p * stride + e] : 0.0;
+    ve[u] = (ok && e < elen) ? in_e[p * stride + e] : 0.0;
+  }
   double S = 0.0, E = 0.0;
-  if (e < len) {
-    for (int k = g; k < 64; k += 4) {
-      const int64_t p = p0 + k;
-      if (p < nparts) {
-        double t;
-        two_sum(S, in_s[p * stride + e], S, t);
-        E += t + (e < elen ? in_e[p * stride + e] : 0.0);
-      }
-    }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    double t;
+    two_sum(S, vs[u], S, t);
+    E += t + ve[u];
   }
   sh_s[threadIdx.x] = S;
   sh_e[threadIdx.x] = E;

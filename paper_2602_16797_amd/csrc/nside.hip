@@ -28,6 +28,7 @@ constexpr int NS_THREADS = 256;
 constexpr int RR_TMAX = 32;
 constexpr int RR_BMAX = 16;
 constexpr int ORTH_KC = 8;  // projections summed per block reduction
+constexpr int RR_PRE_B = 4;  // k_rr loads a trial row's values together up to this B
 
 __device__ inline double absval(double a) { return fabs(a); }
 __device__ inline double absval(cd a) { return hypot(a.x, a.y); }
@@ -51,17 +52,24 @@ __global__ __launch_bounds__(NS_THREADS) void k_trmv(const T* __restrict__ M, in
   for (int l0 = lstart; l0 < lend; l0 += 256) {
     const int cnt = (lend - l0 < 256) ? lend - l0 : 256;
     __syncthreads();
-    for (int e = threadIdx.x; e < cnt * B; e += blockDim.x) xs[e] = X[(int64_t)l0 * B + e];
+    // the chunk of X, zero past its end (the products there are zero)
+    for (int e = threadIdx.x; e < 256 * B; e += blockDim.x) xs[e] = (e < cnt * B) ? X[(int64_t)l0 * B + e] : zero<T>();
     __syncthreads();
-    if (i < n) {
-      const int lo = lower ? l0 : (i > l0 ? i : l0);
-      const int hi = lower ? ((i + 1 < l0 + cnt) ? i + 1 : l0 + cnt) : l0 + cnt;
-      for (int l = l0 + kk; l < l0 + cnt; l += 16) {
-        if (l < lo || l >= hi) continue;
-        const T mv = M[(int64_t)i * n + l];
+    const int lo = lower ? l0 : (i > l0 ? i : l0);
+    const int hi = (i >= n) ? lo : (lower ? ((i + 1 < l0 + cnt) ? i + 1 : l0 + cnt) : l0 + cnt);
+    // a thread's 16 entries of the chunk are loaded together (one memory
+    // latency per chunk instead of one per entry); entries outside the
+    // triangle are zeros
+    T mv[16];
 #pragma unroll
-        for (int j = 0; j < B; ++j) acc[j] = fmac(mv, xs[(l - l0) * B + j], acc[j]);
-      }
+    for (int u = 0; u < 16; ++u) {
+      const int l = l0 + kk + 16 * u;
+      mv[u] = (l >= lo && l < hi) ? M[(int64_t)i * n + l] : zero<T>();
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+#pragma unroll
+      for (int j = 0; j < B; ++j) acc[j] = fmac(mv[u], xs[(kk + 16 * u) * B + j], acc[j]);
     }
   }
   // the 16 threads of a row are one DPP row of the wave
@@ -324,6 +332,8 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
     const T* GV = G3;
     const T* GX = G3 + (int64_t)n * B;
     const T* GW = G3 + 2 * (int64_t)n * B;
+    const T* T1 = (mode == 2) ? X : W;  // second block of the trial space
+    const T* G1 = (mode == 2) ? GX : GW;
     T vals[RR_BMAX];
 #pragma unroll
     for (int j = 0; j < RR_BMAX; ++j) vals[j] = zero<T>();
@@ -335,24 +345,37 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
         v[j] = zero<T>();
         g[j] = zero<T>();
       }
-      for (int c = 0; c < t; ++c) {
-        const int blk = c / B, jc = c - (c / B) * B;
-        const int64_t e = (int64_t)r * B + jc;
-        T trc, grc;
-        if (blk == 0) {
-          trc = V[e];
-          grc = GV[e];
-        } else if (blk == 1) {
-          trc = (mode == 2) ? X[e] : W[e];
-          grc = (mode == 2) ? GX[e] : GW[e];
-        } else {
-          trc = W[e];
-          grc = GW[e];
+      if constexpr (B <= RR_PRE_B) {
+        // the row's 3B trial values and their G_T rows are loaded together
+        // (every block is a valid n x B array; blocks past t are not used)
+        T trv[3 * B], grv[3 * B];
+#pragma unroll
+        for (int c = 0; c < 3 * B; ++c) {
+          const int64_t e = (int64_t)r * B + (c % B);
+          trv[c] = (c < B) ? V[e] : ((c < 2 * B) ? T1[e] : W[e]);
+          grv[c] = (c < B) ? GV[e] : ((c < 2 * B) ? G1[e] : GW[e]);
         }
 #pragma unroll
-        for (int j = 0; j < B; ++j) {
-          v[j] = fmac(trc, CV[c * B + j], v[j]);
-          g[j] = fmac(grc, CV[c * B + j], g[j]);
+        for (int c = 0; c < 3 * B; ++c) {
+          if (c < t) {
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+              v[j] = fmac(trv[c], CV[c * B + j], v[j]);
+              g[j] = fmac(grv[c], CV[c * B + j], g[j]);
+            }
+          }
+        }
+      } else {
+        for (int c = 0; c < t; ++c) {
+          const int blk = c / B, jc = c - (c / B) * B;
+          const int64_t e = (int64_t)r * B + jc;
+          const T trc = (blk == 0) ? V[e] : ((blk == 1) ? T1[e] : W[e]);
+          const T grc = (blk == 0) ? GV[e] : ((blk == 1) ? G1[e] : GW[e]);
+#pragma unroll
+          for (int j = 0; j < B; ++j) {
+            v[j] = fmac(trc, CV[c * B + j], v[j]);
+            g[j] = fmac(grc, CV[c * B + j], g[j]);
+          }
         }
       }
 #pragma unroll
@@ -422,12 +445,29 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
       T x[B];
 #pragma unroll
       for (int j = 0; j < B; ++j) x[j] = zero<T>();
-      for (int c = 0; c < t; ++c) {
-        const int blk = c / B, jc = c - (c / B) * B;
-        const int64_t e = (int64_t)r * B + jc;
-        const T trc = (blk == 0) ? V[e] : ((blk == 1) ? ((mode == 2) ? X[e] : W[e]) : W[e]);
+      const T* T1 = (mode == 2) ? X : W;
+      if constexpr (B <= RR_PRE_B) {
+        T trv[3 * B];
 #pragma unroll
-        for (int j = 0; j < B; ++j) x[j] = fmac(trc, CX[c * B + j], x[j]);
+        for (int c = 0; c < 3 * B; ++c) {
+          const int64_t e = (int64_t)r * B + (c % B);
+          trv[c] = (c < B) ? V[e] : ((c < 2 * B) ? T1[e] : W[e]);
+        }
+#pragma unroll
+        for (int c = 0; c < 3 * B; ++c) {
+          if (c < t) {
+#pragma unroll
+            for (int j = 0; j < B; ++j) x[j] = fmac(trv[c], CX[c * B + j], x[j]);
+          }
+        }
+      } else {
+        for (int c = 0; c < t; ++c) {
+          const int blk = c / B, jc = c - (c / B) * B;
+          const int64_t e = (int64_t)r * B + jc;
+          const T trc = (blk == 0) ? V[e] : ((blk == 1) ? T1[e] : W[e]);
+#pragma unroll
+          for (int j = 0; j < B; ++j) x[j] = fmac(trc, CX[c * B + j], x[j]);
+        }
       }
 #pragma unroll
       for (int j = 0; j < B; ++j) X[(int64_t)r * B + j] = x[j];

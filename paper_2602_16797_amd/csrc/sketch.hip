@@ -88,12 +88,18 @@ __global__ __launch_bounds__(512) void k_sketch_partial(
         load(an, g0 + 64);
         pn = target(g0 + 64);
       }
+      // all targets first, then the adds back to back: a shuffle placed
+      // between two adds would wait for the earlier add to finish.  Rows
+      // past the chunk and columns past the tile hold zeros (see load), so
+      // their adds change nothing and need no guard.
+      int pk[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) pk[q] = __shfl(packed, q * RS + slot, WAVE);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const int pk = __shfl(packed, q * RS + slot, WAVE);
-        const int t = pk & 0x7FFFFFFF;
-        const Acc v = (pk < 0) ? -a[q] : a[q];
-        if ((g0 + q * RS + slot < r1) && colok) atomicAdd(&acc[t * CTP + col], v);
+        const int t = pk[q] & 0x7FFFFFFF;
+        const Acc v = (pk[q] < 0) ? -a[q] : a[q];
+        atomicAdd(&acc[t * CTP + col], v);
       }
     }
   }
