@@ -482,7 +482,10 @@ static void qr_panel_launch(hipStream_t st, T* Y, int d, int p, int nb, int rpt,
 template <typename T, bool BF16IN = false>
 __global__ __launch_bounds__(QR_THREADS) void k_qr_update(T* Y, int ld, int d, int n, int p, int nb,
                                                           const T* __restrict__ Tm) {
-  constexpr int RCH = 32;
+  // rows per chunk of V and C staged in LDS (under 52 KB for either type)
+  constexpr int RCH = sizeof(T) == 16 ? 64 : 128;
+  constexpr int NV = RCH * QR_NB / QR_THREADS;  // V values per thread and chunk
+  constexpr int NC = RCH * QR_CB / QR_THREADS;  // C values per thread and chunk
   __shared__ T Vs[RCH][QR_NB + 1];
   __shared__ T Cs[RCH][QR_CB + 1];
   __shared__ T Wt[QR_NB][QR_CB];
@@ -491,24 +494,43 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr_update(T* Y, int ld, int d, i
   const int c0 = p + nb + blockIdx.x * QR_CB;
   const int ncb = min(QR_CB, n - c0);
   const int q = tid / QR_CB, cb = tid % QR_CB;  // 32 x 8 = 256
-  T acc = zero<T>();
-  for (int r0 = p; r0 < d; r0 += RCH) {
-    for (int i = tid; i < RCH * QR_NB; i += blockDim.x) {
-      const int rr = i % RCH, qq = i / RCH;
-      const int r = r0 + rr;
-      Vs[rr][qq] = (qq < nb && r < d) ? vpanel(Y, ld, p, qq, r) : zero<T>();
-      if constexpr (BF16IN) Vs[rr][qq] = bf16_round(Vs[rr][qq]);
+  // a chunk's values are loaded into registers together, the next chunk's
+  // while the current one is summed
+  T vv[NV], cv[NC];
+  auto load_chunk = [&](int r0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int i = tid + k * QR_THREADS;
+      const int rr = i % RCH, qq = i / RCH, r = r0 + rr;
+      vv[k] = (qq < nb && r < d) ? vpanel(Y, ld, p, qq, r) : zero<T>();
+      if constexpr (BF16IN) vv[k] = bf16_round(vv[k]);
     }
-    for (int i = tid; i < RCH * QR_CB; i += blockDim.x) {
-      const int rr = i % RCH, cc = i / RCH;
-      const int r = r0 + rr;
-      Cs[rr][cc] = (cc < ncb && r < d) ? Y[(int64_t)(c0 + cc) * ld + r] : zero<T>();
-      if constexpr (BF16IN) Cs[rr][cc] = bf16_round(Cs[rr][cc]);
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int i = tid + k * QR_THREADS;
+      const int rr = i % RCH, cc = i / RCH, r = r0 + rr;
+      cv[k] = (cc < ncb && r < d) ? Y[(int64_t)(c0 + cc) * ld + r] : zero<T>();
+      if constexpr (BF16IN) cv[k] = bf16_round(cv[k]);
+    }
+  };
+  T acc = zero<T>();
+  load_chunk(p);
+  for (int r0 = p; r0 < d; r0 += RCH) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int i = tid + k * QR_THREADS;
+      Vs[i % RCH][i / RCH] = vv[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const int i = tid + k * QR_THREADS;
+      Cs[i % RCH][i / RCH] = cv[k];
     }
     __syncthreads();
+    if (r0 + RCH < d) load_chunk(r0 + RCH);
 #pragma unroll 8
     for (int rr = 0; rr < RCH; ++rr) acc = cfmac(Vs[rr][q], Cs[rr][cb], acc);
-    __syncthreads();
   }
   Wt[q][cb] = acc;
   __syncthreads();
@@ -525,19 +547,30 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr_update(T* Y, int ld, int d, i
       vr[qq] = (qq < nb) ? vpanel(Y, ld, p, qq, r) : zero<T>();
       if constexpr (BF16IN) vr[qq] = bf16_round(vr[qq]);
     }
+    // the row's QR_CB trailing entries are loaded together, updated, stored
+    T yv[QR_CB];
+#pragma unroll
+    for (int c = 0; c < QR_CB; ++c) yv[c] = (c < ncb) ? Y[(int64_t)(c0 + c) * ld + r] : zero<T>();
+    // the column loop stays rolled (so the 8 x 32 coefficients are read
+    // from LDS per column, not held in registers); yv is indexed by selects
 #pragma unroll 1
     for (int c = 0; c < QR_CB; ++c) {
-      if (c < ncb) {
-        T* y = Y + (int64_t)(c0 + c) * ld + r;
-        T v = *y;
+      T v = zero<T>();
 #pragma unroll
-        for (int qq = 0; qq < QR_NB; ++qq) {
-          if constexpr (BF16IN) v = fnmac(vr[qq], bf16_round(Wt2[qq][c]), v);
-          else v = fnmac(vr[qq], Wt2[qq][c], v);
-        }
-        *y = v;
+      for (int k = 0; k < QR_CB; ++k)
+        if (k == c) v = yv[k];
+#pragma unroll
+      for (int qq = 0; qq < QR_NB; ++qq) {
+        if constexpr (BF16IN) v = fnmac(vr[qq], bf16_round(Wt2[qq][c]), v);
+        else v = fnmac(vr[qq], Wt2[qq][c], v);
       }
+#pragma unroll
+      for (int k = 0; k < QR_CB; ++k)
+        if (k == c) yv[k] = v;
     }
+#pragma unroll
+    for (int c = 0; c < QR_CB; ++c)
+      if (c < ncb) Y[(int64_t)(c0 + c) * ld + r] = yv[c];
   }
 }
 

