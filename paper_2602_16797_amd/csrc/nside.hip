@@ -541,16 +541,28 @@ __device__ inline void lz_rows(int n, const T* __restrict__ M, int64_t ld, bool 
     for (int r = 0; r < 4; ++r) acc[r] = zero<T>();
     const int lo = upper ? i0 : 0;
     const int hi = upper ? n : ((i0 + 4 < n) ? i0 + 4 : n);
-    for (int l = lo + lane; l < hi; l += 64) {
-      const T xl = xs[l];
+    // LS 64-column slices per step: their 4 LS loads are issued together
+    // (the terms are still added in column order)
+    constexpr int LS = sizeof(T) == 16 ? 1 : 4;  // complex: within 128 registers
+    for (int l0 = lo; l0 < hi; l0 += 64 * LS) {
+      T mv[LS][4], xv[LS];
+      bool ok[LS][4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = i0 + r;
-        if (i < n && (upper ? l >= i : l <= i)) {
-          const T m = M[(int64_t)i * ld + l];
-          acc[r] = CONJ ? cfmac(m, xl, acc[r]) : fmac(m, xl, acc[r]);
+      for (int c = 0; c < LS; ++c) {
+        const int l = l0 + 64 * c + lane;
+        xv[c] = (l < hi) ? xs[l] : zero<T>();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + r;
+          ok[c][r] = l < hi && i < n && (upper ? l >= i : l <= i);
+          mv[c][r] = ok[c][r] ? M[(int64_t)i * ld + l] : zero<T>();
         }
       }
+#pragma unroll
+      for (int c = 0; c < LS; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (ok[c][r]) acc[r] = CONJ ? cfmac(mv[c][r], xv[c], acc[r]) : fmac(mv[c][r], xv[c], acc[r]);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {

@@ -235,6 +235,8 @@ __global__ __launch_bounds__(QRP_THREADS) void k_qr_panel_reg(T* Y, int ld, int 
   __syncthreads();
   // T factor, row q by thread q: T(q, q) = tau_q,
   // T(q, jj) = -tau_jj sum_{l = q}^{jj-1} T(q, l) (V(:, l)^* v_jj)
+  // (the reads of eight terms are issued together: the sum is a chain of
+  // LDS reads otherwise)
   if (tid < QR_NB) {
     const int q = tid;
     for (int jj = 0; jj < QR_NB; ++jj) {
@@ -244,6 +246,7 @@ __global__ __launch_bounds__(QRP_THREADS) void k_qr_panel_reg(T* Y, int ld, int 
           val = taus[q];
         } else if (jj > q) {
           T acc = zero<T>();
+#pragma unroll 8
           for (int l = q; l < jj; ++l) acc = fmac(Tl[q + l * QR_NB], Gm[l * QR_NB + jj], acc);
           val = neg(mul(taus[jj], acc));
         }
@@ -394,6 +397,8 @@ __global__ __launch_bounds__(NW * 64) void k_qr_panel_cw(T* Y, int ld, int d, in
   __syncthreads();
   // T factor, row q by thread q: T(q, q) = tau_q,
   // T(q, jj) = -tau_jj sum_{l = q}^{jj-1} T(q, l) (V(:, l)^* v_jj)
+  // (the reads of eight terms are issued together: the sum is a chain of
+  // LDS reads otherwise)
   if (tid < QR_NB) {
     const int q = tid;
     for (int jj = 0; jj < QR_NB; ++jj) {
@@ -403,6 +408,7 @@ __global__ __launch_bounds__(NW * 64) void k_qr_panel_cw(T* Y, int ld, int d, in
           val = taus[q];
         } else if (jj > q) {
           T acc = zero<T>();
+#pragma unroll 8
           for (int l = q; l < jj; ++l) acc = fmac(Tl[q + l * QR_NB], Gm[l * QR_NB + jj], acc);
           val = neg(mul(taus[jj], acc));
         }
