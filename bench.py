@@ -296,15 +296,18 @@ def main(argv=None):
     # events (the reduction of the per-workgroup partial sums is excluded)
     # Algorithmic bytes of each launch: A once, W, the A_W write, and the
     # panel reads the fused form needs (A_V from the first loop pass on, A_X
-    # from the second); the start pass reads neither.
+    # from the second); the start pass reads neither.  b is the solve's
+    # block size.
     n_as = sum(r.n_astream for r in results)
     t_as = sum(r.t_astream_us for r in results)
     avg_us = t_as / max(n_as, 1)
-    base = m * n * es + m * k * es + n * k * es
+    bb = last.block
+    base = m * n * es + m * bb * es + n * bb * es
+    mv = m * bb * es
     tot_bytes = 0
     for r in results:
         it = r.n_astream - 1
-        tot_bytes += (1 + it) * base + it * m * k * es + max(it - 1, 0) * m * k * es
+        tot_bytes += (1 + it) * base + it * mv + max(it - 1, 0) * mv
     bytes_launch = tot_bytes / max(n_as, 1)
     achieved = bytes_launch / (avg_us * 1e-6) / 1e9
     traffic = measured_traffic(args.workload) if (args.sketch_prec == "f64" and not args.no_dot2) else None
