@@ -33,6 +33,9 @@ Readings where the paper is silent (each listed in the design doc):
   * ``precond="qr"`` uses R from S A = Q R with P = R^{-1}; P P^* = (R^* R)^{-1}
     = ((S A)^* S A)^{-1} = V~ Sigma~^{-2} V~^*, the same operator as the SVD
     route (Sec. 1, footnote on QR), with V_0 taken from the SVD of R.
+  * ``loop_precond`` swaps the loop's preconditioner for the diagonal one
+    (P = diag(||A(:, i)||^{-1})) or none, keeping the sketch-and-solve start
+    (Sec. 1.1 initialises every compared method with v_0).
   * ``dot2=True`` computes every product with A (A V_0, A W, the refresh) and
     the residual's A^* A_V as Dot2-class sums (``oracle.eft``); without it the
     FP64 rounding floor of those products, not the iteration, limits the
@@ -94,7 +97,7 @@ def rlobpcg(A, k: int, *, block: int | None = None, d: int | None = None,
             zeta: int = 8, seed: int = 0, tau: float | None = None,
             max_iter: int | None = None, rule: str = "paper", check_every: int = 5,
             precond: str = "svd", dot2: bool = True, refresh: bool = False,
-            callback=None) -> RLResult:
+            loop_precond: str = "sketch", callback=None) -> RLResult:
     """Return the k smallest singular triplets of the tall matrix A."""
     A = np.asarray(A)
     if A.ndim != 2:
@@ -138,6 +141,22 @@ def rlobpcg(A, k: int, *, block: int | None = None, d: int | None = None,
         V = _ct(Vrh)[:, n - b:].copy()
     else:
         raise ValueError(f"unknown precond {precond!r}")
+    # The loop's preconditioner (Sec. 1.1, the comparison methods): the sketch
+    # preconditioner above, the diagonal P = diag(||A(:, i)||^{-1}) (so
+    # P P^* = diag(||A(:, i)||^{-2})), or none (P = I).  Every variant keeps
+    # the sketch-and-solve start and Sigma~(1,1), as the paper's comparison
+    # initialises all iterative methods with v_0.  A zero column keeps P(i,i) = 1.
+    if loop_precond == "diag":
+        cn2 = np.sum(np.abs(A) ** 2, axis=0)
+        dscale = np.where(cn2 > 0.0, 1.0 / np.where(cn2 > 0.0, cn2, 1.0), 1.0)
+
+        def apply_prec(Rm):
+            return dscale[:, None] * Rm
+    elif loop_precond == "none":
+        def apply_prec(Rm):
+            return Rm.copy()
+    elif loop_precond != "sketch":
+        raise ValueError(f"unknown loop_precond {loop_precond!r}")
 
     # Step 3: sketch-and-solve start.
     AV = mulA(V)

@@ -208,3 +208,50 @@ def test_block_of_one_equals_single_vector_start():
     v0 = np.linalg.svd(SA)[2][-1]
     r0 = A.T @ (A @ v0) - np.linalg.norm(A @ v0) ** 2 * v0
     assert abs(np.linalg.norm(r0) - r.rnorm_hist[0][0]) <= 1e-6 * np.linalg.norm(r0)
+
+
+@pytest.mark.parametrize("lp", ["diag", "none"])
+def test_loop_precond_first_step_minimises_over_span(lp):
+    """The comparison methods of Sec. 1.1 (LOBPCG with P = diag(||A(:, i)||^{-1})
+    and with no preconditioner) keep the sketch-and-solve start v_0; their
+    first iterate minimises ||A z|| / ||z|| over span{v_0, P P^* r_0}, checked
+    against the smallest singular value of A on that 2-dimensional span.
+    Column norms spread over three decades so a wrong power or axis of the
+    diagonal scaling changes the span."""
+    m, n = 2000, 30
+    s = spectrum_gap(n, 1, 1e-6, 10.0)
+    A0, _, _ = planted_numpy(m, n, s, 73)
+    A = A0 * np.logspace(0, 3, n)[None, :]
+    r = rlobpcg(A, 1, seed=2, rule="none", max_iter=1, loop_precond=lp)
+    SA = sparsestack.sketch(A, 4 * n, 8, 2)
+    v0 = np.linalg.svd(SA)[2][-1]
+    Av0 = A @ v0
+    r0 = A.T @ Av0 - (Av0 @ Av0) * v0
+    w0 = r0 / np.sum(A * A, axis=0) if lp == "diag" else r0
+    Q, _ = np.linalg.qr(np.stack([v0, w0], axis=1))
+    expect = np.linalg.svd(A @ Q, compute_uv=False)[-1]
+    assert abs(r.theta_hist[1][0] - expect) <= 1e-9 * expect
+
+
+def test_loop_precond_diag_converges_on_coherent_problem():
+    """On the paper's easy problem shape (right singular vectors close to the
+    standard basis, sigma geometric from 1 to 0.1 and a gap to 1e-7) the
+    diagonally preconditioned loop reaches the dense SVD's smallest triplet."""
+    rng = np.random.default_rng(5)
+    m, n = 3000, 40
+    V, _ = np.linalg.qr(np.diag(rng.standard_normal(n)) + 1e-4 * rng.standard_normal((n, n)))
+    U, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    s = np.geomspace(1.0, 0.1, n)
+    s[-1] = 1e-7
+    A = (U * s[None, :]) @ V.T
+    r = rlobpcg(A, 1, seed=3, loop_precond="diag")
+    sv, Vd = _dense(A)
+    assert r.status == 0
+    assert abs(r.sigma[0] - sv[-1]) <= 1e-12 * sv[0]
+    assert _sin_angle(r.V, Vd[:, -1:]) <= 1e-8
+
+
+def test_loop_precond_rejects_unknown():
+    A = np.random.default_rng(0).standard_normal((200, 12))
+    with pytest.raises(ValueError):
+        rlobpcg(A, 1, loop_precond="jacobi")
