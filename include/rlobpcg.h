@@ -56,6 +56,15 @@ extern "C" {
 #define RL_SKETCH_F32 1  /* FP32 sketch (A rounded once per entry) and FP32 QR; R promoted to FP64 */
 #define RL_SKETCH_BF16 2 /* FP32 sketch; QR trailing updates with bfloat16 inputs and FP32 accumulation */
 
+/* Preconditioner of the LOBPCG loop (rl_opts.loop_precond).  The start block
+ * and Sigma~(1,1) always come from the sketch; the two alternatives are the
+ * comparison methods of Sec. 1.1 (illustrative example):
+ * RL_PREC_DIAG uses P = diag(||A(:, i)||^{-1}), so W = diag(||A(:, i)||^{-2}) R
+ * (a zero column keeps P(i, i) = 1); RL_PREC_NONE uses W = R. */
+#define RL_PREC_SKETCH 0 /* P = R^{-1} from the QR of S*A (the method) */
+#define RL_PREC_DIAG 1
+#define RL_PREC_NONE 2
+
 typedef struct rl_ctx* rl_handle;
 
 /* Options.  rl_default_opts fills the paper's defaults. */
@@ -73,7 +82,8 @@ typedef struct {
   int32_t lanczos_steps; /* Golub-Kahan steps for Sigma~(1,1); default min(n, 64) */
   int32_t profile;    /* 1: time the pass kernels of every A-stream launch with HIP events (rl_info.t_astream_us) */
   int32_t sketch_prec; /* RL_SKETCH_*: precision of the sketch S*A and its QR (real A only); default FP64 */
-  int32_t reserved[4];
+  int32_t loop_precond; /* RL_PREC_*: preconditioner of the LOBPCG loop; default RL_PREC_SKETCH */
+  int32_t reserved[3];
 } rl_opts;
 
 /* Per-solve report (host).  theta_hist / rnorm_hist are optional host arrays

@@ -69,6 +69,13 @@ hipError_t launch_panel(hipStream_t st, bool cplx, void* AV, void* AX, const voi
 hipError_t launch_final_u(hipStream_t st, bool cplx, const void* AV, const void* AX, const void* AW, int64_t m, int B,
                           int k, const void* CV, const double* thb, void* U, int64_t ldu, const Ctl* ctl);
 
+// precond.hip
+int64_t colnorm_groups(int64_t m);
+hipError_t launch_colnorm_scale(hipStream_t st, bool cplx, const double* A, int64_t lda_d, int64_t m, int n,
+                                double* part, double* dscale);
+hipError_t launch_prec_apply(hipStream_t st, bool cplx, int n, int B, const double* dscale, const void* R, void* W,
+                             const Ctl* ctl);
+
 // tsqr.hip
 int64_t tsqr_groups(int64_t m, int t);
 hipError_t launch_tsqr(hipStream_t st, bool cplx, const void* P0, int b0, const void* P1, int b1, const void* P2,

@@ -97,6 +97,7 @@ struct Layout {
   size_t ctl, ht, hr, Y, Yf, Tmf, part, Tm, Rrow, RH, Rinv, RinvH;
   size_t V, X, W, Z, Vn, G3, Rres;
   size_t AV, AX, AW, Gpart, Gtmp, tsA, tsB, CV, CX, thb, Ub, Vb;
+  size_t dsc, cnp;  // diagonal preconditioner scales and their partial sums
   size_t total;
   int KL;
 };
@@ -108,6 +109,7 @@ struct Problem {
   size_t es;
   int max_iter;
   int sketch_prec;
+  int loop_precond;
 };
 
 static Layout plan(const Problem& p, int64_t lds_budget) {
@@ -158,6 +160,9 @@ static Layout plan(const Problem& p, int64_t lds_budget) {
   L.tsB = a.take(es * (size_t)g * t * t);
   L.CV = a.take(es * 32 * 16);
   L.CX = a.take(es * 32 * 16);
+  const bool diag = p.loop_precond == RL_PREC_DIAG;
+  L.dsc = a.take(sizeof(double) * (size_t)(diag ? n : 1));
+  L.cnp = a.take(sizeof(double) * (size_t)(diag ? colnorm_groups(m) * ncols_d : 1));
   L.thb = a.take(sizeof(double) * 32);
   L.KL = (int)std::min<int64_t>(n, 64);
   L.Ub = a.take(es * (size_t)(L.KL + 1) * n);
@@ -221,6 +226,7 @@ static int check_opts(int64_t m, int64_t n, int32_t k, const rl_opts& o) {
   if (o.stop_rule < 0 || o.stop_rule > 2) return RL_ERR_ARG;
   if (o.init_iters < 0 || o.lanczos_steps < 1) return RL_ERR_ARG;
   if (o.sketch_prec < RL_SKETCH_F64 || o.sketch_prec > RL_SKETCH_BF16) return RL_ERR_ARG;
+  if (o.loop_precond < RL_PREC_SKETCH || o.loop_precond > RL_PREC_NONE) return RL_ERR_ARG;
   if (n > 1024 || o.block > 10) return RL_ERR_UNSUPPORTED;
   if (o.d > INT32_MAX / 2) return RL_ERR_ARG;
   return RL_OK;
@@ -253,7 +259,8 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   if (lda < n || ldv < k || (Uout && ldu < k)) return RL_ERR_ARG;
   if (cplx && o.sketch_prec != RL_SKETCH_F64) return RL_ERR_UNSUPPORTED;
   if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;
-  Problem p{m, n, o.d, o.block, k, o.zeta, cplx, (size_t)(cplx ? 16 : 8), o.max_iter, o.sketch_prec};
+  Problem p{m, n, o.d, o.block, k, o.zeta, cplx, (size_t)(cplx ? 16 : 8), o.max_iter, o.sketch_prec,
+            o.loop_precond};
   const Layout L = plan(p, h->lds_budget);
   // a previous solve that returned early may have left work on the second stream
   if (h->aux) CK(hipStreamWaitEvent(h->stream, h->join, 0));
@@ -337,6 +344,10 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   CK(launch_rr(st, cplx, (int)n, B, 1, 0, Rt, at<void>(ws, L.V), at<void>(ws, L.X), at<void>(ws, L.W),
                at<void>(ws, L.G3), at<void>(ws, L.Vn), at<void>(ws, L.Rres), at<void>(ws, L.CV), at<void>(ws, L.CX),
                at<double>(ws, L.thb), at<double>(ws, L.ht), at<double>(ws, L.hr), ctl));
+  // diagonal loop preconditioner: one more pass over A for the column norms
+  if (o.loop_precond == RL_PREC_DIAG)
+    CK(launch_colnorm_scale(st, cplx, (const double*)A, lda * es_d, m, (int)n, at<double>(ws, L.cnp),
+                            at<double>(ws, L.dsc)));
   CK(hipStreamWaitEvent(st, h->join, 0));
   CK(launch_publish(st, ctl, h->host_ctl_dev));
   CK(hipEventRecord(h->ev[1], st));
@@ -348,8 +359,15 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   for (; it < o.max_iter; ++it) {
     CK(launch_panel(st, cplx, at<void>(ws, L.AV), at<void>(ws, L.AX), at<void>(ws, L.AW), m, B, at<void>(ws, L.CV),
                     at<void>(ws, L.CX), ctl));
-    CK(launch_trmv(st, cplx, B, at<void>(ws, L.RinvH), (int)n, 1, at<void>(ws, L.Rres), at<void>(ws, L.Z), ctl, 1));
-    CK(launch_trmv(st, cplx, B, at<void>(ws, L.Rinv), (int)n, 0, at<void>(ws, L.Z), at<void>(ws, L.W), ctl, 1));
+    if (o.loop_precond == RL_PREC_SKETCH) {
+      CK(launch_trmv(st, cplx, B, at<void>(ws, L.RinvH), (int)n, 1, at<void>(ws, L.Rres), at<void>(ws, L.Z), ctl,
+                     1));
+      CK(launch_trmv(st, cplx, B, at<void>(ws, L.Rinv), (int)n, 0, at<void>(ws, L.Z), at<void>(ws, L.W), ctl, 1));
+    } else {
+      CK(launch_prec_apply(st, cplx, (int)n, B,
+                           o.loop_precond == RL_PREC_DIAG ? at<double>(ws, L.dsc) : (const double*)nullptr,
+                           at<void>(ws, L.Rres), at<void>(ws, L.W), ctl));
+    }
     const int with_x = it > 0 ? 1 : 0;
     CK(launch_orth(st, cplx, (int)n, B, at<void>(ws, L.V), at<void>(ws, L.X), 1, with_x, at<void>(ws, L.W), ctl, 1));
     if (prof) CK(hipEventRecord(h->prof[2 * nprof], st));
@@ -386,7 +404,7 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   if (info) {
     info->status = status;
     info->iters = fc.iter;
-    info->a_passes = 2 + fc.iter;
+    info->a_passes = 2 + fc.iter + (o.loop_precond == RL_PREC_DIAG ? 1 : 0);
     info->degenerate = fc.degenerate;
     info->zero_theta = fc.zero_theta;
     info->block = B;
@@ -420,7 +438,8 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
 // Workspace bytes one solve of this shape and these options needs (the
 // server's admission unit).
 static int64_t planned_bytes(bool cplx, int64_t m, int64_t n, int32_t k, const rl_opts& o, int64_t lds_budget) {
-  Problem p{m, n, o.d, o.block, k, o.zeta, cplx, (size_t)(cplx ? 16 : 8), o.max_iter, o.sketch_prec};
+  Problem p{m, n, o.d, o.block, k, o.zeta, cplx, (size_t)(cplx ? 16 : 8), o.max_iter, o.sketch_prec,
+            o.loop_precond};
   return (int64_t)plan(p, lds_budget).total;
 }
 
