@@ -36,6 +36,9 @@ Readings where the paper is silent (each listed in the design doc):
   * ``loop_precond`` swaps the loop's preconditioner for the diagonal one
     (P = diag(||A(:, i)||^{-1})) or none, keeping the sketch-and-solve start
     (Sec. 1.1 initialises every compared method with v_0).
+  * ``orth="svqb"`` replaces Orth(W) after the two block projections by
+    SVQB (Gram matrix, eigendecomposition), the faster, less stable option
+    the paper names for this step.
   * ``dot2=True`` computes every product with A (A V_0, A W, the refresh) and
     the residual's A^* A_V as Dot2-class sums (``oracle.eft``); without it the
     FP64 rounding floor of those products, not the iteration, limits the
@@ -93,11 +96,32 @@ def _orth(M: np.ndarray):
     return Q, False
 
 
+def _svqb(M: np.ndarray):
+    """Orth by SVQB (Stathopoulos and Wu, the faster alternative the paper
+    names for the orthogonalisation step): G = M^* M scaled to unit diagonal,
+    D G D = Z Lambda Z^*, result M D Z Lambda^{-1/2}.  Eigenvalues below
+    eps * max(Lambda) are raised to that value (their safeguard); a zero
+    column, or a block with no positive eigenvalue, falls back to Orth."""
+    G = _ct(M) @ M
+    dg = np.real(np.diag(G))
+    if np.any(dg <= 0.0) or not np.all(np.isfinite(dg)):
+        Q, _ = _orth(M)
+        return Q, True
+    dsc = 1.0 / np.sqrt(dg)
+    lam, Z = np.linalg.eigh(dsc[:, None] * G * dsc[None, :])
+    lmax = float(lam.max())
+    if not lmax > 0.0:
+        Q, _ = _orth(M)
+        return Q, True
+    lam = np.maximum(lam, EPS_MATLAB * lmax)
+    return M @ (dsc[:, None] * Z / np.sqrt(lam)[None, :]), False
+
+
 def rlobpcg(A, k: int, *, block: int | None = None, d: int | None = None,
             zeta: int = 8, seed: int = 0, tau: float | None = None,
             max_iter: int | None = None, rule: str = "paper", check_every: int = 5,
             precond: str = "svd", dot2: bool = True, refresh: bool = False,
-            loop_precond: str = "sketch", callback=None) -> RLResult:
+            loop_precond: str = "sketch", orth: str = "cgs2", callback=None) -> RLResult:
     """Return the k smallest singular triplets of the tall matrix A."""
     A = np.asarray(A)
     if A.ndim != 2:
@@ -157,6 +181,15 @@ def rlobpcg(A, k: int, *, block: int | None = None, d: int | None = None,
             return Rm.copy()
     elif loop_precond != "sketch":
         raise ValueError(f"unknown loop_precond {loop_precond!r}")
+    # Orth of W after the two block projections on [V X]: Householder QR
+    # (the CGS2 of the paper yields the same orthonormal basis up to rounding
+    # and column signs) or SVQB.
+    if orth == "cgs2":
+        orth_fn = _orth
+    elif orth == "svqb":
+        orth_fn = _svqb
+    else:
+        raise ValueError(f"unknown orth {orth!r}")
 
     # Step 3: sketch-and-solve start.
     AV = mulA(V)
@@ -184,7 +217,7 @@ def rlobpcg(A, k: int, *, block: int | None = None, d: int | None = None,
         W = apply_prec(R)
         B = np.hstack([V, X])
         W = W - B @ (_ct(B) @ W)
-        W, flag = _orth(W - B @ (_ct(B) @ W))
+        W, flag = orth_fn(W - B @ (_ct(B) @ W))
         degenerate |= flag
         T = np.hstack([V, X, W])
         AT = np.hstack([AV, AX, mulA(W)])

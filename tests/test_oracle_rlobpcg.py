@@ -255,3 +255,42 @@ def test_loop_precond_rejects_unknown():
     A = np.random.default_rng(0).standard_normal((200, 12))
     with pytest.raises(ValueError):
         rlobpcg(A, 1, loop_precond="jacobi")
+
+
+def test_svqb_is_an_orthonormal_basis_of_the_same_span():
+    """SVQB returns orthonormal columns spanning span(W) (checked against the
+    Householder QR basis); its loss of orthogonality grows like eps * cond^2
+    (Stathopoulos and Wu), so an ill-conditioned block stays within that."""
+    from oracle.rlobpcg import _svqb
+    rng = np.random.default_rng(9)
+    W = rng.standard_normal((60, 5)) * np.array([1.0, 3.0, 0.5, 10.0, 2.0])[None, :]
+    Q, flag = _svqb(W)
+    assert not flag
+    assert np.linalg.norm(Q.T @ Q - np.eye(5)) <= 1e-14
+    assert _sin_angle(Q, W) <= 1e-14
+    U, _ = np.linalg.qr(rng.standard_normal((60, 4)))
+    Vt, _ = np.linalg.qr(rng.standard_normal((4, 4)))
+    Wc = (U * np.array([1.0, 1e-2, 1e-4, 1e-6])[None, :]) @ Vt.T
+    Qc, _ = _svqb(Wc)
+    assert np.linalg.norm(Qc.T @ Qc - np.eye(4)) <= 1e3 * 2.0 ** -52 * 1e12
+    assert _sin_angle(Qc[:, :], Wc) <= 1e-4
+    Zc = np.zeros((20, 3)) + 1j * 0.0
+    Zc[:, 0] = 1.0
+    _, flag = _svqb(Zc)
+    assert flag                                    # zero columns fall back to Orth
+
+
+def test_svqb_solve_reaches_dense_triplets():
+    """RLOBPCG with SVQB in the orthogonalisation step converges to the dense
+    SVD's smallest triplets on a block problem with a gap.  (Here the paper's
+    stagnation test does not fire before max_iter with SVQB, while it stops
+    the CGS2 run at iteration 81: the triplets are reached either way.)"""
+    m, n, k = 3000, 40, 3
+    s = spectrum_gap(n, k, 1e-6, 10.0)
+    A, _, s = planted_numpy(m, n, s, 77)
+    r = rlobpcg(A, k, seed=4, orth="svqb")
+    sv, Vd = _dense(A)
+    assert np.max(np.abs(r.sigma - sv[::-1][:k])) <= 1e-12 * sv[0]
+    assert _sin_angle(r.V, Vd[:, -k:]) <= 1e-10
+    with pytest.raises(ValueError):
+        rlobpcg(A, k, orth="mgs")
