@@ -218,6 +218,8 @@ def main(argv=None):
     ap.add_argument("--sketch-prec", default="f64", choices=["f64", "f32", "bf16"],
                     help="precision of the sketch and its QR (the rest stays FP64)")
     ap.add_argument("--no-dot2", action="store_true", help="plain FP64 products of A (no compensation)")
+    ap.add_argument("--orth", default="cgs2", choices=["cgs2", "svqb"],
+                    help="Orth of the new search block after its block projections: CGS2 (the method) or SVQB")
     ap.add_argument("--loop-precond", default="sketch", choices=["sketch", "diag", "none"],
                     help="preconditioner of the LOBPCG loop: the sketch's (the method) or the diagonal / no "
                          "preconditioner of the paper's comparison methods (same sketch-and-solve start)")
@@ -255,7 +257,7 @@ def main(argv=None):
     torch.cuda.synchronize()
     es = 16 if cplx else 8
     kw = dict(seed=sseed, d=d, zeta=zeta, sketch_prec=args.sketch_prec, dot2=not args.no_dot2,
-              loop_precond=args.loop_precond)
+              loop_precond=args.loop_precond, orth=args.orth)
 
     for w in range(args.warmup):
         r = rl.rl_svds_smallest(A, k, **kw)
@@ -315,7 +317,8 @@ def main(argv=None):
     bytes_launch = tot_bytes / max(n_as, 1)
     achieved = bytes_launch / (avg_us * 1e-6) / 1e9
     traffic = (measured_traffic(args.workload)
-               if (args.sketch_prec == "f64" and not args.no_dot2 and args.loop_precond == "sketch") else None)
+               if (args.sketch_prec == "f64" and not args.no_dot2 and args.loop_precond == "sketch"
+                   and args.orth == "cgs2") else None)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": astream_kernel(cplx, n, last.block), "avg_launch_us": round(avg_us, 2),
@@ -352,7 +355,7 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "k": k, "d": d, "zeta": zeta,
                    "spectrum": list(spec), "stop_rule": "paper", "dot2": not args.no_dot2,
-                   "sketch_prec": args.sketch_prec, "loop_precond": args.loop_precond},
+                   "sketch_prec": args.sketch_prec, "loop_precond": args.loop_precond, "orth": args.orth},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail": {"iters": last.iters, "a_passes": last.a_passes, "status": last.status,

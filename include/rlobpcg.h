@@ -65,6 +65,14 @@ extern "C" {
 #define RL_PREC_DIAG 1
 #define RL_PREC_NONE 2
 
+/* Orth of the new search block W in the loop (rl_opts.orth), after its two
+ * block projections on [V X] (Sec. 2.1: CGS2; SVQB is the faster, less stable
+ * alternative the paper names).  RL_ORTH_SVQB forms G = W^* W, scales it to a
+ * unit diagonal D G D, takes its eigenvectors Z and eigenvalues Lambda (raised
+ * to eps * max where smaller) and sets W <- W D Z Lambda^{-1/2}. */
+#define RL_ORTH_CGS2 0
+#define RL_ORTH_SVQB 1
+
 typedef struct rl_ctx* rl_handle;
 
 /* Options.  rl_default_opts fills the paper's defaults. */
@@ -83,7 +91,8 @@ typedef struct {
   int32_t profile;    /* 1: time the pass kernels of every A-stream launch with HIP events (rl_info.t_astream_us) */
   int32_t sketch_prec; /* RL_SKETCH_*: precision of the sketch S*A and its QR (real A only); default FP64 */
   int32_t loop_precond; /* RL_PREC_*: preconditioner of the LOBPCG loop; default RL_PREC_SKETCH */
-  int32_t reserved[3];
+  int32_t orth;       /* RL_ORTH_*: Orth of W in the loop after the block projections; default RL_ORTH_CGS2 */
+  int32_t reserved[2];
 } rl_opts;
 
 /* Per-solve report (host).  theta_hist / rnorm_hist are optional host arrays

@@ -34,6 +34,7 @@ RL_SKETCH_F32 = 1
 RL_SKETCH_BF16 = 2
 SKETCH_PRECS = {"f64": RL_SKETCH_F64, "f32": RL_SKETCH_F32, "bf16": RL_SKETCH_BF16}
 LOOP_PRECONDS = {"sketch": 0, "diag": 1, "none": 2}  # RL_PREC_*
+ORTHS = {"cgs2": 0, "svqb": 1}  # RL_ORTH_*
 STOP_RULES = {"paper": 0, "tol": 1, "none": 2}
 
 EXPORTED = (
@@ -61,7 +62,8 @@ class RlOpts(ctypes.Structure):
         ("profile", ctypes.c_int32),
         ("sketch_prec", ctypes.c_int32),
         ("loop_precond", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("orth", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -264,7 +266,7 @@ class SolveResult:
 
 def make_opts(m: int, n: int, k: int, *, block=None, d=None, zeta=None, seed=0, tau=None, max_iter=None,
               check_every=None, rule="paper", dot2=None, init_iters=None, lanczos_steps=None,
-              profile=False, sketch_prec="f64", loop_precond="sketch") -> RlOpts:
+              profile=False, sketch_prec="f64", loop_precond="sketch", orth="cgs2") -> RlOpts:
     o = default_opts(m, n, k if block is None else block)
     o.block = k if block is None else block
     if block is not None:
@@ -290,6 +292,7 @@ def make_opts(m: int, n: int, k: int, *, block=None, d=None, zeta=None, seed=0, 
     o.profile = int(bool(profile))
     o.sketch_prec = SKETCH_PRECS[sketch_prec]
     o.loop_precond = LOOP_PRECONDS[loop_precond]
+    o.orth = ORTHS[orth]
     return o
 
 

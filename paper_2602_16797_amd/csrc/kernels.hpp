@@ -88,6 +88,8 @@ hipError_t launch_publish(hipStream_t st, const Ctl* src, Ctl* dst);
 // nside.hip
 hipError_t launch_trmv(hipStream_t st, bool cplx, int B, const void* M, int n, int lower, const void* X, void* Y,
                        const Ctl* ctl, int check_done);
+hipError_t launch_orth_svqb(hipStream_t st, bool cplx, int n, int B, const void* V, const void* X, int project,
+                            int with_x, void* W, Ctl* ctl, int check_done);
 hipError_t launch_orth(hipStream_t st, bool cplx, int n, int B, const void* V, const void* X, int project, int with_x,
                        void* W, Ctl* ctl, int check_done);
 hipError_t launch_rr(hipStream_t st, bool cplx, int n, int B, int init_mode, int with_x, const void* Rt, void* V,

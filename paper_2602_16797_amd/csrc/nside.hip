@@ -8,6 +8,8 @@
 // k_orth     BCGS2 of W against [V X] (two classical Gram-Schmidt passes,
 //            Alg. rlobpcg) followed by Orth(W) as column-wise CGS2 (b = 1:
 //            Normalize, Alg. rlopcg).
+// k_orth_svqb the same two block projections, then Orth(W) by SVQB (the
+//            faster, less stable choice the paper names for this step).
 // k_rr       Rayleigh-Ritz from R_T (the TSQR factor of A_T): one-sided Jacobi
 //            SVD of R_T gives Theta and C (descending, as MATLAB's svd); then
 //            V = T C(:, t-b+1:t), the residual R = G_T C(:, t-b+1:t) - V Theta_b^2
@@ -90,8 +92,8 @@ __global__ __launch_bounds__(NS_THREADS) void k_trmv(const T* __restrict__ M, in
 // that keeps norm above 1/2 after the same projections.
 template <typename T, int KM>
 __device__ void orth_project(int n, int B, int j, const T* __restrict__ V, const T* __restrict__ X, int nvx,
-                             T* __restrict__ W, T* scratch, T* h) {
-  const int K = nvx + j;
+                             T* __restrict__ W, T* scratch, T* h, int kw) {
+  const int K = nvx + kw;  // [V X] and the first kw columns of W
   // the K projections are summed in chunks of ORTH_KC, so the per-thread
   // partial sums stay in registers for any b
   for (int k0 = 0; k0 < K; k0 += ORTH_KC) {
@@ -147,12 +149,12 @@ __device__ void orth_block(int n, int B, const T* __restrict__ V, const T* __res
         __syncthreads();
       }
       if (nvx + j > 0) {
-        orth_project<T, KM>(n, B, j, V, X, nvx, W, scratch, h);
+        orth_project<T, KM>(n, B, j, V, X, nvx, W, scratch, h, j);
         const double n1 = col_norm<T>(n, B, j, W, red);
-        orth_project<T, KM>(n, B, j, V, X, nvx, W, scratch, h);
+        orth_project<T, KM>(n, B, j, V, X, nvx, W, scratch, h, j);
         nrm = col_norm<T>(n, B, j, W, red);
         if (nrm < 0.5 * n1) {
-          orth_project<T, KM>(n, B, j, V, X, nvx, W, scratch, h);
+          orth_project<T, KM>(n, B, j, V, X, nvx, W, scratch, h, j);
           nrm = col_norm<T>(n, B, j, W, red);
         }
       } else {
@@ -174,6 +176,100 @@ __global__ __launch_bounds__(NS_THREADS) void k_orth(int n, int B, const T* __re
                                                      int check_done) {
   if (check_done && ctl->done) return;
   orth_block<T, KM>(n, B, V, X, project, with_x, W, ctl);
+}
+
+template <typename T>
+__device__ void jacobi_block(T* M, T* Vj, int t);
+
+// W <- Orth(W - [V X]([V X]^* W)) with the two block projections of BCGS2
+// and SVQB (Stathopoulos and Wu) for Orth: G = W^* W, D = diag(G)^{-1/2},
+// D G D = Z Lambda Z^* by one-sided Jacobi on D G D (Hermitian positive
+// semidefinite, so its singular vectors are its eigenvectors and the column
+// norms after the rotations its eigenvalues), eigenvalues below
+// eps * max raised to it, W <- W D Z Lambda^{-1/2}.  A column that vanishes
+// after the projections (zero diagonal of G) hands the block to orth_block.
+template <typename T, int KM>
+__global__ __launch_bounds__(NS_THREADS) void k_orth_svqb(int n, int B, const T* __restrict__ V,
+                                                          const T* __restrict__ X, int project, int with_x,
+                                                          T* __restrict__ W, Ctl* __restrict__ ctl, int check_done) {
+  if (check_done && ctl->done) return;
+  __shared__ T scratch[(NS_THREADS / 16) * ORTH_KC];
+  __shared__ T h[KM];
+  __shared__ T M[RR_TMAX * 32];   // D G D, rotated in place (column-major, ld 32)
+  __shared__ T Vj[RR_TMAX * 32];  // Z
+  __shared__ T Gs[RR_BMAX * RR_BMAX];
+  __shared__ T Fm[RR_BMAX * RR_BMAX];  // D Z Lambda^{-1/2}, row-major B x B
+  __shared__ double dsc[RR_BMAX], lam[RR_BMAX];
+  __shared__ int fallback;
+  const int tid = threadIdx.x;
+  const int nvx = project ? (with_x ? 2 * B : B) : 0;
+  if (nvx > 0) {
+    for (int pass = 0; pass < 2; ++pass)
+      for (int j = 0; j < B; ++j) orth_project<T, KM>(n, B, j, V, X, nvx, W, scratch, h, 0);
+  }
+  // Gram matrix G(p, q) = W(:, p)^* W(:, q), in chunks of ORTH_KC entries
+  const int npair = B * B;
+  for (int e0 = 0; e0 < npair; e0 += ORTH_KC) {
+    T vals[ORTH_KC];
+#pragma unroll
+    for (int kk = 0; kk < ORTH_KC; ++kk) vals[kk] = zero<T>();
+    for (int r = tid; r < n; r += blockDim.x) {
+#pragma unroll
+      for (int kk = 0; kk < ORTH_KC; ++kk) {
+        const int e = e0 + kk;
+        if (e < npair) vals[kk] = cfmac(W[(int64_t)r * B + e / B], W[(int64_t)r * B + e % B], vals[kk]);
+      }
+    }
+    block_sum_many<T, ORTH_KC>(vals, (npair - e0 < ORTH_KC) ? npair - e0 : ORTH_KC, scratch, Gs + e0);
+  }
+  if (tid == 0) {
+    fallback = 0;
+    for (int p = 0; p < B; ++p) {
+      const double g = re_(Gs[p * B + p]);
+      if (!(g > 0.0) || !isfinite(g)) fallback = 1;
+      dsc[p] = (g > 0.0) ? 1.0 / sqrt(g) : 1.0;
+    }
+  }
+  __syncthreads();
+  if (fallback) {
+    if (tid == 0) ctl->degenerate = 1;
+    orth_block<T, KM>(n, B, V, X, project, with_x, W, ctl);
+    return;
+  }
+  for (int e = tid; e < RR_TMAX * 32; e += blockDim.x) {
+    const int c = e / 32, r = e % 32;
+    M[e] = (r < B && c < B) ? scal(Gs[r * B + c], dsc[r] * dsc[c]) : zero<T>();
+    Vj[e] = from_real<T>((r == c) ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  jacobi_block<T>(M, Vj, B);
+  if (tid < 64) {
+    const int lane = tid;
+    double lmax = 0.0;
+    for (int c = 0; c < B; ++c) {
+      const T v = (lane < B) ? M[c * 32 + lane] : zero<T>();
+      const double l = sqrt(wave_sum(abs2(v)));
+      if (lane == 0) lam[c] = l;
+      lmax = fmax(lmax, l);
+    }
+    if (lane == 0)
+      for (int c = 0; c < B; ++c) lam[c] = fmax(lam[c], 2.220446049250313e-16 * lmax);
+  }
+  __syncthreads();
+  for (int e = tid; e < B * B; e += blockDim.x) {
+    const int p = e / B, q = e % B;
+    Fm[e] = scal(Vj[q * 32 + p], dsc[p] / sqrt(lam[q]));
+  }
+  __syncthreads();
+  for (int r = tid; r < n; r += blockDim.x) {
+    T wr[RR_BMAX];
+    for (int p = 0; p < B; ++p) wr[p] = W[(int64_t)r * B + p];
+    for (int q = 0; q < B; ++q) {
+      T acc = zero<T>();
+      for (int p = 0; p < B; ++p) acc = fmac(wr[p], Fm[p * B + q], acc);
+      W[(int64_t)r * B + q] = acc;
+    }
+  }
 }
 
 
@@ -805,6 +901,32 @@ static void orth_dispatch(hipStream_t st, int n, int B, const void* V, const voi
   else if (need <= 16) orth_go<T, 16>(st, n, B, V, X, project, with_x, W, ctl, check_done);
   else if (need <= 32) orth_go<T, 32>(st, n, B, V, X, project, with_x, W, ctl, check_done);
   else orth_go<T, 3 * RR_BMAX>(st, n, B, V, X, project, with_x, W, ctl, check_done);
+}
+
+template <typename T, int KM>
+static void svqb_go(hipStream_t st, int n, int B, const void* V, const void* X, int project, int with_x, void* W,
+                    Ctl* ctl, int check_done) {
+  hipLaunchKernelGGL((k_orth_svqb<T, KM>), dim3(1), dim3(NS_THREADS), 0, st, n, B, (const T*)V, (const T*)X, project,
+                     with_x, (T*)W, ctl, check_done);
+}
+
+template <typename T>
+static void svqb_dispatch(hipStream_t st, int n, int B, const void* V, const void* X, int project, int with_x,
+                          void* W, Ctl* ctl, int check_done) {
+  const int need = 3 * B;
+  if (need <= 4) svqb_go<T, 4>(st, n, B, V, X, project, with_x, W, ctl, check_done);
+  else if (need <= 8) svqb_go<T, 8>(st, n, B, V, X, project, with_x, W, ctl, check_done);
+  else if (need <= 16) svqb_go<T, 16>(st, n, B, V, X, project, with_x, W, ctl, check_done);
+  else if (need <= 32) svqb_go<T, 32>(st, n, B, V, X, project, with_x, W, ctl, check_done);
+  else svqb_go<T, 3 * RR_BMAX>(st, n, B, V, X, project, with_x, W, ctl, check_done);
+}
+
+hipError_t launch_orth_svqb(hipStream_t st, bool cplx, int n, int B, const void* V, const void* X, int project,
+                            int with_x, void* W, Ctl* ctl, int check_done) {
+  if (B < 1 || B > RR_BMAX) return hipErrorInvalidValue;
+  if (cplx) svqb_dispatch<cd>(st, n, B, V, X, project, with_x, W, ctl, check_done);
+  else svqb_dispatch<double>(st, n, B, V, X, project, with_x, W, ctl, check_done);
+  return hipGetLastError();
 }
 
 hipError_t launch_orth(hipStream_t st, bool cplx, int n, int B, const void* V, const void* X, int project, int with_x,

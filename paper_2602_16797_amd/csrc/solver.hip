@@ -227,6 +227,7 @@ static int check_opts(int64_t m, int64_t n, int32_t k, const rl_opts& o) {
   if (o.init_iters < 0 || o.lanczos_steps < 1) return RL_ERR_ARG;
   if (o.sketch_prec < RL_SKETCH_F64 || o.sketch_prec > RL_SKETCH_BF16) return RL_ERR_ARG;
   if (o.loop_precond < RL_PREC_SKETCH || o.loop_precond > RL_PREC_NONE) return RL_ERR_ARG;
+  if (o.orth < RL_ORTH_CGS2 || o.orth > RL_ORTH_SVQB) return RL_ERR_ARG;
   if (n > 1024 || o.block > 10) return RL_ERR_UNSUPPORTED;
   if (o.d > INT32_MAX / 2) return RL_ERR_ARG;
   return RL_OK;
@@ -369,7 +370,12 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
                            at<void>(ws, L.Rres), at<void>(ws, L.W), ctl));
     }
     const int with_x = it > 0 ? 1 : 0;
-    CK(launch_orth(st, cplx, (int)n, B, at<void>(ws, L.V), at<void>(ws, L.X), 1, with_x, at<void>(ws, L.W), ctl, 1));
+    if (o.orth == RL_ORTH_SVQB)
+      CK(launch_orth_svqb(st, cplx, (int)n, B, at<void>(ws, L.V), at<void>(ws, L.X), 1, with_x, at<void>(ws, L.W),
+                          ctl, 1));
+    else
+      CK(launch_orth(st, cplx, (int)n, B, at<void>(ws, L.V), at<void>(ws, L.X), 1, with_x, at<void>(ws, L.W), ctl,
+                     1));
     if (prof) CK(hipEventRecord(h->prof[2 * nprof], st));
     CK(launch_astream(st, cplx, B, dot2, A, lda, m, (int)n, at<void>(ws, L.W), at<void>(ws, L.AW),
                       at<void>(ws, L.AV), with_x ? at<void>(ws, L.AX) : nullptr, 0, at<double>(ws, L.Gpart),

@@ -53,7 +53,7 @@ def test_struct_layout_matches_ctypes(tmp_path):
         "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(rl_opts), sizeof(rl_info),"
         " offsetof(rl_opts, tau), offsetof(rl_opts, lanczos_steps), offsetof(rl_info, sigma1),"
         " offsetof(rl_info, hist_cap), offsetof(rl_info, rnorm_hist));"
-        "printf(\"%zu %zu\\n\", offsetof(rl_opts, sketch_prec), offsetof(rl_opts, loop_precond));"
+        "printf(\"%zu %zu %zu\\n\", offsetof(rl_opts, sketch_prec), offsetof(rl_opts, loop_precond), offsetof(rl_opts, orth));"
         "printf(\"%zu %zu %zu %zu\\n\", sizeof(rl_request), offsetof(rl_request, opts), offsetof(rl_request, ldu),"
         " sizeof(rl_job_times));return 0;}\n")
     exe = tmp_path / "layout"
@@ -61,7 +61,7 @@ def test_struct_layout_matches_ctypes(tmp_path):
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     O, I = rl.RlOpts, rl.RlInfo
     assert vals == [ctypes.sizeof(O), ctypes.sizeof(I), O.tau.offset, O.lanczos_steps.offset, I.sigma1.offset,
-                    I.hist_cap.offset, I.rnorm_hist.offset, O.sketch_prec.offset, O.loop_precond.offset,
+                    I.hist_cap.offset, I.rnorm_hist.offset, O.sketch_prec.offset, O.loop_precond.offset, O.orth.offset,
                     ctypes.sizeof(rl.RlRequest), rl.RlRequest.opts.offset, rl.RlRequest.ldu.offset,
                     ctypes.sizeof(rl.RlJobTimes)]
 
