@@ -17,10 +17,12 @@ hipError_t launch_sketch(hipStream_t st, const double* A, int64_t lda_d, int64_t
                          int64_t lds_budget, bool fp32);
 
 // qr.hip
+// r_ready (optional) is recorded on st once R is complete (in Y and Rrow),
+// before the inverses are formed.
 hipError_t launch_qr_lowp(hipStream_t st, float* Yf, int d, int n, float* Tmf, double* Y, double* Rrow, double* RH,
-                          double* Rinv, double* RinvH, bool bf16);
+                          double* Rinv, double* RinvH, bool bf16, hipEvent_t r_ready = nullptr);
 hipError_t launch_qr(hipStream_t st, bool cplx, void* Y, int d, int n, void* Tm, void* Rrow, void* RH, void* Rinv,
-                     void* RinvH);
+                     void* RinvH, hipEvent_t r_ready = nullptr);
 
 // astream.hip
 int astream_ns(int n);

@@ -641,9 +641,15 @@ static void qr_factor(hipStream_t st, T* Y, int d, int n, T* Tm) {
 
 // R (upper triangle of Y) in row-major form and R^{-1}, R^{-*}.
 template <typename T>
-static hipError_t qr_finish(hipStream_t st, const T* Y, int d, int n, T* Rrow, T* RH, T* Rinv, T* RinvH) {
+static hipError_t qr_finish(hipStream_t st, const T* Y, int d, int n, T* Rrow, T* RH, T* Rinv, T* RinvH,
+                            hipEvent_t r_ready) {
   const int64_t nn = (int64_t)n * n;
   hipLaunchKernelGGL(k_qr_extract<T>, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, Y, d, n, Rrow, RH);
+  // R is complete here (in Y and Rrow); the inverses follow
+  if (r_ready != nullptr) {
+    const hipError_t e = hipEventRecord(r_ready, st);
+    if (e != hipSuccess) return e;
+  }
   const size_t lds = (size_t)4 * n * sizeof(T);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void*)k_trinv<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -654,9 +660,10 @@ static hipError_t qr_finish(hipStream_t st, const T* Y, int d, int n, T* Rrow, T
 }
 
 template <typename T>
-static hipError_t qr_impl(hipStream_t st, T* Y, int d, int n, T* Tm, T* Rrow, T* RH, T* Rinv, T* RinvH) {
+static hipError_t qr_impl(hipStream_t st, T* Y, int d, int n, T* Tm, T* Rrow, T* RH, T* Rinv, T* RinvH,
+                          hipEvent_t r_ready) {
   qr_factor<T>(st, Y, d, n, Tm);
-  return qr_finish<T>(st, Y, d, n, Rrow, RH, Rinv, RinvH);
+  return qr_finish<T>(st, Y, d, n, Rrow, RH, Rinv, RinvH, r_ready);
 }
 
 // Upper triangle (rows 0..n-1) of the FP32 factor into the FP64 Y (ld d).
@@ -668,18 +675,18 @@ __global__ void k_promote_upper(const float* __restrict__ Yf, int d, int n, doub
 }
 
 hipError_t launch_qr(hipStream_t st, bool cplx, void* Y, int d, int n, void* Tm, void* Rrow, void* RH, void* Rinv,
-                     void* RinvH) {
+                     void* RinvH, hipEvent_t r_ready) {
   if (cplx)
-    return qr_impl<cd>(st, (cd*)Y, d, n, (cd*)Tm, (cd*)Rrow, (cd*)RH, (cd*)Rinv, (cd*)RinvH);
+    return qr_impl<cd>(st, (cd*)Y, d, n, (cd*)Tm, (cd*)Rrow, (cd*)RH, (cd*)Rinv, (cd*)RinvH, r_ready);
   return qr_impl<double>(st, (double*)Y, d, n, (double*)Tm, (double*)Rrow, (double*)RH, (double*)Rinv,
-                         (double*)RinvH);
+                         (double*)RinvH, r_ready);
 }
 
 // Reduced-precision QR of a real sketch: factor the FP32 Yf (trailing updates
 // in FP32, or with bfloat16 inputs and FP32 accumulation), promote R to FP64
 // into Y, then R^{-1} and the row-major copies in FP64.
 hipError_t launch_qr_lowp(hipStream_t st, float* Yf, int d, int n, float* Tmf, double* Y, double* Rrow, double* RH,
-                          double* Rinv, double* RinvH, bool bf16) {
+                          double* Rinv, double* RinvH, bool bf16, hipEvent_t r_ready) {
   if (bf16) qr_factor<float, true>(st, Yf, d, n, Tmf);
   else qr_factor<float, false>(st, Yf, d, n, Tmf);
   const int64_t nn = (int64_t)n * n;
@@ -687,7 +694,7 @@ hipError_t launch_qr_lowp(hipStream_t st, float* Yf, int d, int n, float* Tmf, d
                      Y);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return qr_finish<double>(st, Y, d, n, Rrow, RH, Rinv, RinvH);
+  return qr_finish<double>(st, Y, d, n, Rrow, RH, Rinv, RinvH, r_ready);
 }
 
 }  // namespace rl

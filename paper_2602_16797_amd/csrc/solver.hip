@@ -287,20 +287,22 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   CK(hipEventRecord(h->ev[0], st));
   CK(launch_publish(st, h->host_ctl_dev, ctl));
 
-  // Step 1-2: sketch and QR
+  // Step 1-2: sketch and QR (fork: recorded once R is complete)
+  rc = ensure_aux(h);
+  if (rc != RL_OK) return rc;
   const double scale = 1.0 / sqrt((double)o.zeta);
   if (o.sketch_prec == RL_SKETCH_F64) {
     CK(launch_sketch(st, (const double*)A, lda * es_d, m, n * es_d, es_d, (int)o.d, o.zeta, o.seed, scale,
                      at<void>(ws, L.part), at<void>(ws, L.Y), ctl, h->lds_budget, false));
     CK(launch_qr(st, cplx, at<void>(ws, L.Y), (int)o.d, (int)n, at<void>(ws, L.Tm), at<void>(ws, L.Rrow),
-                 at<void>(ws, L.RH), at<void>(ws, L.Rinv), at<void>(ws, L.RinvH)));
+                 at<void>(ws, L.RH), at<void>(ws, L.Rinv), at<void>(ws, L.RinvH), h->fork));
   } else {
     // reduced-precision sketch and QR; R is promoted to FP64 for everything after
     CK(launch_sketch(st, (const double*)A, lda, m, n, 1, (int)o.d, o.zeta, o.seed, scale, at<void>(ws, L.part),
                      at<void>(ws, L.Yf), ctl, h->lds_budget, true));
     CK(launch_qr_lowp(st, at<float>(ws, L.Yf), (int)o.d, (int)n, at<float>(ws, L.Tmf), at<double>(ws, L.Y),
                       at<double>(ws, L.Rrow), at<double>(ws, L.RH), at<double>(ws, L.Rinv), at<double>(ws, L.RinvH),
-                      o.sketch_prec == RL_SKETCH_BF16));
+                      o.sketch_prec == RL_SKETCH_BF16, h->fork));
   }
   {
     const int64_t cnt = n * n * es_d;
@@ -308,11 +310,9 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
                        st, at<double>(ws, L.Rinv), cnt, ctl);
     CK(hipGetLastError());
   }
-  // Sigma~(1,1) on the second stream: it only reads R and writes sigma1, which
-  // the first stopping test needs; the start block proceeds meanwhile
-  rc = ensure_aux(h);
-  if (rc != RL_OK) return rc;
-  CK(hipEventRecord(h->fork, st));
+  // Sigma~(1,1) on the second stream from the moment R is complete (beside
+  // the inverses and the start block): it only reads R and writes sigma1,
+  // which the first stopping test needs
   CK(hipStreamWaitEvent(h->aux, h->fork, 0));
   const int KL = std::min<int>(L.KL, o.lanczos_steps);
   CK(launch_lanczos(h->aux, cplx, (int)n, at<void>(ws, L.Y), (int)o.d, at<void>(ws, L.Rrow), at<void>(ws, L.Ub),
