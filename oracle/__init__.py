@@ -20,8 +20,10 @@ Modules
 
 Every function is pinned by ``tests/test_oracle_*.py`` against facts fixed by
 the paper or by mathematics (dense LAPACK SVD on small inputs, planted
-spectra, exact rational arithmetic, the theory's inequalities); the pins and
-the one reading that stays "parity unpinned" are listed in the design doc.
+spectra, exact rational arithmetic, the theory's inequalities).  Parity
+unpinned: iteration counts against the paper's figures (not in its text) and
+the stagnation rule's literal typeset form, for which the equation form is
+implemented here and on the GPU alike.
 """
 
 from . import eft, sparsestack, termination  # noqa: F401

@@ -18,7 +18,7 @@ Steps, in the paper's order and notation (Sec. 1 steps 1-4; Sec. 2.1; Sec. 2.3):
        Q = Orth(C(1:b, 1:t-b)^*);  X = T C(:, 1:t-b) Q;  A_X = A_T C(:, 1:t-b) Q   [eq:x-defining]
   Output: sigma = Theta_b, V; here sorted ascending.
 
-Readings where the paper is silent (each listed in the design doc):
+Readings where the paper is silent:
   * The loop is written once for all b; with b = 1 it is Alg. rlopcg line by
     line (Normalize is Orth of one column; the b = 1 start keeps theta_0 = inf).
   * On the first pass X is empty, so t = 2b, V takes the last b columns of C
