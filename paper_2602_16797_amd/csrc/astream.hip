@@ -31,6 +31,7 @@
 #include "common.hpp"
 #include "astream_kernels.hpp"
 #include "kernels.hpp"
+#include "colsum.hpp"
 
 namespace rl {
 
@@ -38,50 +39,7 @@ namespace rl {
 // in_s[p*stride + e] and, for e < elen, errors at in_e[p*stride + e];
 // block y of the grid sums parts [64y, 64y+64) and writes (sum, error) to
 // out_s/out_e[y*len + e].
-__global__ __launch_bounds__(256) void k_colsum2(const double* __restrict__ in_s, const double* __restrict__ in_e,
-                                                 int64_t stride, int64_t elen, int64_t nparts, int64_t len,
-                                                 double* __restrict__ out_s, double* __restrict__ out_e,
-                                                 double* __restrict__ fin, const Ctl* __restrict__ ctl) {
-  if (ctl != nullptr && ctl->done) return;
-  __shared__ double sh_s[256], sh_e[256];
-  const int el = threadIdx.x & 63, g = threadIdx.x >> 6;  // 64 elements x 4 groups
-  const int64_t e = (int64_t)blockIdx.x * 64 + el;
-  const int64_t p0 = (int64_t)blockIdx.y * 64;
-  // the thread's 16 records are loaded together (one memory latency instead
-  // of one per record); records past the end are zeros, which change neither
-  // the sum nor its error
-  double vs[16], ve[16];
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int64_t p = p0 + g + 4 * u;
-    const bool ok = (e < len) && (p < nparts);
-    vs[u] = ok ? in_s[p * stride + e] : 0.0;
-    ve[u] = (ok && e < elen) ? in_e[p * stride + e] : 0.0;
-  }
-  double S = 0.0, E = 0.0;
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    double t;
-    two_sum(S, vs[u], S, t);
-    E += t + ve[u];
-  }
-  sh_s[threadIdx.x] = S;
-  sh_e[threadIdx.x] = E;
-  __syncthreads();
-  if (g == 0 && e < len) {
-    double s0 = sh_s[el], e0 = sh_e[el], t;
-    for (int q = 1; q < 4; ++q) {
-      two_sum(s0, sh_s[64 * q + el], s0, t);
-      e0 += t + sh_e[64 * q + el];
-    }
-    if (fin != nullptr) {
-      fin[e] = s0 + e0;  // single group: the finished sums
-    } else {
-      out_s[(int64_t)blockIdx.y * len + e] = s0;
-      out_e[(int64_t)blockIdx.y * len + e] = e0;
-    }
-  }
-}
+__global__ __launch_bounds__(256) void k_colsum2(ColsumJob J) { colsum2_block(J, blockIdx.x, blockIdx.y); }
 
 
 // Row-local panel update.  mode: 0 A_T = [A_V] (t = B), 1 [A_V A_W] (t = 2B),
@@ -238,9 +196,11 @@ hipError_t launch_astream_pass(hipStream_t st, bool cplx, int B, bool dot2, cons
   return hipGetLastError();
 }
 
-// Compensated reduction of the np partial records into G3 (n x 3B).
-hipError_t launch_astream_reduce(hipStream_t st, bool cplx, int B, int n, int64_t np, const double* Gpart,
-                                 double* tmp, double* G3, const Ctl* ctl) {
+// The levels of the compensated reduction of the np partial records into G3
+// (n x 3B): level 0 reads the records, each later level the previous level's
+// (sum, error) pairs, the last writes G3.  Returns the number of levels.
+int astream_reduce_plan(bool cplx, int B, int n, int64_t np, const double* Gpart, double* tmp, double* G3,
+                        const Ctl* ctl, ColsumJob* lev, int maxlev) {
   const int es_d = cplx ? 2 : 1;
   const int64_t plen = (int64_t)n * B * es_d;
   const int64_t len = 3 * plen;
@@ -248,16 +208,15 @@ hipError_t launch_astream_reduce(hipStream_t st, bool cplx, int B, int n, int64_
   const double* cur_s = Gpart;
   const double* cur_e = Gpart + len;
   int64_t stride = 4 * plen, elen = plen;
-  int flip = 0;
-  while (true) {
+  int flip = 0, nl = 0;
+  while (nl < maxlev) {
     const int64_t groups = (np + 63) / 64;
     double* ds = tmp + (int64_t)flip * 2 * g1 * len;
     double* de = ds + g1 * len;
-    hipLaunchKernelGGL(k_colsum2, dim3((unsigned)((len + 63) / 64), (unsigned)groups), dim3(256), 0, st, cur_s,
-                       cur_e, stride, elen, np, len, ds, de, groups == 1 ? G3 : nullptr, ctl);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (groups == 1) return hipSuccess;
+    ColsumJob& J = lev[nl++];
+    J = ColsumJob{cur_s, cur_e, stride, elen, np, len, ds, de, groups == 1 ? G3 : nullptr, ctl,
+                  (int)((len + 63) / 64), (int)groups};
+    if (groups == 1) return nl;
     cur_s = ds;
     cur_e = de;
     stride = len;
@@ -265,6 +224,24 @@ hipError_t launch_astream_reduce(hipStream_t st, bool cplx, int B, int n, int64_
     np = groups;
     flip ^= 1;
   }
+  return -1;
+}
+
+hipError_t launch_colsum_job(hipStream_t st, const ColsumJob& J) {
+  hipLaunchKernelGGL(k_colsum2, dim3((unsigned)J.gx, (unsigned)J.gy), dim3(256), 0, st, J);
+  return hipGetLastError();
+}
+
+hipError_t launch_astream_reduce(hipStream_t st, bool cplx, int B, int n, int64_t np, const double* Gpart,
+                                 double* tmp, double* G3, const Ctl* ctl) {
+  ColsumJob lev[16];
+  const int nl = astream_reduce_plan(cplx, B, n, np, Gpart, tmp, G3, ctl, lev, 16);
+  if (nl < 1) return hipErrorInvalidValue;
+  for (int i = 0; i < nl; ++i) {
+    const hipError_t e = launch_colsum_job(st, lev[i]);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const void* A, int64_t lda, int64_t m, int n,

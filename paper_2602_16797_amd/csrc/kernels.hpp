@@ -63,6 +63,20 @@ hipError_t launch_astream_pass(hipStream_t st, bool cplx, int B, bool dot2, cons
                                double* Gpart, const Ctl* ctl, int64_t* np_out);
 hipError_t launch_astream_reduce(hipStream_t st, bool cplx, int B, int n, int64_t np, const double* Gpart,
                                  double* tmp, double* G3, const Ctl* ctl);
+// One level of that reduction (k_colsum2): grid gx x gy of 256 threads.
+struct ColsumJob {
+  const double* in_s;
+  const double* in_e;
+  int64_t stride, elen, nparts, len;
+  double* out_s;
+  double* out_e;
+  double* fin;
+  const Ctl* ctl;
+  int gx, gy;
+};
+int astream_reduce_plan(bool cplx, int B, int n, int64_t np, const double* Gpart, double* tmp, double* G3,
+                        const Ctl* ctl, ColsumJob* lev, int maxlev);
+hipError_t launch_colsum_job(hipStream_t st, const ColsumJob& J);
 hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const void* A, int64_t lda, int64_t m, int n,
                           const void* W, void* AW, const void* AVp, const void* AXp, int init, double* Gpart,
                           double* tmp, double* G3, const Ctl* ctl, hipEvent_t pass_done = nullptr);
@@ -80,8 +94,11 @@ hipError_t launch_prec_apply(hipStream_t st, bool cplx, int n, int B, const doub
 
 // tsqr.hip
 int64_t tsqr_groups(int64_t m, int t);
+// side (optional): one level of the partial-sum reduction, run as extra
+// workgroups of the first TSQR launch (t <= 8) or launched just before it.
 hipError_t launch_tsqr(hipStream_t st, bool cplx, const void* P0, int b0, const void* P1, int b1, const void* P2,
-                       int b2, int64_t m, void* bufA, void* bufB, void** Rfinal, Ctl* ctl, int check_done);
+                       int b2, int64_t m, void* bufA, void* bufB, void** Rfinal, Ctl* ctl, int check_done,
+                       const ColsumJob* side = nullptr);
 
 // Copies the control block between device memory and the handle's mapped
 // host block (either direction) with vector stores.

@@ -377,12 +377,23 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
       CK(launch_orth(st, cplx, (int)n, B, at<void>(ws, L.V), at<void>(ws, L.X), 1, with_x, at<void>(ws, L.W), ctl,
                      1));
     if (prof) CK(hipEventRecord(h->prof[2 * nprof], st));
-    CK(launch_astream(st, cplx, B, dot2, A, lda, m, (int)n, at<void>(ws, L.W), at<void>(ws, L.AW),
-                      at<void>(ws, L.AV), with_x ? at<void>(ws, L.AX) : nullptr, 0, at<double>(ws, L.Gpart),
-                      at<double>(ws, L.Gtmp), at<double>(ws, L.G3), ctl, prof ? h->prof[2 * nprof + 1] : nullptr));
-    if (prof) ++nprof;
+    // the pass, then its partial sums reduced beside the TSQR of [A_V A_X A_W]
+    // (the first reduction level runs inside the first TSQR launch)
+    int64_t np = 0;
+    CK(launch_astream_pass(st, cplx, B, dot2, A, lda, m, (int)n, at<void>(ws, L.W), at<void>(ws, L.AW),
+                           at<void>(ws, L.AV), with_x ? at<void>(ws, L.AX) : nullptr, 0, at<double>(ws, L.Gpart),
+                           ctl, &np));
+    if (prof) {
+      CK(hipEventRecord(h->prof[2 * nprof + 1], st));
+      ++nprof;
+    }
+    ColsumJob lev[16];
+    const int nlev = astream_reduce_plan(cplx, B, (int)n, np, at<double>(ws, L.Gpart), at<double>(ws, L.Gtmp),
+                                         at<double>(ws, L.G3), ctl, lev, 16);
+    if (nlev < 1) return RL_ERR_DEVICE;
     CK(launch_tsqr(st, cplx, at<void>(ws, L.AV), B, with_x ? at<void>(ws, L.AX) : nullptr, with_x ? B : 0,
-                   at<void>(ws, L.AW), B, m, at<void>(ws, L.tsA), at<void>(ws, L.tsB), &Rt, ctl, 1));
+                   at<void>(ws, L.AW), B, m, at<void>(ws, L.tsA), at<void>(ws, L.tsB), &Rt, ctl, 1, &lev[0]));
+    for (int q = 1; q < nlev; ++q) CK(launch_colsum_job(st, lev[q]));
     CK(launch_rr(st, cplx, (int)n, B, 0, with_x, Rt, at<void>(ws, L.V), at<void>(ws, L.X), at<void>(ws, L.W),
                  at<void>(ws, L.G3), at<void>(ws, L.Vn), at<void>(ws, L.Rres), at<void>(ws, L.CV), at<void>(ws, L.CX),
                  at<double>(ws, L.thb), at<double>(ws, L.ht), at<double>(ws, L.hr), ctl));

@@ -18,6 +18,7 @@
 // (k_tsqr_cw).
 #include "common.hpp"
 #include "kernels.hpp"
+#include "colsum.hpp"
 #include "tr_reduce.hpp"
 
 namespace rl {
@@ -200,11 +201,19 @@ __device__ __forceinline__ void tw_block_merge(T (&x)[RPL][TT], T* Rs, int t, in
   }
 }
 
+// Workgroups g_tsqr and up run one level of the partial-sum reduction
+// (side), which reads only what the preceding pass wrote.
 template <typename T, int TT, int RPL>
 __global__ __launch_bounds__(TW_THREADS) void k_tsqr_w(const T* __restrict__ P0, int b0, const T* __restrict__ P1,
                                                        int b1, const T* __restrict__ P2, int b2, int64_t m,
                                                        int64_t rows_per_block, T* __restrict__ Rpart,
-                                                       const Ctl* __restrict__ ctl, int check_done) {
+                                                       const Ctl* __restrict__ ctl, int check_done, int g_tsqr,
+                                                       ColsumJob side) {
+  if ((int)blockIdx.x >= g_tsqr) {
+    const int b = (int)blockIdx.x - g_tsqr;
+    colsum2_block(side, b % side.gx, b / side.gx);
+    return;
+  }
   if (check_done && ctl->done) return;
   constexpr int NW = TW_THREADS / 64;
   __shared__ T Rs[NW * TT * TT];
@@ -279,7 +288,7 @@ static int64_t tsqr_w_groups(int64_t m, int t, bool cplx) {
 
 template <typename T, int TT>
 static void tsqr_w_go(hipStream_t st, const T* P0, int b0, const T* P1, int b1, const T* P2, int b2, int64_t m,
-                      int64_t g, T* bufA, T* bufB, const Ctl* ctl, int check_done) {
+                      int64_t g, T* bufA, T* bufB, const Ctl* ctl, int check_done, const ColsumJob* side) {
   constexpr int RPL = TwRpl<T, TT>::value;
   constexpr int NWM = TwMergeWaves<T, TT>::value;
   const int t = b0 + b1 + b2;
@@ -287,8 +296,14 @@ static void tsqr_w_go(hipStream_t st, const T* P0, int b0, const T* P1, int b1, 
   // never-read panels still get a valid pointer
   if (P1 == nullptr) P1 = P0;
   if (P2 == nullptr) P2 = P0;
-  hipLaunchKernelGGL((k_tsqr_w<T, TT, RPL>), dim3((unsigned)g), dim3(TW_THREADS), 0, st, P0, b0, P1, b1, P2, b2, m,
-                     rows, bufA, ctl, check_done);
+  ColsumJob sj{};
+  int64_t extra = 0;
+  if (side != nullptr) {
+    sj = *side;
+    extra = (int64_t)sj.gx * sj.gy;
+  }
+  hipLaunchKernelGGL((k_tsqr_w<T, TT, RPL>), dim3((unsigned)(g + extra)), dim3(TW_THREADS), 0, st, P0, b0, P1, b1, P2,
+                     b2, m, rows, bufA, ctl, check_done, (int)g, sj);
   hipLaunchKernelGGL((k_tsqr_w_merge<T, TT, RPL, NWM>), dim3(1), dim3(NWM * 64), 0, st, (const T*)bufA, t, g * t,
                      bufB, ctl, check_done);
 }
@@ -519,25 +534,30 @@ int64_t tsqr_groups(int64_t m, int t) {
 
 template <typename T>
 static hipError_t tsqr_impl(hipStream_t st, const T* P0, int b0, const T* P1, int b1, const T* P2, int b2, int64_t m,
-                            T* bufA, T* bufB, T** Rfinal, Ctl* ctl, int check_done) {
+                            T* bufA, T* bufB, T** Rfinal, Ctl* ctl, int check_done, const ColsumJob* side) {
   const int t = b0 + b1 + b2;
   if (t < 1 || t > TS_TMAX) return hipErrorInvalidValue;
+  if (t > 8 && side != nullptr) {
+    const hipError_t e = launch_colsum_job(st, *side);
+    if (e != hipSuccess) return e;
+  }
   if (t > 16) return tsqr_cw_impl<T, 32>(st, P0, b0, P1, b1, P2, b2, m, bufA, bufB, Rfinal, ctl, check_done);
   if (t > 8) return tsqr_cw_impl<T, 16>(st, P0, b0, P1, b1, P2, b2, m, bufA, bufB, Rfinal, ctl, check_done);
   const int64_t g = tsqr_w_groups(m, t, sizeof(T) == 16);
-  if (t <= 4) tsqr_w_go<T, 4>(st, P0, b0, P1, b1, P2, b2, m, g, bufA, bufB, ctl, check_done);
-  else tsqr_w_go<T, 8>(st, P0, b0, P1, b1, P2, b2, m, g, bufA, bufB, ctl, check_done);
+  if (t <= 4) tsqr_w_go<T, 4>(st, P0, b0, P1, b1, P2, b2, m, g, bufA, bufB, ctl, check_done, side);
+  else tsqr_w_go<T, 8>(st, P0, b0, P1, b1, P2, b2, m, g, bufA, bufB, ctl, check_done, side);
   *Rfinal = bufB;
   return hipGetLastError();
 }
 
 hipError_t launch_tsqr(hipStream_t st, bool cplx, const void* P0, int b0, const void* P1, int b1, const void* P2,
-                       int b2, int64_t m, void* bufA, void* bufB, void** Rfinal, Ctl* ctl, int check_done) {
+                       int b2, int64_t m, void* bufA, void* bufB, void** Rfinal, Ctl* ctl, int check_done,
+                       const ColsumJob* side) {
   if (cplx)
     return tsqr_impl<cd>(st, (const cd*)P0, b0, (const cd*)P1, b1, (const cd*)P2, b2, m, (cd*)bufA, (cd*)bufB,
-                         (cd**)Rfinal, ctl, check_done);
+                         (cd**)Rfinal, ctl, check_done, side);
   return tsqr_impl<double>(st, (const double*)P0, b0, (const double*)P1, b1, (const double*)P2, b2, m,
-                           (double*)bufA, (double*)bufB, (double**)Rfinal, ctl, check_done);
+                           (double*)bufA, (double*)bufB, (double**)Rfinal, ctl, check_done, side);
 }
 
 }  // namespace rl
