@@ -236,7 +236,7 @@ def main(argv=None):
     ap.add_argument("--served-budget-gb", type=float, default=16.0)
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
+        print(json.dumps({"error": "one process drives one GPU here; --gpus above 1 is not supported (the row-sharded multi-GPU path is a design, not code)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.served:
