@@ -137,19 +137,45 @@ def _tree_sum(P: np.ndarray, E: np.ndarray):
     return P[0], E[0]
 
 
-def _dot2_cols(X: np.ndarray, y: np.ndarray, row_chunk: int):
-    """sum_r X[r, c] * y[r] for every column c, Dot2-class (real X, y)."""
-    n = X.shape[1]
+def _stacked_rows(parts, r0: int, r1: int) -> np.ndarray:
+    """Rows r0:r1 of the vertical stack of ``parts`` (each rows x n), built
+    without forming the whole stack."""
+    out, base = [], 0
+    for p in parts:
+        lo, hi = max(r0, base), min(r1, base + p.shape[0])
+        if lo < hi:
+            out.append(p[lo - base:hi - base])
+        base += p.shape[0]
+    return out[0] if len(out) == 1 else np.concatenate(out, axis=0)
+
+
+def _dot2_cols(parts, y: np.ndarray, row_chunk: int):
+    """sum_r X[r, c] * y[r] for every column c, Dot2-class (real X, y), where X
+    is the vertical stack of ``parts``; it is read in chunks of ``row_chunk``
+    rows, so only one chunk of the stack is ever formed."""
+    n = parts[0].shape[1]
+    total = sum(p.shape[0] for p in parts)
     acc_s = np.zeros(n)
     acc_e = np.zeros(n)
-    for r0 in range(0, X.shape[0], row_chunk):
-        blk = X[r0:r0 + row_chunk]
+    for r0 in range(0, total, row_chunk):
+        blk = _stacked_rows(parts, r0, min(r0 + row_chunk, total))
         yb = y[r0:r0 + row_chunk][:, None]
         P, E = two_prod(blk, yb)
         ps, pe = _tree_sum(P, E)
         acc_s, t = two_sum(acc_s, ps)
         acc_e = acc_e + pe + t
     return acc_s + acc_e
+
+
+class _Negated:
+    """-M, negated one slice at a time (a row block of -A.imag on demand)."""
+
+    def __init__(self, M):
+        self.M = M
+        self.shape = M.shape
+
+    def __getitem__(self, idx):
+        return -self.M[idx]
 
 
 def matmul_h(A, Y, row_chunk: int = 8192) -> np.ndarray:
@@ -165,14 +191,13 @@ def matmul_h(A, Y, row_chunk: int = 8192) -> np.ndarray:
     if cplx:
         A = np.asarray(A, dtype=np.complex128)
         # conj(a) y: Re = [ar; ai] . [yr; yi], Im = [ar; -ai] . [yi; yr] (sums over 2m terms)
-        Xs = np.concatenate([A.real, A.imag], axis=0)
-        Xt = np.concatenate([A.real, -A.imag], axis=0)
+        ar, ai = A.real, A.imag
         for j in range(b):
             y = Y[:, j].astype(np.complex128)
-            re = _dot2_cols(Xs, np.concatenate([y.real, y.imag]), row_chunk)
-            im = _dot2_cols(Xt, np.concatenate([y.imag, y.real]), row_chunk)
+            re = _dot2_cols((ar, ai), np.concatenate([y.real, y.imag]), row_chunk)
+            im = _dot2_cols((ar, _Negated(ai)), np.concatenate([y.imag, y.real]), row_chunk)
             out[:, j] = re + 1j * im
     else:
         for j in range(b):
-            out[:, j] = _dot2_cols(np.asarray(A, dtype=np.float64), Y[:, j].astype(np.float64), row_chunk)
+            out[:, j] = _dot2_cols((np.asarray(A, dtype=np.float64),), Y[:, j].astype(np.float64), row_chunk)
     return out[:, 0] if vec else out

@@ -1,35 +1,49 @@
-"""RLOBPCG, plain CPU FP64 (paper Alg. rlopcg for b = 1, Alg. rlobpcg for b > 1).
+"""RLOBPCG, plain CPU FP64: the k smallest singular triplets of a tall A.
 
 Test infrastructure only (see ``oracle/__init__``).
 
-Steps, in the paper's order and notation (Sec. 1 steps 1-4; Sec. 2.1; Sec. 2.3):
-  1  S <- SparseStack (d x m, zeta nonzeros per column)        [Sec. 2.2]
-  2  [~, Sigma~, V~] = svd(S A)                                 [Alg. rlopcg, sketch-and-SVD]
-  3  P = V~ Sigma~^{-1};  V_0 = V~(:, n-b+1:n);  A_V = A V_0    [sketch-and-solve start]
-     b = 1: theta_0 = inf, r_0 = A^* A_v - ||A_v||^2 v_0
-     b > 1: Rayleigh-Ritz of A_V (its SVD) rotates V_0, A_V; R_0 = A^* A_V - V_0 Theta^2
-  4  for i = 0 .. max_iter-1:
-       W = P (P^* R)                                           [eq:search-direction]
-       W <- W - [V X]([V X]^* W);  W <- Orth(W - [V X]([V X]^* W))   [CGS2 / BCGS2]
-       T = [V X W];  A_T = [A_V A_X A W];  [~, Theta, C] = svd(A_T)  [Rayleigh-Ritz]
-       V = T C(:, t-b+1:t);  A_V = A_T C(:, t-b+1:t)
-       R = A^* A_V - V Theta_b^2
-       stop? (oracle.termination)
-       Q = Orth(C(1:b, 1:t-b)^*);  X = T C(:, 1:t-b) Q;  A_X = A_T C(:, 1:t-b) Q   [eq:x-defining]
-  Output: sigma = Theta_b, V; here sorted ascending.
+What is computed (Sec. 1, Sec. 2.1, Sec. 2.3): LOBPCG for the smallest
+eigenpairs of the Gram matrix A^* A, preconditioned by P P^* = ((S A)^* S A)^{-1}
+from a SparseStack sketch S A (Sec. 2.2), started from the sketch-and-solve
+block (the smallest right singular vectors of S A), with the paper's stopping
+rule.  b = 1 is Alg. rlopcg and b > 1 Alg. rlobpcg; both are the same
+iteration on a block of width b.  The code is organised by the mathematical
+pieces the method is built from, each a function below:
+
+  sketch preconditioner   P, Sigma~(1,1) and the start block from S A
+  rayleigh_ritz           Ritz pairs of A^* A on span(T) for an orthonormal T,
+                          read off the SVD of the product A T (the Ritz values
+                          are the singular values of A T)
+  search_block            eq:search-direction: W = P P^* R, made orthonormal
+                          and orthogonal to the current basis [V X] (two block
+                          Gram-Schmidt projections, then Orth)
+  previous_direction      eq:x-defining: the part of the new Ritz block that
+                          lies outside the old V, as an orthonormal block X
+                          with its product A X, both from the Ritz
+                          coefficients (no product with A)
+  residual                R = A^* (A V) - V Theta^2, one column per Ritz pair
+  left_vectors            U-hat from the Ritz block's product A V
+
+Each step of the loop builds the trial basis T = [V X W] (t = 3b columns; 2b
+while X is still empty), applies Rayleigh-Ritz to it, keeps the b smallest
+Ritz pairs as the new V, forms their residual, consults the stopping rule
+(``oracle.termination``) and, if the loop goes on, the next X.
 
 Readings where the paper is silent:
-  * The loop is written once for all b; with b = 1 it is Alg. rlopcg line by
-    line (Normalize is Orth of one column; the b = 1 start keeps theta_0 = inf).
-  * On the first pass X is empty, so t = 2b, V takes the last b columns of C
-    and Q = Orth(C(1:b, 1:b)^*).
-  * Orth is the thin Householder QR (numpy/LAPACK); Normalize of a zero vector
-    returns e_1 and raises the ``degenerate`` flag.
-  * svd returns singular values in descending order, as MATLAB's does.
+  * On the first step X is empty, so t = 2b, and the next X comes from the
+    b x b block of coefficients of the old V.
+  * Orth is the thin Householder QR (numpy/LAPACK); Normalize (Orth of one
+    column) of a zero or non-finite vector returns e_1 and raises the
+    ``degenerate`` flag.
+  * Singular values come in descending order, as MATLAB's svd returns them;
+    the output is sorted ascending.
   * ^* is the conjugate transpose throughout; S is real.
-  * U-hat_j = A_V(:, j) / theta_j (zero, with a flag, if theta_j = 0).
-    ``refresh=True`` recomputes A_V = A V-hat once at the end and rotates
-    (V-hat, sigma, U-hat) by the SVD of that m x b block.
+  * The b = 1 start keeps theta_0 = inf and v_0 unrotated (Alg. rlopcg); for
+    b > 1 the start block is first rotated by Rayleigh-Ritz on span(V_0)
+    (Alg. rlobpcg).
+  * U-hat_j = A_V(:, j) / theta_j (zero, with the ``zero_theta`` flag, if
+    theta_j = 0).  ``refresh=True`` recomputes A_V = A V-hat once at the end
+    and rotates (V-hat, sigma, U-hat) by the SVD of that m x b block.
   * ``precond="qr"`` uses R from S A = Q R with P = R^{-1}; P P^* = (R^* R)^{-1}
     = ((S A)^* S A)^{-1} = V~ Sigma~^{-2} V~^*, the same operator as the SVD
     route (Sec. 1, footnote on QR), with V_0 taken from the SVD of R.
@@ -83,8 +97,12 @@ def _ct(M: np.ndarray) -> np.ndarray:
     return M.conj().T
 
 
+# ---------------------------------------------------------------- orthonormal bases
+
 def _orth(M: np.ndarray):
-    """Orth (thin Householder QR); a single column is Normalize."""
+    """Orth (thin Householder QR); a single column is Normalize.  Returns the
+    basis and whether Normalize met a zero (or non-finite) vector, in which
+    case the basis is e_1."""
     if M.shape[1] == 1:
         nrm = np.linalg.norm(M[:, 0])
         if nrm == 0.0 or not np.isfinite(nrm):
@@ -117,6 +135,104 @@ def _svqb(M: np.ndarray):
     return M @ (dsc[:, None] * Z / np.sqrt(lam)[None, :]), False
 
 
+# ---------------------------------------------------------------- preconditioners
+
+@dataclass
+class _SketchData:
+    sigma1: float          # Sigma~(1,1), the largest singular value of S A
+    V0: np.ndarray         # the b smallest right singular vectors of S A (n x b)
+    apply_prec: object     # R -> P P^* R
+
+
+def _sketch_preconditioner(SA: np.ndarray, b: int, precond: str) -> _SketchData:
+    """Sec. 1 step 2 and the sketch-and-solve start: from S A, the operator
+    P P^* = ((S A)^* S A)^{-1}, Sigma~(1,1) and the smallest right singular
+    subspace of S A.  "svd": P = V~ Sigma~^{-1} from the SVD of S A (the
+    paper's route); "qr": P = R^{-1} from S A = Q R (the same operator)."""
+    n = SA.shape[1]
+    if precond == "svd":
+        _, St, Vth = np.linalg.svd(SA, full_matrices=False)
+        Vt = _ct(Vth)
+        P = Vt / St[None, :]                                  # P = V~ Sigma~^{-1}
+
+        def apply_prec(Rm):
+            return P @ (_ct(P) @ Rm)
+        return _SketchData(float(St[0]), Vt[:, n - b:].copy(), apply_prec)
+    if precond == "qr":
+        Rf = np.linalg.qr(SA, mode="r")
+        _, Sr, Vrh = np.linalg.svd(Rf)
+
+        def apply_prec(Rm):
+            Z = sla.solve_triangular(Rf, Rm, trans="C", lower=False)
+            return sla.solve_triangular(Rf, Z, lower=False)
+        return _SketchData(float(Sr[0]), _ct(Vrh)[:, n - b:].copy(), apply_prec)
+    raise ValueError(f"unknown precond {precond!r}")
+
+
+def _loop_preconditioner(A: np.ndarray, kind: str, sketch_prec):
+    """The preconditioner of the LOBPCG loop (Sec. 1.1's comparison methods):
+    the sketch's, the diagonal P = diag(||A(:, i)||^{-1}) (P P^* =
+    diag(||A(:, i)||^{-2}); a zero column keeps P(i, i) = 1), or none."""
+    if kind == "sketch":
+        return sketch_prec
+    if kind == "diag":
+        cn2 = np.sum(np.abs(A) ** 2, axis=0)
+        dscale = np.where(cn2 > 0.0, 1.0 / np.where(cn2 > 0.0, cn2, 1.0), 1.0)
+
+        def apply_prec(Rm):
+            return dscale[:, None] * Rm
+        return apply_prec
+    if kind == "none":
+        def apply_prec(Rm):
+            return Rm.copy()
+        return apply_prec
+    raise ValueError(f"unknown loop_precond {kind!r}")
+
+
+# ---------------------------------------------------------------- the LOBPCG pieces
+
+def rayleigh_ritz(AT: np.ndarray):
+    """Ritz data of A^* A on span(T), T orthonormal, from the product A T:
+    A T = U_T Theta C^* gives the Ritz values Theta^2 (descending Theta) and
+    the coefficients C of the Ritz vectors T C (Sec. 2.1, the SVD of A_T)."""
+    _, Th, Ch = np.linalg.svd(AT, full_matrices=False)
+    return Th, _ct(Ch)
+
+
+def search_block(R: np.ndarray, apply_prec, basis: np.ndarray, orth_fn):
+    """eq:search-direction: W = P P^* R, then two block projections against
+    span(basis) (block classical Gram-Schmidt, twice) and an orthonormal basis
+    of the result.  Returns W and Orth's degenerate flag."""
+    W = apply_prec(R)
+    W = W - basis @ (_ct(basis) @ W)
+    return orth_fn(W - basis @ (_ct(basis) @ W))
+
+
+def previous_direction(T: np.ndarray, AT: np.ndarray, C: np.ndarray, b: int):
+    """eq:x-defining: X spans the components of the non-selected Ritz vectors
+    along the old V, i.e. X = T C(:, 1:t-b) Q with Q = Orth(C(1:b, 1:t-b)^*),
+    and A X = A_T C(:, 1:t-b) Q.  Returns X, A X and Orth's degenerate flag."""
+    t = T.shape[1]
+    Q, flag = _orth(_ct(C[:b, :t - b]))
+    CX = C[:, :t - b] @ Q
+    return T @ CX, AT @ CX, flag
+
+
+def residual(AV: np.ndarray, V: np.ndarray, theta: np.ndarray, mulAh) -> np.ndarray:
+    """R = A^* (A V) - V Theta^2 (Sec. 2.1; one column per Ritz pair)."""
+    return mulAh(AV) - V * (theta * theta)[None, :]
+
+
+def left_vectors(AV: np.ndarray, sig: np.ndarray):
+    """U-hat(:, j) = A v_j / sigma_j; a zero sigma_j gives a zero column and
+    the zero_theta flag."""
+    zero = sig == 0.0
+    U = np.where(zero[None, :], 0.0, AV / np.where(zero, 1.0, sig)[None, :])
+    return U, bool(zero.any())
+
+
+# ---------------------------------------------------------------- the solver
+
 def rlobpcg(A, k: int, *, block: int | None = None, d: int | None = None,
             zeta: int = 8, seed: int = 0, tau: float | None = None,
             max_iter: int | None = None, rule: str = "paper", check_every: int = 5,
@@ -136,6 +252,9 @@ def rlobpcg(A, k: int, *, block: int | None = None, d: int | None = None,
     A = A.astype(dt, copy=False)
     tau = default_tau(n) if tau is None else tau
     max_iter = (200 if b == 1 else 100) if max_iter is None else max_iter
+    orth_fn = {"cgs2": _orth, "svqb": _svqb}.get(orth)
+    if orth_fn is None:
+        raise ValueError(f"unknown orth {orth!r}")
 
     def mulA(M):
         return eft.matmul(A, M) if dot2 else A @ M
@@ -143,67 +262,23 @@ def rlobpcg(A, k: int, *, block: int | None = None, d: int | None = None,
     def mulAh(M):
         return eft.matmul_h(A, M) if dot2 else _ct(A) @ M
 
-    # Steps 1-2: embedding, sketch, factorisation.
-    SA = sparsestack.sketch(A, d, zeta, seed)
-    if precond == "svd":
-        _, St, Vth = np.linalg.svd(SA, full_matrices=False)
-        Vt = _ct(Vth)
-        sigma1 = float(St[0])
-        P = Vt / St[None, :]                                  # P = V~ Sigma~^{-1}
+    # The sketch (Sec. 2.2), its preconditioner and the start block.
+    sk = _sketch_preconditioner(sparsestack.sketch(A, d, zeta, seed), b, precond)
+    apply_prec = _loop_preconditioner(A, loop_precond, sk.apply_prec)
 
-        def apply_prec(Rm):
-            return P @ (_ct(P) @ Rm)
-        V = Vt[:, n - b:].copy()
-    elif precond == "qr":
-        Rf = np.linalg.qr(SA, mode="r")
-        _, Sr, Vrh = np.linalg.svd(Rf)
-        sigma1 = float(Sr[0])
-
-        def apply_prec(Rm):
-            Z = sla.solve_triangular(Rf, Rm, trans="C", lower=False)
-            return sla.solve_triangular(Rf, Z, lower=False)
-        V = _ct(Vrh)[:, n - b:].copy()
-    else:
-        raise ValueError(f"unknown precond {precond!r}")
-    # The loop's preconditioner (Sec. 1.1, the comparison methods): the sketch
-    # preconditioner above, the diagonal P = diag(||A(:, i)||^{-1}) (so
-    # P P^* = diag(||A(:, i)||^{-2})), or none (P = I).  Every variant keeps
-    # the sketch-and-solve start and Sigma~(1,1), as the paper's comparison
-    # initialises all iterative methods with v_0.  A zero column keeps P(i,i) = 1.
-    if loop_precond == "diag":
-        cn2 = np.sum(np.abs(A) ** 2, axis=0)
-        dscale = np.where(cn2 > 0.0, 1.0 / np.where(cn2 > 0.0, cn2, 1.0), 1.0)
-
-        def apply_prec(Rm):
-            return dscale[:, None] * Rm
-    elif loop_precond == "none":
-        def apply_prec(Rm):
-            return Rm.copy()
-    elif loop_precond != "sketch":
-        raise ValueError(f"unknown loop_precond {loop_precond!r}")
-    # Orth of W after the two block projections on [V X]: Householder QR
-    # (the CGS2 of the paper yields the same orthonormal basis up to rounding
-    # and column signs) or SVQB.
-    if orth == "cgs2":
-        orth_fn = _orth
-    elif orth == "svqb":
-        orth_fn = _svqb
-    else:
-        raise ValueError(f"unknown orth {orth!r}")
-
-    # Step 3: sketch-and-solve start.
+    # Sketch-and-solve start.
+    V = sk.V0
     AV = mulA(V)
     if b == 1:
-        th2 = np.array([np.vdot(AV[:, 0], AV[:, 0]).real])
         theta = np.array([np.inf])                            # theta_0 = inf
+        th2 = np.array([np.vdot(AV[:, 0], AV[:, 0]).real])
+        R = mulAh(AV) - V * th2[None, :]
     else:
-        _, Th, Ch = np.linalg.svd(AV, full_matrices=False)
-        C0 = _ct(Ch)
+        theta, C0 = rayleigh_ritz(AV)
         V = V @ C0
         AV = AV @ C0
-        theta = Th.copy()
-        th2 = Th * Th
-    R = mulAh(AV) - V * th2[None, :]
+        theta = theta.copy()
+        R = residual(AV, V, theta, mulAh)
     X = np.zeros((n, 0), dtype=dt)
     AX = np.zeros((m, 0), dtype=dt)
     theta_hist = [theta.copy()]
@@ -212,37 +287,30 @@ def rlobpcg(A, k: int, *, block: int | None = None, d: int | None = None,
     status = 1
     iters = 0
 
-    # Step 4: LOBPCG on A^* A with preconditioner P P^*.
-    for i in range(max_iter):
-        W = apply_prec(R)
-        B = np.hstack([V, X])
-        W = W - B @ (_ct(B) @ W)
-        W, flag = orth_fn(W - B @ (_ct(B) @ W))
+    # LOBPCG on A^* A, preconditioned by P P^*, until the stopping rule holds.
+    while iters < max_iter:
+        W, flag = search_block(R, apply_prec, np.hstack([V, X]), orth_fn)
         degenerate |= flag
         T = np.hstack([V, X, W])
         AT = np.hstack([AV, AX, mulA(W)])
-        _, Th, Ch = np.linalg.svd(AT, full_matrices=False)
-        C = _ct(Ch)
+        Th, C = rayleigh_ritz(AT)
         t = T.shape[1]
-        Cv = C[:, t - b:]
+        Cv = C[:, t - b:]                                     # the b smallest Ritz pairs
         V = T @ Cv
         AV = AT @ Cv
         theta = Th[t - b:].copy()
-        R = mulAh(AV) - V * (theta * theta)[None, :]
+        R = residual(AV, V, theta, mulAh)
         theta_hist.append(theta.copy())
         rnorm_hist.append(np.linalg.norm(R, axis=0))
-        iters = i + 1
         if callback is not None:
-            callback(i=i, T=T, AT=AT, C=C, Theta=Th, V=V, AV=AV, R=R, W=W)
-        if termination.should_stop(i, theta_hist, rnorm_hist, sigma1, tau,
+            callback(i=iters, T=T, AT=AT, C=C, Theta=Th, V=V, AV=AV, R=R, W=W)
+        iters += 1
+        if termination.should_stop(iters - 1, theta_hist, rnorm_hist, sk.sigma1, tau,
                                    rule=rule, check_every=check_every):
             status = 0
             break
-        Q, flag = _orth(_ct(C[:b, :t - b]))
+        X, AX, flag = previous_direction(T, AT, C, b)
         degenerate |= flag
-        CX = C[:, :t - b] @ Q
-        X = T @ CX
-        AX = AT @ CX
 
     V_block, theta_block = V.copy(), theta.copy()
     if refresh:
@@ -254,10 +322,8 @@ def rlobpcg(A, k: int, *, block: int | None = None, d: int | None = None,
     # Ascending order; the first k of the block.
     order = np.argsort(theta, kind="stable")[:k]
     sig = theta[order]
-    Vk = V[:, order]
-    zero = sig == 0.0
-    U = np.where(zero[None, :], 0.0, AV[:, order] / np.where(zero, 1.0, sig)[None, :])
-    return RLResult(sigma=sig, V=Vk, U=U.astype(dt), iters=iters, status=status,
-                    sigma1=sigma1, theta_hist=theta_hist, rnorm_hist=rnorm_hist,
-                    degenerate=degenerate, zero_theta=bool(zero.any()),
+    U, zero_theta = left_vectors(AV[:, order], sig)
+    return RLResult(sigma=sig, V=V[:, order], U=U.astype(dt), iters=iters, status=status,
+                    sigma1=sk.sigma1, theta_hist=theta_hist, rnorm_hist=rnorm_hist,
+                    degenerate=degenerate, zero_theta=zero_theta,
                     V_block=V_block, theta_block=theta_block)

@@ -294,3 +294,84 @@ def test_svqb_solve_reaches_dense_triplets():
     assert _sin_angle(r.V, Vd[:, -k:]) <= 1e-10
     with pytest.raises(ValueError):
         rlobpcg(A, k, orth="mgs")
+
+
+def test_normalize_of_a_zero_vector_is_e1_with_the_flag():
+    """Orth of one column (Normalize): a zero or non-finite vector gives e_1
+    and raises the degenerate flag; any other vector is scaled to unit norm."""
+    from oracle.rlobpcg import _orth
+    for bad in (np.zeros((7, 1)), np.zeros((7, 1), dtype=np.complex128), np.full((7, 1), np.nan)):
+        q, flag = _orth(bad)
+        assert flag
+        assert q.shape == (7, 1) and q[0, 0] == 1.0 and np.count_nonzero(q) == 1
+    x = np.arange(1.0, 8.0)[:, None] * (1 - 2j)
+    q, flag = _orth(x)
+    assert not flag
+    assert abs(np.linalg.norm(q) - 1.0) <= 1e-15
+    assert np.linalg.norm(q - x / np.linalg.norm(x)) <= 1e-15
+
+
+def test_previous_direction_when_the_old_block_does_not_mix():
+    """eq:x-defining with C(1:b, 1:t-b) = 0: the old V is itself the selected
+    Ritz vector, Q = Orth(0) = e_1 with the degenerate flag, and X = T C(:, 1)
+    is still a unit vector orthogonal to the new V, with A X = A_T C(:, 1)."""
+    from oracle.rlobpcg import previous_direction
+    rng = np.random.default_rng(3)
+    T, _ = np.linalg.qr(rng.standard_normal((20, 3)))
+    AT = rng.standard_normal((50, 3))
+    c, s = math.cos(0.3), math.sin(0.3)
+    C = np.array([[0.0, 0.0, 1.0], [c, s, 0.0], [-s, c, 0.0]])      # orthogonal, C(1, 1:2) = 0
+    X, AX, flag = previous_direction(T, AT, C, 1)
+    assert flag
+    assert np.allclose(X[:, 0], T @ C[:, 0], atol=1e-15, rtol=0)
+    assert np.allclose(AX[:, 0], AT @ C[:, 0], atol=1e-15, rtol=0)
+    assert abs(np.linalg.norm(X) - 1.0) <= 1e-14
+    assert abs(float(X[:, 0] @ (T @ C[:, 2]))) <= 1e-14
+    # with a mixing block the same call needs no fallback
+    C2, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+    X2, _, flag2 = previous_direction(T, AT, C2, 1)
+    assert not flag2 and abs(np.linalg.norm(X2) - 1.0) <= 1e-14
+
+
+def test_left_vectors_of_a_zero_singular_value():
+    """U-hat(:, j) = A v_j / sigma_j, and a zero sigma_j gives a zero column
+    with the zero_theta flag instead of a division by zero."""
+    from oracle.rlobpcg import left_vectors
+    AV = np.array([[3.0, 0.0], [4.0, 0.0], [0.0, 0.0]])
+    U, flag = left_vectors(AV, np.array([5.0, 0.0]))
+    assert flag
+    assert np.array_equal(U[:, 1], np.zeros(3))
+    assert np.allclose(U[:, 0], [0.6, 0.8, 0.0], rtol=0, atol=1e-16)
+    _, flag = left_vectors(AV[:, :1], np.array([5.0]))
+    assert not flag
+
+
+def test_refresh_recomputes_the_product_and_rotates():
+    """refresh=True recomputes A V-hat from V-hat and rotates (V-hat, sigma,
+    U-hat) by the SVD of that m x b block.  The maintained A_V is corrupted
+    after the last step, so only a real recomputation meets the residual
+    gate; the refreshed triplets then match the dense SVD, U-hat has
+    orthonormal columns, and V-hat spans the final Ritz block."""
+    m, n, k = 3000, 60, 3
+    A, _, s = planted_numpy(m, n, spectrum_gap(n, k, 1e-9, 10.0), 7)
+    sv, Vd = _dense(A)
+    last = 59
+
+    def corrupt(**kw):
+        if kw["i"] == last:
+            kw["AV"][:] += 1e-6 * np.random.default_rng(0).standard_normal(kw["AV"].shape)
+
+    plain = rlobpcg(A, k, seed=3, rule="none", max_iter=last + 1, callback=corrupt)
+    res_plain = np.linalg.norm(A @ plain.V - plain.U * plain.sigma[None, :], axis=0).max()
+    assert res_plain > 1e-9                               # U-hat came from the corrupted A_V
+    r = rlobpcg(A, k, seed=3, rule="none", max_iter=last + 1, callback=corrupt, refresh=True)
+    res = np.linalg.norm(A @ r.V - r.U * r.sigma[None, :], axis=0).max()
+    assert res <= 1e-12 * sv[0]
+    assert np.all(np.diff(r.sigma) >= 0)
+    assert np.max(np.abs(r.sigma - sv[::-1][:k])) <= 1e-12 * sv[0]
+    assert np.linalg.norm(r.U.conj().T @ r.U - np.eye(k)) <= 1e-13
+    assert _sin_angle(r.V, r.V_block) <= 1e-13
+    assert _sin_angle(r.V, Vd[:, -k:]) <= 1e-10
+    # the rotation diagonalises A^* A on the block: V-hat^* A^* A V-hat = Sigma^2
+    G = (A @ r.V).conj().T @ (A @ r.V)
+    assert np.linalg.norm(G - np.diag(r.sigma ** 2)) <= 1e-12 * sv[0] ** 2
