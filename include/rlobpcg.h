@@ -125,8 +125,9 @@ int rl_set_stream(rl_handle h, void* hip_stream);
 /* Fill defaults for an m x n problem with k wanted triplets (host only). */
 int rl_default_opts(rl_opts* o, int64_t m, int64_t n, int32_t k);
 
-/* The k smallest singular triplets of A (Sec. 1, "a small number, say 1 to
- * 10, of minimum singular vectors"; Alg. rlopcg / Alg. rlobpcg).
+/* The k smallest singular triplets of A: a few (1 to 10 in the paper's use)
+ * of its smallest singular values with their vectors (Sec. 1; Alg. rlopcg /
+ * Alg. rlobpcg).
  *   A      device, m x n, row-major, leading dimension lda
  *   sigma  device, k doubles, ascending
  *   V      device, n x k (ldv >= k): right singular vectors, column j <-> sigma[j]

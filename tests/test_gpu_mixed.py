@@ -114,7 +114,9 @@ def test_solve_block_lowp(rl, prec):
     banner(f"solve 30000x90 k=3 sketch {prec}")
     sig = spectrum_gap(90, 3, 1e-4, 100.0)
     A, _, _ = planted_numpy(30_000, 90, sig, 17)
-    _solve_vs_oracle(rl, A, 3, 23, prec, 1.0, allow_max_iter=True)
+    # FP32 converges by the rule here (as the FP64 path does); the bfloat16
+    # preconditioner may need more than max_iter steps
+    _solve_vs_oracle(rl, A, 3, 23, prec, 1.0, allow_max_iter=(prec == "bf16"))
 
 
 def test_lowp_rejects_complex(rl):
