@@ -41,6 +41,7 @@ extern "C" {
 #define RL_PENDING 2             /* served job not finished (rl_server_poll / rl_server_wait time-out) */
 #define RL_ERR_ADMISSION (-5)    /* a served request whose workspace can never fit the server's budget */
 #define RL_ERR_CANCELLED (-6)    /* a request submitted to a server that is shutting down */
+#define RL_ERR_SCRATCH (-8)      /* rl_step_astream_iter_noalloc: the shape needs more than its 32 MiB of scratch */
 
 /* Stopping rules (oracle.termination documents the same three). */
 #define RL_STOP_PAPER 0 /* at i = 0 mod check_every: tolerance and both stagnation checks, every column */
@@ -190,6 +191,22 @@ int rl_step_astream(rl_handle h, int is_complex, int64_t m, int64_t n, const dou
  * n > 1024 or b > 10. */
 int rl_step_astream_iter(rl_handle h, int is_complex, int64_t m, int64_t n, const double* A, int64_t lda, int32_t b,
                          const double* W, const double* AV, const double* AX, double* AW, double* G3, int32_t dot2);
+
+/* rl_step_astream_iter without any device allocation, for callers that
+ * cannot allocate: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, kernels and results
+ * (bit for bit) as rl_step_astream_iter; the caller still passes every input
+ * and output.  The pass's partial sums live in a static scratch area of
+ * 32 MiB per device, held from module load until the process ends; shapes
+ * whose partial records need more return RL_ERR_SCRATCH before anything is
+ * enqueued (every real shape with n <= 200 and b = 1, for instance, fits at
+ * any m).  The call only enqueues on the handle's stream and returns: the
+ * results are ready when that stream's work is done.  All calls on one GPU
+ * share that GPU's scratch, so calls that overlap on one GPU (other streams,
+ * other threads, other handles) race; serialise them. */
+int rl_step_astream_iter_noalloc(rl_handle h, int is_complex, int64_t m, int64_t n, const double* A, int64_t lda,
+                                 int32_t b, const double* W, const double* AV, const double* AX, double* AW,
+                                 double* G3, int32_t dot2);
 
 /* Rayleigh-Ritz data of a tall m x t block P (row-major, dense, t <= 32):
  * singular values (descending, device t doubles) and right singular vectors

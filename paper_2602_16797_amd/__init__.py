@@ -28,6 +28,7 @@ RL_ERR_UNSUPPORTED = -7
 RL_PENDING = 2
 RL_ERR_ADMISSION = -5
 RL_ERR_CANCELLED = -6
+RL_ERR_SCRATCH = -8
 
 RL_SKETCH_F64 = 0
 RL_SKETCH_F32 = 1
@@ -40,7 +41,8 @@ STOP_RULES = {"paper": 0, "tol": 1, "none": 2}
 EXPORTED = (
     "rl_create", "rl_destroy", "rl_set_stream", "rl_default_opts",
     "rl_svds_smallest_d", "rl_svds_smallest_z",
-    "rl_step_sketch", "rl_step_qr", "rl_step_astream", "rl_step_astream_iter", "rl_step_tall_svd",
+    "rl_step_sketch", "rl_step_qr", "rl_step_astream", "rl_step_astream_iter", "rl_step_astream_iter_noalloc",
+    "rl_step_tall_svd",
     "rl_step_sketch_f32", "rl_step_qr_lowp", "rl_status_string",
     "rl_server_create", "rl_server_submit", "rl_server_poll", "rl_server_wait", "rl_server_destroy",
 )
@@ -148,6 +150,7 @@ def load_library() -> ctypes.CDLL:
     lib.rl_step_qr_lowp.argtypes = [P, I64, I64, P, I64, I32, P, P]
     lib.rl_step_astream.argtypes = [P, ctypes.c_int, I64, I64, P, I64, I32, P, P, P, I32]
     lib.rl_step_astream_iter.argtypes = [P, ctypes.c_int, I64, I64, P, I64, I32, P, P, P, P, P, I32]
+    lib.rl_step_astream_iter_noalloc.argtypes = [P, ctypes.c_int, I64, I64, P, I64, I32, P, P, P, P, P, I32]
     lib.rl_step_tall_svd.argtypes = [P, ctypes.c_int, I64, I32, P, P, P]
     lib.rl_status_string.argtypes = [ctypes.c_int]
     lib.rl_server_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.c_size_t, I32]
@@ -421,6 +424,35 @@ def rl_step_astream_iter(A, W, AV, AX=None, dot2: bool = False):
                                     _ptr(AX) if AX is not None else None, _ptr(AW), _ptr(G3), int(bool(dot2)))
     if rc != RL_OK:
         raise RlError(rc, "rl_step_astream_iter")
+    return AW, G3
+
+
+def rl_step_astream_iter_noalloc(A, W, AV, AX=None, dot2: bool = False, AW=None, G3=None):
+    """rl_step_astream_iter through the allocation-free entry point: the
+    library allocates nothing (its scratch is a static 32 MiB per device).
+    AW (m x b) and G3 (3 x n x b) may be passed preallocated; otherwise torch
+    allocates them here.  The call only enqueues on the current stream."""
+    torch = _torch()
+    _check_matrix(A, torch)
+    m, n = A.shape
+    b = W.shape[1]
+    for t in (W, AV) + ((AX,) if AX is not None else ()):
+        if not t.is_contiguous():
+            raise ValueError("rl_step_astream_iter_noalloc: W, AV and AX must be contiguous")
+    if AV.shape != (m, b) or (AX is not None and AX.shape != (m, b)) or W.shape != (n, b):
+        raise ValueError("rl_step_astream_iter_noalloc: W must be n x b, AV and AX m x b")
+    if AW is None:
+        AW = torch.empty((m, b), dtype=A.dtype, device=A.device)
+    if G3 is None:
+        G3 = torch.empty((3, n, b), dtype=A.dtype, device=A.device)
+    if AW.shape != (m, b) or G3.shape != (3, n, b) or not (AW.is_contiguous() and G3.is_contiguous()):
+        raise ValueError("rl_step_astream_iter_noalloc: AW must be m x b and G3 3 x n x b, contiguous")
+    h = handle(A.device.index or 0)
+    rc = h.lib.rl_step_astream_iter_noalloc(h.h, int(A.is_complex()), m, n, _ptr(A), A.stride(0), b, _ptr(W),
+                                            _ptr(AV), _ptr(AX) if AX is not None else None, _ptr(AW), _ptr(G3),
+                                            int(bool(dot2)))
+    if rc != RL_OK:
+        raise RlError(rc, "rl_step_astream_iter_noalloc")
     return AW, G3
 
 

@@ -586,12 +586,46 @@ static void fill_times(const rl_job* j, rl_job_times* t) {
   t->workspace_bytes = j->bytes;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free pass (rl_step_astream_iter_noalloc): the
+// per-workgroup partial records of one pass and the levels of their
+// reduction.  Every GPU the library runs on holds its own copy from module
+// load until the process ends.  In host code the symbol is only a stand-in:
+// each device's address comes from hipGetSymbolAddress (resolved by
+// rl_create with that device current) and only that address is ever passed
+// to kernels.  No part of it needs to start at zero: each pass writes every
+// record it later reads.
+#define RL_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+#define RL_MAX_DEVICES 64
+static __device__ __align__(256) unsigned char scratch[RL_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[RL_MAX_DEVICES] = {};
+
+// Resolves the current device's scratch address once per device.
+static int resolve_scratch(int device) {
+  if (device < 0 || device >= RL_MAX_DEVICES) return RL_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return RL_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return RL_ERR_DEVICE;
+  g_scratch_ptr[device] = p;
+  return RL_OK;
+}
+
+static void* scratch_of(int device) {
+  if (device < 0 || device >= RL_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
 extern "C" {
 
 int rl_create(rl_handle* out, int device, void* stream) {
   if (!out) return RL_ERR_ARG;
   *out = nullptr;
   if (hipSetDevice(device) != hipSuccess) return RL_ERR_DEVICE;
+  const int src = resolve_scratch(device);
+  if (src != RL_OK) return src;
   rl_ctx* h = new (std::nothrow) rl_ctx();
   if (!h) return RL_ERR_NOMEM;
   h->device = device;
@@ -804,6 +838,24 @@ int rl_step_astream_iter(rl_handle h, int is_complex, int64_t m, int64_t n, cons
   return RL_OK;
 }
 
+int rl_step_astream_iter_noalloc(rl_handle h, int is_complex, int64_t m, int64_t n, const double* A, int64_t lda,
+                                 int32_t b, const double* W, const double* AV, const double* AX, double* AW,
+                                 double* G3, int32_t dot2) {
+  if (!h || !A || !W || !AV || !AW || !G3 || m < 1 || n < 1 || lda < n || b < 1) return RL_ERR_ARG;
+  if (n > 1024 || b > 10) return RL_ERR_UNSUPPORTED;
+  const int es = is_complex ? 2 : 1;
+  Arena a;
+  const size_t o_part = a.take(sizeof(double) * astream_part_doubles(m, (int)n, b, es)),
+               o_tmp = a.take(sizeof(double) * astream_tmp_doubles(m, (int)n, b, es));
+  if (a.off > RL_NOALLOC_SCRATCH_BYTES) return RL_ERR_SCRATCH;
+  if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;
+  void* base = scratch_of(h->device);
+  if (base == nullptr) return RL_ERR_DEVICE;
+  CK(launch_astream(h->stream, is_complex != 0, b, dot2 != 0, A, lda, m, (int)n, W, AW, AV, AX, 0,
+                    at<double>(base, o_part), at<double>(base, o_tmp), G3, nullptr));
+  return RL_OK;
+}
+
 int rl_step_tall_svd(rl_handle h, int is_complex, int64_t m, int32_t t, const double* P, double* sigma, double* C) {
   if (!h || !P || !sigma || !C || m < 1 || t < 1 || t > 32) return RL_ERR_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;
@@ -973,6 +1025,7 @@ const char* rl_status_string(int code) {
     case RL_PENDING: return "the served job has not finished";
     case RL_ERR_ADMISSION: return "the request can never fit the server's HBM budget";
     case RL_ERR_CANCELLED: return "the server is shutting down";
+    case RL_ERR_SCRATCH: return "the shape needs more scratch than the allocation-free entry point holds (32 MiB)";
     default: return "unknown status";
   }
 }
