@@ -10,7 +10,10 @@ Modules
   sparsestack  SparseStack embedding S (Sec. 2.2) drawn from a counter hash,
                and the sketch S*A.
   eft          Error-free transformations and the compensated dot product
-               (Ogita, Rump and Oishi 2005, "Accurate sum and dot product").
+               (Ogita, Rump and Oishi 2005, "Accurate sum and dot product");
+               its products run in plain C with OpenMP threads
+               (eft_c.c, built by oracle/build.py) when built, else in numpy,
+               with identical bits either way.
   termination  Stopping rule: tolerance (eq:est_conv_criterion) plus the two
                stagnation checks (eq:stagnation-check), Alg. rlopcg.
   rlobpcg      Alg. rlopcg (b = 1) and Alg. rlobpcg (block), including the

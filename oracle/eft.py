@@ -31,9 +31,14 @@ applied as Dot2 as well.
 
 from __future__ import annotations
 
+import ctypes
+import os
+
 import numpy as np
 
 _SPLITTER = 134217729.0  # 2^27 + 1
+_CLIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_eft_c.so")
+_clib_handle = None
 
 
 def two_sum(a, b):
@@ -96,8 +101,8 @@ def _dot2_rows(XT: np.ndarray, y: np.ndarray) -> np.ndarray:
     return p + s
 
 
-def matmul(A, W, row_chunk: int = 16384) -> np.ndarray:
-    """A @ W with every entry computed by Dot2 (real or complex A, W)."""
+def _matmul_numpy(A, W, row_chunk: int = 16384) -> np.ndarray:
+    """A @ W with every entry computed by Dot2 (real or complex A, W), in numpy."""
     A = np.asarray(A)
     W = np.asarray(W)
     vec = W.ndim == 1
@@ -178,8 +183,8 @@ class _Negated:
         return -self.M[idx]
 
 
-def matmul_h(A, Y, row_chunk: int = 8192) -> np.ndarray:
-    """A^* @ Y (A m x n, Y m x b) with every entry Dot2-class accurate."""
+def _matmul_h_numpy(A, Y, row_chunk: int = 8192) -> np.ndarray:
+    """A^* @ Y (A m x n, Y m x b) with every entry Dot2-class accurate, in numpy."""
     A = np.asarray(A)
     Y = np.asarray(Y)
     vec = Y.ndim == 1
@@ -200,4 +205,98 @@ def matmul_h(A, Y, row_chunk: int = 8192) -> np.ndarray:
     else:
         for j in range(b):
             out[:, j] = _dot2_cols((np.asarray(A, dtype=np.float64),), Y[:, j].astype(np.float64), row_chunk)
+    return out[:, 0] if vec else out
+
+
+# ---------------------------------------------------------------- C forms
+#
+# ``oracle/eft_c.c`` performs the same operations in the same order as the
+# numpy forms above (so the same bits; tests/test_oracle_eft.py checks it)
+# with OpenMP threads over rows (A W) or columns (A^* Y).  The C forms are
+# used when ``oracle/_eft_c.so`` is built (``oracle/build.py``).
+
+def _clib():
+    global _clib_handle
+    if _clib_handle is None:
+        if os.environ.get("RL_ORACLE_NUMPY") == "1" or not os.path.exists(_CLIB_PATH):
+            _clib_handle = False
+        else:
+            lib = ctypes.CDLL(_CLIB_PATH)
+            P, I64 = ctypes.c_void_p, ctypes.c_int64
+            lib.eft_matmul.argtypes = [P, I64, I64, I64, P, I64, I64, ctypes.c_int, P, I64]
+            lib.eft_matmul_h.argtypes = [P, I64, I64, I64, P, I64, I64, ctypes.c_int, I64, P, I64]
+            lib.eft_set_threads.argtypes = [ctypes.c_int]
+            lib.eft_get_threads.restype = ctypes.c_int
+            _clib_handle = lib
+    return _clib_handle or None
+
+
+def have_c() -> bool:
+    return _clib() is not None
+
+
+def set_threads(nt: int) -> None:
+    """Threads of the C forms (OpenMP); no effect on the numpy forms."""
+    lib = _clib()
+    if lib is not None:
+        lib.eft_set_threads(int(nt))
+
+
+def get_threads() -> int:
+    lib = _clib()
+    return int(lib.eft_get_threads()) if lib is not None else 1
+
+
+def _as_rows(M, dt):
+    """M as a C-ordered array of dtype dt whose rows may be strided."""
+    M = np.asarray(M, dtype=dt)
+    if M.ndim != 2 or M.strides[1] != M.itemsize or M.strides[0] % M.itemsize:
+        M = np.ascontiguousarray(M)
+    return M, M.strides[0] // M.itemsize
+
+
+def matmul(A, W, row_chunk: int = 16384) -> np.ndarray:
+    """A @ W with every entry computed by Dot2 (real or complex A, W)."""
+    lib = _clib()
+    if lib is None:
+        return _matmul_numpy(A, W, row_chunk)
+    A = np.asarray(A)
+    W = np.asarray(W)
+    vec = W.ndim == 1
+    if vec:
+        W = W[:, None]
+    cplx = np.iscomplexobj(A) or np.iscomplexobj(W)
+    dt = np.complex128 if cplx else np.float64
+    A, lda = _as_rows(A, dt)
+    W, ldw = _as_rows(W, dt)
+    m, n = A.shape
+    b = W.shape[1]
+    if W.shape[0] != n:
+        raise ValueError("matmul: W must have as many rows as A has columns")
+    out = np.empty((m, b), dtype=dt)
+    lib.eft_matmul(A.ctypes.data, m, n, lda, W.ctypes.data, b, ldw, int(cplx), out.ctypes.data, b)
+    return out[:, 0] if vec else out
+
+
+def matmul_h(A, Y, row_chunk: int = 8192) -> np.ndarray:
+    """A^* @ Y (A m x n, Y m x b) with every entry Dot2-class accurate."""
+    lib = _clib()
+    if lib is None:
+        return _matmul_h_numpy(A, Y, row_chunk)
+    A = np.asarray(A)
+    Y = np.asarray(Y)
+    vec = Y.ndim == 1
+    if vec:
+        Y = Y[:, None]
+    cplx = np.iscomplexobj(A) or np.iscomplexobj(Y)
+    dt = np.complex128 if cplx else np.float64
+    A, lda = _as_rows(A, dt)
+    Y, ldy = _as_rows(Y, dt)
+    m, n = A.shape
+    b = Y.shape[1]
+    if Y.shape[0] != m:
+        raise ValueError("matmul_h: Y must have as many rows as A")
+    out = np.empty((n, b), dtype=dt)
+    lib.eft_matmul_h(A.ctypes.data, m, n, lda, Y.ctypes.data, b, ldy, int(cplx), int(row_chunk),
+                     out.ctypes.data, b)
     return out[:, 0] if vec else out

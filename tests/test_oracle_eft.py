@@ -3,6 +3,7 @@
 from fractions import Fraction
 
 import numpy as np
+import pytest
 
 from oracle import eft
 
@@ -120,3 +121,36 @@ def test_matmul_h_complex_against_exact():
             assert abs(Fraction(float(got[c, j].real)) - re) <= Fraction(U * abs(float(re)) + g * g * sc)
             assert abs(Fraction(float(got[c, j].imag)) - im) <= Fraction(U * abs(float(im)) + g * g * sc)
     assert np.allclose(got, A.conj().T @ Y, rtol=1e-12, atol=1e-12)
+
+
+def test_c_forms_give_the_numpy_forms_bits():
+    """oracle/eft_c.c performs the numpy forms' operations in the same order,
+    so both give identical bits (real and complex, ragged row chunks, chunk
+    boundaries across the stacked real and imaginary rows, every thread
+    count)."""
+    if not eft.have_c():
+        from oracle import build as obuild
+        obuild.build()
+        eft._clib_handle = None
+    assert eft.have_c()
+    rng = np.random.default_rng(11)
+    for (m, n, b, cp) in [(20001, 7, 3, False), (257, 3, 2, True), (5000, 40, 2, True), (16385, 33, 1, False),
+                          (3, 5, 2, True), (1, 1, 1, False)]:
+        A = rng.standard_normal((m, n)) * np.logspace(0, -12, n)[None, :]
+        W = rng.standard_normal((n, b))
+        Y = rng.standard_normal((m, b))
+        if cp:
+            A = A + 1j * rng.standard_normal((m, n))
+            W = W + 1j * rng.standard_normal((n, b))
+            Y = Y + 1j * rng.standard_normal((m, b))
+        for nt in (1, 3):
+            eft.set_threads(nt)
+            assert np.array_equal(eft.matmul(A, W), eft._matmul_numpy(A, W))
+            for rc in (64, 8192):
+                assert np.array_equal(eft.matmul_h(A, Y, row_chunk=rc), eft._matmul_h_numpy(A, Y, row_chunk=rc))
+    # a strided row view is read through its leading dimension
+    A = rng.standard_normal((300, 40))
+    W = rng.standard_normal((25, 2))
+    assert np.array_equal(eft.matmul(A[:, :25], W), eft._matmul_numpy(A[:, :25], W))
+    with pytest.raises(ValueError):
+        eft.matmul_h(A, rng.standard_normal((299, 1)))
