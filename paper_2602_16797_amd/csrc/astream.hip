@@ -147,6 +147,41 @@ static int64_t astream_max_parts(int64_t m, int n, int B, int es_d) {
   return std::max(std::max(g, cc), std::max(r, c));
 }
 
+// Compute units and the largest dynamic LDS a workgroup may take, per device
+// (queried once per device).
+static int g_cu[64];
+static int64_t g_lds[64];
+static void device_caps(int* cu, int64_t* lds) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    *cu = 256;
+    *lds = 64 * 1024;
+    return;
+  }
+  if (g_cu[dev] == 0) {
+    int c = 0, l = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1) c = 256;
+    if (hipDeviceGetAttribute(&l, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || l < 1)
+      l = 64 * 1024;
+    g_lds[dev] = std::min<int64_t>(l, 160 * 1024);
+    g_cu[dev] = c;
+  }
+  *cu = g_cu[dev];
+  *lds = g_lds[dev];
+}
+int device_cu_count() {
+  int c;
+  int64_t l;
+  device_caps(&c, &l);
+  return c;
+}
+int64_t device_lds_max() {
+  int c;
+  int64_t l;
+  device_caps(&c, &l);
+  return l;
+}
+
 int64_t astream_part_doubles(int64_t m, int n, int B, int es_d) {
   return astream_max_parts(m, n, B, es_d) * 4 * (int64_t)n * B * es_d;
 }
@@ -179,6 +214,12 @@ hipError_t launch_astream_pass(hipStream_t st, bool cplx, int B, bool dot2, cons
     np = nb;
     ok = dispatch_astream_cs(dot2, init, B, st, nb, (const double*)A, lda, m, n, (const double*)W, (double*)AW,
                              (const double*)AVp, (const double*)AXp, Gpart, ctl);
+  } else if (cplx && !dot2 && astream_zm_fits(B, n, ((reinterpret_cast<uintptr_t>(A) & 15) == 0),
+                                                device_lds_max())) {
+    // plain sums: the two contractions on the FP64 matrix cores
+    nb = astream_c2_ranges(m, n, B);
+    np = nb;
+    ok = dispatch_astream_zm(init, B, st, nb, A, lda, m, n, W, AW, AVp, AXp, Gpart, device_cu_count(), ctl);
   } else if (cplx && astream_c2_fits(B, n, ((reinterpret_cast<uintptr_t>(A) & 15) == 0))) {
     nb = astream_c2_ranges(m, n, B);
     np = nb;

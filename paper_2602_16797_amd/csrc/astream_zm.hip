@@ -1,0 +1,361 @@
+// Complex A-stream on the FP64 matrix cores (v_mfma_f64_16x16x4f64), for
+// wide problems (256 < n <= 1024, b <= 10), with plain FP64 accumulation.
+//
+// The iteration's pass (Alg. rlobpcg: the product A W of the new search block
+// and the Gram data A^* [A_V A_X A_W] of the Rayleigh-Ritz step) is two dense
+// contractions with a 1e6-long dimension.  In real form, with
+//   Ar (m x 2n)  = A with (re, im) interleaved, exactly A's memory layout,
+//   Wr (2n x 2b) = [[Re W, Im W], [-Im W, Re W]] interleaved the same way,
+//   Tr (m x 6b)  = [A_V A_X A_W] with (re, im) interleaved,
+// they read  A_W = Ar Wr  (rows of A against a small matrix) and
+// Gr = Ar^T Tr  (a 2n x 6b Gram block summed over all rows), whose 2 x 2
+// blocks combine into A^* T:  Re = Gr(2c, 2v) + Gr(2c+1, 2v+1),
+// Im = Gr(2c, 2v+1) - Gr(2c+1, 2v).  A_W must be complete for a row before
+// the row can enter Gr, and a row of A (16 KB at n = 1000) is too wide to keep
+// on chip next to the accumulators of all of Gr, so each product takes one
+// read of A:
+//
+//   k_zm_aw  A_W = Ar Wr.  W (n x b complex, at most 160 KB) sits in LDS; a
+//            wave owns 32 rows (two 16-row M tiles) and walks k in blocks of
+//            16 real columns.  Lane (q, t) = (lane / 16, lane % 16) loads 32
+//            bytes, columns k0 + 4q .. k0 + 4q + 3 of row t; the four MFMA
+//            steps of the block use k = k0 + 4q + s (a permutation of the
+//            contraction index, applied to both operands), so one wide load
+//            feeds all four steps and a wave load covers 128 contiguous bytes
+//            of 16 rows.  The B operand Wr(k, j) is read from W in LDS with
+//            the sign pattern of Wr.
+//   k_zm_g   Gr = Ar^T Tr over a row range, written as one partial record
+//            [G_V | G_X | G_W | 0] per row range (the layout every pass
+//            writes; the compensated reduction of the records follows).  A
+//            wave owns 64 real columns of A: lane (q, t) loads 32 bytes of
+//            row i0 + q, columns kw + 4t .. kw + 4t + 3, and each of the four
+//            values feeds its own M tile (tile u holds the columns
+//            kw + 4t + u), so the 16 x 16 accumulator tiles are 4 M tiles by
+//            up to 4 N tiles.  Tr's rows are staged in LDS per 32-row chunk,
+//            double buffered, with the column order chosen so a lane reads
+//            its N tiles' values in one access.  Tiles u and u + 1 hold the
+//            real and imaginary parts of the same complex column at the same
+//            lane and register, so the 2 x 2 combination needs only a swap
+//            of neighbouring lanes before the record is written.
+//
+// Matrix-core operand layout of v_mfma_f64_16x16x4f64 (checked on gfx950):
+// lane l supplies A(l % 16, l / 16) and B(l / 16, l % 16), and register r of
+// the result holds D(4 r + l / 16, l % 16).
+#include "astream_kernels.hpp"
+#include "kernels.hpp"
+
+namespace rl {
+
+typedef double zm_v4d __attribute__((ext_vector_type(4)));
+
+__device__ inline zm_v4d zm_mfma(double a, double b, zm_v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int ZM_AW_THREADS = 1024;  // 16 waves: one workgroup per CU holds W in LDS
+constexpr int ZM_G_THREADS = 256;    // 4 waves: 256 real columns per workgroup
+constexpr int ZM_G_RC = 32;          // rows of Tr per LDS chunk
+
+// ----------------------------------------------------------------------------
+// A_W = A W (real form Ar Wr).  NT = N tiles of 16 real output columns (2b).
+template <int NT>
+__global__ __launch_bounds__(ZM_AW_THREADS) void k_zm_aw(const double* __restrict__ A, int64_t lda2, int64_t m,
+                                                         int n, int B, const cd* __restrict__ W,
+                                                         double* __restrict__ AW, const Ctl* __restrict__ ctl) {
+  if (ctl != nullptr && ctl->done) return;
+  extern __shared__ double zm_lds[];
+  cd* Ws = reinterpret_cast<cd*>(zm_lds);  // Ws[c * B + v] = W(c, v)
+  const int nwb = n * B;
+  for (int e = threadIdx.x; e < nwb; e += ZM_AW_THREADS) Ws[e] = W[e];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = wave_index();
+  const int q = lane >> 4, t = lane & 15;
+  const int n2 = 2 * n, B2 = 2 * B;
+  const int nkb = (n2 + 15) / 16;
+  // this lane's output columns per N tile: vector v, part r (Wr's sign pattern)
+  int vcol[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) vcol[nt] = (16 * nt + t) >> 1;
+  const int rpart = t & 1;
+  const int64_t ntile = (m + 31) / 32;
+  const int64_t gw = (int64_t)blockIdx.x * (ZM_AW_THREADS / 64) + wave;
+  const int64_t nwave = (int64_t)gridDim.x * (ZM_AW_THREADS / 64);
+  for (int64_t tile = gw; tile < ntile; tile += nwave) {
+    const int64_t r0 = tile * 32;
+    int64_t row[2];
+    bool rok[2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      row[mt] = r0 + 16 * mt + t;
+      rok[mt] = row[mt] < m;
+    }
+    // 32 bytes per lane and M tile: columns k0 + 4q .. +3 of its row; the
+    // two 16-byte halves are valid or invalid together (2n is even)
+    auto load = [&](double2 (&a)[2][2], int kb) {
+      const int k = 16 * kb + 4 * q;
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        const double* p = A + row[mt] * lda2 + k;
+        a[mt][0] = (rok[mt] && k < n2) ? ld_stream2(p) : make_double2(0.0, 0.0);
+        a[mt][1] = (rok[mt] && k + 2 < n2) ? ld_stream2(p + 2) : make_double2(0.0, 0.0);
+      }
+    };
+    zm_v4d acc[2][NT];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = zm_v4d{0.0, 0.0, 0.0, 0.0};
+    double2 an[2][2];
+    load(an, 0);
+    for (int kb = 0; kb < nkb; ++kb) {
+      double2 a[2][2];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        a[mt][0] = an[mt][0];
+        a[mt][1] = an[mt][1];
+      }
+      if (kb + 1 < nkb) load(an, kb + 1);
+      // steps s = 0, 1 use complex column c0 = 8 kb + 2q (re, im); s = 2, 3 use c0 + 1
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = 8 * kb + 2 * q + h;
+        double b_re[NT], b_im[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const cd w = (c < n && vcol[nt] < B) ? Ws[c * B + vcol[nt]] : cd{0.0, 0.0};
+          // Wr(2c, 2v) = Re w, Wr(2c, 2v+1) = Im w, Wr(2c+1, 2v) = -Im w, Wr(2c+1, 2v+1) = Re w
+          b_re[nt] = rpart ? w.y : w.x;
+          b_im[nt] = rpart ? w.x : -w.y;
+        }
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+          const double a_re = h ? a[mt][1].x : a[mt][0].x;
+          const double a_im = h ? a[mt][1].y : a[mt][0].y;
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            acc[mt][nt] = zm_mfma(a_re, b_re[nt], acc[mt][nt]);
+            acc[mt][nt] = zm_mfma(a_im, b_im[nt], acc[mt][nt]);
+          }
+        }
+      }
+    }
+    // register r of a tile holds output row 4r + q, column 16 nt + t
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t orow = r0 + 16 * mt + 4 * r + q;
+          const int col = 16 * nt + t;
+          if (orow < m && col < B2) AW[orow * B2 + col] = acc[mt][nt][r];
+        }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Partial records of A^* [P0 P1 P2] over row ranges (real form Ar^T Tr).
+// NT = N tiles over the used columns of Tr (np planes of 2b real columns).
+// Tr plane g goes to record plane g (init: the single plane A_W to plane 0).
+template <int NT>
+__global__ __launch_bounds__(ZM_G_THREADS, 2) void k_zm_g(const double* __restrict__ A, int64_t lda2, int64_t m, int n,
+                                                       int B, const double* __restrict__ P0,
+                                                       const double* __restrict__ P1, const double* __restrict__ P2,
+                                                       int np, int init, double* __restrict__ Gpart,
+                                                       int64_t rows_per_range, int64_t nrr, int nslice,
+                                                       const Ctl* __restrict__ ctl) {
+  if (ctl != nullptr && ctl->done) return;
+  constexpr int TW = 16 * NT;  // Tr columns staged per row
+  __shared__ double Ts[2][ZM_G_RC * TW];
+  // block -> (row range, column slice): the slices of a row range are
+  // neighbouring blocks of one XCD, so the staged rows of Tr come from L2
+  const int64_t bid = blockIdx.x;
+  const int64_t kx = bid >> 3;
+  const int slice = (int)(kx % nslice);
+  const int64_t rr = (kx / nslice) * 8 + (bid & 7);
+  if (rr >= nrr) return;  // uniform over the workgroup
+  const int lane = threadIdx.x & 63, wave = wave_index();
+  const int q = lane >> 4, t = lane & 15;
+  const int n2 = 2 * n, B2 = 2 * B;
+  const int kw = 256 * slice + 64 * wave;  // this wave's first real column of A
+  const bool active = kw < n2;
+  const int64_t r0 = rr * rows_per_range;
+  const int64_t r1 = (r0 + rows_per_range < m) ? r0 + rows_per_range : m;
+  const int ncol = np * B2;
+  const double* Pg[3] = {P0, P1, P2};
+  // staging: element e of a chunk is (row e / TW, Tr column e % TW); it is
+  // stored at row * TW + (col % 16) * NT + col / 16 so that lane t finds its
+  // NT values (columns t, 16 + t, ...) side by side
+  constexpr int PER = (ZM_G_RC * TW + ZM_G_THREADS - 1) / ZM_G_THREADS;
+  auto fetch = [&](double (&v)[PER], int64_t cb) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + i * ZM_G_THREADS;
+      const int rw = e / TW, col = e - (e / TW) * TW;
+      const int64_t grow = cb + rw;
+      double x = 0.0;
+      if (e < ZM_G_RC * TW && grow < r1 && col < ncol) {
+        const int g = col / B2;
+        const double* P = Pg[g];
+        if (P != nullptr) x = P[grow * B2 + (col - g * B2)];
+      }
+      v[i] = x;
+    }
+  };
+  auto stage = [&](const double (&v)[PER], int buf) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + i * ZM_G_THREADS;
+      if (e < ZM_G_RC * TW) {
+        const int rw = e / TW, col = e - (e / TW) * TW;
+        Ts[buf][rw * TW + (col & 15) * NT + (col >> 4)] = v[i];
+      }
+    }
+  };
+  zm_v4d acc[4][NT];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[u][nt] = zm_v4d{0.0, 0.0, 0.0, 0.0};
+  const int kcol = kw + 4 * t;  // this lane's four columns of A: kcol .. kcol + 3
+  auto loada = [&](double2 (&a)[2], int64_t grow) {
+    const double* p = A + grow * lda2 + kcol;
+    const bool ok = active && grow < r1;
+    a[0] = (ok && kcol < n2) ? ld_stream2(p) : make_double2(0.0, 0.0);
+    a[1] = (ok && kcol + 2 < n2) ? ld_stream2(p + 2) : make_double2(0.0, 0.0);
+  };
+  {
+    double v[PER];
+    fetch(v, r0);
+    stage(v, 0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t cb = r0; cb < r1; cb += ZM_G_RC) {
+    double v[PER];
+    const bool more = cb + ZM_G_RC < r1;
+    if (more) fetch(v, cb + ZM_G_RC);
+    if (active) {
+      double2 an[2];
+      loada(an, cb + q);
+      const double* Tb = Ts[buf];
+#pragma unroll 2
+      for (int ks = 0; ks < ZM_G_RC / 4; ++ks) {
+        double2 a[2] = {an[0], an[1]};
+        if (ks + 1 < ZM_G_RC / 4) loada(an, cb + 4 * (ks + 1) + q);
+        const double* tr = Tb + (4 * ks + q) * TW + t * NT;
+        double bv[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) bv[nt] = tr[nt];
+        const double av[4] = {a[0].x, a[0].y, a[1].x, a[1].y};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) acc[u][nt] = zm_mfma(av[u], bv[nt], acc[u][nt]);
+      }
+    }
+    if (more) stage(v, buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  if (!active) return;
+  // 2 x 2 combination: tile u (even) holds Gr(2c, .), tile u + 1 Gr(2c + 1, .)
+  // at the same lane and register; columns 2v and 2v + 1 are lanes t and t + 1.
+  const int64_t plane = 2 * (int64_t)n * B;
+  double* gp = Gpart + rr * 4 * plane;
+  const int rp = t & 1;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double x0 = acc[2 * h][nt][r], x1 = acc[2 * h + 1][nt][r];
+        const double y0 = dpp_d<0xB1>(x0), y1 = dpp_d<0xB1>(x1);  // the neighbour lane t ^ 1
+        // output row 4r + q of the tile is the column group kcol' = kw + 4 (4r + q)
+        const int c = (kw + 4 * (4 * r + q)) / 2 + h;
+        const int colr = 16 * nt + t;  // Tr column of this lane (even t: re part)
+        if (rp == 0 && c < n && colr < ncol) {
+          const int g = colr / B2, vv = (colr - g * B2) >> 1;
+          const double re = x0 + y1;  // Gr(2c, 2v) + Gr(2c+1, 2v+1)
+          const double im = y0 - x1;  // Gr(2c, 2v+1) - Gr(2c+1, 2v)
+          const int pl = init ? 0 : g;
+          double* dst = gp + (int64_t)pl * plane + 2 * ((int64_t)c * B + vv);
+          dst[0] = re;
+          dst[1] = im;
+        }
+      }
+  // the planes this pass does not form, and the error plane, are zero
+  for (int cc = lane; cc < 32 * B; cc += 64) {
+    const int c = kw / 2 + cc / B, vv = cc - (cc / B) * B;
+    if (c < n) {
+      const int64_t e = 2 * ((int64_t)c * B + vv);
+      for (int pl = (init ? 1 : 3); pl < 4; ++pl) {
+        gp[pl * plane + e] = 0.0;
+        gp[pl * plane + e + 1] = 0.0;
+      }
+    }
+  }
+}
+
+bool astream_zm_fits(int B, int n, bool aligned, int64_t lds_max) {
+  return aligned && n > 256 && n <= 1024 && B >= 1 && B <= 10 && (int64_t)n * B * 16 <= lds_max;
+}
+
+template <int NT>
+static hipError_t zm_aw_go(hipStream_t st, int grid, const double* A, int64_t lda2, int64_t m, int n, int B,
+                           const cd* W, double* AW, const Ctl* ctl) {
+  const size_t lds = sizeof(cd) * (size_t)n * B;
+  const hipError_t e = hipFuncSetAttribute((const void*)k_zm_aw<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zm_aw<NT>, dim3((unsigned)grid), dim3(ZM_AW_THREADS), lds, st, A, lda2, m, n, B, W, AW, ctl);
+  return hipGetLastError();
+}
+
+template <int NT>
+static void zm_g_go(hipStream_t st, int64_t nblk, const double* A, int64_t lda2, int64_t m, int n, int B,
+                    const double* P0, const double* P1, const double* P2, int np, int init, double* Gpart,
+                    int64_t rows, int64_t nrr, int nslice, const Ctl* ctl) {
+  hipLaunchKernelGGL(k_zm_g<NT>, dim3((unsigned)nblk), dim3(ZM_G_THREADS), 0, st, A, lda2, m, n, B, P0, P1, P2, np,
+                     init, Gpart, rows, nrr, nslice, ctl);
+}
+
+// A_W = A W, then the partial records of A^* [A_V A_X A_W] (init: A^* A_W in
+// the first plane) over nrr row ranges.
+bool dispatch_astream_zm(int init, int B, hipStream_t st, int64_t nrr, const void* A, int64_t lda, int64_t m, int n,
+                         const void* W, void* AW, const void* AVp, const void* AXp, double* Gpart, int n_cu,
+                         const Ctl* ctl) {
+  if (n <= 256 || n > 1024 || B < 1 || B > 10 || nrr < 1) return false;
+  const double* Ad = (const double*)A;
+  const int64_t lda2 = 2 * lda;
+  // one workgroup per CU (W fills the LDS), at most one per 32-row tile per wave
+  const int64_t tiles = (m + 31) / 32;
+  int grid = n_cu > 0 ? n_cu : 256;
+  if ((int64_t)grid * (ZM_AW_THREADS / 64) > tiles) grid = (int)((tiles + 15) / 16);
+  if (grid < 1) grid = 1;
+  hipError_t e;
+  if (2 * B <= 16)
+    e = zm_aw_go<1>(st, grid, Ad, lda2, m, n, B, (const cd*)W, (double*)AW, ctl);
+  else
+    e = zm_aw_go<2>(st, grid, Ad, lda2, m, n, B, (const cd*)W, (double*)AW, ctl);
+  if (e != hipSuccess) return false;
+  const int64_t rows = (m + nrr - 1) / nrr;
+  const int nslice = (2 * n + 255) / 256;
+  const int64_t nblk = ((nrr + 7) / 8) * 8 * nslice;
+  const double* P0 = init ? (const double*)AW : (const double*)AVp;
+  const double* P1 = init ? nullptr : (const double*)AXp;
+  const double* P2 = init ? nullptr : (const double*)AW;
+  const int np = init ? 1 : 3;
+  const int nt = (np * 2 * B + 15) / 16;
+  switch (nt) {
+    case 1: zm_g_go<1>(st, nblk, Ad, lda2, m, n, B, P0, P1, P2, np, init, Gpart, rows, nrr, nslice, ctl); break;
+    case 2: zm_g_go<2>(st, nblk, Ad, lda2, m, n, B, P0, P1, P2, np, init, Gpart, rows, nrr, nslice, ctl); break;
+    case 3: zm_g_go<3>(st, nblk, Ad, lda2, m, n, B, P0, P1, P2, np, init, Gpart, rows, nrr, nslice, ctl); break;
+    case 4: zm_g_go<4>(st, nblk, Ad, lda2, m, n, B, P0, P1, P2, np, init, Gpart, rows, nrr, nslice, ctl); break;
+    default: return false;
+  }
+  return hipGetLastError() == hipSuccess;
+}
+
+}  // namespace rl

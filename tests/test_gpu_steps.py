@@ -84,7 +84,8 @@ def test_qr_and_inverse(rl, d, n, cplx):
                                              (3000, 256, 3, False, False), (2049, 65, 2, True, False),
                                              (2049, 65, 2, True, True), (1500, 1000, 10, True, False), (999, 1024, 10, False, True),
                                              (17, 130, 3, False, True), (40_000, 300, 4, False, True),
-                                             (30_000, 500, 5, False, False)])
+                                             (30_000, 500, 5, False, False), (1001, 301, 1, True, False),
+                                             (5000, 1024, 10, True, False)])
 def test_astream(rl, m, n, b, cplx, dot2):
     banner(f"astream m={m} n={n} b={b} complex={cplx} dot2={dot2}")
     rng = np.random.default_rng(m + n + b)
@@ -124,7 +125,11 @@ def _rand(rng, shape, cplx):
     (4001, 700, 7, False, True, True), (3000, 1024, 10, False, False, False),
     (2049, 65, 2, True, True, True), (3001, 1000, 10, True, True, True), (3001, 1000, 10, True, False, True),
     (5000, 777, 7, True, False, False), (1234, 1024, 5, True, True, True), (40, 64, 3, True, False, True),
-    (7777, 513, 5, False, True, True)])
+    (7777, 513, 5, False, True, True),
+    # complex plain sums on the matrix cores: odd n (a ragged last k block),
+    # n just above 256, b = 1 and b = 8 (one N tile), fewer rows than a tile
+    (3001, 301, 1, True, False, True), (977, 257, 8, True, False, True), (33, 600, 3, True, False, False),
+    (20_011, 1000, 10, True, False, True)])
 def test_astream_iter(rl, m, n, b, cplx, dot2, with_x):
     """Iteration form of the pass: A W and A^* [A_V A_X A_W] from one read of A."""
     banner(f"astream_iter m={m} n={n} b={b} complex={cplx} dot2={dot2} AX={with_x}")
