@@ -73,3 +73,28 @@ def test_full_size_workload(rl, m, n, k, d, dseed, sseed, smin, gap):
     assert np.max(np.abs(Av - Ug * sg[None, :])) <= 1e-12 * normA
     del A
     torch.cuda.empty_cache()
+
+
+def test_full_size_single_vector_against_the_oracle(rl):
+    """The 10^6 x 200, k = 1 workload solved by the oracle as well (its
+    compensated products run in C threads): the GPU's sigma within
+    1e-12 ||A|| and its vector within a principal-angle sine of 1e-10 of the
+    oracle's, both sides working on the same stored A."""
+    from oracle import eft as oeft
+    from oracle import rlobpcg
+    m, n, k, d, dseed, sseed, smin, gap = CASES[0]
+    banner(f"full size against the oracle m={m} n={n} k={k} (oracle threads {oeft.get_threads()})")
+    sig = spectrum_gap(n, k, smin, gap)
+    A, _, _ = planted_torch(m, n, sig, dseed, device="cuda")
+    torch.cuda.synchronize()
+    r = rl.rl_svds_smallest(A, k, seed=sseed, d=d, zeta=8)
+    sg, Vg = to_np(r.sigma), to_np(r.V)
+    Ah = to_np(A)
+    del A
+    torch.cuda.empty_cache()
+    o = rlobpcg(Ah, k, seed=sseed, d=d, zeta=8)
+    ang = sin_angle(Vg, o.V)
+    banner(f"  gpu iters {r.iters} oracle iters {o.iters}; sigma gpu {sg} oracle {o.sigma}; sin angle {ang:.2e}")
+    assert o.status == 0 and r.status == 0
+    assert np.max(np.abs(sg - o.sigma)) <= 1e-12 * float(np.max(sig))
+    assert ang <= 1e-10

@@ -29,16 +29,21 @@ def rl():
 
 
 def _check(rl, A, k, *, seed, normA, block=None, gap_ok=True, rule="paper", max_iter=None, dot2=True,
-           angle_tol=1e-10):
+           angle_tol=1e-10, oracle_dot2=None, d=None, oracle=None):
+    """GPU solve (products with or without Dot2) against the oracle (with
+    Dot2 unless oracle_dot2 says otherwise), on the gates of the module doc."""
     At = torch.from_numpy(A).cuda()
     kw = dict(seed=seed, rule=rule, dot2=dot2)
     if block is not None:
         kw["block"] = block
     if max_iter is not None:
         kw["max_iter"] = max_iter
+    if d is not None:
+        kw["d"] = d
     r = rl.rl_svds_smallest(At, k, **kw)
     sg, Vg, Ug = to_np(r.sigma), to_np(r.V), to_np(r.U)
-    o = rlobpcg(A, k, seed=seed, block=block, rule=rule, max_iter=max_iter, dot2=dot2)
+    o = oracle if oracle is not None else rlobpcg(A, k, seed=seed, block=block, rule=rule, max_iter=max_iter, d=d,
+                                                  dot2=dot2 if oracle_dot2 is None else oracle_dot2)
     banner(f"  gpu iters {r.iters} status {r.status}; oracle iters {o.iters} status {o.status}; "
            f"sigma gpu {sg} oracle {o.sigma}")
     assert np.all(np.diff(sg) >= 0)

@@ -1,0 +1,59 @@
+"""Full solves on the wide and wide-block paths against the CPU oracle.
+
+* The complex null-space workload's structure (rank n - 10 plus complex
+  Gaussian noise of std 1e-14, k = b = 10, sketch d = 3n) at 8000 x 400, so
+  the solve runs the kernels of the 10^6 x 1000 workload: the complex sketch
+  QR above n = 256, the wide complex pass (compensated sums on the vector
+  units, or plain sums on the matrix cores), TSQR of the 30-column trial
+  basis, and the Rayleigh-Ritz, panel and orthogonalisation kernels at
+  b = 10.  The oracle uses compensated products either way; the plain-sum
+  GPU path must still meet every gate (its rounding moves the null space's
+  vectors by about u ||A||_F / (sqrt(m) sigma_{n-10}) = 1e-13 here).
+* Real blocks of 8 and 10 vectors at n = 300 (the column-split pass and the
+  column-wave TSQR at t = 24 and 30).
+
+Gates as in test_gpu_parity: |sigma - sigma_oracle| <= 1e-12 ||A||, the
+residual ||A v - sigma u|| <= 1e-12 ||A||, the principal-angle sine to the
+oracle's subspace <= 1e-10, and the GPU's stop re-derived from its own
+histories by the oracle's stopping rule.
+"""
+
+import pytest
+
+from oracle import rlobpcg
+from workloads import planted_numpy, spectrum_gap, spectrum_nullspace
+
+from .gpu_util import banner
+from .test_gpu_parity import _check
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rl():
+    import paper_2602_16797_amd as rl
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return rl
+
+
+@pytest.fixture(scope="module")
+def nullspace_8000x400():
+    """The input and the oracle's solve (compensated products), shared by both GPU variants."""
+    A, _, s = planted_numpy(8000, 400, spectrum_nullspace(400, 10, 1e-4), 1313, is_complex=True, noise_std=1e-14)
+    return A, s, rlobpcg(A, 10, seed=2313, d=1200, dot2=True)
+
+
+@pytest.mark.parametrize("dot2", [True, False])
+def test_complex_nullspace_block10_wide(rl, nullspace_8000x400, dot2):
+    A, s, o = nullspace_8000x400
+    banner(f"parity complex nullspace 8000x400 k=b=10 d=3n, GPU dot2={dot2}")
+    _check(rl, A, 10, seed=2313, normA=s[0], dot2=dot2, d=1200, oracle=o)
+
+
+@pytest.mark.parametrize("k", [8, 10])
+def test_real_block_wide(rl, k):
+    banner(f"parity real 20000x300 k=b={k}")
+    A, _, s = planted_numpy(20_000, 300, spectrum_gap(300, k, 1e-8, 10.0), 1400 + k)
+    _check(rl, A, k, seed=2400 + k, normA=s[0])
