@@ -1,16 +1,25 @@
 """Benchmark: one RLOBPCG solve per step on one MI355X.
 
-Workload (default): the real FP64 tall matrix of the 10^6 x 200, k = 1 case:
-A = U diag(sigma) V^T with U, V from seeded Gaussians, sigma geometric from 1
-with a drop of 10 onto sigma_n = 1e-12, sketch d = 4n = 800 with 8 nonzeros
-per column.  A is drawn on the device (torch RNG, Cholesky-QR2 for U) and is
-resident in HBM before the timed region.  One step = one full solve (sketch,
-QR, preconditioner, start block, LOBPCG to the stopping rule, outputs).
+Workload (default): the complex null-space problem at 10^6 x 1000, k = 10
+(complex128): A = U diag(sigma) V^H plus i.i.d. complex Gaussian noise of std
+1e-14, sigma_1..sigma_990 log-spaced from 1 to 1e-4 and the last 10 zero,
+sketch d = 3n = 3000 with 8 nonzeros per column, block b = k = 10.  A is drawn
+on the device (torch RNG, Cholesky-QR2 for U) and is resident in HBM before
+the timed region.  One step = one full solve (sketch, QR, preconditioner,
+start block, LOBPCG to the stopping rule or max_iter, outputs).  Its pass
+runs the products with A on the FP64 matrix cores with plain sums (see
+the design doc for why the compensated sums are not the default there).  The other
+workloads (--workload) are the real 10^6 x 200 (k = 1), 2*10^6 x 500 (k = 5)
+and 4000 x 50 (k = 1) problems, with compensated (Dot2) products.
 
 The JSON line reports solves/s as ``value``; time-to-solution as
-``ms_per_step``; the fused A-stream kernel (A W and A^* A W in one read of A)
-against the HBM roofline, timed with HIP events around each launch on the
-solve's stream; and the CPU oracle on a bounded sample of the same solve.
+``ms_per_step``; the dominant kernel against its roofline (the Gram
+contraction A^* [A_V A_X A_W] against the FP64 matrix-core peak for the
+complex workload, the fused one-read pass against HBM for the real ones),
+timed with HIP events around each launch on the solve's stream, plus the
+whole pass against max(bytes / HBM peak, flops / FP64 peak); and the CPU
+oracle timed on a row sample of the same input with all host cores and with
+one thread, scaled to the full solve.
 """
 
 from __future__ import annotations
@@ -28,6 +37,11 @@ if ROOT not in sys.path:
 
 METRIC = "time-to-solution & A-stream HBM GB/s at resid≤1e-12‖A‖; solves/s + p99 served"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+DEFAULT_WORKLOAD = "tall-1e6x1000c-k10"
+# products with A per workload: compensated (Dot2) sums, or plain sums (the
+# complex null-space workload, whose pass then runs on the matrix cores)
+DEFAULT_DOT2 = {"tall-1e6x1000c-k10": False}
 
 WORKLOADS = {
     # name: (m, n, k, d, zeta, complex, data seed, sketch seed, spectrum)
@@ -52,10 +66,12 @@ def spectrum(n, k, spec):
     return spectrum_logspace_tail(n, spec[1], spec[2])
 
 
-def astream_kernel(cplx: bool, n: int, b: int) -> str:
+def astream_kernel(cplx: bool, n: int, b: int, dot2: bool = True) -> str:
     """The pass kernel(s) the library launches for this shape (the dispatch
     rule of launch_astream, for a dense A with 16-byte aligned rows)."""
     if cplx:
+        if 256 < n <= 1024 and not dot2:
+            return "k_zm_aw + k_zm_g (A W, then A^* [A_V A_X A_W] on the FP64 matrix cores: two reads of A)"
         if 256 < n <= 1024:
             return "k_c2_rows + k_c2_cols (A W, then A^* [A_V A_X A_W]: two reads of A)"
         if n <= 1024:
@@ -90,38 +106,64 @@ def measured_traffic(workload: str):
     return int(data["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(A_dev, k, seed, d, zeta, gpu_iters, budget_s=25.0):
-    """The oracle timed on this host: its setup (sketch, SVD, start) plus a few
-    LOBPCG iterations on the full input, scaled to the GPU's iteration count."""
+def _oracle_sample_times(A, k, seed, d, zeta, dot2, threads, extra=5):
+    """Times of the oracle on the row sample A with the given thread count
+    (BLAS and the compensated products): setup (sketch, SVD of S*A, start),
+    the SVD of S*A alone, and one LOBPCG iteration (from runs of 1 and
+    1 + extra iterations, after an untimed warm-up run)."""
     import numpy as np
-    from oracle import rlobpcg
-    A = A_dev.cpu().numpy()
-    t0 = time.perf_counter()
-    rlobpcg(A, k, seed=seed, d=d, zeta=zeta, max_iter=0, rule="none")
-    t_setup = time.perf_counter() - t0
-    iters = 1
-    t1 = time.perf_counter()
-    rlobpcg(A, k, seed=seed, d=d, zeta=zeta, max_iter=iters, rule="none")
-    t_one = time.perf_counter() - t1
-    per_iter = max(t_one - t_setup, 1e-9) / iters
-    extra = int(max(0, min(4, (budget_s - (t_setup + t_one)) / max(per_iter, 1e-9) - 1)))
-    if extra >= 1:
-        t2 = time.perf_counter()
-        rlobpcg(A, k, seed=seed, d=d, zeta=zeta, max_iter=1 + extra, rule="none")
-        t_more = time.perf_counter() - t2
-        per_iter = max(t_more - t_setup, 1e-9) / (1 + extra)
-        iters = 1 + extra
-    t_solve = t_setup + gpu_iters * per_iter
+    from threadpoolctl import threadpool_limits
+
+    from oracle import eft, rlobpcg, sparsestack
+    eft.set_threads(threads)
+    with threadpool_limits(limits=threads):
+        rlobpcg(A, k, seed=seed, d=d, zeta=zeta, max_iter=0, rule="none", dot2=dot2, refresh=False)
+
+        def run(iters):
+            t0 = time.perf_counter()
+            rlobpcg(A, k, seed=seed, d=d, zeta=zeta, max_iter=iters, rule="none", dot2=dot2, refresh=False)
+            return time.perf_counter() - t0
+        t_a = run(1)
+        t_b = run(1 + extra)
+        t_iter = max(t_b - t_a, 1e-9) / extra
+        SA = sparsestack.sketch(A, d, zeta, seed)
+        t0 = time.perf_counter()
+        np.linalg.svd(SA, full_matrices=False)
+        t_svd = time.perf_counter() - t0
+    return max(t_a - t_iter, t_svd), t_svd, t_iter
+
+
+def cpu_baseline(A_dev, k, seed, d, zeta, gpu_iters, dot2, sample_rows):
+    """The oracle timed on this host on a bounded sample: its first
+    sample_rows rows, run with all host cores and with one thread; every
+    cost that grows with m (the sketch, the products with A, the tall
+    Rayleigh-Ritz) is scaled by m / sample_rows, the SVD of the d x n sketch
+    is counted once, and the iteration count is the GPU's."""
+    m, n = A_dev.shape
+    ms = int(min(m, max(sample_rows, d + 1, n + 1)))
+    A = A_dev[:ms].cpu().numpy()
+    f = m / ms
     cores = len(os.sched_getaffinity(0))
-    del A, np
+    res = {}
+    for thr in (cores, 1):
+        t_setup, t_svd, t_iter = _oracle_sample_times(A, k, seed, d, zeta, dot2, thr)
+        t_solve = t_svd + (t_setup - t_svd) * f + gpu_iters * t_iter * f
+        res[thr] = (t_solve, t_setup, t_svd, t_iter)
+    del A
+    tN, t1 = res[cores], res[1]
     return {
-        "value": 1.0 / t_solve,
+        "value": 1.0 / tN[0],
         "unit": "solves/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": (f"oracle setup (sketch, SVD of S*A, start) plus {iters} LOBPCG iteration(s) with Dot2 "
-                   f"products on the full input, scaled to the GPU's {gpu_iters} iterations "
-                   f"(setup {t_setup:.2f} s, {per_iter:.2f} s/iteration)"),
+        "value_1thread": 1.0 / t1[0],
+        "sample": (f"oracle (compensated products {'on' if dot2 else 'off'}, as the GPU run) on the first {ms} of "
+                   f"{m} rows: setup and LOBPCG iterations timed (runs of 1 and 6 iterations after a warm-up), "
+                   f"the m-proportional parts scaled by "
+                   f"{f:.1f}, the SVD of the {d}x{n} sketch counted once, {gpu_iters} iterations as on the GPU; "
+                   f"{cores} threads: setup {tN[1]:.2f} s (SVD {tN[2]:.2f} s), {tN[3]:.4f} s/iteration on the "
+                   f"sample; 1 thread: setup {t1[1]:.2f} s (SVD {t1[2]:.2f} s), {t1[3]:.4f} s/iteration; the refresh "
+                   f"pass (one more product) is not counted"),
     }
 
 
@@ -213,11 +255,16 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="tall-1e6x200-k1", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sketch-prec", default="f64", choices=["f64", "f32", "bf16"],
                     help="precision of the sketch and its QR (the rest stays FP64)")
-    ap.add_argument("--no-dot2", action="store_true", help="plain FP64 products of A (no compensation)")
+    ap.add_argument("--dot2", default="auto", choices=["auto", "on", "off"],
+                    help="compensated (Dot2) products with A; auto: off for the complex null-space workload "
+                         "(its pass then runs on the matrix cores), on for the others")
+    ap.add_argument("--no-dot2", action="store_true", help="same as --dot2 off")
+    ap.add_argument("--cpu-sample-rows", type=int, default=0,
+                    help="rows of A in the oracle's timed sample (default: about 15 s of oracle work)")
     ap.add_argument("--orth", default="cgs2", choices=["cgs2", "svqb"],
                     help="Orth of the new search block after its block projections: CGS2 (the method) or SVQB")
     ap.add_argument("--loop-precond", default="sketch", choices=["sketch", "diag", "none"],
@@ -250,13 +297,16 @@ def main(argv=None):
     from workloads import planted_torch
 
     m, n, k, d, zeta, cplx, dseed, sseed, spec = WORKLOADS[args.workload]
+    if args.no_dot2:
+        args.dot2 = "off"
+    dot2 = DEFAULT_DOT2.get(args.workload, True) if args.dot2 == "auto" else args.dot2 == "on"
     sig = spectrum(n, k, spec)
     log(f"drawing {args.workload}: {m}x{n} on cuda:0")
     noise = spec[2] if spec[0] == "null" else 0.0
     A, Vp, s = planted_torch(m, n, sig, dseed, device="cuda", is_complex=cplx, noise_std=noise)
     torch.cuda.synchronize()
     es = 16 if cplx else 8
-    kw = dict(seed=sseed, d=d, zeta=zeta, sketch_prec=args.sketch_prec, dot2=not args.no_dot2,
+    kw = dict(seed=sseed, d=d, zeta=zeta, sketch_prec=args.sketch_prec, dot2=dot2,
               loop_precond=args.loop_precond, orth=args.orth)
 
     for w in range(args.warmup):
@@ -298,12 +348,12 @@ def main(argv=None):
                                  "fp64_iters": ref.iters}
         log(f"vs FP64 Dot2 solve: {gates['vs_fp64_dot2']}")
 
-    # dominant kernel: the A-stream pass, its kernels timed per launch with HIP
-    # events (the reduction of the per-workgroup partial sums is excluded)
-    # Algorithmic bytes of each launch: A once, W, the A_W write, and the
-    # panel reads the fused form needs (A_V from the first loop pass on, A_X
-    # from the second); the start pass reads neither.  b is the solve's
-    # block size.
+    # The A-stream pass, its kernels timed per launch with HIP events on the
+    # solve's stream (the reduction of the per-workgroup partial sums is
+    # excluded).  Algorithmic bytes of each launch: A once, W, the A_W write,
+    # and the panel reads the fused form needs (A_V from the first loop pass
+    # on, A_X from the second); the start pass reads neither.  b is the
+    # solve's block size.
     n_as = sum(r.n_astream for r in results)
     t_as = sum(r.t_astream_us for r in results)
     avg_us = t_as / max(n_as, 1)
@@ -315,14 +365,39 @@ def main(argv=None):
         it = r.n_astream - 1
         tot_bytes += (1 + it) * base + it * mv + max(it - 1, 0) * mv
     bytes_launch = tot_bytes / max(n_as, 1)
-    achieved = bytes_launch / (avg_us * 1e-6) / 1e9
+    # flops of the two products of an iteration in the paper's form (A W and
+    # A^* A_V): 2 x 8 m n b real flops for complex data, 2 x 2 m n b for real
+    cflop = 8 if cplx else 2
+    pass_flops = 2 * cflop * m * n * bb
+    bound_us = 1e6 * max(bytes_launch / (HBM_PEAK_GBS * 1e9), pass_flops / (FP64_PEAK_TFS * 1e12))
+    pass_line = {"avg_launch_us": round(avg_us, 2), "algorithmic_bytes": round(bytes_launch),
+                 "flops": pass_flops, "bound_us": round(bound_us, 2), "frac": round(bound_us / avg_us, 4),
+                 "bound_rule": "max(bytes / 8 TB/s, flops / 78.6 TFLOP/s)"}
+    n_g = sum(r.n_pass_g for r in results)
     traffic = (measured_traffic(args.workload)
-               if (args.sketch_prec == "f64" and not args.no_dot2 and args.loop_precond == "sketch"
-                   and args.orth == "cgs2") else None)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": astream_kernel(cplx, n, last.block), "avg_launch_us": round(avg_us, 2),
-                "launches": n_as, "algorithmic_bytes_per_launch": round(bytes_launch)}
+               if (args.sketch_prec == "f64" and dot2 == DEFAULT_DOT2.get(args.workload, True)
+                   and args.loop_precond == "sketch" and args.orth == "cgs2") else None)
+    if n_g > 0:
+        # the dominant kernel is the Gram contraction A^* [A_V A_X A_W] on the
+        # matrix cores: 8 m n b flops per block with data (A_V and A_W on the
+        # first loop pass, A_X too from the second on)
+        t_g = sum(r.t_pass_g_us for r in results)
+        g_us = t_g / n_g
+        g_flops = sum(cflop * m * n * bb * (2 + 3 * (r.n_pass_g - 1)) for r in results if r.n_pass_g > 0)
+        g_flops_launch = g_flops / n_g
+        achieved = g_flops_launch / (g_us * 1e-6) / 1e12
+        roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP64_PEAK_TFS, 4), "traffic": traffic,
+                    "kernel": "k_zm_g (A^* [A_V A_X A_W] on the FP64 matrix cores)", "avg_launch_us": round(g_us, 2),
+                    "launches": n_g, "algorithmic_flops_per_launch": round(g_flops_launch),
+                    "pass": astream_kernel(cplx, n, bb, dot2), "pass_roofline": pass_line}
+    else:
+        achieved = bytes_launch / (avg_us * 1e-6) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "kernel": astream_kernel(cplx, n, bb, dot2), "avg_launch_us": round(avg_us, 2),
+                    "launches": n_as, "algorithmic_bytes_per_launch": round(bytes_launch),
+                    "pass_roofline": pass_line}
 
     if args.copy_calibration:
         src = torch.empty(200_000_000, dtype=torch.float64, device="cuda")
@@ -337,7 +412,10 @@ def main(argv=None):
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(A, k, sseed, d, zeta, last.iters)
+        # about 15 s of oracle work on all cores: the products with A cost
+        # about 50 (real) or 200 (complex) flops per element and vector
+        rows = args.cpu_sample_rows or int(min(m, max(2 * d, 3e10 / (n * bb * (200 if cplx else 50)))))
+        cpu = cpu_baseline(A, k, sseed, d, zeta, last.iters, dot2, rows)
         log(f"cpu baseline: {cpu}")
 
     line = {
@@ -354,7 +432,7 @@ def main(argv=None):
         "dtype": "c128" if cplx else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "k": k, "d": d, "zeta": zeta,
-                   "spectrum": list(spec), "stop_rule": "paper", "dot2": not args.no_dot2,
+                   "spectrum": list(spec), "stop_rule": "paper", "dot2": dot2,
                    "sketch_prec": args.sketch_prec, "loop_precond": args.loop_precond, "orth": args.orth},
         "roofline": roofline,
         "cpu_baseline": cpu,

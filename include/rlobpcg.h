@@ -93,7 +93,10 @@ typedef struct {
   int32_t sketch_prec; /* RL_SKETCH_*: precision of the sketch S*A and its QR (real A only); default FP64 */
   int32_t loop_precond; /* RL_PREC_*: preconditioner of the LOBPCG loop; default RL_PREC_SKETCH */
   int32_t orth;       /* RL_ORTH_*: Orth of W in the loop after the block projections; default RL_ORTH_CGS2 */
-  int32_t reserved[2];
+  int32_t refresh;    /* 1 (default): after the loop, A V-hat afresh (one more pass over A) and its thin SVD
+                         rotate (V-hat, sigma, U-hat), so the outputs carry no drift of the products the loop
+                         maintains by recurrence; 0: the last Rayleigh-Ritz's triplets, U-hat = A_V / theta */
+  int32_t reserved;
 } rl_opts;
 
 /* Per-solve report (host).  theta_hist / rnorm_hist are optional host arrays
@@ -102,7 +105,7 @@ typedef struct {
 typedef struct {
   int32_t status;      /* RL_OK or RL_NOT_CONVERGED */
   int32_t iters;       /* loop iterations executed */
-  int32_t a_passes;    /* full passes over A (sketch + start + one per iteration) */
+  int32_t a_passes;    /* full passes over A (sketch + start + one per iteration, + 1 with refresh) */
   int32_t degenerate;  /* a Normalize/Orth met a zero vector */
   int32_t zero_theta;  /* some returned sigma is exactly 0 (its U column is 0) */
   int32_t block;       /* b used */
@@ -116,6 +119,9 @@ typedef struct {
   double t_astream_us; /* summed duration of their pass kernels (the reduction of the partial sums excluded) */
   double* theta_hist;  /* host, may be NULL */
   double* rnorm_hist;  /* host, may be NULL */
+  int32_t n_pass_g;    /* timed launches made of two kernels (A W, then the Gram contraction A^* [A_V A_X A_W]) */
+  int32_t pad0;
+  double t_pass_g_us;  /* summed duration of their second kernel (opts.profile) */
 } rl_info;
 
 /* Handle: one per (device, stream).  stream may be NULL (the null stream). */
@@ -132,8 +138,8 @@ int rl_default_opts(rl_opts* o, int64_t m, int64_t n, int32_t k);
  *   A      device, m x n, row-major, leading dimension lda
  *   sigma  device, k doubles, ascending
  *   V      device, n x k (ldv >= k): right singular vectors, column j <-> sigma[j]
- *   U      device, m x k (ldu >= k) or NULL: U(:, j) = A V(:, j) / sigma[j]
- *          from the final Rayleigh-Ritz basis
+ *   U      device, m x k (ldu >= k) or NULL: U(:, j) = A V(:, j) / sigma[j], from the
+ *          refreshed product A V (opts.refresh) or the final Rayleigh-Ritz basis
  *   opts   host, may be NULL (defaults); info host, may be NULL
  * Vectors are defined up to a unit phase per column, and inside a cluster of
  * equal sigma only their span is defined. */

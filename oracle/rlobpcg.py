@@ -42,8 +42,10 @@ Readings where the paper is silent:
     b > 1 the start block is first rotated by Rayleigh-Ritz on span(V_0)
     (Alg. rlobpcg).
   * U-hat_j = A_V(:, j) / theta_j (zero, with the ``zero_theta`` flag, if
-    theta_j = 0).  ``refresh=True`` recomputes A_V = A V-hat once at the end
-    and rotates (V-hat, sigma, U-hat) by the SVD of that m x b block.
+    theta_j = 0).  ``refresh=True`` (the default) recomputes A_V = A V-hat
+    once at the end and rotates (V-hat, sigma, U-hat) by the SVD of that
+    m x b block, so the outputs carry no drift of the maintained products;
+    ``refresh=False`` returns the last Rayleigh-Ritz triplets as they are.
   * ``precond="qr"`` uses R from S A = Q R with P = R^{-1}; P P^* = (R^* R)^{-1}
     = ((S A)^* S A)^{-1} = V~ Sigma~^{-2} V~^*, the same operator as the SVD
     route (Sec. 1, footnote on QR), with V_0 taken from the SVD of R.
@@ -236,7 +238,7 @@ def left_vectors(AV: np.ndarray, sig: np.ndarray):
 def rlobpcg(A, k: int, *, block: int | None = None, d: int | None = None,
             zeta: int = 8, seed: int = 0, tau: float | None = None,
             max_iter: int | None = None, rule: str = "paper", check_every: int = 5,
-            precond: str = "svd", dot2: bool = True, refresh: bool = False,
+            precond: str = "svd", dot2: bool = True, refresh: bool = True,
             loop_precond: str = "sketch", orth: str = "cgs2", callback=None) -> RLResult:
     """Return the k smallest singular triplets of the tall matrix A."""
     A = np.asarray(A)

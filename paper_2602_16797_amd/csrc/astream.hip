@@ -197,7 +197,9 @@ int64_t astream_tmp_doubles(int64_t m, int n, int B, int es_d) {
 // records for launch_astream_reduce.
 hipError_t launch_astream_pass(hipStream_t st, bool cplx, int B, bool dot2, const void* A, int64_t lda, int64_t m,
                                int n, const void* W, void* AW, const void* AVp, const void* AXp, int init,
-                               double* Gpart, const Ctl* ctl, int64_t* np_out) {
+                               double* Gpart, const Ctl* ctl, int64_t* np_out, hipEvent_t mid,
+                               bool* mid_recorded) {
+  if (mid_recorded != nullptr) *mid_recorded = false;
   const int es_d = cplx ? 2 : 1;
   const int ns = astream_ns(n);
   int64_t nb = astream_blocks(m, n, B, es_d);
@@ -219,7 +221,8 @@ hipError_t launch_astream_pass(hipStream_t st, bool cplx, int B, bool dot2, cons
     // plain sums: the two contractions on the FP64 matrix cores
     nb = astream_c2_ranges(m, n, B);
     np = nb;
-    ok = dispatch_astream_zm(init, B, st, nb, A, lda, m, n, W, AW, AVp, AXp, Gpart, device_cu_count(), ctl);
+    ok = dispatch_astream_zm(init, B, st, nb, A, lda, m, n, W, AW, AVp, AXp, Gpart, device_cu_count(), ctl, mid);
+    if (ok && mid != nullptr && mid_recorded != nullptr) *mid_recorded = true;
   } else if (cplx && astream_c2_fits(B, n, ((reinterpret_cast<uintptr_t>(A) & 15) == 0))) {
     nb = astream_c2_ranges(m, n, B);
     np = nb;
@@ -339,6 +342,74 @@ hipError_t launch_final_u(hipStream_t st, bool cplx, const void* AV, const void*
   else
     hipLaunchKernelGGL(k_final_u<double>, dim3((unsigned)nb), dim3(256), 0, st, (const double*)AV,
                        (const double*)AX, (const double*)AW, m, B, k, (const double*)CV, thb, (double*)U, ldu, ctl);
+  return hipGetLastError();
+}
+
+// Outputs of the refresh step (the fresh A V-hat and its thin SVD,
+// A V-hat = U_r diag(s) C^*): V-hat C, sigma = s and U-hat = (A V-hat) C / s,
+// the k smallest in ascending order (s and C come descending from the SVD of
+// the TSQR factor: column B-1-j holds the j-th smallest).
+template <typename T>
+__global__ __launch_bounds__(256) void k_refresh_v(int n, int B, int k, const T* __restrict__ V,
+                                                   const T* __restrict__ C, const double* __restrict__ s,
+                                                   double* __restrict__ sigma, T* __restrict__ Vout, int64_t ldv,
+                                                   Ctl* __restrict__ ctl) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < k) {
+    const double sj = s[B - 1 - idx];
+    sigma[idx] = sj;
+    if (sj == 0.0) ctl->zero_theta = 1;
+  }
+  if (idx < (int64_t)n * k) {
+    const int64_t r = idx / k;
+    const int j = B - 1 - (int)(idx % k);
+    T acc = zero<T>();
+    for (int c = 0; c < B; ++c) acc = fmac(V[r * B + c], C[c * B + j], acc);
+    Vout[r * ldv + (idx % k)] = acc;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_refresh_u(int64_t m, int B, int k, const T* __restrict__ AVf,
+                                                   const T* __restrict__ Cg, const double* __restrict__ s,
+                                                   T* __restrict__ U, int64_t ldu) {
+  __shared__ T C[16 * 16];
+  __shared__ double inv[16];
+  for (int i = threadIdx.x; i < B * B; i += blockDim.x) C[i] = Cg[i];
+  if (threadIdx.x < B) inv[threadIdx.x] = (s[threadIdx.x] != 0.0) ? 1.0 / s[threadIdx.x] : 0.0;
+  __syncthreads();
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
+    T a[16];
+    for (int c = 0; c < B; ++c) a[c] = AVf[r * B + c];
+    for (int jo = 0; jo < k; ++jo) {
+      const int j = B - 1 - jo;
+      T acc = zero<T>();
+      for (int c = 0; c < B; ++c) acc = fmac(a[c], C[c * B + j], acc);
+      U[r * ldu + jo] = scal(acc, inv[j]);
+    }
+  }
+}
+
+hipError_t launch_refresh_out(hipStream_t st, bool cplx, int n, int64_t m, int B, int k, const void* V,
+                              const void* AVf, const void* C, const double* s, double* sigma, void* Vout,
+                              int64_t ldv, void* U, int64_t ldu, Ctl* ctl) {
+  if (B < 1 || B > 16 || k < 1 || k > B) return hipErrorInvalidValue;
+  const int gv = (int)(((int64_t)n * k + 255) / 256);
+  int64_t gu = (m + 255) / 256;
+  if (gu > 2048) gu = 2048;
+  if (cplx) {
+    hipLaunchKernelGGL(k_refresh_v<cd>, dim3(gv), dim3(256), 0, st, n, B, k, (const cd*)V, (const cd*)C, s, sigma,
+                       (cd*)Vout, ldv, ctl);
+    if (U != nullptr)
+      hipLaunchKernelGGL(k_refresh_u<cd>, dim3((unsigned)gu), dim3(256), 0, st, m, B, k, (const cd*)AVf,
+                         (const cd*)C, s, (cd*)U, ldu);
+  } else {
+    hipLaunchKernelGGL(k_refresh_v<double>, dim3(gv), dim3(256), 0, st, n, B, k, (const double*)V,
+                       (const double*)C, s, sigma, (double*)Vout, ldv, ctl);
+    if (U != nullptr)
+      hipLaunchKernelGGL(k_refresh_u<double>, dim3((unsigned)gu), dim3(256), 0, st, m, B, k, (const double*)AVf,
+                         (const double*)C, s, (double*)U, ldu);
+  }
   return hipGetLastError();
 }
 

@@ -57,8 +57,11 @@ constexpr int ZM_G_THREADS = 256;    // 4 waves: 256 real columns per workgroup
 constexpr int ZM_G_RC = 32;          // rows of Tr per LDS chunk
 
 // ----------------------------------------------------------------------------
-// A_W = A W (real form Ar Wr).  NT = N tiles of 16 real output columns (2b).
-template <int NT>
+// A_W = A W (real form Ar Wr).  NT = N tiles of 16 real output columns (2b);
+// KH = 16-byte loads per lane, M tile and k block (a k block is 8 KH real
+// columns, so each of a tile's 16 rows is read KH * 64 contiguous bytes at a
+// time).
+template <int NT, int KH>
 __global__ __launch_bounds__(ZM_AW_THREADS) void k_zm_aw(const double* __restrict__ A, int64_t lda2, int64_t m,
                                                          int n, int B, const cd* __restrict__ W,
                                                          double* __restrict__ AW, const Ctl* __restrict__ ctl) {
@@ -71,7 +74,8 @@ __global__ __launch_bounds__(ZM_AW_THREADS) void k_zm_aw(const double* __restric
   const int lane = threadIdx.x & 63, wave = wave_index();
   const int q = lane >> 4, t = lane & 15;
   const int n2 = 2 * n, B2 = 2 * B;
-  const int nkb = (n2 + 15) / 16;
+  constexpr int KBW = 8 * KH;  // real columns per k block
+  const int nkb = (n2 + KBW - 1) / KBW;
   // this lane's output columns per N tile: vector v, part r (Wr's sign pattern)
   int vcol[NT];
 #pragma unroll
@@ -82,22 +86,24 @@ __global__ __launch_bounds__(ZM_AW_THREADS) void k_zm_aw(const double* __restric
   const int64_t nwave = (int64_t)gridDim.x * (ZM_AW_THREADS / 64);
   for (int64_t tile = gw; tile < ntile; tile += nwave) {
     const int64_t r0 = tile * 32;
-    int64_t row[2];
-    bool rok[2];
+    // Loads are unconditional (addresses clamped into A, so no branch or
+    // exec mask sits between a load and its use and the compiler can keep
+    // them in flight).  Lane (q, t) reads columns k0 + 2 KH q .. + 2 KH - 1
+    // of row t of each M tile; each 16-byte pair is valid or invalid as a
+    // whole (2n is even).
+    const double* rowp[2];
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt) {
-      row[mt] = r0 + 16 * mt + t;
-      rok[mt] = row[mt] < m;
+      const int64_t row = r0 + 16 * mt + t;
+      rowp[mt] = A + (row < m ? row : m - 1) * lda2;
     }
-    // 32 bytes per lane and M tile: columns k0 + 4q .. +3 of its row; the
-    // two 16-byte halves are valid or invalid together (2n is even)
-    auto load = [&](double2 (&a)[2][2], int kb) {
-      const int k = 16 * kb + 4 * q;
+    auto load = [&](double2 (&a)[2][KH], int kb) {
+      const int k = KBW * kb + 2 * KH * q;
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt) {
-        const double* p = A + row[mt] * lda2 + k;
-        a[mt][0] = (rok[mt] && k < n2) ? ld_stream2(p) : make_double2(0.0, 0.0);
-        a[mt][1] = (rok[mt] && k + 2 < n2) ? ld_stream2(p + 2) : make_double2(0.0, 0.0);
+      for (int i = 0; i < KH; ++i) {
+        const int kc = k + 2 * i < n2 - 2 ? k + 2 * i : n2 - 2;
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) a[mt][i] = ld_stream2(rowp[mt] + kc);
       }
     };
     zm_v4d acc[2][NT];
@@ -105,38 +111,46 @@ __global__ __launch_bounds__(ZM_AW_THREADS) void k_zm_aw(const double* __restric
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = zm_v4d{0.0, 0.0, 0.0, 0.0};
-    double2 an[2][2];
-    load(an, 0);
-    for (int kb = 0; kb < nkb; ++kb) {
-      double2 a[2][2];
+    // one k block of MFMA steps on the values of buffer a: step s uses
+    // k = k0 + 2 KH q + s (a permutation of the contraction index, the same
+    // for both operands), i.e. complex column c = k0 / 2 + KH q + s / 2, part s % 2
+    auto step = [&](const double2 (&a)[2][KH], int kb) {
 #pragma unroll
-      for (int mt = 0; mt < 2; ++mt) {
-        a[mt][0] = an[mt][0];
-        a[mt][1] = an[mt][1];
-      }
-      if (kb + 1 < nkb) load(an, kb + 1);
-      // steps s = 0, 1 use complex column c0 = 8 kb + 2q (re, im); s = 2, 3 use c0 + 1
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int c = 8 * kb + 2 * q + h;
+      for (int h = 0; h < KH; ++h) {
+        const int c = (KBW / 2) * kb + KH * q + h;
         double b_re[NT], b_im[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-          const cd w = (c < n && vcol[nt] < B) ? Ws[c * B + vcol[nt]] : cd{0.0, 0.0};
+          const bool wok = c < n && vcol[nt] < B;
+          const int wi = wok ? c * B + vcol[nt] : 0;
+          const cd w = Ws[wi];
           // Wr(2c, 2v) = Re w, Wr(2c, 2v+1) = Im w, Wr(2c+1, 2v) = -Im w, Wr(2c+1, 2v+1) = Re w
-          b_re[nt] = rpart ? w.y : w.x;
-          b_im[nt] = rpart ? w.x : -w.y;
+          b_re[nt] = wok ? (rpart ? w.y : w.x) : 0.0;
+          b_im[nt] = wok ? (rpart ? w.x : -w.y) : 0.0;
         }
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
-          const double a_re = h ? a[mt][1].x : a[mt][0].x;
-          const double a_im = h ? a[mt][1].y : a[mt][0].y;
+          // no mask on A: a clamped row's results are never stored, and a
+          // clamped column meets a zero of Wr
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt) {
-            acc[mt][nt] = zm_mfma(a_re, b_re[nt], acc[mt][nt]);
-            acc[mt][nt] = zm_mfma(a_im, b_im[nt], acc[mt][nt]);
+            acc[mt][nt] = zm_mfma(a[mt][h].x, b_re[nt], acc[mt][nt]);
+            acc[mt][nt] = zm_mfma(a[mt][h].y, b_im[nt], acc[mt][nt]);
           }
         }
+      }
+    };
+    // two buffers, each refilled two k blocks ahead right after its use (no
+    // register copies between a load and its use, so the loads stay in flight)
+    double2 a0[2][KH], a1[2][KH];
+    load(a0, 0);
+    load(a1, 1);
+    for (int kb = 0; kb < nkb; kb += 2) {
+      step(a0, kb);
+      load(a0, kb + 2);
+      if (kb + 1 < nkb) {
+        step(a1, kb + 1);
+        load(a1, kb + 3);
       }
     }
     // register r of a tile holds output row 4r + q, column 16 nt + t
@@ -187,28 +201,33 @@ __global__ __launch_bounds__(ZM_G_THREADS, 2) void k_zm_g(const double* __restri
   // stored at row * TW + (col % 16) * NT + col / 16 so that lane t finds its
   // NT values (columns t, 16 + t, ...) side by side
   constexpr int PER = (ZM_G_RC * TW + ZM_G_THREADS - 1) / ZM_G_THREADS;
+  // fetch(v, cb): this thread's share of the chunk's rows of Tr, loaded
+  // unconditionally from clamped addresses (no branch between a load and its
+  // use); stage() zeroes what lies outside Tr when it writes the chunk to LDS
   auto fetch = [&](double (&v)[PER], int64_t cb) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int e = threadIdx.x + i * ZM_G_THREADS;
       const int rw = e / TW, col = e - (e / TW) * TW;
       const int64_t grow = cb + rw;
-      double x = 0.0;
-      if (e < ZM_G_RC * TW && grow < r1 && col < ncol) {
-        const int g = col / B2;
-        const double* P = Pg[g];
-        if (P != nullptr) x = P[grow * B2 + (col - g * B2)];
-      }
-      v[i] = x;
+      const int g = col < ncol ? col / B2 : 0;
+      const double* P = Pg[g] != nullptr ? Pg[g] : P0;
+      const int64_t gr = grow < r1 ? grow : r1 - 1;
+      const int cw = col < ncol ? col - g * B2 : 0;
+      v[i] = P[gr * B2 + cw];
     }
   };
-  auto stage = [&](const double (&v)[PER], int buf) {
+  auto valid = [&](int e, int64_t cb) {
+    const int rw = e / TW, col = e - (e / TW) * TW;
+    return e < ZM_G_RC * TW && cb + rw < r1 && col < ncol && Pg[col < ncol ? col / B2 : 0] != nullptr;
+  };
+  auto stage = [&](const double (&v)[PER], int buf, int64_t cb) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int e = threadIdx.x + i * ZM_G_THREADS;
       if (e < ZM_G_RC * TW) {
         const int rw = e / TW, col = e - (e / TW) * TW;
-        Ts[buf][rw * TW + (col & 15) * NT + (col >> 4)] = v[i];
+        Ts[buf][rw * TW + (col & 15) * NT + (col >> 4)] = valid(e, cb) ? v[i] : 0.0;
       }
     }
   };
@@ -218,17 +237,27 @@ __global__ __launch_bounds__(ZM_G_THREADS, 2) void k_zm_g(const double* __restri
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[u][nt] = zm_v4d{0.0, 0.0, 0.0, 0.0};
   const int kcol = kw + 4 * t;  // this lane's four columns of A: kcol .. kcol + 3
+  // unconditional loads from clamped addresses (rows past r1 read row
+  // r1 - 1)
+  // (each 16-byte half is clamped on its own: a half past 2n reads the last
+  // pair, and its rows of Gr, c >= n, are never written)
+  const int kc0 = kcol < n2 - 2 ? kcol : n2 - 2;
+  const int kc1 = kcol + 2 < n2 - 2 ? kcol + 2 : n2 - 2;
   auto loada = [&](double2 (&a)[2], int64_t grow) {
-    const double* p = A + grow * lda2 + kcol;
-    const bool ok = active && grow < r1;
-    a[0] = (ok && kcol < n2) ? ld_stream2(p) : make_double2(0.0, 0.0);
-    a[1] = (ok && kcol + 2 < n2) ? ld_stream2(p + 2) : make_double2(0.0, 0.0);
+    const double* p = A + (grow < r1 ? grow : r1 - 1) * lda2;
+    a[0] = ld_stream2(p + kc0);
+    a[1] = ld_stream2(p + kc1);
   };
   {
     double v[PER];
     fetch(v, r0);
-    stage(v, 0);
+    stage(v, 0, r0);
   }
+  // four buffers of A rows, each refilled four K steps (16 rows) ahead
+  // right after its use, across chunk boundaries (a chunk is 8 K steps)
+  double2 ab[4][2];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) loada(ab[j], r0 + 4 * j + q);
   __syncthreads();
   int buf = 0;
   for (int64_t cb = r0; cb < r1; cb += ZM_G_RC) {
@@ -236,25 +265,25 @@ __global__ __launch_bounds__(ZM_G_THREADS, 2) void k_zm_g(const double* __restri
     const bool more = cb + ZM_G_RC < r1;
     if (more) fetch(v, cb + ZM_G_RC);
     if (active) {
-      double2 an[2];
-      loada(an, cb + q);
       const double* Tb = Ts[buf];
-#pragma unroll 2
+#pragma unroll
       for (int ks = 0; ks < ZM_G_RC / 4; ++ks) {
-        double2 a[2] = {an[0], an[1]};
-        if (ks + 1 < ZM_G_RC / 4) loada(an, cb + 4 * (ks + 1) + q);
         const double* tr = Tb + (4 * ks + q) * TW + t * NT;
         double bv[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) bv[nt] = tr[nt];
-        const double av[4] = {a[0].x, a[0].y, a[1].x, a[1].y};
+        // no mask on A: a clamped row meets the zero rows of Tr staged past
+        // r1, and the rows of Gr of clamped columns are never written
+        const double2* a0 = ab[ks & 3];
+        const double av[4] = {a0[0].x, a0[0].y, a0[1].x, a0[1].y};
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt) acc[u][nt] = zm_mfma(av[u], bv[nt], acc[u][nt]);
+        loada(ab[ks & 3], cb + 4 * ks + 16 + q);
       }
     }
-    if (more) stage(v, buf ^ 1);
+    if (more) stage(v, buf ^ 1, cb + ZM_G_RC);
     __syncthreads();
     buf ^= 1;
   }
@@ -302,14 +331,17 @@ bool astream_zm_fits(int B, int n, bool aligned, int64_t lds_max) {
   return aligned && n > 256 && n <= 1024 && B >= 1 && B <= 10 && (int64_t)n * B * 16 <= lds_max;
 }
 
+constexpr int ZM_AW_KH = 2;  // 32 contiguous bytes per row and lane per k block
+
 template <int NT>
 static hipError_t zm_aw_go(hipStream_t st, int grid, const double* A, int64_t lda2, int64_t m, int n, int B,
                            const cd* W, double* AW, const Ctl* ctl) {
   const size_t lds = sizeof(cd) * (size_t)n * B;
-  const hipError_t e = hipFuncSetAttribute((const void*)k_zm_aw<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds);
+  const hipError_t e = hipFuncSetAttribute((const void*)k_zm_aw<NT, ZM_AW_KH>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_zm_aw<NT>, dim3((unsigned)grid), dim3(ZM_AW_THREADS), lds, st, A, lda2, m, n, B, W, AW, ctl);
+  hipLaunchKernelGGL((k_zm_aw<NT, ZM_AW_KH>), dim3((unsigned)grid), dim3(ZM_AW_THREADS), lds, st, A, lda2, m, n, B,
+                     W, AW, ctl);
   return hipGetLastError();
 }
 
@@ -325,7 +357,7 @@ static void zm_g_go(hipStream_t st, int64_t nblk, const double* A, int64_t lda2,
 // the first plane) over nrr row ranges.
 bool dispatch_astream_zm(int init, int B, hipStream_t st, int64_t nrr, const void* A, int64_t lda, int64_t m, int n,
                          const void* W, void* AW, const void* AVp, const void* AXp, double* Gpart, int n_cu,
-                         const Ctl* ctl) {
+                         const Ctl* ctl, hipEvent_t mid) {
   if (n <= 256 || n > 1024 || B < 1 || B > 10 || nrr < 1) return false;
   const double* Ad = (const double*)A;
   const int64_t lda2 = 2 * lda;
@@ -340,6 +372,8 @@ bool dispatch_astream_zm(int init, int B, hipStream_t st, int64_t nrr, const voi
   else
     e = zm_aw_go<2>(st, grid, Ad, lda2, m, n, B, (const cd*)W, (double*)AW, ctl);
   if (e != hipSuccess) return false;
+  // the second kernel's start, for timing the Gram contraction on its own
+  if (mid != nullptr && hipEventRecord(mid, st) != hipSuccess) return false;
   const int64_t rows = (m + nrr - 1) / nrr;
   const int nslice = (2 * n + 255) / 256;
   const int64_t nblk = ((nrr + 7) / 8) * 8 * nslice;

@@ -35,7 +35,7 @@ bool astream_c2_fits(int B, int n, bool aligned);
 bool astream_zm_fits(int B, int n, bool aligned, int64_t lds_max);
 bool dispatch_astream_zm(int init, int B, hipStream_t st, int64_t nrr, const void* A, int64_t lda, int64_t m, int n,
                          const void* W, void* AW, const void* AVp, const void* AXp, double* Gpart, int n_cu,
-                         const Ctl* ctl);
+                         const Ctl* ctl, hipEvent_t mid = nullptr);
 int device_cu_count();
 int64_t device_lds_max();
 int64_t astream_c2_ranges(int64_t m, int n, int B);
@@ -66,7 +66,8 @@ bool dispatch_astream_gc(bool dot2, int ns, int B, hipStream_t st, int64_t nb, c
                          const Ctl* ctl);
 hipError_t launch_astream_pass(hipStream_t st, bool cplx, int B, bool dot2, const void* A, int64_t lda, int64_t m,
                                int n, const void* W, void* AW, const void* AVp, const void* AXp, int init,
-                               double* Gpart, const Ctl* ctl, int64_t* np_out);
+                               double* Gpart, const Ctl* ctl, int64_t* np_out, hipEvent_t mid = nullptr,
+                               bool* mid_recorded = nullptr);
 hipError_t launch_astream_reduce(hipStream_t st, bool cplx, int B, int n, int64_t np, const double* Gpart,
                                  double* tmp, double* G3, const Ctl* ctl);
 // One level of that reduction (k_colsum2): grid gx x gy of 256 threads.
@@ -88,6 +89,9 @@ hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const voi
                           double* tmp, double* G3, const Ctl* ctl, hipEvent_t pass_done = nullptr);
 hipError_t launch_panel(hipStream_t st, bool cplx, void* AV, void* AX, const void* AW, int64_t m, int B,
                         const void* CV, const void* CX, const Ctl* ctl);
+hipError_t launch_refresh_out(hipStream_t st, bool cplx, int n, int64_t m, int B, int k, const void* V,
+                              const void* AVf, const void* C, const double* s, double* sigma, void* Vout,
+                              int64_t ldv, void* U, int64_t ldu, Ctl* ctl);
 hipError_t launch_final_u(hipStream_t st, bool cplx, const void* AV, const void* AX, const void* AW, int64_t m, int B,
                           int k, const void* CV, const double* thb, void* U, int64_t ldu, const Ctl* ctl);
 

@@ -495,46 +495,50 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
     }
     __threadfence_block();
     stop_s = init_mode ? 0 : (dev_should_stop(iter, hist_theta, hist_rnorm, B, ctl) ? 1 : 0);
-    if (!init_mode && !stop_s) {
-      // Q = Orth(C(1:B, 1:t-B)^*), (t-B) x B, by modified Gram-Schmidt applied
-      // twice.  A column that vanishes (at full convergence C(1:B, 1:t-B) can be
-      // exactly 0) is completed, as Householder QR would, by the first unit
-      // vector that keeps norm above 1/2 after projection on the earlier ones.
-      const int tb = t - B;
-      for (int a = 0; a < tb; ++a)
-        for (int j = 0; j < B; ++j) Qm[a * B + j] = conj_(C[a * 32 + j]);
-      for (int j = 0; j < B; ++j) {
-        double nrm = 0.0;
-        for (int cand = -1; cand < tb; ++cand) {
-          if (cand >= 0)
-            for (int a = 0; a < tb; ++a) Qm[a * B + j] = from_real<T>(a == cand ? 1.0 : 0.0);
-          for (int pass = 0; pass < 2; ++pass) {
-            for (int q = 0; q < j; ++q) {
-              T sp = zero<T>();
-              for (int a = 0; a < tb; ++a) sp = cfmac(Qm[a * B + q], Qm[a * B + j], sp);
-              for (int a = 0; a < tb; ++a) Qm[a * B + j] = fnmac(Qm[a * B + q], sp, Qm[a * B + j]);
-            }
-          }
-          double s2 = 0.0;
-          for (int a = 0; a < tb; ++a) s2 += abs2(Qm[a * B + j]);
-          nrm = sqrt(s2);
-          if (cand < 0 && nrm > 0.0 && isfinite(nrm)) break;
-          if (cand >= 0 && nrm > 0.5) break;
-          if (cand < 0) ctl->degenerate = 1;
-        }
-        for (int a = 0; a < tb; ++a) Qm[a * B + j] = scal(Qm[a * B + j], 1.0 / nrm);
-      }
-      // C_X = C(:, 1:t-B) Q  (t x B)
-      for (int c = 0; c < t; ++c)
-        for (int j = 0; j < B; ++j) {
-          T s = zero<T>();
-          for (int a = 0; a < tb; ++a) s = fmac(C[a * 32 + c], Qm[a * B + j], s);
-          CX[c * B + j] = s;
-        }
-    }
   }
   __syncthreads();
   const bool xupd = !init_mode && !stop_s;
+  if (xupd && wid == 0) {
+    // Q = Orth(C(1:B, 1:t-B)^*), (t-B) x B, by modified Gram-Schmidt applied
+    // twice, row a of Q held by lane a.  A column that vanishes (at full
+    // convergence C(1:B, 1:t-B) can be exactly 0) is completed, as Householder
+    // QR would, by the first unit vector that keeps norm above 1/2 after
+    // projection on the earlier ones.
+    const int tb = t - B;
+    const int a = lane;
+    const bool own = a < tb;
+    for (int j = 0; j < B; ++j)
+      if (own) Qm[a * B + j] = conj_(C[a * 32 + j]);
+    for (int j = 0; j < B; ++j) {
+      double nrm = 0.0;
+      for (int cand = -1; cand < tb; ++cand) {
+        if (cand >= 0 && own) Qm[a * B + j] = from_real<T>(a == cand ? 1.0 : 0.0);
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int q = 0; q < j; ++q) {
+            const T sp = wave_sum(own ? cfmac(Qm[a * B + q], Qm[a * B + j], zero<T>()) : zero<T>());
+            if (own) Qm[a * B + j] = fnmac(Qm[a * B + q], sp, Qm[a * B + j]);
+          }
+        }
+        nrm = sqrt(wave_sum(own ? abs2(Qm[a * B + j]) : 0.0));
+        if (cand < 0 && nrm > 0.0 && isfinite(nrm)) break;
+        if (cand >= 0 && nrm > 0.5) break;
+        if (cand < 0 && lane == 0) ctl->degenerate = 1;
+      }
+      if (own) Qm[a * B + j] = scal(Qm[a * B + j], 1.0 / nrm);
+    }
+  }
+  __syncthreads();
+  if (xupd) {
+    // C_X = C(:, 1:t-B) Q  (t x B), one entry per thread
+    const int tb = t - B;
+    for (int e = tid; e < t * B; e += blockDim.x) {
+      const int c = e / B, j = e - (e / B) * B;
+      T sx = zero<T>();
+      for (int a = 0; a < tb; ++a) sx = fmac(C[a * 32 + c], Qm[a * B + j], sx);
+      CX[e] = sx;
+    }
+  }
+  __syncthreads();
   // pass 2: X = T C_X from the old T, then V <- V_new
   for (int r = tid; r < n; r += blockDim.x) {
     if (xupd) {

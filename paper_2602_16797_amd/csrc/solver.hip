@@ -51,7 +51,8 @@ struct rl_ctx {
   Ctl* host_ctl_dev = nullptr;  // its device address
   int64_t lds_budget = 64 * 1024;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  std::vector<hipEvent_t> prof;  // pairs around A-stream launches
+  std::vector<hipEvent_t> prof;  // triples around A-stream launches: start, mid (two-kernel passes), end
+  std::vector<char> prof_mid;    // the launch recorded its mid event
   bool ws_async = false;         // workspace from the stream-ordered allocator (server slots)
   hipStream_t aux = nullptr;     // second stream: Sigma~(1,1) beside the start block
   hipEvent_t fork = nullptr, join = nullptr;
@@ -70,8 +71,9 @@ static int ensure_aux(rl_ctx* h) {
   return RL_OK;
 }
 
-static int ensure_prof_events(rl_ctx* h, size_t pairs) {
-  while (h->prof.size() < 2 * pairs) {
+static int ensure_prof_events(rl_ctx* h, size_t launches) {
+  if (h->prof_mid.size() < launches) h->prof_mid.resize(launches);
+  while (h->prof.size() < 3 * launches) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return RL_ERR_DEVICE;
     h->prof.push_back(e);
@@ -228,6 +230,7 @@ static int check_opts(int64_t m, int64_t n, int32_t k, const rl_opts& o) {
   if (o.sketch_prec < RL_SKETCH_F64 || o.sketch_prec > RL_SKETCH_BF16) return RL_ERR_ARG;
   if (o.loop_precond < RL_PREC_SKETCH || o.loop_precond > RL_PREC_NONE) return RL_ERR_ARG;
   if (o.orth < RL_ORTH_CGS2 || o.orth > RL_ORTH_SVQB) return RL_ERR_ARG;
+  if (o.refresh < 0 || o.refresh > 1) return RL_ERR_ARG;
   if (n > 1024 || o.block > 10) return RL_ERR_UNSUPPORTED;
   if (o.d > INT32_MAX / 2) return RL_ERR_ARG;
   return RL_OK;
@@ -332,12 +335,13 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   if (prof) {
     rc = ensure_prof_events(h, (size_t)o.max_iter + 1);
     if (rc != RL_OK) return rc;
-    CK(hipEventRecord(h->prof[2 * nprof], st));
+    CK(hipEventRecord(h->prof[3 * nprof], st));
+    h->prof_mid[nprof] = 0;
   }
   // start pass: A_V = A V_0 and A^* A_V (into the first block of G3)
   CK(launch_astream(st, cplx, B, dot2, A, lda, m, (int)n, at<void>(ws, L.V), at<void>(ws, L.AV), nullptr, nullptr, 1,
                     at<double>(ws, L.Gpart), at<double>(ws, L.Gtmp), at<double>(ws, L.G3), ctl,
-                    prof ? h->prof[2 * nprof + 1] : nullptr));
+                    prof ? h->prof[3 * nprof + 2] : nullptr));
   if (prof) ++nprof;
   void* Rt = nullptr;
   CK(launch_tsqr(st, cplx, at<void>(ws, L.AV), B, nullptr, 0, nullptr, 0, m, at<void>(ws, L.tsA),
@@ -376,15 +380,17 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
     else
       CK(launch_orth(st, cplx, (int)n, B, at<void>(ws, L.V), at<void>(ws, L.X), 1, with_x, at<void>(ws, L.W), ctl,
                      1));
-    if (prof) CK(hipEventRecord(h->prof[2 * nprof], st));
+    if (prof) CK(hipEventRecord(h->prof[3 * nprof], st));
     // the pass, then its partial sums reduced beside the TSQR of [A_V A_X A_W]
     // (the first reduction level runs inside the first TSQR launch)
     int64_t np = 0;
+    bool mid = false;
     CK(launch_astream_pass(st, cplx, B, dot2, A, lda, m, (int)n, at<void>(ws, L.W), at<void>(ws, L.AW),
                            at<void>(ws, L.AV), with_x ? at<void>(ws, L.AX) : nullptr, 0, at<double>(ws, L.Gpart),
-                           ctl, &np));
+                           ctl, &np, prof ? h->prof[3 * nprof + 1] : nullptr, &mid));
     if (prof) {
-      CK(hipEventRecord(h->prof[2 * nprof + 1], st));
+      CK(hipEventRecord(h->prof[3 * nprof + 2], st));
+      h->prof_mid[nprof] = mid ? 1 : 0;
       ++nprof;
     }
     ColsumJob lev[16];
@@ -409,10 +415,26 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   }
   CK(hipEventRecord(h->ev[2], st));
   // outputs
-  CK(launch_final_n(st, cplx, (int)n, B, k, at<void>(ws, L.V), at<double>(ws, L.thb), sigma, Vout, ldv, ctl));
-  if (Uout)
-    CK(launch_final_u(st, cplx, at<void>(ws, L.AV), at<void>(ws, L.AX), at<void>(ws, L.AW), m, B, k,
-                      at<void>(ws, L.CV), at<double>(ws, L.thb), Uout, ldu, ctl));
+  if (o.refresh) {
+    // Refresh: A V-hat afresh in one pass (no accumulated drift of the
+    // maintained products), the thin SVD of that m x b block (TSQR, then
+    // one-sided Jacobi of its b x b factor), and (V-hat, sigma, U-hat)
+    // rotated by its right singular vectors.  The loop's kernels stop at the
+    // device stop flag, so this pass and its TSQR run without it.
+    CK(launch_astream(st, cplx, B, dot2, A, lda, m, (int)n, at<void>(ws, L.V), at<void>(ws, L.AW), nullptr, nullptr,
+                      1, at<double>(ws, L.Gpart), at<double>(ws, L.Gtmp), at<double>(ws, L.G3), nullptr));
+    void* Rr = nullptr;
+    CK(launch_tsqr(st, cplx, at<void>(ws, L.AW), B, nullptr, 0, nullptr, 0, m, at<void>(ws, L.tsA),
+                   at<void>(ws, L.tsB), &Rr, ctl, 0));
+    CK(launch_rt_svd(st, cplx, B, Rr, at<double>(ws, L.thb), at<void>(ws, L.CV)));
+    CK(launch_refresh_out(st, cplx, (int)n, m, B, k, at<void>(ws, L.V), at<void>(ws, L.AW), at<void>(ws, L.CV),
+                          at<double>(ws, L.thb), sigma, Vout, ldv, Uout, ldu, ctl));
+  } else {
+    CK(launch_final_n(st, cplx, (int)n, B, k, at<void>(ws, L.V), at<double>(ws, L.thb), sigma, Vout, ldv, ctl));
+    if (Uout)
+      CK(launch_final_u(st, cplx, at<void>(ws, L.AV), at<void>(ws, L.AX), at<void>(ws, L.AW), m, B, k,
+                        at<void>(ws, L.CV), at<double>(ws, L.thb), Uout, ldu, ctl));
+  }
   CK(hipEventRecord(h->ev[3], st));
   CK(launch_publish(st, ctl, h->host_ctl_dev));
   CK(hipStreamSynchronize(st));
@@ -421,7 +443,7 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   if (info) {
     info->status = status;
     info->iters = fc.iter;
-    info->a_passes = 2 + fc.iter + (o.loop_precond == RL_PREC_DIAG ? 1 : 0);
+    info->a_passes = 2 + fc.iter + (o.loop_precond == RL_PREC_DIAG ? 1 : 0) + (o.refresh ? 1 : 0);
     info->degenerate = fc.degenerate;
     info->zero_theta = fc.zero_theta;
     info->block = B;
@@ -436,10 +458,18 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
     info->bytes_a = (int64_t)info->a_passes * m * n * (int64_t)p.es;
     info->n_astream = prof ? nprof : 0;
     info->t_astream_us = 0.0;
+    info->n_pass_g = 0;
+    info->t_pass_g_us = 0.0;
     for (int q = 0; prof && q < nprof; ++q) {
       float ka = 0.f;
-      (void)hipEventElapsedTime(&ka, h->prof[2 * q], h->prof[2 * q + 1]);
+      (void)hipEventElapsedTime(&ka, h->prof[3 * q], h->prof[3 * q + 2]);
       info->t_astream_us += 1e3 * ka;
+      if (h->prof_mid[q]) {
+        float kg = 0.f;
+        (void)hipEventElapsedTime(&kg, h->prof[3 * q + 1], h->prof[3 * q + 2]);
+        info->t_pass_g_us += 1e3 * kg;
+        ++info->n_pass_g;
+      }
     }
     if (info->hist_cap > 0) {
       const int rowsh = std::min<int>(info->hist_cap, fc.iter + 1);
@@ -690,6 +720,7 @@ int rl_default_opts(rl_opts* o, int64_t m, int64_t n, int32_t k) {
   o->dot2 = 1;
   o->init_iters = 10;
   o->lanczos_steps = 64;
+  o->refresh = 1;
   return RL_OK;
 }
 

@@ -29,11 +29,11 @@ def rl():
 
 
 def _check(rl, A, k, *, seed, normA, block=None, gap_ok=True, rule="paper", max_iter=None, dot2=True,
-           angle_tol=1e-10, oracle_dot2=None, d=None, oracle=None):
+           angle_tol=1e-10, oracle_dot2=None, d=None, oracle=None, refresh=True):
     """GPU solve (products with or without Dot2) against the oracle (with
     Dot2 unless oracle_dot2 says otherwise), on the gates of the module doc."""
     At = torch.from_numpy(A).cuda()
-    kw = dict(seed=seed, rule=rule, dot2=dot2)
+    kw = dict(seed=seed, rule=rule, dot2=dot2, refresh=refresh)
     if block is not None:
         kw["block"] = block
     if max_iter is not None:
@@ -43,7 +43,8 @@ def _check(rl, A, k, *, seed, normA, block=None, gap_ok=True, rule="paper", max_
     r = rl.rl_svds_smallest(At, k, **kw)
     sg, Vg, Ug = to_np(r.sigma), to_np(r.V), to_np(r.U)
     o = oracle if oracle is not None else rlobpcg(A, k, seed=seed, block=block, rule=rule, max_iter=max_iter, d=d,
-                                                  dot2=dot2 if oracle_dot2 is None else oracle_dot2)
+                                                  dot2=dot2 if oracle_dot2 is None else oracle_dot2,
+                                                  refresh=refresh)
     banner(f"  gpu iters {r.iters} status {r.status}; oracle iters {o.iters} status {o.status}; "
            f"sigma gpu {sg} oracle {o.sigma}")
     assert np.all(np.diff(sg) >= 0)
@@ -51,6 +52,8 @@ def _check(rl, A, k, *, seed, normA, block=None, gap_ok=True, rule="paper", max_
     res = A @ Vg - Ug * sg[None, :]
     assert np.linalg.norm(res, axis=0).max() <= 1e-12 * normA
     assert np.allclose(np.linalg.norm(Vg, axis=0), 1.0, atol=1e-12)
+    if refresh and dot2:   # U-hat from the SVD of the fresh, compensated A V-hat: orthonormal columns
+        assert np.linalg.norm(Ug.conj().T @ Ug - np.eye(k)) <= 1e-12
     if gap_ok:
         ang = sin_angle(Vg, o.V)
         banner(f"  sin angle to oracle {ang:.3e}")
@@ -99,6 +102,15 @@ def test_complex_nullspace_small(rl):
     banner("parity complex nullspace 8000x60 k=4")
     A, _, s = planted_numpy(8000, 60, spectrum_nullspace(60, 4, 1e-4), 1303, is_complex=True, noise_std=1e-14)
     _check(rl, A, 4, seed=2303, normA=s[0])
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_without_refresh(rl, cplx):
+    """refresh = 0: the last Rayleigh-Ritz triplets as they are (U-hat = A_V / theta
+    from the maintained products), against the oracle's refresh=False."""
+    banner(f"parity without refresh complex={cplx}")
+    A, _, s = planted_numpy(4000, 60, spectrum_gap(60, 3, 1e-8, 10.0), 91 + cplx, is_complex=cplx)
+    _check(rl, A, 3, seed=12, normA=s[0], refresh=False)
 
 
 def test_oversampled_block(rl):

@@ -361,7 +361,7 @@ def test_refresh_recomputes_the_product_and_rotates():
         if kw["i"] == last:
             kw["AV"][:] += 1e-6 * np.random.default_rng(0).standard_normal(kw["AV"].shape)
 
-    plain = rlobpcg(A, k, seed=3, rule="none", max_iter=last + 1, callback=corrupt)
+    plain = rlobpcg(A, k, seed=3, rule="none", max_iter=last + 1, callback=corrupt, refresh=False)
     res_plain = np.linalg.norm(A @ plain.V - plain.U * plain.sigma[None, :], axis=0).max()
     assert res_plain > 1e-9                               # U-hat came from the corrupted A_V
     r = rlobpcg(A, k, seed=3, rule="none", max_iter=last + 1, callback=corrupt, refresh=True)
