@@ -96,7 +96,10 @@ typedef struct {
   int32_t refresh;    /* 1 (default): after the loop, A V-hat afresh (one more pass over A) and its thin SVD
                          rotate (V-hat, sigma, U-hat), so the outputs carry no drift of the products the loop
                          maintains by recurrence; 0: the last Rayleigh-Ritz's triplets, U-hat = A_V / theta */
-  int32_t reserved;
+  int32_t prec_guard; /* 1 (default): with a reduced-precision sketch_prec, estimate kappa(R) =
+                         ||R||_2 ||R^{-1}||_2 from the Lanczos estimate and the start block and, when
+                         kappa u_low sqrt(n) > 0.1 (u_low = 2^-24 for FP32, 2^-8 for bfloat16), redo
+                         the sketch and QR in FP64 before the start pass (rl_info.sketch_prec_used) */
 } rl_opts;
 
 /* Per-solve report (host).  theta_hist / rnorm_hist are optional host arrays
@@ -120,8 +123,9 @@ typedef struct {
   double* theta_hist;  /* host, may be NULL */
   double* rnorm_hist;  /* host, may be NULL */
   int32_t n_pass_g;    /* timed launches made of two kernels (A W, then the Gram contraction A^* [A_V A_X A_W]) */
-  int32_t pad0;
+  int32_t sketch_prec_used; /* RL_SKETCH_* of the R the loop used (RL_SKETCH_F64 after a guard fallback) */
   double t_pass_g_us;  /* summed duration of their second kernel (opts.profile) */
+  double kappa_est;    /* the guard's estimate of kappa(R) for a reduced-precision sketch, else 0 */
 } rl_info;
 
 /* Handle: one per (device, stream).  stream may be NULL (the null stream). */

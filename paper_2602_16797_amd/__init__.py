@@ -66,7 +66,7 @@ class RlOpts(ctypes.Structure):
         ("loop_precond", ctypes.c_int32),
         ("orth", ctypes.c_int32),
         ("refresh", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("prec_guard", ctypes.c_int32),
     ]
 
 
@@ -89,8 +89,9 @@ class RlInfo(ctypes.Structure):
         ("theta_hist", ctypes.POINTER(ctypes.c_double)),
         ("rnorm_hist", ctypes.POINTER(ctypes.c_double)),
         ("n_pass_g", ctypes.c_int32),
-        ("pad0", ctypes.c_int32),
+        ("sketch_prec_used", ctypes.c_int32),
         ("t_pass_g_us", ctypes.c_double),
+        ("kappa_est", ctypes.c_double),
     ]
 
 
@@ -268,6 +269,8 @@ class SolveResult:
     t_astream_us: float = 0.0
     n_pass_g: int = 0
     t_pass_g_us: float = 0.0
+    sketch_prec_used: int = 0
+    kappa_est: float = 0.0
     block: int = 0
     theta_hist: np.ndarray = field(default=None)
     rnorm_hist: np.ndarray = field(default=None)
@@ -275,7 +278,8 @@ class SolveResult:
 
 def make_opts(m: int, n: int, k: int, *, block=None, d=None, zeta=None, seed=0, tau=None, max_iter=None,
               check_every=None, rule="paper", dot2=None, init_iters=None, lanczos_steps=None,
-              profile=False, sketch_prec="f64", loop_precond="sketch", orth="cgs2", refresh=None) -> RlOpts:
+              profile=False, sketch_prec="f64", loop_precond="sketch", orth="cgs2", refresh=None,
+              prec_guard=None) -> RlOpts:
     o = default_opts(m, n, k if block is None else block)
     o.block = k if block is None else block
     if block is not None:
@@ -304,6 +308,8 @@ def make_opts(m: int, n: int, k: int, *, block=None, d=None, zeta=None, seed=0, 
     o.orth = ORTHS[orth]
     if refresh is not None:
         o.refresh = int(bool(refresh))
+    if prec_guard is not None:
+        o.prec_guard = int(bool(prec_guard))
     return o
 
 
@@ -337,7 +343,8 @@ def rl_svds_smallest(A, k: int, *, want_u: bool = True, history: bool = True, **
                        degenerate=bool(info.degenerate), zero_theta=bool(info.zero_theta),
                        t_setup_us=info.t_setup_us, t_iter_us=info.t_iter_us, t_final_us=info.t_final_us,
                        bytes_a=info.bytes_a, n_astream=info.n_astream, t_astream_us=info.t_astream_us,
-                       n_pass_g=info.n_pass_g, t_pass_g_us=info.t_pass_g_us, block=info.block, theta_hist=th[: it + 1].copy() if history else None,
+                       n_pass_g=info.n_pass_g, t_pass_g_us=info.t_pass_g_us,
+                       sketch_prec_used=info.sketch_prec_used, kappa_est=info.kappa_est, block=info.block, theta_hist=th[: it + 1].copy() if history else None,
                        rnorm_hist=rn[: it + 1].copy() if history else None)
 
 

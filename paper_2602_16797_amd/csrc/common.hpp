@@ -235,7 +235,8 @@ struct Ctl {
   int32_t pad0[3];
   double sigma1;       // Sigma~(1,1) estimate (largest singular value of R)
   double tau;          // tolerance
-  double pad1[8];
+  double rinv_norm;     // max_j ||R^{-*} V_0(:, j)||, about 1/sigma_min(R) (reduced-precision guard)
+  double pad1[7];
 };
 
 }  // namespace rl

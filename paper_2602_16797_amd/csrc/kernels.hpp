@@ -129,6 +129,7 @@ hipError_t launch_lanczos(hipStream_t st, bool cplx, int n, const void* Ycol, in
                           void* Vb, int KL, uint64_t seed, Ctl* ctl);
 hipError_t launch_final_n(hipStream_t st, bool cplx, int n, int B, int k, const void* V, const double* thb,
                           double* sigma, void* Vout, int64_t ldv, Ctl* ctl);
+hipError_t launch_max_colnorm(hipStream_t st, bool cplx, int n, int B, const void* Z, double* out);
 hipError_t launch_rt_svd(hipStream_t st, bool cplx, int t, const void* Rt, double* sigma, void* C);
 
 }  // namespace rl

@@ -29,7 +29,13 @@ namespace rl {
 constexpr int NS_THREADS = 256;
 constexpr int RR_TMAX = 32;
 constexpr int RR_BMAX = 16;
-constexpr int ORTH_KC = 8;  // projections summed per block reduction
+constexpr int ORTH_KC = 8;  // Gram entries summed per block reduction (SVQB)
+// projections summed per block reduction in orth_project (the per-thread
+// partial sums stay in registers)
+template <int KM>
+struct OrthKC {
+  static constexpr int value = 8;
+};
 constexpr int RR_PRE_B = 4;  // k_rr loads a trial row's values together up to this B
 
 __device__ inline double absval(double a) { return fabs(a); }
@@ -93,17 +99,18 @@ __global__ __launch_bounds__(NS_THREADS) void k_trmv(const T* __restrict__ M, in
 template <typename T, int KM>
 __device__ void orth_project(int n, int B, int j, const T* __restrict__ V, const T* __restrict__ X, int nvx,
                              T* __restrict__ W, T* scratch, T* h, int kw) {
+  constexpr int KC = OrthKC<KM>::value;
   const int K = nvx + kw;  // [V X] and the first kw columns of W
-  // the K projections are summed in chunks of ORTH_KC, so the per-thread
+  // the K projections are summed in chunks of KC, so the per-thread
   // partial sums stay in registers for any b
-  for (int k0 = 0; k0 < K; k0 += ORTH_KC) {
-    T vals[ORTH_KC];
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    T vals[KC];
 #pragma unroll
-    for (int kk = 0; kk < ORTH_KC; ++kk) vals[kk] = zero<T>();
+    for (int kk = 0; kk < KC; ++kk) vals[kk] = zero<T>();
     for (int r = threadIdx.x; r < n; r += blockDim.x) {
       const T wr = W[(int64_t)r * B + j];
 #pragma unroll
-      for (int kk = 0; kk < ORTH_KC; ++kk) {
+      for (int kk = 0; kk < KC; ++kk) {
         const int k = k0 + kk;
         if (k < K) {
           const T br = (k < nvx) ? ((k < B) ? V[(int64_t)r * B + k] : X[(int64_t)r * B + (k - B)])
@@ -112,7 +119,7 @@ __device__ void orth_project(int n, int B, int j, const T* __restrict__ V, const
         }
       }
     }
-    block_sum_many<T, ORTH_KC>(vals, (K - k0 < ORTH_KC) ? K - k0 : ORTH_KC, scratch, h + k0);
+    block_sum_many<T, KC>(vals, (K - k0 < KC) ? K - k0 : KC, scratch, h + k0);
   }
   for (int r = threadIdx.x; r < n; r += blockDim.x) {
     T wr = W[(int64_t)r * B + j];
@@ -137,7 +144,7 @@ __device__ double col_norm(int n, int B, int j, const T* __restrict__ W, double*
 template <typename T, int KM>
 __device__ void orth_block(int n, int B, const T* __restrict__ V, const T* __restrict__ X, int project, int with_x,
                            T* __restrict__ W, Ctl* __restrict__ ctl) {
-  __shared__ T scratch[(NS_THREADS / 16) * ORTH_KC];
+  __shared__ T scratch[(NS_THREADS / 16) * OrthKC<KM>::value];
   __shared__ T h[KM];
   __shared__ double red[NS_THREADS / 64];
   const int nvx = project ? (with_x ? 2 * B : B) : 0;
@@ -1062,6 +1069,30 @@ hipError_t launch_rt_svd(hipStream_t st, bool cplx, int t, const void* Rt, doubl
     hipLaunchKernelGGL(k_rt_svd<cd>, dim3(1), dim3(NS_THREADS), 0, st, t, (const cd*)Rt, sigma, (cd*)C);
   else
     hipLaunchKernelGGL(k_rt_svd<double>, dim3(1), dim3(NS_THREADS), 0, st, t, (const double*)Rt, sigma, (double*)C);
+  return hipGetLastError();
+}
+
+// out = max_j ||Z(:, j)||_2 over the B columns of the n x B block Z (one
+// workgroup; the reduced-precision guard's 1 / sigma_min(R) estimate).
+template <typename T>
+__global__ __launch_bounds__(NS_THREADS) void k_max_colnorm(int n, int B, const T* __restrict__ Z,
+                                                            double* __restrict__ out) {
+  __shared__ double red[NS_THREADS / 64];
+  double best = 0.0;
+  for (int j = 0; j < B; ++j) {
+    double s = 0.0;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) s += abs2(Z[(int64_t)r * B + j]);
+    const double nrm = sqrt(block_sum(s, red));
+    best = (nrm > best || !(nrm == nrm)) ? nrm : best;
+  }
+  if (threadIdx.x == 0) *out = best;
+}
+
+hipError_t launch_max_colnorm(hipStream_t st, bool cplx, int n, int B, const void* Z, double* out) {
+  if (cplx)
+    hipLaunchKernelGGL(k_max_colnorm<cd>, dim3(1), dim3(NS_THREADS), 0, st, n, B, (const cd*)Z, out);
+  else
+    hipLaunchKernelGGL(k_max_colnorm<double>, dim3(1), dim3(NS_THREADS), 0, st, n, B, (const double*)Z, out);
   return hipGetLastError();
 }
 

@@ -231,6 +231,7 @@ static int check_opts(int64_t m, int64_t n, int32_t k, const rl_opts& o) {
   if (o.loop_precond < RL_PREC_SKETCH || o.loop_precond > RL_PREC_NONE) return RL_ERR_ARG;
   if (o.orth < RL_ORTH_CGS2 || o.orth > RL_ORTH_SVQB) return RL_ERR_ARG;
   if (o.refresh < 0 || o.refresh > 1) return RL_ERR_ARG;
+  if (o.prec_guard < 0 || o.prec_guard > 1) return RL_ERR_ARG;
   if (n > 1024 || o.block > 10) return RL_ERR_UNSUPPORTED;
   if (o.d > INT32_MAX / 2) return RL_ERR_ARG;
   return RL_OK;
@@ -330,6 +331,41 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
     CK(launch_orth(st, cplx, (int)n, B, nullptr, nullptr, 0, 0, at<void>(ws, L.W), ctl, 0));
   }
   CK(hipMemcpyAsync(at<void>(ws, L.V), at<void>(ws, L.W), p.es * n * B, hipMemcpyDeviceToDevice, st));
+  double kappa_est = 0.0;
+  if (o.sketch_prec != RL_SKETCH_F64 && o.prec_guard) {
+    // Reduced-precision guard: kappa(R) ~ ||R||_2 max_j ||R^{-*} V_0(:, j)||
+    // (V_0 spans the smallest right singular vectors of R, so the second
+    // factor estimates 1 / sigma_min(R)).  A reduced-precision R resolves the
+    // directions of A only down to about u_low sqrt(n) ||A|| (its own
+    // condition number saturates there), so once kappa u_low sqrt(n) > 0.1 it
+    // no longer preconditions the bottom of the spectrum reliably, and the
+    // sketch and QR are redone in FP64 before any pass of the loop is spent
+    // on it.
+    CK(launch_trmv(st, cplx, B, at<void>(ws, L.RinvH), (int)n, 1, at<void>(ws, L.V), at<void>(ws, L.Z), ctl, 0));
+    CK(launch_max_colnorm(st, cplx, (int)n, B, at<void>(ws, L.Z), &ctl->rinv_norm));
+    CK(hipStreamWaitEvent(st, h->join, 0));
+    CK(launch_publish(st, ctl, h->host_ctl_dev));
+    CK(hipStreamSynchronize(st));
+    const double u_low = (o.sketch_prec == RL_SKETCH_BF16) ? 0x1p-8 : 0x1p-24;
+    kappa_est = h->host_ctl->sigma1 * h->host_ctl->rinv_norm;
+    if (!(kappa_est * u_low * sqrt((double)n) <= 0.1)) {
+      float ms_low = 0.f;
+      CK(hipEventRecord(h->ev[1], st));
+      CK(hipEventSynchronize(h->ev[1]));
+      (void)hipEventElapsedTime(&ms_low, h->ev[0], h->ev[1]);
+      rl_opts o64 = o;
+      o64.sketch_prec = RL_SKETCH_F64;
+      const int r64 = solve(h, cplx, m, n, A, lda, k, &o64, sigma, Vout, ldv, Uout, ldu, info);
+      if (info) {
+        info->sketch_prec_used = RL_SKETCH_F64;
+        info->kappa_est = kappa_est;
+        info->a_passes += 1;                // the reduced-precision sketch
+        info->t_setup_us += 1e3 * ms_low;  // and the rest of its setup
+        info->bytes_a = (int64_t)info->a_passes * m * n * (int64_t)p.es;
+      }
+      return r64;
+    }
+  }
   const bool prof = o.profile != 0;
   int nprof = 0;
   if (prof) {
@@ -456,6 +492,8 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
     (void)hipEventElapsedTime(&ms, h->ev[2], h->ev[3]);
     info->t_final_us = 1e3 * ms;
     info->bytes_a = (int64_t)info->a_passes * m * n * (int64_t)p.es;
+    info->sketch_prec_used = o.sketch_prec;
+    info->kappa_est = kappa_est;
     info->n_astream = prof ? nprof : 0;
     info->t_astream_us = 0.0;
     info->n_pass_g = 0;
@@ -721,6 +759,7 @@ int rl_default_opts(rl_opts* o, int64_t m, int64_t n, int32_t k) {
   o->init_iters = 10;
   o->lanczos_steps = 64;
   o->refresh = 1;
+  o->prec_guard = 1;
   return RL_OK;
 }
 

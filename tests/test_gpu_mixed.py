@@ -77,16 +77,19 @@ def test_qr_lowp_backward_error(rl, prec, d, n):
     assert np.linalg.norm(R @ Rinv - np.eye(n)) <= 1e-12 * np.linalg.cond(R)
 
 
-def _solve_vs_oracle(rl, A, k, seed, prec, normA, block=None, allow_max_iter=False):
+def _solve_vs_oracle(rl, A, k, seed, prec, normA, block=None, allow_max_iter=False, guard=True, expect_used=None):
     At = torch.from_numpy(A).cuda()
-    kw = dict(seed=seed, sketch_prec=prec)
+    kw = dict(seed=seed, sketch_prec=prec, prec_guard=guard)
     if block is not None:
         kw["block"] = block
     r = rl.rl_svds_smallest(At, k, **kw)
     o = rlobpcg(A, k, seed=seed, block=block)
     f = rl.rl_svds_smallest(At, k, seed=seed, block=block) if block else rl.rl_svds_smallest(At, k, seed=seed)
     sg, Vg, Ug = to_np(r.sigma), to_np(r.V), to_np(r.U)
-    banner(f"  {prec}: iters {r.iters} status {r.status}; fp64 iters {f.iters}; oracle iters {o.iters}")
+    banner(f"  {prec}: iters {r.iters} status {r.status} sketch used {r.sketch_prec_used} kappa est "
+           f"{r.kappa_est:.3e}; fp64 iters {f.iters}; oracle iters {o.iters}")
+    if expect_used is not None:
+        assert r.sketch_prec_used == rl.SKETCH_PRECS[expect_used]
     # a bfloat16 preconditioner can slow the iteration past max_iter; the last
     # iterate is returned then and must still meet the accuracy gates
     assert r.status == rl.RL_OK or (allow_max_iter and r.status == rl.RL_NOT_CONVERGED)
@@ -96,27 +99,45 @@ def _solve_vs_oracle(rl, A, k, seed, prec, normA, block=None, allow_max_iter=Fal
     ang = sin_angle(Vg, o.V)
     banner(f"  sin angle to the FP64 oracle {ang:.3e}")
     assert ang <= 1e-10
-    return r.iters, f.iters
+    return r
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_solve_single_vector_lowp(rl, prec):
+    """cond(A) = 1e6 at n = 50: kappa u sqrt(n) is about 0.4 for FP32 and far
+    above one for bfloat16, so the guard redoes the sketch and QR in FP64 for
+    both; without the guard the reduced-precision preconditioners still
+    converge here (more slowly for bfloat16)."""
     banner(f"solve 4000x50 k=1 sketch {prec}")
     sig = spectrum_logspace_tail(50, 1e-3, 1e-6)
     A, _, _ = planted_numpy(4000, 50, sig, 1001)
-    _solve_vs_oracle(rl, A, 1, 2001, prec, 1.0)
+    r = _solve_vs_oracle(rl, A, 1, 2001, prec, 1.0, expect_used="f64")
+    if prec == "f32":    # an FP32 R still resolves cond 1e6 (a bfloat16 one saturates far below)
+        assert 1e5 <= r.kappa_est <= 1e8
+    _solve_vs_oracle(rl, A, 1, 2001, prec, 1.0, guard=False, expect_used=prec)
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_solve_block_lowp(rl, prec):
-    # cond(A) = 1e4: cond * u stays below 1 for both reduced precisions, so
-    # the reduced-precision R still preconditions the bottom subspace
+    """cond(A) = 1e4: the FP32 R passes the guard and preconditions the bottom
+    subspace (the solve converges by the rule, as the FP64 one does); the
+    bfloat16 R fails the guard and the solve runs on an FP64 R."""
     banner(f"solve 30000x90 k=3 sketch {prec}")
     sig = spectrum_gap(90, 3, 1e-4, 100.0)
     A, _, _ = planted_numpy(30_000, 90, sig, 17)
-    # FP32 converges by the rule here (as the FP64 path does); the bfloat16
-    # preconditioner may need more than max_iter steps
-    _solve_vs_oracle(rl, A, 3, 23, prec, 1.0, allow_max_iter=(prec == "bf16"))
+    _solve_vs_oracle(rl, A, 3, 23, prec, 1.0, expect_used="f32" if prec == "f32" else "f64")
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_guard_keeps_the_gates_at_cond_1e10(rl, prec):
+    """The 2e6 x 500, k = 5 workload's spectrum (cond 1e10, a drop of 100 at
+    sigma_{n-5}) at 40000 x 200: both reduced precisions fail the guard, and
+    the FP64 redo meets every gate against the oracle."""
+    banner(f"solve 40000x200 k=5 cond 1e10 sketch {prec} (guard)")
+    sig = spectrum_gap(200, 5, 1e-10, 100.0)
+    A, _, _ = planted_numpy(40_000, 200, sig, 1404)
+    r = _solve_vs_oracle(rl, A, 5, 2404, prec, 1.0, expect_used="f64")
+    assert r.kappa_est > 0.1 / ((2.0 ** -24 if prec == "f32" else 2.0 ** -8) * np.sqrt(200))
 
 
 def test_lowp_rejects_complex(rl):
