@@ -303,8 +303,10 @@ def main(argv=None):
     sig = spectrum(n, k, spec)
     log(f"drawing {args.workload}: {m}x{n} on cuda:0")
     noise = spec[2] if spec[0] == "null" else 0.0
+    t_draw = time.perf_counter()
     A, Vp, s = planted_torch(m, n, sig, dseed, device="cuda", is_complex=cplx, noise_std=noise)
     torch.cuda.synchronize()
+    log(f"drew A in {time.perf_counter() - t_draw:.1f} s")
     es = 16 if cplx else 8
     kw = dict(seed=sseed, d=d, zeta=zeta, sketch_prec=args.sketch_prec, dot2=dot2,
               loop_precond=args.loop_precond, orth=args.orth)
@@ -317,8 +319,9 @@ def main(argv=None):
     results = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         results.append(rl.rl_svds_smallest(A, k, profile=True, **kw))
+        log(f"solve {i}: iters {results[-1].iters} status {results[-1].status}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
