@@ -37,7 +37,9 @@ extern "C" {
 #define RL_ERR_DEVICE (-2)    /* a HIP call failed */
 #define RL_ERR_NOMEM (-3)     /* device workspace allocation failed */
 #define RL_ERR_NONFINITE (-4) /* NaN/Inf in S*A or in R^{-1} (S*A numerically rank deficient) */
-#define RL_ERR_UNSUPPORTED (-7) /* a shape outside the compiled kernels (n > 1024 or b > 10) */
+#define RL_ERR_UNSUPPORTED (-7) /* a shape outside the compiled kernels: b > 10, or n > 1024 unless A is
+                                   real, n even and <= 2048, dot2 = 0 and rows 16-byte aligned (lda even);
+                                   or a reduced-precision sketch of complex data */
 #define RL_PENDING 2             /* served job not finished (rl_server_poll / rl_server_wait time-out) */
 #define RL_ERR_ADMISSION (-5)    /* a served request whose workspace can never fit the server's budget */
 #define RL_ERR_CANCELLED (-6)    /* a request submitted to a server that is shutting down */
@@ -86,7 +88,8 @@ typedef struct {
   int32_t max_iter;   /* default 200 for b = 1, 100 for b > 1 (Alg. rlopcg, Alg. rlobpcg) */
   int32_t check_every;/* stagnation-check cadence; default 5 (Alg. rlopcg) */
   int32_t stop_rule;  /* RL_STOP_*; default RL_STOP_PAPER */
-  int32_t dot2;       /* 1: row products of A accumulated as Dot2 (real and complex); default 1 */
+  int32_t dot2;       /* 1: row products of A accumulated as Dot2 (real and complex); default 1 for
+                         n <= 1024, else 0 (real 1024 < n <= 2048 runs plain FP64 sums on the matrix cores) */
   int32_t init_iters; /* inverse-subspace-iteration steps for the start block; default 10 */
   int32_t lanczos_steps; /* Golub-Kahan steps for Sigma~(1,1); default min(n, 64) */
   int32_t profile;    /* 1: time the pass kernels of every A-stream launch with HIP events (rl_info.t_astream_us) */
@@ -198,7 +201,7 @@ int rl_step_astream(rl_handle h, int is_complex, int64_t m, int64_t n, const dou
  * row-major, dense).  AX may be NULL (no previous direction yet): then the
  * middle block is zero.  dot2 = 1 accumulates A W and A^* AV as Dot2 sums.
  * RL_ERR_ARG on a NULL required pointer or bad size, RL_ERR_UNSUPPORTED for
- * n > 1024 or b > 10. */
+ * a shape no pass kernel takes (as for RL_ERR_UNSUPPORTED above). */
 int rl_step_astream_iter(rl_handle h, int is_complex, int64_t m, int64_t n, const double* A, int64_t lda, int32_t b,
                          const double* W, const double* AV, const double* AX, double* AW, double* G3, int32_t dot2);
 

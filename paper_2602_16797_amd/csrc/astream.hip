@@ -182,6 +182,16 @@ int64_t device_lds_max() {
   return l;
 }
 
+// Whether a pass kernel takes the shape: all of them cover n <= 1024 with
+// b <= 10; the real matrix-core pass also covers even n <= 2048 with plain
+// sums and 16-byte aligned rows (W in LDS: n b doubles, at most 160 KB).
+bool astream_shape_ok(bool cplx, bool dot2, int64_t n, int B, const void* A, int64_t lda) {
+  if (n < 1 || B < 1 || B > 10) return false;
+  if (n <= 1024) return true;
+  const bool aligned = (lda % 2 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  return !cplx && !dot2 && n <= 2048 && astream_rm_fits(B, (int)n, aligned, 160 * 1024);
+}
+
 int64_t astream_part_doubles(int64_t m, int n, int B, int es_d) {
   return astream_max_parts(m, n, B, es_d) * 4 * (int64_t)n * B * es_d;
 }
@@ -222,6 +232,12 @@ hipError_t launch_astream_pass(hipStream_t st, bool cplx, int B, bool dot2, cons
     nb = astream_c2_ranges(m, n, B);
     np = nb;
     ok = dispatch_astream_zm(init, B, st, nb, A, lda, m, n, W, AW, AVp, AXp, Gpart, device_cu_count(), ctl, mid);
+    if (ok && mid != nullptr && mid_recorded != nullptr) *mid_recorded = true;
+  } else if (!cplx && !dot2 && astream_rm_fits(B, n, aligned, device_lds_max())) {
+    // real, 1024 < n <= 2048, plain sums: the same two matrix-core kernels
+    nb = astream_c2_ranges(m, n, B);
+    np = nb;
+    ok = dispatch_astream_rm(init, B, st, nb, A, lda, m, n, W, AW, AVp, AXp, Gpart, device_cu_count(), ctl, mid);
     if (ok && mid != nullptr && mid_recorded != nullptr) *mid_recorded = true;
   } else if (cplx && astream_c2_fits(B, n, ((reinterpret_cast<uintptr_t>(A) & 15) == 0))) {
     nb = astream_c2_ranges(m, n, B);

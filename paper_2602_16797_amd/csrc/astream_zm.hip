@@ -61,25 +61,30 @@ constexpr int ZM_G_RC = 32;          // rows of Tr per LDS chunk
 // KH = 16-byte loads per lane, M tile and k block (a k block is 8 KH real
 // columns, so each of a tile's 16 rows is read KH * 64 contiguous bytes at a
 // time).
-template <int NT, int KH>
+//
+// CPLX = false is the same kernel for real A (lda2 = lda, Ar = A, Wr = W):
+// the 16-byte pair a lane loads holds two consecutive columns k, k + 1, and
+// the B operands are W(k, j) and W(k + 1, j).
+template <bool CPLX, int NT, int KH>
 __global__ __launch_bounds__(ZM_AW_THREADS) void k_zm_aw(const double* __restrict__ A, int64_t lda2, int64_t m,
-                                                         int n, int B, const cd* __restrict__ W,
+                                                         int n, int B, const double* __restrict__ W,
                                                          double* __restrict__ AW, const Ctl* __restrict__ ctl) {
   if (ctl != nullptr && ctl->done) return;
   extern __shared__ double zm_lds[];
-  cd* Ws = reinterpret_cast<cd*>(zm_lds);  // Ws[c * B + v] = W(c, v)
-  const int nwb = n * B;
-  for (int e = threadIdx.x; e < nwb; e += ZM_AW_THREADS) Ws[e] = W[e];
+  // W in LDS: complex Ws[2 (c B + v) + part], real Ws[k B + j]
+  const int nwb = (CPLX ? 2 : 1) * n * B;
+  for (int e = threadIdx.x; e < nwb; e += ZM_AW_THREADS) zm_lds[e] = W[e];
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = wave_index();
   const int q = lane >> 4, t = lane & 15;
-  const int n2 = 2 * n, B2 = 2 * B;
+  const int n2 = CPLX ? 2 * n : n, B2 = CPLX ? 2 * B : B;
   constexpr int KBW = 8 * KH;  // real columns per k block
   const int nkb = (n2 + KBW - 1) / KBW;
-  // this lane's output columns per N tile: vector v, part r (Wr's sign pattern)
+  // this lane's output columns per N tile: complex: vector v, part r (Wr's
+  // sign pattern); real: vector 16 nt + t
   int vcol[NT];
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) vcol[nt] = (16 * nt + t) >> 1;
+  for (int nt = 0; nt < NT; ++nt) vcol[nt] = CPLX ? (16 * nt + t) >> 1 : 16 * nt + t;
   const int rpart = t & 1;
   const int64_t ntile = (m + 31) / 32;
   const int64_t gw = (int64_t)blockIdx.x * (ZM_AW_THREADS / 64) + wave;
@@ -119,16 +124,30 @@ __global__ __launch_bounds__(ZM_AW_THREADS) void k_zm_aw(const double* __restric
     auto step = [&](const double2 (&a)[2][KH], int kb) {
 #pragma unroll
       for (int h = 0; h < KH; ++h) {
-        const int c = (KBW / 2) * kb + KH * q + h;
         double b_re[NT], b_im[NT];
+        if constexpr (CPLX) {
+          const int c = (KBW / 2) * kb + KH * q + h;
+          const cd* Ws = reinterpret_cast<const cd*>(zm_lds);
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const bool wok = c < n && vcol[nt] < B;
-          const int wi = wok ? c * B + vcol[nt] : 0;
-          const cd w = Ws[wi];
-          // Wr(2c, 2v) = Re w, Wr(2c, 2v+1) = Im w, Wr(2c+1, 2v) = -Im w, Wr(2c+1, 2v+1) = Re w
-          b_re[nt] = wok ? (rpart ? w.y : w.x) : 0.0;
-          b_im[nt] = wok ? (rpart ? w.x : -w.y) : 0.0;
+          for (int nt = 0; nt < NT; ++nt) {
+            const bool wok = c < n && vcol[nt] < B;
+            const int wi = wok ? c * B + vcol[nt] : 0;
+            const cd w = Ws[wi];
+            // Wr(2c, 2v) = Re w, Wr(2c, 2v+1) = Im w, Wr(2c+1, 2v) = -Im w, Wr(2c+1, 2v+1) = Re w
+            b_re[nt] = wok ? (rpart ? w.y : w.x) : 0.0;
+            b_im[nt] = wok ? (rpart ? w.x : -w.y) : 0.0;
+          }
+        } else {
+          // the pair holds columns k and k + 1 (n may be odd: k + 1 < n is checked on its own)
+          const int k = KBW * kb + 2 * KH * q + 2 * h;
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            const bool ok0 = k < n && vcol[nt] < B, ok1 = k + 1 < n && vcol[nt] < B;
+            const double w0 = zm_lds[ok0 ? k * B + vcol[nt] : 0];
+            const double w1 = zm_lds[ok1 ? (k + 1) * B + vcol[nt] : 0];
+            b_re[nt] = ok0 ? w0 : 0.0;
+            b_im[nt] = ok1 ? w1 : 0.0;
+          }
         }
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
@@ -173,7 +192,10 @@ __global__ __launch_bounds__(ZM_AW_THREADS) void k_zm_aw(const double* __restric
 // Partial records of A^* [P0 P1 P2] over row ranges (real form Ar^T Tr).
 // NT = N tiles over the used columns of Tr (np planes of 2b real columns).
 // Tr plane g goes to record plane g (init: the single plane A_W to plane 0).
-template <int NT>
+//
+// CPLX = false is the same kernel for real A (Ar = A, Tr = [A_V A_X A_W], no
+// 2 x 2 combination: Gr is A^T T itself).
+template <bool CPLX, int NT>
 __global__ __launch_bounds__(ZM_G_THREADS, 2) void k_zm_g(const double* __restrict__ A, int64_t lda2, int64_t m, int n,
                                                        int B, const double* __restrict__ P0,
                                                        const double* __restrict__ P1, const double* __restrict__ P2,
@@ -192,7 +214,7 @@ __global__ __launch_bounds__(ZM_G_THREADS, 2) void k_zm_g(const double* __restri
   if (rr >= nrr) return;  // uniform over the workgroup
   const int lane = threadIdx.x & 63, wave = wave_index();
   const int q = lane >> 4, t = lane & 15;
-  const int n2 = 2 * n, B2 = 2 * B;
+  const int n2 = CPLX ? 2 * n : n, B2 = CPLX ? 2 * B : B;
   const int kw = 256 * slice + 64 * wave;  // this wave's first real column of A
   const bool active = kw < n2;
   const int64_t r0 = rr * rows_per_range;
@@ -290,40 +312,67 @@ __global__ __launch_bounds__(ZM_G_THREADS, 2) void k_zm_g(const double* __restri
     buf ^= 1;
   }
   if (!active) return;
-  // 2 x 2 combination: tile u (even) holds Gr(2c, .), tile u + 1 Gr(2c + 1, .)
-  // at the same lane and register; columns 2v and 2v + 1 are lanes t and t + 1.
-  const int64_t plane = 2 * (int64_t)n * B;
-  double* gp = Gpart + rr * 4 * plane;
-  const int rp = t & 1;
+  if constexpr (CPLX) {
+    // 2 x 2 combination: tile u (even) holds Gr(2c, .), tile u + 1 Gr(2c + 1, .)
+    // at the same lane and register; columns 2v and 2v + 1 are lanes t and t + 1.
+    const int64_t plane = 2 * (int64_t)n * B;
+    double* gp = Gpart + rr * 4 * plane;
+    const int rp = t & 1;
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
+      for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const double x0 = acc[2 * h][nt][r], x1 = acc[2 * h + 1][nt][r];
-        const double y0 = dpp_d<0xB1>(x0), y1 = dpp_d<0xB1>(x1);  // the neighbour lane t ^ 1
-        // output row 4r + q of the tile is the column group kcol' = kw + 4 (4r + q)
-        const int c = (kw + 4 * (4 * r + q)) / 2 + h;
-        const int colr = 16 * nt + t;  // Tr column of this lane (even t: re part)
-        if (rp == 0 && c < n && colr < ncol) {
-          const int g = colr / B2, vv = (colr - g * B2) >> 1;
-          const double re = x0 + y1;  // Gr(2c, 2v) + Gr(2c+1, 2v+1)
-          const double im = y0 - x1;  // Gr(2c, 2v+1) - Gr(2c+1, 2v)
-          const int pl = init ? 0 : g;
-          double* dst = gp + (int64_t)pl * plane + 2 * ((int64_t)c * B + vv);
-          dst[0] = re;
-          dst[1] = im;
+        for (int r = 0; r < 4; ++r) {
+          const double x0 = acc[2 * h][nt][r], x1 = acc[2 * h + 1][nt][r];
+          const double y0 = dpp_d<0xB1>(x0), y1 = dpp_d<0xB1>(x1);  // the neighbour lane t ^ 1
+          // output row 4r + q of the tile is the column group kcol' = kw + 4 (4r + q)
+          const int c = (kw + 4 * (4 * r + q)) / 2 + h;
+          const int colr = 16 * nt + t;  // Tr column of this lane (even t: re part)
+          if (rp == 0 && c < n && colr < ncol) {
+            const int g = colr / B2, vv = (colr - g * B2) >> 1;
+            const double re = x0 + y1;  // Gr(2c, 2v) + Gr(2c+1, 2v+1)
+            const double im = y0 - x1;  // Gr(2c, 2v+1) - Gr(2c+1, 2v)
+            const int pl = init ? 0 : g;
+            double* dst = gp + (int64_t)pl * plane + 2 * ((int64_t)c * B + vv);
+            dst[0] = re;
+            dst[1] = im;
+          }
+        }
+    // the planes this pass does not form, and the error plane, are zero
+    for (int cc = lane; cc < 32 * B; cc += 64) {
+      const int c = kw / 2 + cc / B, vv = cc - (cc / B) * B;
+      if (c < n) {
+        const int64_t e = 2 * ((int64_t)c * B + vv);
+        for (int pl = (init ? 1 : 3); pl < 4; ++pl) {
+          gp[pl * plane + e] = 0.0;
+          gp[pl * plane + e + 1] = 0.0;
         }
       }
-  // the planes this pass does not form, and the error plane, are zero
-  for (int cc = lane; cc < 32 * B; cc += 64) {
-    const int c = kw / 2 + cc / B, vv = cc - (cc / B) * B;
-    if (c < n) {
-      const int64_t e = 2 * ((int64_t)c * B + vv);
-      for (int pl = (init ? 1 : 3); pl < 4; ++pl) {
-        gp[pl * plane + e] = 0.0;
-        gp[pl * plane + e + 1] = 0.0;
+    }
+  } else {
+    // tile u, register r holds G(c, col) for column c = kw + 4 (4r + q) + u of
+    // A and column col = 16 nt + t of Tr
+    const int64_t plane = (int64_t)n * B;
+    double* gp = Gpart + rr * 4 * plane;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int c = kw + 4 * (4 * r + q) + u;
+          const int colr = 16 * nt + t;
+          if (c < n && colr < ncol) {
+            const int g = colr / B2, vv = colr - g * B2;
+            gp[(int64_t)(init ? 0 : g) * plane + (int64_t)c * B + vv] = acc[u][nt][r];
+          }
+        }
+    for (int cc = lane; cc < 64 * B; cc += 64) {
+      const int c = kw + cc / B, vv = cc - (cc / B) * B;
+      if (c < n) {
+        const int64_t e = (int64_t)c * B + vv;
+        for (int pl = (init ? 1 : 3); pl < 4; ++pl) gp[pl * plane + e] = 0.0;
       }
     }
   }
@@ -333,65 +382,85 @@ bool astream_zm_fits(int B, int n, bool aligned, int64_t lds_max) {
   return aligned && n > 256 && n <= 1024 && B >= 1 && B <= 10 && (int64_t)n * B * 16 <= lds_max;
 }
 
+// Real A: even n (each lane's 16-byte pairs are whole columns pairs), W in LDS.
+bool astream_rm_fits(int B, int n, bool aligned, int64_t lds_max) {
+  return aligned && n % 2 == 0 && n > 1024 && n <= 2048 && B >= 1 && B <= 10 && (int64_t)n * B * 8 <= lds_max;
+}
+
 constexpr int ZM_AW_KH = 2;  // 32 contiguous bytes per row and lane per k block
 
-template <int NT>
+template <bool CPLX, int NT>
 static hipError_t zm_aw_go(hipStream_t st, int grid, const double* A, int64_t lda2, int64_t m, int n, int B,
-                           const cd* W, double* AW, const Ctl* ctl) {
-  const size_t lds = sizeof(cd) * (size_t)n * B;
-  const hipError_t e = hipFuncSetAttribute((const void*)k_zm_aw<NT, ZM_AW_KH>,
+                           const double* W, double* AW, const Ctl* ctl) {
+  const size_t lds = (CPLX ? 16 : 8) * (size_t)n * B;
+  const hipError_t e = hipFuncSetAttribute((const void*)k_zm_aw<CPLX, NT, ZM_AW_KH>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_zm_aw<NT, ZM_AW_KH>), dim3((unsigned)grid), dim3(ZM_AW_THREADS), lds, st, A, lda2, m, n, B,
-                     W, AW, ctl);
+  hipLaunchKernelGGL((k_zm_aw<CPLX, NT, ZM_AW_KH>), dim3((unsigned)grid), dim3(ZM_AW_THREADS), lds, st, A, lda2, m,
+                     n, B, W, AW, ctl);
   return hipGetLastError();
 }
 
-template <int NT>
+template <bool CPLX, int NT>
 static void zm_g_go(hipStream_t st, int64_t nblk, const double* A, int64_t lda2, int64_t m, int n, int B,
                     const double* P0, const double* P1, const double* P2, int np, int init, double* Gpart,
                     int64_t rows, int64_t nrr, int nslice, const Ctl* ctl) {
-  hipLaunchKernelGGL(k_zm_g<NT>, dim3((unsigned)nblk), dim3(ZM_G_THREADS), 0, st, A, lda2, m, n, B, P0, P1, P2, np,
-                     init, Gpart, rows, nrr, nslice, ctl);
+  hipLaunchKernelGGL((k_zm_g<CPLX, NT>), dim3((unsigned)nblk), dim3(ZM_G_THREADS), 0, st, A, lda2, m, n, B, P0, P1,
+                     P2, np, init, Gpart, rows, nrr, nslice, ctl);
 }
 
 // A_W = A W, then the partial records of A^* [A_V A_X A_W] (init: A^* A_W in
-// the first plane) over nrr row ranges.
-bool dispatch_astream_zm(int init, int B, hipStream_t st, int64_t nrr, const void* A, int64_t lda, int64_t m, int n,
-                         const void* W, void* AW, const void* AVp, const void* AXp, double* Gpart, int n_cu,
-                         const Ctl* ctl, hipEvent_t mid) {
-  if (n <= 256 || n > 1024 || B < 1 || B > 10 || nrr < 1) return false;
+// the first plane) over nrr row ranges; cplx selects the complex real form.
+template <bool CPLX>
+static bool zm_dispatch(int init, int B, hipStream_t st, int64_t nrr, const void* A, int64_t lda, int64_t m, int n,
+                        const void* W, void* AW, const void* AVp, const void* AXp, double* Gpart, int n_cu,
+                        const Ctl* ctl, hipEvent_t mid) {
   const double* Ad = (const double*)A;
-  const int64_t lda2 = 2 * lda;
+  const int64_t lda2 = CPLX ? 2 * lda : lda;
+  const int n2 = CPLX ? 2 * n : n, B2 = CPLX ? 2 * B : B;
   // one workgroup per CU (W fills the LDS), at most one per 32-row tile per wave
   const int64_t tiles = (m + 31) / 32;
   int grid = n_cu > 0 ? n_cu : 256;
   if ((int64_t)grid * (ZM_AW_THREADS / 64) > tiles) grid = (int)((tiles + 15) / 16);
   if (grid < 1) grid = 1;
   hipError_t e;
-  if (2 * B <= 16)
-    e = zm_aw_go<1>(st, grid, Ad, lda2, m, n, B, (const cd*)W, (double*)AW, ctl);
+  if (B2 <= 16)
+    e = zm_aw_go<CPLX, 1>(st, grid, Ad, lda2, m, n, B, (const double*)W, (double*)AW, ctl);
   else
-    e = zm_aw_go<2>(st, grid, Ad, lda2, m, n, B, (const cd*)W, (double*)AW, ctl);
+    e = zm_aw_go<CPLX, 2>(st, grid, Ad, lda2, m, n, B, (const double*)W, (double*)AW, ctl);
   if (e != hipSuccess) return false;
   // the second kernel's start, for timing the Gram contraction on its own
   if (mid != nullptr && hipEventRecord(mid, st) != hipSuccess) return false;
   const int64_t rows = (m + nrr - 1) / nrr;
-  const int nslice = (2 * n + 255) / 256;
+  const int nslice = (n2 + 255) / 256;
   const int64_t nblk = ((nrr + 7) / 8) * 8 * nslice;
   const double* P0 = init ? (const double*)AW : (const double*)AVp;
   const double* P1 = init ? nullptr : (const double*)AXp;
   const double* P2 = init ? nullptr : (const double*)AW;
   const int np = init ? 1 : 3;
-  const int nt = (np * 2 * B + 15) / 16;
+  const int nt = (np * B2 + 15) / 16;
   switch (nt) {
-    case 1: zm_g_go<1>(st, nblk, Ad, lda2, m, n, B, P0, P1, P2, np, init, Gpart, rows, nrr, nslice, ctl); break;
-    case 2: zm_g_go<2>(st, nblk, Ad, lda2, m, n, B, P0, P1, P2, np, init, Gpart, rows, nrr, nslice, ctl); break;
-    case 3: zm_g_go<3>(st, nblk, Ad, lda2, m, n, B, P0, P1, P2, np, init, Gpart, rows, nrr, nslice, ctl); break;
-    case 4: zm_g_go<4>(st, nblk, Ad, lda2, m, n, B, P0, P1, P2, np, init, Gpart, rows, nrr, nslice, ctl); break;
+    case 1: zm_g_go<CPLX, 1>(st, nblk, Ad, lda2, m, n, B, P0, P1, P2, np, init, Gpart, rows, nrr, nslice, ctl); break;
+    case 2: zm_g_go<CPLX, 2>(st, nblk, Ad, lda2, m, n, B, P0, P1, P2, np, init, Gpart, rows, nrr, nslice, ctl); break;
+    case 3: zm_g_go<CPLX, 3>(st, nblk, Ad, lda2, m, n, B, P0, P1, P2, np, init, Gpart, rows, nrr, nslice, ctl); break;
+    case 4: zm_g_go<CPLX, 4>(st, nblk, Ad, lda2, m, n, B, P0, P1, P2, np, init, Gpart, rows, nrr, nslice, ctl); break;
     default: return false;
   }
   return hipGetLastError() == hipSuccess;
+}
+
+bool dispatch_astream_zm(int init, int B, hipStream_t st, int64_t nrr, const void* A, int64_t lda, int64_t m, int n,
+                         const void* W, void* AW, const void* AVp, const void* AXp, double* Gpart, int n_cu,
+                         const Ctl* ctl, hipEvent_t mid) {
+  if (n <= 256 || n > 1024 || B < 1 || B > 10 || nrr < 1) return false;
+  return zm_dispatch<true>(init, B, st, nrr, A, lda, m, n, W, AW, AVp, AXp, Gpart, n_cu, ctl, mid);
+}
+
+bool dispatch_astream_rm(int init, int B, hipStream_t st, int64_t nrr, const void* A, int64_t lda, int64_t m, int n,
+                         const void* W, void* AW, const void* AVp, const void* AXp, double* Gpart, int n_cu,
+                         const Ctl* ctl, hipEvent_t mid) {
+  if (n <= 1024 || n > 2048 || (n & 1) || B < 1 || B > 10 || nrr < 1) return false;
+  return zm_dispatch<false>(init, B, st, nrr, A, lda, m, n, W, AW, AVp, AXp, Gpart, n_cu, ctl, mid);
 }
 
 }  // namespace rl

@@ -32,6 +32,11 @@ int64_t astream_tmp_doubles(int64_t m, int n, int B, int es_d);
 int64_t astream_r2_blocks(int64_t m);
 int astream_ccs_waves(int n);
 bool astream_c2_fits(int B, int n, bool aligned);
+bool astream_rm_fits(int B, int n, bool aligned, int64_t lds_max);
+bool dispatch_astream_rm(int init, int B, hipStream_t st, int64_t nrr, const void* A, int64_t lda, int64_t m, int n,
+                         const void* W, void* AW, const void* AVp, const void* AXp, double* Gpart, int n_cu,
+                         const Ctl* ctl, hipEvent_t mid);
+bool astream_shape_ok(bool cplx, bool dot2, int64_t n, int B, const void* A, int64_t lda);
 bool astream_zm_fits(int B, int n, bool aligned, int64_t lds_max);
 bool dispatch_astream_zm(int init, int B, hipStream_t st, int64_t nrr, const void* A, int64_t lda, int64_t m, int n,
                          const void* W, void* AW, const void* AVp, const void* AXp, double* Gpart, int n_cu,

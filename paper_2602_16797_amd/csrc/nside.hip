@@ -679,13 +679,18 @@ __device__ inline void lz_rows(int n, const T* __restrict__ M, int64_t ld, bool 
   }
 }
 
-// x <- x - Basis(:, 0:cnt) (Basis(:, 0:cnt)^* x), twice; x is entry tid of a
-// vector, Basis columns have stride n.  xs and hq are LDS work arrays.
-template <typename T>
-__device__ inline void lz_reorth(int n, int cnt, const T* __restrict__ Basis, T& x, T* xs, T* hq, int own) {
+// x <- x - Basis(:, 0:cnt) (Basis(:, 0:cnt)^* x), twice; the thread holds the
+// entries tid + LZ_THREADS e (e < NPT) of the vector, Basis columns have
+// stride n.  xs and hq are LDS work arrays (xs holds n entries).
+template <typename T, int NPT>
+__device__ inline void lz_reorth(int n, int cnt, const T* __restrict__ Basis, T (&x)[NPT], T* xs, T* hq) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int pass = 0; pass < 2; ++pass) {
-    if (own) xs[threadIdx.x] = x;
+#pragma unroll
+    for (int e = 0; e < NPT; ++e) {
+      const int i = threadIdx.x + LZ_THREADS * e;
+      if (i < n) xs[i] = x[e];
+    }
     __syncthreads();
     for (int q = wid; q < cnt; q += LZ_WAVES) {
       T acc = zero<T>();
@@ -695,21 +700,25 @@ __device__ inline void lz_reorth(int n, int cnt, const T* __restrict__ Basis, T&
       if (lane == 0) hq[q] = acc;
     }
     __syncthreads();
-    if (own) {
-      // eight independent loads in flight per step of the loop
-      T acc[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] = zero<T>();
-      int q = 0;
-      for (; q + 8 <= cnt; q += 8) {
+    for (int e = 0; e < NPT; ++e) {
+      const int i = threadIdx.x + LZ_THREADS * e;
+      if (i < n) {
+        // eight independent loads in flight per step of the loop
+        T acc[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc[u] = fmac(Basis[(int64_t)(q + u) * n + threadIdx.x], hq[q + u], acc[u]);
+        for (int u = 0; u < 8; ++u) acc[u] = zero<T>();
+        int q = 0;
+        for (; q + 8 <= cnt; q += 8) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc[u] = fmac(Basis[(int64_t)(q + u) * n + i], hq[q + u], acc[u]);
+        }
+        for (; q < cnt; ++q) acc[0] = fmac(Basis[(int64_t)q * n + i], hq[q], acc[0]);
+        T tot = zero<T>();
+#pragma unroll
+        for (int u = 0; u < 8; ++u) tot = add(tot, acc[u]);
+        x[e] = sub(x[e], tot);
       }
-      for (; q < cnt; ++q) acc[0] = fmac(Basis[(int64_t)q * n + threadIdx.x], hq[q], acc[0]);
-      T tot = zero<T>();
-#pragma unroll
-      for (int u = 0; u < 8; ++u) tot = add(tot, acc[u]);
-      x = sub(x, tot);
     }
     __syncthreads();
   }
@@ -765,70 +774,101 @@ __device__ inline void lz_tridiag(const double* alpha, const double* beta, int k
   }
 }
 
-template <typename T>
+// NPT vector entries per thread (n <= LZ_THREADS NPT); xs and ys (n entries
+// each) are dynamic LDS.
+template <typename T, int NPT>
 __global__ __launch_bounds__(LZ_THREADS) void k_lanczos(int n, const T* __restrict__ Ycol, int ld,
                                                         const T* __restrict__ Rrow, T* __restrict__ Ub,
                                                         T* __restrict__ Vb, int KL, uint64_t seed,
                                                         Ctl* __restrict__ ctl) {
-  __shared__ T xs[LZ_THREADS];
-  __shared__ T ys[LZ_THREADS];
+  extern __shared__ double lz_lds[];
+  T* xs = reinterpret_cast<T*>(lz_lds);
+  T* ys = xs + LZ_THREADS * NPT;
   __shared__ T hq[LZ_MAXK + 1];
   __shared__ double alpha[LZ_MAXK + 1], beta[LZ_MAXK + 1];
   __shared__ double dg[LZ_MAXK + 1], of[LZ_MAXK + 1];
   __shared__ double red[LZ_WAVES];
   __shared__ double est[2];  // previous top Ritz value, converged flag
   const int tid = threadIdx.x;
-  const int own = tid < n;
+  bool own[NPT];
+#pragma unroll
+  for (int e = 0; e < NPT; ++e) own[e] = tid + LZ_THREADS * e < n;
   if (tid == 0) {
     est[0] = -1.0;
     est[1] = 0.0;
   }
   // v_0: deterministic random unit vector
-  T v = zero<T>();
+  T v[NPT], u[NPT], uprev[NPT];
   double s = 0.0;
-  if (own) {
-    const double x = unif_pm1(mix64(seed ^ (uint64_t)(0x5bd1e995ull + tid)));
-    v = from_real<T>(x);
-    s = x * x;
+#pragma unroll
+  for (int e = 0; e < NPT; ++e) {
+    v[e] = zero<T>();
+    u[e] = zero<T>();
+    uprev[e] = zero<T>();
+    if (own[e]) {
+      const double x = unif_pm1(mix64(seed ^ (uint64_t)(0x5bd1e995ull + tid + LZ_THREADS * e)));
+      v[e] = from_real<T>(x);
+      s += x * x;
+    }
   }
   s = block_sum(s, red);
-  v = scal(v, 1.0 / sqrt(s));
-  if (own) Vb[tid] = v;
-  T u = zero<T>(), uprev = zero<T>();
+#pragma unroll
+  for (int e = 0; e < NPT; ++e) {
+    v[e] = scal(v[e], 1.0 / sqrt(s));
+    if (own[e]) Vb[tid + LZ_THREADS * e] = v[e];
+  }
   int k = 0;
   for (int j = 0; j < KL; ++j) {
     // u = R v_j - beta_{j-1} u_{j-1}
-    if (own) xs[tid] = v;
+#pragma unroll
+    for (int e = 0; e < NPT; ++e)
+      if (own[e]) xs[tid + LZ_THREADS * e] = v[e];
     __syncthreads();
     lz_rows<T, false>(n, Rrow, n, true, xs, ys);
     __syncthreads();
-    u = own ? ys[tid] : zero<T>();
-    if (j > 0) u = sub(u, scal(uprev, beta[j - 1]));
-    lz_reorth<T>(n, j, Ub, u, xs, hq, own);
-    s = own ? abs2(u) : 0.0;
+#pragma unroll
+    for (int e = 0; e < NPT; ++e) {
+      u[e] = own[e] ? ys[tid + LZ_THREADS * e] : zero<T>();
+      if (j > 0) u[e] = sub(u[e], scal(uprev[e], beta[j - 1]));
+    }
+    lz_reorth<T, NPT>(n, j, Ub, u, xs, hq);
+    s = 0.0;
+#pragma unroll
+    for (int e = 0; e < NPT; ++e) s += own[e] ? abs2(u[e]) : 0.0;
     s = block_sum(s, red);
     const double a = sqrt(s);
     if (tid == 0) alpha[j] = a;
-    u = scal(u, (a > 0.0) ? 1.0 / a : 0.0);
-    if (own) Ub[(int64_t)j * n + tid] = u;
+#pragma unroll
+    for (int e = 0; e < NPT; ++e) {
+      u[e] = scal(u[e], (a > 0.0) ? 1.0 / a : 0.0);
+      if (own[e]) Ub[(int64_t)j * n + tid + LZ_THREADS * e] = u[e];
+    }
     k = j + 1;
     if (!(a > 0.0)) break;
     // v = R^* u - alpha_j v_j   (column l of R is Ycol[l*ld + 0..l])
-    if (own) xs[tid] = u;
+#pragma unroll
+    for (int e = 0; e < NPT; ++e)
+      if (own[e]) xs[tid + LZ_THREADS * e] = u[e];
     __syncthreads();
     lz_rows<T, true>(n, Ycol, ld, false, xs, ys);
     __syncthreads();
-    v = own ? sub(ys[tid], scal(v, a)) : zero<T>();
-    lz_reorth<T>(n, j + 1, Vb, v, xs, hq, own);
-    s = own ? abs2(v) : 0.0;
+#pragma unroll
+    for (int e = 0; e < NPT; ++e) v[e] = own[e] ? sub(ys[tid + LZ_THREADS * e], scal(v[e], a)) : zero<T>();
+    lz_reorth<T, NPT>(n, j + 1, Vb, v, xs, hq);
+    s = 0.0;
+#pragma unroll
+    for (int e = 0; e < NPT; ++e) s += own[e] ? abs2(v[e]) : 0.0;
     s = block_sum(s, red);
     const double bta = sqrt(s);
     if (tid == 0) beta[j] = bta;
     __syncthreads();
     if (!(bta > 1e-15 * a) || j + 1 >= n) break;
-    v = scal(v, 1.0 / bta);
-    if (own) Vb[(int64_t)(j + 1) * n + tid] = v;
-    uprev = u;
+#pragma unroll
+    for (int e = 0; e < NPT; ++e) {
+      v[e] = scal(v[e], 1.0 / bta);
+      if (own[e]) Vb[(int64_t)(j + 1) * n + tid + LZ_THREADS * e] = v[e];
+      uprev[e] = u[e];
+    }
     // every 8 steps from step 16: stop once the top Ritz value of B^T B has
     // settled to 1e-15 relative (k = j + 1 steps so far)
     if (j + 1 >= 16 && (j + 1) % 8 == 0 && j + 1 < KL) {
@@ -999,16 +1039,28 @@ hipError_t launch_randblk(hipStream_t st, bool cplx, void* Wb, int64_t count, ui
   return hipGetLastError();
 }
 
+template <typename T, int NPT>
+static hipError_t lanczos_go(hipStream_t st, int n, const void* Ycol, int ld, const void* Rrow, void* Ub, void* Vb,
+                             int KL, uint64_t seed, Ctl* ctl) {
+  const size_t lds = 2 * sizeof(T) * (size_t)LZ_THREADS * NPT;
+  const hipError_t e =
+      hipFuncSetAttribute((const void*)k_lanczos<T, NPT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_lanczos<T, NPT>), dim3(1), dim3(LZ_THREADS), lds, st, n, (const T*)Ycol, ld, (const T*)Rrow,
+                     (T*)Ub, (T*)Vb, KL, seed, ctl);
+  return hipGetLastError();
+}
+
+// n <= 1024 (one entry per thread) or n <= 2048 (two)
 hipError_t launch_lanczos(hipStream_t st, bool cplx, int n, const void* Ycol, int ld, const void* Rrow, void* Ub,
                           void* Vb, int KL, uint64_t seed, Ctl* ctl) {
-  if (n > LZ_THREADS) return hipErrorInvalidValue;
-  if (cplx)
-    hipLaunchKernelGGL(k_lanczos<cd>, dim3(1), dim3(LZ_THREADS), 0, st, n, (const cd*)Ycol, ld, (const cd*)Rrow,
-                       (cd*)Ub, (cd*)Vb, KL, seed, ctl);
-  else
-    hipLaunchKernelGGL(k_lanczos<double>, dim3(1), dim3(LZ_THREADS), 0, st, n, (const double*)Ycol, ld,
-                       (const double*)Rrow, (double*)Ub, (double*)Vb, KL, seed, ctl);
-  return hipGetLastError();
+  if (n <= LZ_THREADS)
+    return cplx ? lanczos_go<cd, 1>(st, n, Ycol, ld, Rrow, Ub, Vb, KL, seed, ctl)
+                : lanczos_go<double, 1>(st, n, Ycol, ld, Rrow, Ub, Vb, KL, seed, ctl);
+  if (n <= 2 * LZ_THREADS)
+    return cplx ? lanczos_go<cd, 2>(st, n, Ycol, ld, Rrow, Ub, Vb, KL, seed, ctl)
+                : lanczos_go<double, 2>(st, n, Ycol, ld, Rrow, Ub, Vb, KL, seed, ctl);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_final_n(hipStream_t st, bool cplx, int n, int B, int k, const void* V, const double* thb,

@@ -232,7 +232,7 @@ static int check_opts(int64_t m, int64_t n, int32_t k, const rl_opts& o) {
   if (o.orth < RL_ORTH_CGS2 || o.orth > RL_ORTH_SVQB) return RL_ERR_ARG;
   if (o.refresh < 0 || o.refresh > 1) return RL_ERR_ARG;
   if (o.prec_guard < 0 || o.prec_guard > 1) return RL_ERR_ARG;
-  if (n > 1024 || o.block > 10) return RL_ERR_UNSUPPORTED;
+  if (n > 2048 || o.block > 10) return RL_ERR_UNSUPPORTED;
   if (o.d > INT32_MAX / 2) return RL_ERR_ARG;
   return RL_OK;
 }
@@ -263,6 +263,7 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   if (rc != RL_OK) return rc;
   if (lda < n || ldv < k || (Uout && ldu < k)) return RL_ERR_ARG;
   if (cplx && o.sketch_prec != RL_SKETCH_F64) return RL_ERR_UNSUPPORTED;
+  if (!astream_shape_ok(cplx, o.dot2 != 0, n, o.block, A, lda)) return RL_ERR_UNSUPPORTED;
   if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;
   Problem p{m, n, o.d, o.block, k, o.zeta, cplx, (size_t)(cplx ? 16 : 8), o.max_iter, o.sketch_prec,
             o.loop_precond};
@@ -755,7 +756,7 @@ int rl_default_opts(rl_opts* o, int64_t m, int64_t n, int32_t k) {
   o->max_iter = (k == 1) ? 200 : 100;
   o->check_every = 5;
   o->stop_rule = RL_STOP_PAPER;
-  o->dot2 = 1;
+  o->dot2 = (n <= 1024) ? 1 : 0;  // wider real shapes run the plain-sum matrix-core pass
   o->init_iters = 10;
   o->lanczos_steps = 64;
   o->refresh = 1;
@@ -873,7 +874,7 @@ int rl_step_qr_lowp(rl_handle h, int64_t d, int64_t n, const float* Y, int64_t l
 int rl_step_astream(rl_handle h, int is_complex, int64_t m, int64_t n, const double* A, int64_t lda, int32_t b,
                     const double* W, double* AW, double* G, int32_t dot2) {
   if (!h || !A || !W || !AW || !G || m < 1 || n < 1 || lda < n || b < 1) return RL_ERR_ARG;
-  if (n > 1024 || b > 10) return RL_ERR_UNSUPPORTED;
+  if (!astream_shape_ok(is_complex != 0, dot2 != 0, n, b, A, lda)) return RL_ERR_UNSUPPORTED;
   if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;
   const int es = is_complex ? 2 : 1;
   Arena a;
@@ -893,7 +894,7 @@ int rl_step_astream(rl_handle h, int is_complex, int64_t m, int64_t n, const dou
 int rl_step_astream_iter(rl_handle h, int is_complex, int64_t m, int64_t n, const double* A, int64_t lda, int32_t b,
                          const double* W, const double* AV, const double* AX, double* AW, double* G3, int32_t dot2) {
   if (!h || !A || !W || !AV || !AW || !G3 || m < 1 || n < 1 || lda < n || b < 1) return RL_ERR_ARG;
-  if (n > 1024 || b > 10) return RL_ERR_UNSUPPORTED;
+  if (!astream_shape_ok(is_complex != 0, dot2 != 0, n, b, A, lda)) return RL_ERR_UNSUPPORTED;
   if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;
   const int es = is_complex ? 2 : 1;
   Arena a;
@@ -912,7 +913,7 @@ int rl_step_astream_iter_noalloc(rl_handle h, int is_complex, int64_t m, int64_t
                                  int32_t b, const double* W, const double* AV, const double* AX, double* AW,
                                  double* G3, int32_t dot2) {
   if (!h || !A || !W || !AV || !AW || !G3 || m < 1 || n < 1 || lda < n || b < 1) return RL_ERR_ARG;
-  if (n > 1024 || b > 10) return RL_ERR_UNSUPPORTED;
+  if (!astream_shape_ok(is_complex != 0, dot2 != 0, n, b, A, lda)) return RL_ERR_UNSUPPORTED;
   const int es = is_complex ? 2 : 1;
   Arena a;
   const size_t o_part = a.take(sizeof(double) * astream_part_doubles(m, (int)n, b, es)),
@@ -983,6 +984,7 @@ int rl_server_submit(rl_server_h s, const rl_request* req, uint64_t* ticket) {
   if (rc != RL_OK) return rc;
   if (req->lda < req->n || req->ldv < req->k || (req->U && req->ldu < req->k)) return RL_ERR_ARG;
   if (cplx && o.sketch_prec != RL_SKETCH_F64) return RL_ERR_UNSUPPORTED;
+  if (!astream_shape_ok(cplx, o.dot2 != 0, req->n, o.block, req->A, req->lda)) return RL_ERR_UNSUPPORTED;
   rl_job* j = new (std::nothrow) rl_job();
   if (!j) return RL_ERR_NOMEM;
   j->cplx = cplx;
@@ -1091,7 +1093,9 @@ const char* rl_status_string(int code) {
     case RL_ERR_DEVICE: return "HIP runtime error";
     case RL_ERR_NOMEM: return "device allocation failed";
     case RL_ERR_NONFINITE: return "NaN or Inf in the sketch or in R^{-1}";
-    case RL_ERR_UNSUPPORTED: return "shape outside the compiled kernels (n > 1024 or b > 10)";
+    case RL_ERR_UNSUPPORTED:
+      return "shape outside the compiled kernels (b > 10, or n > 1024 unless real, even n <= 2048, plain sums, "
+             "16-byte aligned rows; or a reduced-precision sketch of complex data)";
     case RL_PENDING: return "the served job has not finished";
     case RL_ERR_ADMISSION: return "the request can never fit the server's HBM budget";
     case RL_ERR_CANCELLED: return "the server is shutting down";

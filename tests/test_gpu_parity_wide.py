@@ -11,6 +11,13 @@
   vectors by about u ||A||_F / (sqrt(m) sigma_{n-10}) = 1e-13 here).
 * Real blocks of 8 and 10 vectors at n = 300 (the column-split pass and the
   column-wave TSQR at t = 24 and 30).
+* Real n in (1024, 2048], where the pass runs plain sums on the matrix cores
+  and the Lanczos estimate holds two vector entries per thread: a gapped
+  spectrum (sigma_{n-k+1} = 1e-4 below a drop of 10, so plain products move
+  the vectors by about u sqrt(n) / 1e-3 and the angle gate holds), and the
+  clustered spectrum of the block-size study (Sec. 5.2) at reduced m, where
+  the bottom gap is 9e-5 relative and only sigma, the residual and the
+  stopping rule are gated.  The oracle uses plain products too.
 
 Gates as in test_gpu_parity: |sigma - sigma_oracle| <= 1e-12 ||A||, the
 residual ||A v - sigma u|| <= 1e-12 ||A||, the principal-angle sine to the
@@ -21,7 +28,7 @@ histories by the oracle's stopping rule.
 import pytest
 
 from oracle import rlobpcg
-from workloads import planted_numpy, spectrum_gap, spectrum_nullspace
+from workloads import planted_numpy, spectrum_clustered, spectrum_gap, spectrum_nullspace
 
 from .gpu_util import banner
 from .test_gpu_parity import _check
@@ -57,3 +64,17 @@ def test_real_block_wide(rl, k):
     banner(f"parity real 20000x300 k=b={k}")
     A, _, s = planted_numpy(20_000, 300, spectrum_gap(300, k, 1e-8, 10.0), 1400 + k)
     _check(rl, A, k, seed=2400 + k, normA=s[0])
+
+
+@pytest.mark.parametrize("m,n,k,b", [(12_000, 1100, 1, 1), (8000, 2048, 3, 5)])
+def test_real_wide_plain(rl, m, n, k, b):
+    banner(f"parity real {m}x{n} k={k} b={b}, plain products (matrix-core pass)")
+    A, _, s = planted_numpy(m, n, spectrum_gap(n, k, 1e-4, 10.0), 1500 + n)
+    _check(rl, A, k, seed=2500 + n, normA=s[0], block=b, dot2=False)
+
+
+@pytest.mark.parametrize("b", [1, 3])
+def test_real_clustered_wide(rl, b):
+    banner(f"parity real 10000x2000 clustered spectrum (Sec. 5.2) k=1 b={b}, plain products")
+    A, _, s = planted_numpy(10_000, 2000, spectrum_clustered(2000), 1600)
+    _check(rl, A, 1, seed=2600, normA=s[0], block=b, dot2=False, gap_ok=False)

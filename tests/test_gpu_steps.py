@@ -85,7 +85,10 @@ def test_qr_and_inverse(rl, d, n, cplx):
                                              (2049, 65, 2, True, True), (1500, 1000, 10, True, False), (999, 1024, 10, False, True),
                                              (17, 130, 3, False, True), (40_000, 300, 4, False, True),
                                              (30_000, 500, 5, False, False), (1001, 301, 1, True, False),
-                                             (5000, 1024, 10, True, False)])
+                                             (5000, 1024, 10, True, False),
+                                             # real plain sums on the matrix cores past n = 1024
+                                             (5000, 2048, 10, False, False), (3001, 1026, 1, False, False),
+                                             (777, 1500, 5, False, False)])
 def test_astream(rl, m, n, b, cplx, dot2):
     banner(f"astream m={m} n={n} b={b} complex={cplx} dot2={dot2}")
     rng = np.random.default_rng(m + n + b)
@@ -129,7 +132,11 @@ def _rand(rng, shape, cplx):
     # complex plain sums on the matrix cores: odd n (a ragged last k block),
     # n just above 256, b = 1 and b = 8 (one N tile), fewer rows than a tile
     (3001, 301, 1, True, False, True), (977, 257, 8, True, False, True), (33, 600, 3, True, False, False),
-    (20_011, 1000, 10, True, False, True)])
+    (20_011, 1000, 10, True, False, True),
+    # real plain sums on the matrix cores, 1024 < n <= 2048 (even): a ragged
+    # last k block (n % 16 != 0), b = 1, 3, 8 and 10, fewer rows than a tile
+    (4001, 1100, 3, False, False, True), (20_011, 2000, 10, False, False, True),
+    (33, 1202, 8, False, False, False), (3000, 2048, 1, False, False, True)])
 def test_astream_iter(rl, m, n, b, cplx, dot2, with_x):
     """Iteration form of the pass: A W and A^* [A_V A_X A_W] from one read of A."""
     banner(f"astream_iter m={m} n={n} b={b} complex={cplx} dot2={dot2} AX={with_x}")
@@ -158,6 +165,25 @@ def test_astream_iter(rl, m, n, b, cplx, dot2, with_x):
     else:
         assert np.all(G3[1] == 0)
     assert np.all(np.abs(G3[2] - A.conj().T @ AW) <= 2 * m * U * (absA.T @ np.abs(AW)))
+
+
+@pytest.mark.parametrize("n,cplx,dot2,odd_lda", [(1025, False, False, False), (1100, False, True, False),
+                                                (1100, True, False, False), (1100, False, False, True),
+                                                (2050, False, False, False)])
+def test_astream_wide_shapes_no_kernel_takes(rl, n, cplx, dot2, odd_lda):
+    """Past n = 1024 only real, even n <= 2048, plain sums and 16-byte aligned
+    rows have a pass kernel; every other shape is refused before any launch."""
+    banner(f"astream refuses n={n} complex={cplx} dot2={dot2} odd lda={odd_lda}")
+    m, b = 64, 3
+    dt = torch.complex128 if cplx else torch.float64
+    if odd_lda:
+        A = torch.zeros((m, n + 1), dtype=dt, device="cuda")[:, :n]
+    else:
+        A = torch.zeros((m, n), dtype=dt, device="cuda")
+    W = torch.zeros((n, b), dtype=dt, device="cuda")
+    with pytest.raises(rl.RlError) as e:
+        rl.rl_step_astream(A, W, dot2=dot2)
+    assert e.value.code == rl.RL_ERR_UNSUPPORTED
 
 
 def test_astream_misaligned_complex(rl):

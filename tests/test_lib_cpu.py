@@ -78,6 +78,9 @@ def test_host_only_calls():
     assert o.sketch_prec == rl.RL_SKETCH_F64
     assert o.refresh == 1 and o.prec_guard == 1
     assert rl.default_opts(10_000, 200, 3).max_iter == 100
+    # wide real shapes default to the plain-sum pass (the only one past n = 1024)
+    assert rl.default_opts(10_000, 1024, 1).dot2 == 1
+    assert rl.default_opts(100_000, 2000, 1).dot2 == 0
     assert rl.status_string(rl.RL_ERR_ARG) == "invalid argument"
     assert lib.rl_default_opts(None, 1, 1, 1) == rl.RL_ERR_ARG
     # argument errors are caught on the host before any device work

@@ -12,6 +12,7 @@ from .planted import (  # noqa: F401
     config_spec,
     spectrum_gap,
     spectrum_logspace_tail,
+    spectrum_clustered,
     spectrum_nullspace,
     planted_numpy,
     planted_torch,

@@ -13,6 +13,8 @@ Spectra follow the five workload descriptions of the hot path:
   the last 10 zero, plus complex Gaussian noise with E|N_ij|^2 = (1e-14)^2.
 * ``cfg4``  2e6 x 500, k=5: as cfg2 with sigma_min = 1e-10 and a drop of 100
   between sigma_{n-5} and sigma_{n-4}.
+* ``e5``    1e6 x 2000, the block-size study (Sec. 5.2): clustered spectrum
+  sigma_i = exp(-log(1e10) ((i-1)/(n-1))^(1/256)), k = 1, blocks 1, 3, 5, 10.
 * ``cfg5``  the served stream: m ~ U[1e4, 5e5], n ~ U[20, 400], k ~ U{1..10},
   a drop of 10 at sigma_{n-k}, sigma_min = 10^U[-12,-4], Poisson arrivals.
 
@@ -51,6 +53,7 @@ CONFIGS = {
     "cfg2": ConfigSpec("cfg2", 1_000_000, 200, 1, 800, 8, False, 1002, 2002),
     "cfg3": ConfigSpec("cfg3", 1_000_000, 1000, 10, 3000, 8, True, 1003, 2003, 1e-14),
     "cfg4": ConfigSpec("cfg4", 2_000_000, 500, 5, 2000, 8, False, 1004, 2004),
+    "e5": ConfigSpec("e5", 1_000_000, 2000, 1, 8000, 8, False, 1005, 2005),
 }
 
 
@@ -88,6 +91,16 @@ def spectrum_nullspace(n: int, k: int, lo: float) -> np.ndarray:
     return s
 
 
+def spectrum_clustered(n: int, a: float = 1.0 / 256.0, cond: float = 1e10) -> np.ndarray:
+    """sigma_i = exp(-log(cond) ((i-1)/(n-1))^a), i = 1..n (Sec. 5.2): sigma_1 = 1,
+    sigma_n = 1/cond, with the values crowded towards 1/cond for small a (at
+    n = 2000 and a = 1/256, (sigma_{n-1}^2 - sigma_n^2)/sigma_n^2 = 9e-5)."""
+    if n < 2:
+        raise ValueError("spectrum_clustered needs n >= 2")
+    x = np.arange(n, dtype=np.float64) / (n - 1)
+    return np.exp(-math.log(cond) * x ** a)
+
+
 def config_spectrum(name: str) -> np.ndarray:
     c = CONFIGS[name]
     if name == "cfg1":
@@ -98,6 +111,8 @@ def config_spectrum(name: str) -> np.ndarray:
         return spectrum_nullspace(c.n, c.k, 1e-4)
     if name == "cfg4":
         return spectrum_gap(c.n, c.k, 1e-10, 100.0)
+    if name == "e5":
+        return spectrum_clustered(c.n)
     raise KeyError(name)
 
 
