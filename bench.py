@@ -10,7 +10,9 @@ start block, LOBPCG to the stopping rule or max_iter, outputs).  Its pass
 runs the products with A on the FP64 matrix cores with plain sums (see
 the design doc for why the compensated sums are not the default there).  The other
 workloads (--workload) are the real 10^6 x 200 (k = 1), 2*10^6 x 500 (k = 5)
-and 4000 x 50 (k = 1) problems, with compensated (Dot2) products.
+and 4000 x 50 (k = 1) problems, with compensated (Dot2) products, and the
+block-size study's 10^6 x 2000 clustered problem (k = 1, --block 1, 3, 5 or
+10; plain sums on the matrix cores, the only pass past n = 1024).
 
 The JSON line reports solves/s as ``value``; time-to-solution as
 ``ms_per_step``; the dominant kernel against its roofline (the Gram
@@ -41,7 +43,7 @@ FP64_PEAK_TFS = 78.6
 DEFAULT_WORKLOAD = "tall-1e6x1000c-k10"
 # products with A per workload: compensated (Dot2) sums, or plain sums (the
 # complex null-space workload, whose pass then runs on the matrix cores)
-DEFAULT_DOT2 = {"tall-1e6x1000c-k10": False}
+DEFAULT_DOT2 = {"tall-1e6x1000c-k10": False, "clustered-1e6x2000-k1": False}
 
 WORKLOADS = {
     # name: (m, n, k, d, zeta, complex, data seed, sketch seed, spectrum)
@@ -50,6 +52,9 @@ WORKLOADS = {
     "tall-2e6x500-k5": (2_000_000, 500, 5, 2000, 8, False, 1004, 2004, ("gap", 1e-10, 100.0)),
     # complex nullspace: rank n-k plus complex Gaussian noise of std 1e-14
     "tall-1e6x1000c-k10": (1_000_000, 1000, 10, 3000, 8, True, 1003, 2003, ("null", 1e-4, 1e-14)),
+    # the block-size study (Sec. 5.2): clustered spectrum, exponent 1/256, condition 1e10;
+    # real n = 2000 runs plain sums on the matrix cores (the only pass past n = 1024)
+    "clustered-1e6x2000-k1": (1_000_000, 2000, 1, 8000, 8, False, 1005, 2005, ("clustered", 1.0 / 256.0, 1e10)),
 }
 
 
@@ -58,7 +63,9 @@ def log(msg: str) -> None:
 
 
 def spectrum(n, k, spec):
-    from workloads import spectrum_gap, spectrum_logspace_tail, spectrum_nullspace
+    from workloads import spectrum_clustered, spectrum_gap, spectrum_logspace_tail, spectrum_nullspace
+    if spec[0] == "clustered":
+        return spectrum_clustered(n, spec[1], spec[2])
     if spec[0] == "gap":
         return spectrum_gap(n, k, spec[1], spec[2])
     if spec[0] == "null":
@@ -77,6 +84,8 @@ def astream_kernel(cplx: bool, n: int, b: int, dot2: bool = True) -> str:
         if n <= 1024:
             return "k_astream_ccs (A W and A^* [A_V A_X A_W] in one read of A)"
         return "k_astream<cd> (A W and A^* [A_V A_X A_W] in one read of A)"
+    if 1024 < n <= 2048 and n % 2 == 0 and not dot2:
+        return "k_zm_aw + k_zm_g (A W, then A^* [A_V A_X A_W] on the FP64 matrix cores: two reads of A)"
     if n % 2 == 0 and n <= 256 and b <= 2:
         return "k_astream_r2 (A W and A^* [A_V A_X A_W] in one read of A)"
     if n <= 1024 and b <= 10:
@@ -256,6 +265,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
+    ap.add_argument("--block", type=int, default=0, help="block size b >= k (default k)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sketch-prec", default="f64", choices=["f64", "f32", "bf16"],
                     help="precision of the sketch and its QR (the rest stays FP64)")
@@ -310,6 +320,8 @@ def main(argv=None):
     es = 16 if cplx else 8
     kw = dict(seed=sseed, d=d, zeta=zeta, sketch_prec=args.sketch_prec, dot2=dot2,
               loop_precond=args.loop_precond, orth=args.orth)
+    if args.block:
+        kw["block"] = args.block
 
     for w in range(args.warmup):
         r = rl.rl_svds_smallest(A, k, **kw)
@@ -339,6 +351,13 @@ def main(argv=None):
     sig_tol = 1e-12 * sig[0] if not noise else 10.0 * noise * math.sqrt(m)
     gates = {"resid_max": res, "resid_gate": 1e-12 * float(sig[0]), "sigma_err_vs_planted": sig_err,
              "sigma_gate": sig_tol, "passed": bool(res <= 1e-12 * sig[0] and sig_err <= sig_tol)}
+    if not noise:
+        # the angle to the planted right singular vectors of the k smallest values
+        with torch.no_grad():
+            order = torch.from_numpy(np.argsort(sig)[:k].copy()).to(Vp.device)
+            P = Vp[:, order]
+            Qa, _ = torch.linalg.qr(last.V)
+            gates["sin_angle_vs_planted"] = torch.linalg.matrix_norm(P - Qa @ (Qa.conj().T @ P), ord=2).item()
     log(f"gates: {gates}")
     if args.vs_fp64:
         ref = rl.rl_svds_smallest(A, k, seed=sseed, d=d, zeta=zeta)
@@ -379,7 +398,7 @@ def main(argv=None):
     n_g = sum(r.n_pass_g for r in results)
     traffic = (measured_traffic(args.workload)
                if (args.sketch_prec == "f64" and dot2 == DEFAULT_DOT2.get(args.workload, True)
-                   and args.loop_precond == "sketch" and args.orth == "cgs2") else None)
+                   and args.loop_precond == "sketch" and args.orth == "cgs2" and not args.block) else None)
     if n_g > 0:
         # the dominant kernel is the Gram contraction A^* [A_V A_X A_W] on the
         # matrix cores: 8 m n b flops per block with data (A_V and A_W on the
@@ -388,12 +407,23 @@ def main(argv=None):
         g_us = t_g / n_g
         g_flops = sum(cflop * m * n * bb * (2 + 3 * (r.n_pass_g - 1)) for r in results if r.n_pass_g > 0)
         g_flops_launch = g_flops / n_g
-        achieved = g_flops_launch / (g_us * 1e-6) / 1e12
-        roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-                    "frac": round(achieved / FP64_PEAK_TFS, 4), "traffic": traffic,
-                    "kernel": "k_zm_g (A^* [A_V A_X A_W] on the FP64 matrix cores)", "avg_launch_us": round(g_us, 2),
-                    "launches": n_g, "algorithmic_flops_per_launch": round(g_flops_launch),
-                    "pass": astream_kernel(cplx, n, bb, dot2), "pass_roofline": pass_line}
+        # its bytes: A once and the blocks with data (A_V and A_W, then A_X too)
+        g_bytes = sum(r.n_pass_g * m * n * es + m * bb * es * (2 + 3 * (r.n_pass_g - 1))
+                      for r in results if r.n_pass_g > 0)
+        g_bytes_launch = g_bytes / n_g
+        common = {"kernel": "k_zm_g (A^* [A_V A_X A_W] on the FP64 matrix cores)", "avg_launch_us": round(g_us, 2),
+                  "launches": n_g, "algorithmic_flops_per_launch": round(g_flops_launch),
+                  "algorithmic_bytes_per_launch": round(g_bytes_launch),
+                  "pass": astream_kernel(cplx, n, bb, dot2), "pass_roofline": pass_line}
+        # the bound is whichever of the flops and the bytes takes longer at peak
+        if g_flops_launch / (FP64_PEAK_TFS * 1e12) >= g_bytes_launch / (HBM_PEAK_GBS * 1e9):
+            achieved = g_flops_launch / (g_us * 1e-6) / 1e12
+            roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                        "frac": round(achieved / FP64_PEAK_TFS, 4), "traffic": traffic, **common}
+        else:
+            achieved = g_bytes_launch / (g_us * 1e-6) / 1e9
+            roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, **common}
     else:
         achieved = bytes_launch / (avg_us * 1e-6) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -434,12 +464,13 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "c128" if cplx else "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "m": m, "n": n, "k": k, "d": d, "zeta": zeta,
+        "config": {"workload": args.workload, "m": m, "n": n, "k": k, "block": last.block, "d": d, "zeta": zeta,
                    "spectrum": list(spec), "stop_rule": "paper", "dot2": dot2,
                    "sketch_prec": args.sketch_prec, "loop_precond": args.loop_precond, "orth": args.orth},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "detail": {"iters": last.iters, "a_passes": last.a_passes, "status": last.status,
+        "detail": {"iters": last.iters, "a_passes": last.a_passes, "matvecs": last.a_passes * last.block,
+                   "status": last.status,
                    "t_setup_ms": round(last.t_setup_us / 1e3, 4), "t_loop_ms": round(last.t_iter_us / 1e3, 4),
                    "t_final_ms": round(last.t_final_us / 1e3, 4),
                    "a_stream_gbs_whole_solve": round(last.bytes_a / (ms_per_step * 1e-3) / 1e9, 1),
