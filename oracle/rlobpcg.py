@@ -55,6 +55,16 @@ Readings where the paper is silent:
   * ``orth="svqb"`` replaces Orth(W) after the two block projections by
     SVQB (Gram matrix, eigendecomposition), the faster, less stable option
     the paper names for this step.
+  * ``lock=True`` (Sec. 2.3, the locking paragraph; soft locking): once column
+    j of V meets eq:est_conv_criterion on its own (||R(:, j)|| <=
+    Sigma~(1,1)^2 tau) it is locked for good.  A locked column stays in V and
+    in every Rayleigh-Ritz step, but gets no search direction: W = P P^* R
+    over the active columns only, and the next X is built from the active
+    columns of the old V only, X = T C(:, 1:t-b) Orth(C(act, 1:t-b)^*) (the
+    part of span{V_i(:, act)} outside the new V; with every column active
+    this is eq:x-defining).  So t = b + a_X + a_W, and both added blocks are
+    orthogonal to every column of V, the locked ones included.  The loop also
+    ends (status 0) once every column is locked.
   * ``dot2=True`` computes every product with A (A V_0, A W, the refresh) and
     the residual's A^* A_V as Dot2-class sums (``oracle.eft``); without it the
     FP64 rounding floor of those products, not the iteration, limits the
@@ -93,6 +103,7 @@ class RLResult:
     zero_theta: bool = False
     V_block: np.ndarray | None = None     # final block V (n x b), paper order
     theta_block: np.ndarray | None = None
+    lock_hist: list = field(default_factory=list)    # active mask after each iterate (lock=True)
 
 
 def _ct(M: np.ndarray) -> np.ndarray:
@@ -210,14 +221,24 @@ def search_block(R: np.ndarray, apply_prec, basis: np.ndarray, orth_fn):
     return orth_fn(W - basis @ (_ct(basis) @ W))
 
 
-def previous_direction(T: np.ndarray, AT: np.ndarray, C: np.ndarray, b: int):
+def previous_direction(T: np.ndarray, AT: np.ndarray, C: np.ndarray, b: int, act=None):
     """eq:x-defining: X spans the components of the non-selected Ritz vectors
     along the old V, i.e. X = T C(:, 1:t-b) Q with Q = Orth(C(1:b, 1:t-b)^*),
-    and A X = A_T C(:, 1:t-b) Q.  Returns X, A X and Orth's degenerate flag."""
+    and A X = A_T C(:, 1:t-b) Q.  With a lock mask ``act`` only the active
+    columns of the old V contribute: Q = Orth(C(act, 1:t-b)^*), one column
+    of X per active index.  Returns X, A X and Orth's degenerate flag."""
     t = T.shape[1]
-    Q, flag = _orth(_ct(C[:b, :t - b]))
+    rows = np.arange(b) if act is None else np.flatnonzero(act)
+    Q, flag = _orth(_ct(C[rows, :t - b]))
     CX = C[:, :t - b] @ Q
     return T @ CX, AT @ CX, flag
+
+
+def lock_update(act: np.ndarray, R: np.ndarray, sigma1: float, tau: float) -> np.ndarray:
+    """Sec. 2.3 (locking): column j stays active until its residual meets
+    eq:est_conv_criterion, ||R(:, j)|| <= Sigma~(1,1)^2 tau; a locked column
+    never becomes active again."""
+    return act & ~(np.linalg.norm(R, axis=0) <= sigma1 * sigma1 * tau)
 
 
 def residual(AV: np.ndarray, V: np.ndarray, theta: np.ndarray, mulAh) -> np.ndarray:
@@ -239,7 +260,8 @@ def rlobpcg(A, k: int, *, block: int | None = None, d: int | None = None,
             zeta: int = 8, seed: int = 0, tau: float | None = None,
             max_iter: int | None = None, rule: str = "paper", check_every: int = 5,
             precond: str = "svd", dot2: bool = True, refresh: bool = True,
-            loop_precond: str = "sketch", orth: str = "cgs2", callback=None) -> RLResult:
+            loop_precond: str = "sketch", orth: str = "cgs2", lock: bool = False,
+            callback=None) -> RLResult:
     """Return the k smallest singular triplets of the tall matrix A."""
     A = np.asarray(A)
     if A.ndim != 2:
@@ -288,10 +310,18 @@ def rlobpcg(A, k: int, *, block: int | None = None, d: int | None = None,
     degenerate = False
     status = 1
     iters = 0
+    # the lock mask (every column active without locking)
+    act = np.ones(b, dtype=bool)
+    if lock:
+        act = lock_update(act, R, sk.sigma1, tau)
+    lock_hist = [act.copy()]
 
     # LOBPCG on A^* A, preconditioned by P P^*, until the stopping rule holds.
     while iters < max_iter:
-        W, flag = search_block(R, apply_prec, np.hstack([V, X]), orth_fn)
+        if lock and not act.any():
+            status = 0                                        # every column is locked
+            break
+        W, flag = search_block(R[:, act] if lock else R, apply_prec, np.hstack([V, X]), orth_fn)
         degenerate |= flag
         T = np.hstack([V, X, W])
         AT = np.hstack([AV, AX, mulA(W)])
@@ -305,13 +335,19 @@ def rlobpcg(A, k: int, *, block: int | None = None, d: int | None = None,
         theta_hist.append(theta.copy())
         rnorm_hist.append(np.linalg.norm(R, axis=0))
         if callback is not None:
-            callback(i=iters, T=T, AT=AT, C=C, Theta=Th, V=V, AV=AV, R=R, W=W)
+            callback(i=iters, T=T, AT=AT, C=C, Theta=Th, V=V, AV=AV, R=R, W=W, X=X, act=act.copy())
         iters += 1
         if termination.should_stop(iters - 1, theta_hist, rnorm_hist, sk.sigma1, tau,
                                    rule=rule, check_every=check_every):
             status = 0
             break
-        X, AX, flag = previous_direction(T, AT, C, b)
+        if lock:
+            act = lock_update(act, R, sk.sigma1, tau)
+            lock_hist.append(act.copy())
+            if not act.any():
+                status = 0                                    # every column is locked
+                break
+        X, AX, flag = previous_direction(T, AT, C, b, act if lock else None)
         degenerate |= flag
 
     V_block, theta_block = V.copy(), theta.copy()
@@ -328,4 +364,4 @@ def rlobpcg(A, k: int, *, block: int | None = None, d: int | None = None,
     return RLResult(sigma=sig, V=V[:, order], U=U.astype(dt), iters=iters, status=status,
                     sigma1=sk.sigma1, theta_hist=theta_hist, rnorm_hist=rnorm_hist,
                     degenerate=degenerate, zero_theta=zero_theta,
-                    V_block=V_block, theta_block=theta_block)
+                    V_block=V_block, theta_block=theta_block, lock_hist=lock_hist)

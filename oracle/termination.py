@@ -18,6 +18,10 @@ Rules
   "tol"    the tolerance alone, every iteration (the block algorithm as typeset).
   "none"   never stop early (run max_iter iterations).
 
+With locking (Sec. 2.3, ``rlobpcg(lock=True)``) a column whose residual meets
+the tolerance on its own is locked for good, and the loop also ends once
+every column is locked (``first_stop_locked``).
+
 Readings where the paper is silent or inconsistent:
   * The algorithm divides by theta_i in stag2 while eq:stagnation-check divides
     by the newest value; the equation is followed (theta_{i+1}).
@@ -86,5 +90,31 @@ def first_stop(theta, rnorm, sigma1: float, tau: float, *, rule: str = "paper",
     last = len(theta) - 2 if max_iter is None else min(len(theta) - 2, max_iter - 1)
     for i in range(0, last + 1):
         if should_stop(i, theta, rnorm, sigma1, tau, rule=rule, check_every=check_every):
+            return i
+    return None
+
+
+def locked_mask(act, rn, sigma1: float, tau: float):
+    """The lock update of Sec. 2.3: column j stays active while ||r(:, j)|| >
+    Sigma~(1,1)^2 tau; a locked column stays locked."""
+    return np.asarray(act, dtype=bool) & ~(np.asarray(rn, dtype=np.float64) <= sigma1 * sigma1 * tau)
+
+
+def first_stop_locked(theta, rnorm, sigma1: float, tau: float, *, rule: str = "paper",
+                      check_every: int = 5, max_iter: int | None = None):
+    """Where a solve with locking ends on the given histories: -1 if every
+    column is locked by the start block's residual, else the first loop index
+    at which the rule fires or, after the rule's check, the last active column
+    locks; None if neither happens."""
+    b = len(rnorm[0])
+    act = locked_mask(np.ones(b, dtype=bool), rnorm[0], sigma1, tau)
+    if not act.any():
+        return -1
+    last = len(theta) - 2 if max_iter is None else min(len(theta) - 2, max_iter - 1)
+    for i in range(0, last + 1):
+        if should_stop(i, theta, rnorm, sigma1, tau, rule=rule, check_every=check_every):
+            return i
+        act = locked_mask(act, rnorm[i + 1], sigma1, tau)
+        if not act.any():
             return i
     return None

@@ -375,3 +375,111 @@ def test_refresh_recomputes_the_product_and_rotates():
     # the rotation diagonalises A^* A on the block: V-hat^* A^* A V-hat = Sigma^2
     G = (A @ r.V).conj().T @ (A @ r.V)
     assert np.linalg.norm(G - np.diag(r.sigma ** 2)) <= 1e-12 * sv[0] ** 2
+
+
+# ---------------------------------------------------------------- locking (Sec. 2.3)
+
+def _davis_kahan(A, V, sig, sv, k):
+    """Davis-Kahan sin-theta bound for span(V) against the k smallest right
+    singular vectors of A: sqrt(k) max_j ||A^* A v_j - sigma_j^2 v_j|| /
+    (sigma_{n-k}^2 - max_j sigma_j^2), the residual recomputed here from
+    the returned triplets with compensated products (their error, about
+    u ||A|| ||A v|| + u sigma^2, is covered by the allowance added)."""
+    from oracle import eft
+    AV = eft.matmul(A, V)
+    R = eft.matmul_h(A, AV) - V * (sig * sig)[None, :]
+    res = float(np.linalg.norm(R, axis=0).max()) + 8 * U * (sv[0] * float(np.linalg.norm(AV))
+                                                             + float(np.max(sig)) ** 2)
+    gap = sv[-k - 1] ** 2 - float(np.max(sig)) ** 2
+    return math.sqrt(k) * res / gap
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_lock_solve_matches_dense_svd(cplx):
+    """Locked solve: sigma to 1e-12 ||A|| of the dense SVD, residual gate, and
+    the subspace inside the Davis-Kahan bound its own residual gives; the
+    columns lock at different iterations and the solve ends when the last
+    one does."""
+    m, n, k = 3000, 60, 3
+    A, _, s = planted_numpy(m, n, spectrum_logspace_tail(n, 1e-3, 1e-6), 13, is_complex=cplx)
+    sv, Vd = _dense(A)
+    r = rlobpcg(A, k, seed=3, lock=True)
+    counts = [int(a.sum()) for a in r.lock_hist]
+    assert r.status == 0 and counts[-1] == 0
+    assert len(set(counts)) > 2                          # staggered locks
+    assert np.max(np.abs(r.sigma - np.sort(sv)[:k])) <= 1e-12 * sv[0]
+    assert np.linalg.norm(A @ r.V - r.U * r.sigma[None, :], axis=0).max() <= 1e-12 * sv[0]
+    bound = _davis_kahan(A, r.V, r.sigma, sv, k)
+    assert bound < 1e-6
+    assert _sin_angle(r.V, Vd[:, -k:]) <= bound
+
+
+def test_lock_search_blocks_are_orthogonal_to_every_column_of_v():
+    """Every step's trial basis [V X W] is orthonormal, so X and W are
+    orthogonal to all of V, the locked columns included (the property the
+    paper gives locking); W has one column per active index and X one per
+    active index of the previous step."""
+    m, n, k = 3000, 60, 3
+    A, _, _ = planted_numpy(m, n, spectrum_logspace_tail(n, 1e-3, 1e-6), 13)
+    log = []
+
+    def cb(**kw):
+        log.append((kw["T"].copy(), kw["W"].shape[1], kw["X"].shape[1], kw["act"].copy()))
+
+    r = rlobpcg(A, k, seed=3, lock=True, callback=cb)
+    saw_locked = False
+    for i, (T, nw, nx, act) in enumerate(log):
+        b = k
+        assert nw == int(act.sum())
+        assert nx in (0, nw)
+        assert T.shape[1] == b + nx + nw
+        assert np.linalg.norm(T.conj().T @ T - np.eye(T.shape[1])) <= 1e-12
+        if not act.all():
+            saw_locked = True
+            locked = T[:, :b][:, ~act]
+            assert np.abs(locked.conj().T @ T[:, b:]).max() <= 1e-13
+    assert saw_locked and len(log) == r.iters
+
+
+def test_lock_decisions_follow_the_criterion():
+    """The lock mask only shrinks, a column locks exactly when its residual
+    first meets Sigma~(1,1)^2 tau, and the stop is where the last one locks
+    (re-derived from the histories alone)."""
+    from oracle import termination
+    m, n, k = 3000, 60, 3
+    A, _, _ = planted_numpy(m, n, spectrum_logspace_tail(n, 1e-3, 1e-6), 13)
+    r = rlobpcg(A, k, seed=3, lock=True)
+    thr = r.sigma1 ** 2 * default_tau(n)
+    act = np.ones(k, dtype=bool)
+    for j, (mask, rn) in enumerate(zip(r.lock_hist, r.rnorm_hist)):
+        want = act & ~(np.asarray(rn) <= thr)
+        assert mask.tolist() == want.tolist()
+        act = want
+    assert termination.first_stop_locked(r.theta_hist, r.rnorm_hist, r.sigma1, default_tau(n)) == r.iters - 1
+
+
+def test_lock_without_converged_columns_is_the_plain_iteration():
+    """With a tolerance no column can meet, locking changes nothing: the
+    same bits as the solve without it."""
+    m, n, k = 2000, 45, 3
+    A, _, _ = planted_numpy(m, n, spectrum_gap(n, k, 1e-6, 10.0), 21)
+    a = rlobpcg(A, k, seed=4, lock=False, rule="none", max_iter=15, tau=1e-40)
+    b = rlobpcg(A, k, seed=4, lock=True, rule="none", max_iter=15, tau=1e-40)
+    assert np.array_equal(a.sigma, b.sigma) and np.array_equal(a.V, b.V) and np.array_equal(a.U, b.U)
+    assert np.array_equal(np.array(a.theta_hist), np.array(b.theta_hist))
+    assert all(h.all() for h in b.lock_hist)
+
+
+def test_lock_uses_fewer_search_columns_at_equal_sigma():
+    """Locked columns get no search direction: fewer columns of W in all
+    (fewer products with A) for the same sigma to 1e-12 ||A||."""
+    m, n, k = 3000, 60, 3
+    A, _, s = planted_numpy(m, n, spectrum_logspace_tail(n, 1e-3, 1e-6), 13)
+    cols = {}
+    res = {}
+    for lock in (False, True):
+        w = []
+        res[lock] = rlobpcg(A, k, seed=3, lock=lock, callback=lambda **kw: w.append(kw["W"].shape[1]))
+        cols[lock] = sum(w)
+    assert cols[True] < cols[False]
+    assert np.max(np.abs(res[True].sigma - res[False].sigma)) <= 1e-12 * s[0]

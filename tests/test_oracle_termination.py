@@ -71,3 +71,25 @@ def test_equation_denominator_is_newest_theta():
     theta = [np.array([math.inf])] + [np.array([vals.get(j, 5.0)]) for j in range(1, 12)]
     rnorm = [np.array([1e-30])] * 12
     assert term.should_stop(10, theta, rnorm, 1.0, 1e-15)
+
+
+def test_locked_stop_on_hand_built_histories():
+    """Locking: columns lock one by one as their residual meets sigma1^2 tau;
+    the solve ends at the loop index whose new residuals lock the last one,
+    unless the rule fires first; all locked at the start gives -1."""
+    thr = 1e-3
+    theta = [[1.0, 2.0]] * 8
+    rn = [[1.0, 1.0], [1e-4, 1.0], [1.0, 1.0], [1.0, 1e-4], [1.0, 1.0], [1.0, 1.0], [1.0, 1.0], [1.0, 1.0]]
+    # column 0 locks at iterate 1 (loop index 0) and stays locked although its
+    # residual grows again; column 1 locks at iterate 3 (loop index 2)
+    assert term.first_stop_locked(theta, rn, 1.0, thr, rule="none") == 2
+    assert term.first_stop(theta, rn, 1.0, thr, rule="none") is None
+    # Sigma~(1,1)^2 scales the threshold: with sigma1 = 0.001 nothing locks
+    assert term.first_stop_locked(theta, rn, 1e-3, thr, rule="none") is None
+    # every column below the threshold at the start
+    assert term.first_stop_locked(theta, [[1e-4, 1e-5]] + rn[1:], 1.0, thr, rule="none") == -1
+    # the tol rule fires at loop index 0 only when both columns meet it at once
+    rn2 = [[1.0, 1.0], [1e-4, 1e-4]] + rn[2:]
+    assert term.first_stop_locked(theta, rn2, 1.0, thr, rule="tol") == 0
+    m = term.locked_mask([True, True, False], [1e-4, 1.0, 1.0], 1.0, thr)
+    assert m.tolist() == [False, True, False]
