@@ -103,6 +103,11 @@ typedef struct {
                          ||R||_2 ||R^{-1}||_2 from the Lanczos estimate and the start block and, when
                          kappa u_low sqrt(n) > 0.1 (u_low = 2^-24 for FP32, 2^-8 for bfloat16), redo
                          the sketch and QR in FP64 before the start pass (rl_info.sketch_prec_used) */
+  int32_t lock;       /* 1: locking of converged columns (Sec. 2.3): once column j's residual meets
+                         ||r_j|| <= Sigma~(1,1)^2 tau it is locked for good; it stays in V and in every
+                         Rayleigh-Ritz step but gets no search direction (its columns of W and X are
+                         zero), and the loop ends once every column is locked.  Default 0; not with
+                         RL_ORTH_SVQB (RL_ERR_UNSUPPORTED) */
 } rl_opts;
 
 /* Per-solve report (host).  theta_hist / rnorm_hist are optional host arrays
@@ -129,6 +134,8 @@ typedef struct {
   int32_t sketch_prec_used; /* RL_SKETCH_* of the R the loop used (RL_SKETCH_F64 after a guard fallback) */
   double t_pass_g_us;  /* summed duration of their second kernel (opts.profile) */
   double kappa_est;    /* the guard's estimate of kappa(R) for a reduced-precision sketch, else 0 */
+  int32_t n_locked;    /* columns locked when the loop ended (opts.lock), else 0 */
+  int32_t act_mask;    /* bit j set: column j of the block still active at the end (all b bits without lock) */
 } rl_info;
 
 /* Handle: one per (device, stream).  stream may be NULL (the null stream). */

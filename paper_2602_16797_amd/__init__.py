@@ -67,6 +67,7 @@ class RlOpts(ctypes.Structure):
         ("orth", ctypes.c_int32),
         ("refresh", ctypes.c_int32),
         ("prec_guard", ctypes.c_int32),
+        ("lock", ctypes.c_int32),
     ]
 
 
@@ -92,6 +93,8 @@ class RlInfo(ctypes.Structure):
         ("sketch_prec_used", ctypes.c_int32),
         ("t_pass_g_us", ctypes.c_double),
         ("kappa_est", ctypes.c_double),
+        ("n_locked", ctypes.c_int32),
+        ("act_mask", ctypes.c_int32),
     ]
 
 
@@ -271,6 +274,8 @@ class SolveResult:
     t_pass_g_us: float = 0.0
     sketch_prec_used: int = 0
     kappa_est: float = 0.0
+    n_locked: int = 0
+    act_mask: int = 0
     block: int = 0
     theta_hist: np.ndarray = field(default=None)
     rnorm_hist: np.ndarray = field(default=None)
@@ -279,7 +284,7 @@ class SolveResult:
 def make_opts(m: int, n: int, k: int, *, block=None, d=None, zeta=None, seed=0, tau=None, max_iter=None,
               check_every=None, rule="paper", dot2=None, init_iters=None, lanczos_steps=None,
               profile=False, sketch_prec="f64", loop_precond="sketch", orth="cgs2", refresh=None,
-              prec_guard=None) -> RlOpts:
+              prec_guard=None, lock=None) -> RlOpts:
     o = default_opts(m, n, k if block is None else block)
     o.block = k if block is None else block
     if block is not None:
@@ -310,6 +315,8 @@ def make_opts(m: int, n: int, k: int, *, block=None, d=None, zeta=None, seed=0, 
         o.refresh = int(bool(refresh))
     if prec_guard is not None:
         o.prec_guard = int(bool(prec_guard))
+    if lock is not None:
+        o.lock = int(bool(lock))
     return o
 
 
@@ -344,7 +351,8 @@ def rl_svds_smallest(A, k: int, *, want_u: bool = True, history: bool = True, **
                        t_setup_us=info.t_setup_us, t_iter_us=info.t_iter_us, t_final_us=info.t_final_us,
                        bytes_a=info.bytes_a, n_astream=info.n_astream, t_astream_us=info.t_astream_us,
                        n_pass_g=info.n_pass_g, t_pass_g_us=info.t_pass_g_us,
-                       sketch_prec_used=info.sketch_prec_used, kappa_est=info.kappa_est, block=info.block, theta_hist=th[: it + 1].copy() if history else None,
+                       sketch_prec_used=info.sketch_prec_used, kappa_est=info.kappa_est,
+                       n_locked=info.n_locked, act_mask=info.act_mask, block=info.block, theta_hist=th[: it + 1].copy() if history else None,
                        rnorm_hist=rn[: it + 1].copy() if history else None)
 
 

@@ -232,7 +232,9 @@ struct Ctl {
   int32_t b;           // block size
   int32_t rr_mode;     // trial basis of the last Rayleigh-Ritz: 0 [V], 1 [V W], 2 [V X W]
   int32_t x_update;    // the last Rayleigh-Ritz produced C_X (X is updated)
-  int32_t pad0[3];
+  int32_t lock;        // locking of converged columns is on
+  int32_t act;         // bit j set: column j of the block is active (not locked)
+  int32_t pad0[1];
   double sigma1;       // Sigma~(1,1) estimate (largest singular value of R)
   double tau;          // tolerance
   double rinv_norm;     // max_j ||R^{-*} V_0(:, j)||, about 1/sigma_min(R) (reduced-precision guard)

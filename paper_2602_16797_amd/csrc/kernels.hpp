@@ -124,8 +124,10 @@ hipError_t launch_trmv(hipStream_t st, bool cplx, int B, const void* M, int n, i
                        const Ctl* ctl, int check_done);
 hipError_t launch_orth_svqb(hipStream_t st, bool cplx, int n, int B, const void* V, const void* X, int project,
                             int with_x, void* W, Ctl* ctl, int check_done);
+// masked = 1: with locking on (ctl->lock), the locked columns of W are set
+// to zero instead of orthonormalised
 hipError_t launch_orth(hipStream_t st, bool cplx, int n, int B, const void* V, const void* X, int project, int with_x,
-                       void* W, Ctl* ctl, int check_done);
+                       void* W, Ctl* ctl, int check_done, int masked = 0);
 hipError_t launch_rr(hipStream_t st, bool cplx, int n, int B, int init_mode, int with_x, const void* Rt, void* V,
                      void* X, const void* W, const void* G3, void* Vn, void* Rres, void* CV, void* CX, double* thb,
                      double* ht, double* hr, Ctl* ctl);

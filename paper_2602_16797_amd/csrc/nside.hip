@@ -140,15 +140,22 @@ __device__ double col_norm(int n, int B, int j, const T* __restrict__ W, double*
   return sqrt(block_sum(s, red));
 }
 
-// KM bounds the number of projections of one column, 3B - 1.
+// KM bounds the number of projections of one column, 3B - 1.  Bit j of
+// `keep` clear: column j is a locked index's and is set to zero (a zero
+// column costs the later projections nothing).
 template <typename T, int KM>
 __device__ void orth_block(int n, int B, const T* __restrict__ V, const T* __restrict__ X, int project, int with_x,
-                           T* __restrict__ W, Ctl* __restrict__ ctl) {
+                           T* __restrict__ W, Ctl* __restrict__ ctl, int keep = -1) {
   __shared__ T scratch[(NS_THREADS / 16) * OrthKC<KM>::value];
   __shared__ T h[KM];
   __shared__ double red[NS_THREADS / 64];
   const int nvx = project ? (with_x ? 2 * B : B) : 0;
   for (int j = 0; j < B; ++j) {
+    if (!((keep >> j) & 1)) {
+      for (int r = threadIdx.x; r < n; r += blockDim.x) W[(int64_t)r * B + j] = zero<T>();
+      __syncthreads();
+      continue;
+    }
     double nrm = 0.0;
     for (int cand = -1; cand < n; ++cand) {
       if (cand >= 0) {
@@ -180,9 +187,9 @@ __device__ void orth_block(int n, int B, const T* __restrict__ V, const T* __res
 template <typename T, int KM>
 __global__ __launch_bounds__(NS_THREADS) void k_orth(int n, int B, const T* __restrict__ V, const T* __restrict__ X,
                                                      int project, int with_x, T* __restrict__ W, Ctl* __restrict__ ctl,
-                                                     int check_done) {
+                                                     int check_done, int masked) {
   if (check_done && ctl->done) return;
-  orth_block<T, KM>(n, B, V, X, project, with_x, W, ctl);
+  orth_block<T, KM>(n, B, V, X, project, with_x, W, ctl, (masked && ctl->lock) ? ctl->act : -1);
 }
 
 template <typename T>
@@ -392,10 +399,19 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
   __shared__ T scratch[(NS_THREADS / 16) * RR_BMAX];
   __shared__ T hsum[RR_BMAX];
   __shared__ int stop_s;
+  __shared__ int newact_s;
+  __shared__ int padsorted[RR_TMAX];  // sorted column c is a locked index's zero column
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int mode = init_mode ? 0 : (with_x ? 2 : 1);
   const int t = (mode == 0) ? B : (mode == 1 ? 2 * B : 3 * B);
   const int iter = ctl->iter;
+  // Locking (Sec. 2.3): the X and W columns of locked indices are zero, so
+  // their columns of R_T are zero, the Jacobi sweeps never rotate them and
+  // they come out as unit singular vectors of value 0.  They rank above every
+  // real Ritz value here, so they are never selected and never enter X.
+  const int lockon = ctl->lock;
+  const int act0 = lockon ? ctl->act : (1 << B) - 1;
+  auto padded = [&](int c) { return lockon && c >= B && !((act0 >> ((c - B) % B)) & 1); };
   for (int e = tid; e < RR_TMAX * 32; e += blockDim.x) {
     const int c = e / 32, r = e % 32;
     M[e] = (r < t && c < t) ? Rt[r * t + c] : zero<T>();
@@ -415,10 +431,17 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
       for (int c = 0; c < t; ++c) used[c] = 0;
       for (int c = 0; c < t; ++c) {
         int best = -1;
-        for (int q = 0; q < t; ++q)
-          if (!used[q] && (best < 0 || sig[q] > sig[best])) best = q;
+        double kb = 0.0;
+        for (int q = 0; q < t; ++q) {
+          const double kq = padded(q) ? INFINITY : sig[q];
+          if (!used[q] && (best < 0 || kq > kb)) {
+            best = q;
+            kb = kq;
+          }
+        }
         used[best] = 1;
         th[c] = sig[best];
+        padsorted[c] = padded(best) ? 1 : 0;
         for (int r = 0; r < t; ++r) C[c * 32 + r] = Vj[best * 32 + r];
       }
     }
@@ -502,23 +525,38 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
     }
     __threadfence_block();
     stop_s = init_mode ? 0 : (dev_should_stop(iter, hist_theta, hist_rnorm, B, ctl) ? 1 : 0);
+    // the lock update: a column whose residual meets Sigma~(1,1)^2 tau is
+    // locked for good (after the rule's check, as the oracle orders them)
+    int na = act0;
+    if (lockon && !stop_s) {
+      const double thr = ctl->sigma1 * ctl->sigma1 * ctl->tau;
+      for (int j = 0; j < B; ++j)
+        if (rn[j] <= thr) na &= ~(1 << j);
+    }
+    newact_s = na;
   }
   __syncthreads();
-  const bool xupd = !init_mode && !stop_s;
+  const int newact = newact_s;
+  const bool all_locked = lockon && newact == 0;
+  const bool xupd = !init_mode && !stop_s && !all_locked;
   if (xupd && wid == 0) {
     // Q = Orth(C(1:B, 1:t-B)^*), (t-B) x B, by modified Gram-Schmidt applied
     // twice, row a of Q held by lane a.  A column that vanishes (at full
     // convergence C(1:B, 1:t-B) can be exactly 0) is completed, as Householder
     // QR would, by the first unit vector that keeps norm above 1/2 after
     // projection on the earlier ones.
+    // With locking only the active rows of C enter (X gets one column per
+    // active index; the others are zero).
     const int tb = t - B;
     const int a = lane;
     const bool own = a < tb;
     for (int j = 0; j < B; ++j)
-      if (own) Qm[a * B + j] = conj_(C[a * 32 + j]);
+      if (own) Qm[a * B + j] = ((newact >> j) & 1) ? conj_(C[a * 32 + j]) : zero<T>();
     for (int j = 0; j < B; ++j) {
+      if (!((newact >> j) & 1)) continue;
       double nrm = 0.0;
       for (int cand = -1; cand < tb; ++cand) {
+        if (cand >= 0 && padsorted[cand]) continue;  // a zero column of T
         if (cand >= 0 && own) Qm[a * B + j] = from_real<T>(a == cand ? 1.0 : 0.0);
         for (int pass = 0; pass < 2; ++pass) {
           for (int q = 0; q < j; ++q) {
@@ -589,15 +627,19 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
   if (tid == 0) {
     ctl->rr_mode = mode;
     ctl->x_update = xupd ? 1 : 0;
+    if (lockon) ctl->act = newact;
     if (!init_mode) {
       ctl->iter = iter + 1;
-      if (stop_s) {
+      if (stop_s || all_locked) {
         ctl->done = 1;
         ctl->status = 0;
       } else {
         ctl->has_x = 1;
         if (iter + 1 >= ctl->max_iter) ctl->status = 1;
       }
+    } else if (all_locked) {  // every column met the tolerance at the start
+      ctl->done = 1;
+      ctl->status = 0;
     }
   }
 }
@@ -938,20 +980,20 @@ hipError_t launch_trmv(hipStream_t st, bool cplx, int B, const void* M, int n, i
 
 template <typename T, int KM>
 static void orth_go(hipStream_t st, int n, int B, const void* V, const void* X, int project, int with_x, void* W,
-                    Ctl* ctl, int check_done) {
+                    Ctl* ctl, int check_done, int masked) {
   hipLaunchKernelGGL((k_orth<T, KM>), dim3(1), dim3(NS_THREADS), 0, st, n, B, (const T*)V, (const T*)X, project,
-                     with_x, (T*)W, ctl, check_done);
+                     with_x, (T*)W, ctl, check_done, masked);
 }
 
 template <typename T>
 static void orth_dispatch(hipStream_t st, int n, int B, const void* V, const void* X, int project, int with_x,
-                          void* W, Ctl* ctl, int check_done) {
+                          void* W, Ctl* ctl, int check_done, int masked) {
   const int need = 3 * B;
-  if (need <= 4) orth_go<T, 4>(st, n, B, V, X, project, with_x, W, ctl, check_done);
-  else if (need <= 8) orth_go<T, 8>(st, n, B, V, X, project, with_x, W, ctl, check_done);
-  else if (need <= 16) orth_go<T, 16>(st, n, B, V, X, project, with_x, W, ctl, check_done);
-  else if (need <= 32) orth_go<T, 32>(st, n, B, V, X, project, with_x, W, ctl, check_done);
-  else orth_go<T, 3 * RR_BMAX>(st, n, B, V, X, project, with_x, W, ctl, check_done);
+  if (need <= 4) orth_go<T, 4>(st, n, B, V, X, project, with_x, W, ctl, check_done, masked);
+  else if (need <= 8) orth_go<T, 8>(st, n, B, V, X, project, with_x, W, ctl, check_done, masked);
+  else if (need <= 16) orth_go<T, 16>(st, n, B, V, X, project, with_x, W, ctl, check_done, masked);
+  else if (need <= 32) orth_go<T, 32>(st, n, B, V, X, project, with_x, W, ctl, check_done, masked);
+  else orth_go<T, 3 * RR_BMAX>(st, n, B, V, X, project, with_x, W, ctl, check_done, masked);
 }
 
 template <typename T, int KM>
@@ -981,10 +1023,10 @@ hipError_t launch_orth_svqb(hipStream_t st, bool cplx, int n, int B, const void*
 }
 
 hipError_t launch_orth(hipStream_t st, bool cplx, int n, int B, const void* V, const void* X, int project, int with_x,
-                       void* W, Ctl* ctl, int check_done) {
+                       void* W, Ctl* ctl, int check_done, int masked) {
   if (B < 1 || B > RR_BMAX) return hipErrorInvalidValue;
-  if (cplx) orth_dispatch<cd>(st, n, B, V, X, project, with_x, W, ctl, check_done);
-  else orth_dispatch<double>(st, n, B, V, X, project, with_x, W, ctl, check_done);
+  if (cplx) orth_dispatch<cd>(st, n, B, V, X, project, with_x, W, ctl, check_done, masked);
+  else orth_dispatch<double>(st, n, B, V, X, project, with_x, W, ctl, check_done, masked);
   return hipGetLastError();
 }
 

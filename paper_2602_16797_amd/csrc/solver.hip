@@ -232,6 +232,8 @@ static int check_opts(int64_t m, int64_t n, int32_t k, const rl_opts& o) {
   if (o.orth < RL_ORTH_CGS2 || o.orth > RL_ORTH_SVQB) return RL_ERR_ARG;
   if (o.refresh < 0 || o.refresh > 1) return RL_ERR_ARG;
   if (o.prec_guard < 0 || o.prec_guard > 1) return RL_ERR_ARG;
+  if (o.lock < 0 || o.lock > 1) return RL_ERR_ARG;
+  if (o.lock && o.orth == RL_ORTH_SVQB) return RL_ERR_UNSUPPORTED;
   if (n > 2048 || o.block > 10) return RL_ERR_UNSUPPORTED;
   if (o.d > INT32_MAX / 2) return RL_ERR_ARG;
   return RL_OK;
@@ -288,6 +290,8 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   hc.b = B;
   hc.tau = o.tau;
   hc.status = 1;
+  hc.lock = o.lock;
+  hc.act = (1 << B) - 1;
   *h->host_ctl = hc;
   CK(hipEventRecord(h->ev[0], st));
   CK(launch_publish(st, h->host_ctl_dev, ctl));
@@ -416,7 +420,7 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
                           ctl, 1));
     else
       CK(launch_orth(st, cplx, (int)n, B, at<void>(ws, L.V), at<void>(ws, L.X), 1, with_x, at<void>(ws, L.W), ctl,
-                     1));
+                     1, 1));
     if (prof) CK(hipEventRecord(h->prof[3 * nprof], st));
     // the pass, then its partial sums reduced beside the TSQR of [A_V A_X A_W]
     // (the first reduction level runs inside the first TSQR launch)
@@ -495,6 +499,8 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
     info->bytes_a = (int64_t)info->a_passes * m * n * (int64_t)p.es;
     info->sketch_prec_used = o.sketch_prec;
     info->kappa_est = kappa_est;
+    info->act_mask = fc.act;
+    info->n_locked = o.lock ? B - __builtin_popcount((unsigned)fc.act) : 0;
     info->n_astream = prof ? nprof : 0;
     info->t_astream_us = 0.0;
     info->n_pass_g = 0;

@@ -56,6 +56,7 @@ def test_struct_layout_matches_ctypes(tmp_path):
         "printf(\"%zu %zu %zu %zu %zu\\n\", offsetof(rl_info, n_pass_g), offsetof(rl_info, t_pass_g_us),"
         " offsetof(rl_opts, refresh), offsetof(rl_opts, prec_guard), offsetof(rl_info, kappa_est));"
         "printf(\"%zu %zu %zu\\n\", offsetof(rl_opts, sketch_prec), offsetof(rl_opts, loop_precond), offsetof(rl_opts, orth));"
+        "printf(\"%zu %zu %zu\\n\", offsetof(rl_opts, lock), offsetof(rl_info, n_locked), offsetof(rl_info, act_mask));"
         "printf(\"%zu %zu %zu %zu\\n\", sizeof(rl_request), offsetof(rl_request, opts), offsetof(rl_request, ldu),"
         " sizeof(rl_job_times));return 0;}\n")
     exe = tmp_path / "layout"
@@ -66,6 +67,7 @@ def test_struct_layout_matches_ctypes(tmp_path):
                     I.hist_cap.offset, I.rnorm_hist.offset, I.n_pass_g.offset, I.t_pass_g_us.offset, O.refresh.offset,
                     O.prec_guard.offset, I.kappa_est.offset,
                     O.sketch_prec.offset, O.loop_precond.offset, O.orth.offset,
+                    O.lock.offset, I.n_locked.offset, I.act_mask.offset,
                     ctypes.sizeof(rl.RlRequest), rl.RlRequest.opts.offset, rl.RlRequest.ldu.offset,
                     ctypes.sizeof(rl.RlJobTimes)]
 
@@ -76,7 +78,7 @@ def test_host_only_calls():
     assert o.d == 800 and o.zeta == 8 and o.block == 1 and o.max_iter == 200 and o.check_every == 5
     assert o.tau == 2.0 * 200 ** 0.5 * 2.0 ** -52
     assert o.sketch_prec == rl.RL_SKETCH_F64
-    assert o.refresh == 1 and o.prec_guard == 1
+    assert o.refresh == 1 and o.prec_guard == 1 and o.lock == 0
     assert rl.default_opts(10_000, 200, 3).max_iter == 100
     # wide real shapes default to the plain-sum pass (the only one past n = 1024)
     assert rl.default_opts(10_000, 1024, 1).dot2 == 1
