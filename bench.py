@@ -78,14 +78,16 @@ def astream_kernel(cplx: bool, n: int, b: int, dot2: bool = True) -> str:
     rule of launch_astream, for a dense A with 16-byte aligned rows)."""
     if cplx:
         if 256 < n <= 1024 and not dot2:
-            return "k_zm_aw + k_zm_g (A W, then A^* [A_V A_X A_W] on the FP64 matrix cores: two reads of A)"
+            return ("k_zm_aw + k_zm_g (A W, then after the Rayleigh-Ritz A^* A_{V_{i+1}}, both on the FP64 "
+                    "matrix cores: two reads of A)")
         if 256 < n <= 1024:
             return "k_c2_rows + k_c2_cols (A W, then A^* [A_V A_X A_W]: two reads of A)"
         if n <= 1024:
             return "k_astream_ccs (A W and A^* [A_V A_X A_W] in one read of A)"
         return "k_astream<cd> (A W and A^* [A_V A_X A_W] in one read of A)"
     if 1024 < n <= 2048 and n % 2 == 0 and not dot2:
-        return "k_zm_aw + k_zm_g (A W, then A^* [A_V A_X A_W] on the FP64 matrix cores: two reads of A)"
+        return ("k_zm_aw + k_zm_g (A W, then after the Rayleigh-Ritz A^* A_{V_{i+1}}, both on the FP64 "
+                "matrix cores: two reads of A)")
     if n % 2 == 0 and n <= 256 and b <= 2:
         return "k_astream_r2 (A W and A^* [A_V A_X A_W] in one read of A)"
     if n <= 1024 and b <= 10:
@@ -400,18 +402,15 @@ def main(argv=None):
                if (args.sketch_prec == "f64" and dot2 == DEFAULT_DOT2.get(args.workload, True)
                    and args.loop_precond == "sketch" and args.orth == "cgs2" and not args.block) else None)
     if n_g > 0:
-        # the dominant kernel is the Gram contraction A^* [A_V A_X A_W] on the
-        # matrix cores: 8 m n b flops per block with data (A_V and A_W on the
-        # first loop pass, A_X too from the second on)
+        # the second kernel of the two-read passes is the Gram contraction on
+        # the matrix cores; in a solve it forms one m x b block per launch
+        # (A^* A_W of the start pass, then the loop's late residual
+        # A^* A_{V_{i+1}}): cflop m n b flops, A once plus that block
         t_g = sum(r.t_pass_g_us for r in results)
         g_us = t_g / n_g
-        g_flops = sum(cflop * m * n * bb * (2 + 3 * (r.n_pass_g - 1)) for r in results if r.n_pass_g > 0)
-        g_flops_launch = g_flops / n_g
-        # its bytes: A once and the blocks with data (A_V and A_W, then A_X too)
-        g_bytes = sum(r.n_pass_g * m * n * es + m * bb * es * (2 + 3 * (r.n_pass_g - 1))
-                      for r in results if r.n_pass_g > 0)
-        g_bytes_launch = g_bytes / n_g
-        common = {"kernel": "k_zm_g (A^* [A_V A_X A_W] on the FP64 matrix cores)", "avg_launch_us": round(g_us, 2),
+        g_flops_launch = cflop * m * n * bb
+        g_bytes_launch = m * n * es + m * bb * es
+        common = {"kernel": "k_zm_g (A^* A_V on the FP64 matrix cores)", "avg_launch_us": round(g_us, 2),
                   "launches": n_g, "algorithmic_flops_per_launch": round(g_flops_launch),
                   "algorithmic_bytes_per_launch": round(g_bytes_launch),
                   "pass": astream_kernel(cplx, n, bb, dot2), "pass_roofline": pass_line}

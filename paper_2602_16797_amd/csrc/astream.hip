@@ -44,14 +44,18 @@ __global__ __launch_bounds__(256) void k_colsum2(ColsumJob J) { colsum2_block(J,
 
 // Row-local panel update.  mode: 0 A_T = [A_V] (t = B), 1 [A_V A_W] (t = 2B),
 // 2 [A_V A_X A_W] (t = 3B).  C_V, C_X are t x B row-major.  Each thread owns
-// rows; the row of A_T sits in registers.
+// rows; the row of A_T sits in registers.  pmode 0: A_V <- A_T C_V and
+// A_X <- A_T C_X in place (AVout == AV); 1: AVout <- A_T C_V only, A_T left
+// as it is; 2: A_X <- A_T C_X only (the late-residual form, whose new A_V was
+// formed by pmode 1 before the Gram pass).
 template <typename T, int B>
-__global__ __launch_bounds__(256) void k_panel(T* __restrict__ AV, T* __restrict__ AX, const T* __restrict__ AW,
+__global__ __launch_bounds__(256) void k_panel(const T* AV, T* AVout, T* __restrict__ AX, const T* __restrict__ AW,
                                                int64_t m, const T* __restrict__ CVg, const T* __restrict__ CXg,
-                                               const Ctl* __restrict__ ctl) {
+                                               const Ctl* __restrict__ ctl, int pmode) {
   if (ctl->done) return;
   const int mode = ctl->rr_mode;
-  const int xupd = ctl->x_update;
+  const int xupd = (pmode != 1) && ctl->x_update;
+  const bool vupd = pmode != 2;
   const int t = (mode == 0) ? B : (mode == 1 ? 2 * B : 3 * B);
   __shared__ T CV[3 * B * B];
   __shared__ T CX[3 * B * B];
@@ -78,7 +82,7 @@ __global__ __launch_bounds__(256) void k_panel(T* __restrict__ AV, T* __restrict
         sv = fmac(at[c], CV[c * B + j], sv);
         sx = fmac(at[c], CX[c * B + j], sx);
       }
-      AV[r * B + j] = sv;
+      if (vupd) AVout[r * B + j] = sv;
       if (xupd) AX[r * B + j] = sx;
     }
   }
@@ -190,6 +194,33 @@ bool astream_shape_ok(bool cplx, bool dot2, int64_t n, int B, const void* A, int
   if (n <= 1024) return true;
   const bool aligned = (lda % 2 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
   return !cplx && !dot2 && n <= 2048 && astream_rm_fits(B, (int)n, aligned, 160 * 1024);
+}
+
+// The pass kernels of this shape read A twice (the matrix-core pair), so the
+// loop takes the late-residual form: A W alone, the Rayleigh-Ritz, then
+// A^* A_{V_{i+1}} alone.
+bool astream_late_residual(bool cplx, bool dot2, int n, int B, const void* A, int64_t lda) {
+  if (dot2) return false;
+  const bool aligned16 = ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  const bool aligned = (lda % 2 == 0) && aligned16;
+  if (cplx) return astream_zm_fits(B, n, aligned16, device_lds_max());
+  return astream_rm_fits(B, n, aligned, device_lds_max());
+}
+
+// A W alone on the late-residual path.
+hipError_t launch_astream_aw(hipStream_t st, bool cplx, int B, const void* A, int64_t lda, int64_t m, int n,
+                             const void* W, void* AW, const Ctl* ctl) {
+  if (!dispatch_zm_aw_only(cplx, B, st, A, lda, m, n, W, AW, device_cu_count(), ctl)) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// A^* P0 alone (plane 0 of the partial records; *np_out records).
+hipError_t launch_astream_gram(hipStream_t st, bool cplx, int B, const void* A, int64_t lda, int64_t m, int n,
+                               const void* P0, double* Gpart, const Ctl* ctl, int64_t* np_out) {
+  const int64_t nb = astream_c2_ranges(m, n, B);
+  if (!dispatch_zm_gram(cplx, B, st, nb, A, lda, m, n, P0, Gpart, ctl)) return hipErrorInvalidValue;
+  *np_out = nb;
+  return hipGetLastError();
 }
 
 int64_t astream_part_doubles(int64_t m, int n, int B, int es_d) {
@@ -319,18 +350,18 @@ hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const voi
 }
 
 template <typename T, int B>
-static void panel_go(hipStream_t st, int64_t nb, void* AV, void* AX, const void* AW, int64_t m, const void* CV,
-                     const void* CX, const Ctl* ctl) {
-  hipLaunchKernelGGL((k_panel<T, B>), dim3((unsigned)nb), dim3(256), 0, st, (T*)AV, (T*)AX, (const T*)AW, m,
-                     (const T*)CV, (const T*)CX, ctl);
+static void panel_go(hipStream_t st, int64_t nb, const void* AV, void* AVout, void* AX, const void* AW, int64_t m,
+                     const void* CV, const void* CX, const Ctl* ctl, int pmode) {
+  hipLaunchKernelGGL((k_panel<T, B>), dim3((unsigned)nb), dim3(256), 0, st, (const T*)AV, (T*)AVout, (T*)AX,
+                     (const T*)AW, m, (const T*)CV, (const T*)CX, ctl, pmode);
 }
 
 template <typename T>
-static bool panel_by_b(int B, hipStream_t st, int64_t nb, void* AV, void* AX, const void* AW, int64_t m,
-                       const void* CV, const void* CX, const Ctl* ctl) {
+static bool panel_by_b(int B, hipStream_t st, int64_t nb, const void* AV, void* AVout, void* AX, const void* AW,
+                       int64_t m, const void* CV, const void* CX, const Ctl* ctl, int pmode) {
   switch (B) {
 #define RL_CASE(BB) \
-  case BB: panel_go<T, BB>(st, nb, AV, AX, AW, m, CV, CX, ctl); return true;
+  case BB: panel_go<T, BB>(st, nb, AV, AVout, AX, AW, m, CV, CX, ctl, pmode); return true;
     RL_CASE(1) RL_CASE(2) RL_CASE(3) RL_CASE(4) RL_CASE(5)
     RL_CASE(6) RL_CASE(7) RL_CASE(8) RL_CASE(9) RL_CASE(10)
 #undef RL_CASE
@@ -339,11 +370,13 @@ static bool panel_by_b(int B, hipStream_t st, int64_t nb, void* AV, void* AX, co
 }
 
 hipError_t launch_panel(hipStream_t st, bool cplx, void* AV, void* AX, const void* AW, int64_t m, int B,
-                        const void* CV, const void* CX, const Ctl* ctl) {
+                        const void* CV, const void* CX, const Ctl* ctl, int pmode, void* AVout) {
   int64_t nb = (m + 255) / 256;
   if (nb > 2048) nb = 2048;
-  const bool ok = cplx ? panel_by_b<cd>(B, st, nb, AV, AX, AW, m, CV, CX, ctl)
-                       : panel_by_b<double>(B, st, nb, AV, AX, AW, m, CV, CX, ctl);
+  if (pmode == 1 && (AVout == nullptr || AVout == AV)) return hipErrorInvalidValue;
+  void* out = (pmode == 1) ? AVout : AV;
+  const bool ok = cplx ? panel_by_b<cd>(B, st, nb, AV, out, AX, AW, m, CV, CX, ctl, pmode)
+                       : panel_by_b<double>(B, st, nb, AV, out, AX, AW, m, CV, CX, ctl, pmode);
   if (!ok) return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -449,6 +449,60 @@ static bool zm_dispatch(int init, int B, hipStream_t st, int64_t nrr, const void
   return hipGetLastError() == hipSuccess;
 }
 
+// The Gram contraction alone: the partial records of A^* P0 over nrr row
+// ranges (plane 0; the other planes zero), for the late residual
+// A^* A_{V_{i+1}} of an iteration whose A W came from its own pass.
+template <bool CPLX>
+static bool zm_gram(int B, hipStream_t st, int64_t nrr, const void* A, int64_t lda, int64_t m, int n, const void* P0,
+                    double* Gpart, const Ctl* ctl) {
+  const double* Ad = (const double*)A;
+  const int64_t lda2 = CPLX ? 2 * lda : lda;
+  const int n2 = CPLX ? 2 * n : n, B2 = CPLX ? 2 * B : B;
+  const int64_t rows = (m + nrr - 1) / nrr;
+  const int nslice = (n2 + 255) / 256;
+  const int64_t nblk = ((nrr + 7) / 8) * 8 * nslice;
+  const double* P = (const double*)P0;
+  switch ((B2 + 15) / 16) {
+    case 1: zm_g_go<CPLX, 1>(st, nblk, Ad, lda2, m, n, B, P, nullptr, nullptr, 1, 1, Gpart, rows, nrr, nslice, ctl); break;
+    case 2: zm_g_go<CPLX, 2>(st, nblk, Ad, lda2, m, n, B, P, nullptr, nullptr, 1, 1, Gpart, rows, nrr, nslice, ctl); break;
+    default: return false;
+  }
+  return hipGetLastError() == hipSuccess;
+}
+
+// A W alone (the first read of an iteration on the late-residual path).
+template <bool CPLX>
+static bool zm_aw_only(int B, hipStream_t st, const void* A, int64_t lda, int64_t m, int n, const void* W, void* AW,
+                       int n_cu, const Ctl* ctl) {
+  const double* Ad = (const double*)A;
+  const int64_t lda2 = CPLX ? 2 * lda : lda;
+  const int B2 = CPLX ? 2 * B : B;
+  const int64_t tiles = (m + 31) / 32;
+  int grid = n_cu > 0 ? n_cu : 256;
+  if ((int64_t)grid * (ZM_AW_THREADS / 64) > tiles) grid = (int)((tiles + 15) / 16);
+  if (grid < 1) grid = 1;
+  hipError_t e;
+  if (B2 <= 16)
+    e = zm_aw_go<CPLX, 1>(st, grid, Ad, lda2, m, n, B, (const double*)W, (double*)AW, ctl);
+  else
+    e = zm_aw_go<CPLX, 2>(st, grid, Ad, lda2, m, n, B, (const double*)W, (double*)AW, ctl);
+  return e == hipSuccess;
+}
+
+bool dispatch_zm_aw_only(bool cplx, int B, hipStream_t st, const void* A, int64_t lda, int64_t m, int n,
+                         const void* W, void* AW, int n_cu, const Ctl* ctl) {
+  if (B < 1 || B > 10) return false;
+  return cplx ? zm_aw_only<true>(B, st, A, lda, m, n, W, AW, n_cu, ctl)
+              : zm_aw_only<false>(B, st, A, lda, m, n, W, AW, n_cu, ctl);
+}
+
+bool dispatch_zm_gram(bool cplx, int B, hipStream_t st, int64_t nrr, const void* A, int64_t lda, int64_t m, int n,
+                      const void* P0, double* Gpart, const Ctl* ctl) {
+  if (B < 1 || B > 10 || nrr < 1) return false;
+  return cplx ? zm_gram<true>(B, st, nrr, A, lda, m, n, P0, Gpart, ctl)
+              : zm_gram<false>(B, st, nrr, A, lda, m, n, P0, Gpart, ctl);
+}
+
 bool dispatch_astream_zm(int init, int B, hipStream_t st, int64_t nrr, const void* A, int64_t lda, int64_t m, int n,
                          const void* W, void* AW, const void* AVp, const void* AXp, double* Gpart, int n_cu,
                          const Ctl* ctl, hipEvent_t mid) {

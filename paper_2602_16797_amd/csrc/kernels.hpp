@@ -36,6 +36,15 @@ bool astream_rm_fits(int B, int n, bool aligned, int64_t lds_max);
 bool dispatch_astream_rm(int init, int B, hipStream_t st, int64_t nrr, const void* A, int64_t lda, int64_t m, int n,
                          const void* W, void* AW, const void* AVp, const void* AXp, double* Gpart, int n_cu,
                          const Ctl* ctl, hipEvent_t mid);
+bool dispatch_zm_aw_only(bool cplx, int B, hipStream_t st, const void* A, int64_t lda, int64_t m, int n,
+                         const void* W, void* AW, int n_cu, const Ctl* ctl);
+bool dispatch_zm_gram(bool cplx, int B, hipStream_t st, int64_t nrr, const void* A, int64_t lda, int64_t m, int n,
+                      const void* P0, double* Gpart, const Ctl* ctl);
+bool astream_late_residual(bool cplx, bool dot2, int n, int B, const void* A, int64_t lda);
+hipError_t launch_astream_aw(hipStream_t st, bool cplx, int B, const void* A, int64_t lda, int64_t m, int n,
+                             const void* W, void* AW, const Ctl* ctl);
+hipError_t launch_astream_gram(hipStream_t st, bool cplx, int B, const void* A, int64_t lda, int64_t m, int n,
+                               const void* P0, double* Gpart, const Ctl* ctl, int64_t* np_out);
 bool astream_shape_ok(bool cplx, bool dot2, int64_t n, int B, const void* A, int64_t lda);
 bool astream_zm_fits(int B, int n, bool aligned, int64_t lds_max);
 bool dispatch_astream_zm(int init, int B, hipStream_t st, int64_t nrr, const void* A, int64_t lda, int64_t m, int n,
@@ -92,8 +101,9 @@ hipError_t launch_colsum_job(hipStream_t st, const ColsumJob& J);
 hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const void* A, int64_t lda, int64_t m, int n,
                           const void* W, void* AW, const void* AVp, const void* AXp, int init, double* Gpart,
                           double* tmp, double* G3, const Ctl* ctl, hipEvent_t pass_done = nullptr);
+// pmode 0: A_V and A_X in place; 1: AVout <- A_T C_V only; 2: A_X only
 hipError_t launch_panel(hipStream_t st, bool cplx, void* AV, void* AX, const void* AW, int64_t m, int B,
-                        const void* CV, const void* CX, const Ctl* ctl);
+                        const void* CV, const void* CX, const Ctl* ctl, int pmode = 0, void* AVout = nullptr);
 hipError_t launch_refresh_out(hipStream_t st, bool cplx, int n, int64_t m, int B, int k, const void* V,
                               const void* AVf, const void* C, const double* s, double* sigma, void* Vout,
                               int64_t ldv, void* U, int64_t ldu, Ctl* ctl);
@@ -128,9 +138,14 @@ hipError_t launch_orth_svqb(hipStream_t st, bool cplx, int n, int B, const void*
 // to zero instead of orthonormalised
 hipError_t launch_orth(hipStream_t st, bool cplx, int n, int B, const void* V, const void* X, int project, int with_x,
                        void* W, Ctl* ctl, int check_done, int masked = 0);
+// phase 0: the whole Rayleigh-Ritz step; 1: Rayleigh-Ritz and V_new (into
+// Vn) only, C, Theta and padding flags saved to Cst (RR_CST_DOUBLES); 2: the
+// residual from G3's first block (A^* A_{V_new}), the stopping rule, the
+// lock update, X and V <- V_new
+constexpr int RR_CST_DOUBLES = 32 * 32 * 2 + 2 * 32;
 hipError_t launch_rr(hipStream_t st, bool cplx, int n, int B, int init_mode, int with_x, const void* Rt, void* V,
                      void* X, const void* W, const void* G3, void* Vn, void* Rres, void* CV, void* CX, double* thb,
-                     double* ht, double* hr, Ctl* ctl);
+                     double* ht, double* hr, Ctl* ctl, int phase = 0, double* Cst = nullptr);
 hipError_t launch_randblk(hipStream_t st, bool cplx, void* Wb, int64_t count, uint64_t seed);
 hipError_t launch_lanczos(hipStream_t st, bool cplx, int n, const void* Ycol, int ld, const void* Rrow, void* Ub,
                           void* Vb, int KL, uint64_t seed, Ctl* ctl);

@@ -29,6 +29,7 @@ namespace rl {
 constexpr int NS_THREADS = 256;
 constexpr int RR_TMAX = 32;
 constexpr int RR_BMAX = 16;
+static_assert(RR_CST_DOUBLES >= RR_TMAX * 32 * 2 + 2 * RR_TMAX, "saved Rayleigh-Ritz data of k_rr's phases");
 constexpr int ORTH_KC = 8;  // Gram entries summed per block reduction (SVQB)
 // projections summed per block reduction in orth_project (the per-thread
 // partial sums stay in registers)
@@ -385,7 +386,8 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
                                                    const T* __restrict__ G3, T* __restrict__ Vn,
                                                    T* __restrict__ Rres, T* __restrict__ CVout, T* __restrict__ CXout,
                                                    double* __restrict__ thb, double* __restrict__ hist_theta,
-                                                   double* __restrict__ hist_rnorm, Ctl* __restrict__ ctl) {
+                                                   double* __restrict__ hist_rnorm, Ctl* __restrict__ ctl, int phase,
+                                                   double* __restrict__ Cst) {
   if (ctl->done) return;
   __shared__ T M[RR_TMAX * 32];
   __shared__ T Vj[RR_TMAX * 32];
@@ -412,6 +414,20 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
   const int lockon = ctl->lock;
   const int act0 = lockon ? ctl->act : (1 << B) - 1;
   auto padded = [&](int c) { return lockon && c >= B && !((act0 >> ((c - B) % B)) & 1); };
+  // phase 0: the whole step; 1: the Rayleigh-Ritz and V_new only, with C,
+  // Theta and the padding flags saved to Cst; 2: the rest from Cst, the
+  // residual from G3's first block = A^* A_{V_new} (the late-residual form)
+  T* Cs = reinterpret_cast<T*>(Cst);
+  double* ths = Cst + RR_TMAX * 32 * (sizeof(T) / sizeof(double));
+  double* pads = ths + RR_TMAX;
+  if (phase == 2) {
+    for (int e = tid; e < RR_TMAX * 32; e += blockDim.x) C[e] = Cs[e];
+    for (int c = tid; c < RR_TMAX; c += blockDim.x) {
+      th[c] = ths[c];
+      padsorted[c] = pads[c] != 0.0 ? 1 : 0;
+    }
+    __syncthreads();
+  } else {
   for (int e = tid; e < RR_TMAX * 32; e += blockDim.x) {
     const int c = e / 32, r = e % 32;
     M[e] = (r < t && c < t) ? Rt[r * t + c] : zero<T>();
@@ -447,12 +463,42 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
     }
   }
   __syncthreads();
+  }
   for (int e = tid; e < t * B; e += blockDim.x) {
     const int r = e / B, j = e % B;
     CV[e] = C[(t - B + j) * 32 + r];
   }
-  if (tid < B) thb[tid] = th[t - B + tid];
+  if (tid < B && phase != 2) thb[tid] = th[t - B + tid];
+  if (phase == 1) {
+    // C is complete only in the rows and columns below t; the rest is unused
+    for (int e = tid; e < RR_TMAX * 32; e += blockDim.x) Cs[e] = C[e];
+    for (int c = tid; c < RR_TMAX; c += blockDim.x) {
+      ths[c] = c < t ? th[c] : 0.0;
+      pads[c] = (c < t && padsorted[c]) ? 1.0 : 0.0;
+    }
+  }
   __syncthreads();
+  if (phase == 1) {
+    // V_new = T C_V into Vn (V, X, W stay as they are for phase 2's X)
+    const T* T1 = (mode == 2) ? X : W;
+    for (int r = tid; r < n; r += blockDim.x) {
+      T v[B];
+#pragma unroll
+      for (int j = 0; j < B; ++j) v[j] = zero<T>();
+      for (int c = 0; c < t; ++c) {
+        const int blk = c / B, jc = c - (c / B) * B;
+        const int64_t e = (int64_t)r * B + jc;
+        const T trc = (blk == 0) ? V[e] : ((blk == 1) ? T1[e] : W[e]);
+#pragma unroll
+        for (int j = 0; j < B; ++j) v[j] = fmac(trc, CV[c * B + j], v[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < B; ++j) Vn[(int64_t)r * B + j] = v[j];
+    }
+    for (int e = tid; e < t * B; e += blockDim.x) CVout[e] = CV[e];
+    if (tid == 0) ctl->rr_mode = mode;
+    return;
+  }
   // pass 1: V_new = T C_V and the residual G_T C_V - V_new Theta_b^2, with its column norms
   {
     const T* GV = G3;
@@ -463,7 +509,18 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
     T vals[RR_BMAX];
 #pragma unroll
     for (int j = 0; j < RR_BMAX; ++j) vals[j] = zero<T>();
-    for (int r = tid; r < n; r += blockDim.x) {
+    // phase 2: V_new is in Vn and the first block of G3 is A^* A_{V_new}
+    for (int r = tid; phase == 2 && r < n; r += blockDim.x) {
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        const double th2 = th[t - B + j] * th[t - B + j];
+        const int64_t e = (int64_t)r * B + j;
+        const T res = sub(GV[e], scal(Vn[e], th2));
+        Rres[e] = res;
+        vals[j] = add(vals[j], from_real<T>(abs2(res)));
+      }
+    }
+    for (int r = tid; phase != 2 && r < n; r += blockDim.x) {
       // [V X W](r, :) C_V and G_T(r, :) C_V, one trial-space column at a time
       T v[B], g[B];
 #pragma unroll
@@ -1033,18 +1090,19 @@ hipError_t launch_orth(hipStream_t st, bool cplx, int n, int B, const void* V, c
 template <typename T, int B>
 static void rr_go(hipStream_t st, int n, int init_mode, int with_x, const void* Rt, void* V, void* X, const void* W,
                   const void* G3, void* Vn, void* Rres, void* CV, void* CX, double* thb, double* ht, double* hr,
-                  Ctl* ctl) {
+                  Ctl* ctl, int phase, double* Cst) {
   hipLaunchKernelGGL((k_rr<T, B>), dim3(1), dim3(NS_THREADS), 0, st, n, init_mode, with_x, (const T*)Rt, (T*)V,
-                     (T*)X, (const T*)W, (const T*)G3, (T*)Vn, (T*)Rres, (T*)CV, (T*)CX, thb, ht, hr, ctl);
+                     (T*)X, (const T*)W, (const T*)G3, (T*)Vn, (T*)Rres, (T*)CV, (T*)CX, thb, ht, hr, ctl, phase, Cst);
 }
 
 template <typename T>
 static bool rr_by_b(int B, hipStream_t st, int n, int init_mode, int with_x, const void* Rt, void* V, void* X,
                     const void* W, const void* G3, void* Vn, void* Rres, void* CV, void* CX, double* thb, double* ht,
-                    double* hr, Ctl* ctl) {
+                    double* hr, Ctl* ctl, int phase, double* Cst) {
   switch (B) {
 #define RL_CASE(BB) \
-  case BB: rr_go<T, BB>(st, n, init_mode, with_x, Rt, V, X, W, G3, Vn, Rres, CV, CX, thb, ht, hr, ctl); return true;
+  case BB: rr_go<T, BB>(st, n, init_mode, with_x, Rt, V, X, W, G3, Vn, Rres, CV, CX, thb, ht, hr, ctl, phase, Cst); \
+    return true;
     RL_CASE(1) RL_CASE(2) RL_CASE(3) RL_CASE(4) RL_CASE(5)
     RL_CASE(6) RL_CASE(7) RL_CASE(8) RL_CASE(9) RL_CASE(10)
 #undef RL_CASE
@@ -1054,10 +1112,12 @@ static bool rr_by_b(int B, hipStream_t st, int n, int init_mode, int with_x, con
 
 hipError_t launch_rr(hipStream_t st, bool cplx, int n, int B, int init_mode, int with_x, const void* Rt, void* V,
                      void* X, const void* W, const void* G3, void* Vn, void* Rres, void* CV, void* CX, double* thb,
-                     double* ht, double* hr, Ctl* ctl) {
-  const bool ok = cplx ? rr_by_b<cd>(B, st, n, init_mode, with_x, Rt, V, X, W, G3, Vn, Rres, CV, CX, thb, ht, hr, ctl)
+                     double* ht, double* hr, Ctl* ctl, int phase, double* Cst) {
+  if (phase < 0 || phase > 2 || (phase != 0 && (Cst == nullptr || init_mode))) return hipErrorInvalidValue;
+  const bool ok = cplx ? rr_by_b<cd>(B, st, n, init_mode, with_x, Rt, V, X, W, G3, Vn, Rres, CV, CX, thb, ht, hr, ctl,
+                                     phase, Cst)
                        : rr_by_b<double>(B, st, n, init_mode, with_x, Rt, V, X, W, G3, Vn, Rres, CV, CX, thb, ht, hr,
-                                         ctl);
+                                         ctl, phase, Cst);
   if (!ok) return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -27,6 +27,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <utility>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -73,7 +74,7 @@ static int ensure_aux(rl_ctx* h) {
 
 static int ensure_prof_events(rl_ctx* h, size_t launches) {
   if (h->prof_mid.size() < launches) h->prof_mid.resize(launches);
-  while (h->prof.size() < 3 * launches) {
+  while (h->prof.size() < 4 * launches) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return RL_ERR_DEVICE;
     h->prof.push_back(e);
@@ -99,6 +100,7 @@ struct Layout {
   size_t ctl, ht, hr, Y, Yf, Tmf, part, Tm, Rrow, RH, Rinv, RinvH;
   size_t V, X, W, Z, Vn, G3, Rres;
   size_t AV, AX, AW, Gpart, Gtmp, tsA, tsB, CV, CX, thb, Ub, Vb;
+  size_t AV2, Cst;  // late-residual form: the other A_V buffer and the saved Rayleigh-Ritz data
   size_t dsc, cnp;  // diagonal preconditioner scales and their partial sums
   size_t total;
   int KL;
@@ -112,7 +114,14 @@ struct Problem {
   int max_iter;
   int sketch_prec;
   int loop_precond;
+  bool late = false;  // the loop may take the late-residual form (two reads of A per iteration)
 };
+
+// Shapes whose loop may take the late-residual form (the pass kernels read A
+// twice there); the workspace holds its second A_V buffer for all of them.
+static bool late_shape(bool cplx, bool dot2, int64_t n) {
+  return !dot2 && (cplx ? (n > 256 && n <= 1024) : (n > 1024 && n <= 2048));
+}
 
 static Layout plan(const Problem& p, int64_t lds_budget) {
   Layout L{};
@@ -166,6 +175,8 @@ static Layout plan(const Problem& p, int64_t lds_budget) {
   L.dsc = a.take(sizeof(double) * (size_t)(diag ? n : 1));
   L.cnp = a.take(sizeof(double) * (size_t)(diag ? colnorm_groups(m) * ncols_d : 1));
   L.thb = a.take(sizeof(double) * 32);
+  L.AV2 = a.take(p.late ? mb : 256);
+  L.Cst = a.take(sizeof(double) * RR_CST_DOUBLES);
   L.KL = (int)std::min<int64_t>(n, 64);
   L.Ub = a.take(es * (size_t)(L.KL + 1) * n);
   L.Vb = a.take(es * (size_t)(L.KL + 1) * n);
@@ -269,7 +280,11 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;
   Problem p{m, n, o.d, o.block, k, o.zeta, cplx, (size_t)(cplx ? 16 : 8), o.max_iter, o.sketch_prec,
             o.loop_precond};
+  p.late = late_shape(cplx, o.dot2 != 0, n);
   const Layout L = plan(p, h->lds_budget);
+  // the pass reads A twice (matrix-core kernels): A W, the Rayleigh-Ritz, then
+  // A^* A_{V_{i+1}} alone (a third of the Gram work of A^* [A_V A_X A_W])
+  const bool late = p.late && astream_late_residual(cplx, o.dot2 != 0, (int)n, o.block, A, lda);
   // a previous solve that returned early may have left work on the second stream
   if (h->aux) CK(hipStreamWaitEvent(h->stream, h->join, 0));
   rc = ensure_ws(h, L.total);
@@ -376,13 +391,13 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   if (prof) {
     rc = ensure_prof_events(h, (size_t)o.max_iter + 1);
     if (rc != RL_OK) return rc;
-    CK(hipEventRecord(h->prof[3 * nprof], st));
+    CK(hipEventRecord(h->prof[4 * nprof], st));
     h->prof_mid[nprof] = 0;
   }
   // start pass: A_V = A V_0 and A^* A_V (into the first block of G3)
   CK(launch_astream(st, cplx, B, dot2, A, lda, m, (int)n, at<void>(ws, L.V), at<void>(ws, L.AV), nullptr, nullptr, 1,
                     at<double>(ws, L.Gpart), at<double>(ws, L.Gtmp), at<double>(ws, L.G3), ctl,
-                    prof ? h->prof[3 * nprof + 2] : nullptr));
+                    prof ? h->prof[4 * nprof + 3] : nullptr));
   if (prof) ++nprof;
   void* Rt = nullptr;
   CK(launch_tsqr(st, cplx, at<void>(ws, L.AV), B, nullptr, 0, nullptr, 0, m, at<void>(ws, L.tsA),
@@ -402,9 +417,19 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
 
   // Step 4: LOBPCG
   int it = 0;
+  // late-residual form: A_V alternates between two buffers (the new one is
+  // formed before the Gram pass, while the old one is still part of A_T)
+  void* AVcur = at<void>(ws, L.AV);
+  void* AVoth = at<void>(ws, L.AV2);
   for (; it < o.max_iter; ++it) {
-    CK(launch_panel(st, cplx, at<void>(ws, L.AV), at<void>(ws, L.AX), at<void>(ws, L.AW), m, B, at<void>(ws, L.CV),
-                    at<void>(ws, L.CX), ctl));
+    if (late && it > 0) {
+      // A_X <- A_T C_X with the previous iteration's A_T (its A_V is AVoth)
+      CK(launch_panel(st, cplx, AVoth, at<void>(ws, L.AX), at<void>(ws, L.AW), m, B, at<void>(ws, L.CV),
+                      at<void>(ws, L.CX), ctl, 2));
+    } else {
+      CK(launch_panel(st, cplx, AVcur, at<void>(ws, L.AX), at<void>(ws, L.AW), m, B, at<void>(ws, L.CV),
+                      at<void>(ws, L.CX), ctl));
+    }
     if (o.loop_precond == RL_PREC_SKETCH) {
       CK(launch_trmv(st, cplx, B, at<void>(ws, L.RinvH), (int)n, 1, at<void>(ws, L.Rres), at<void>(ws, L.Z), ctl,
                      1));
@@ -421,16 +446,46 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
     else
       CK(launch_orth(st, cplx, (int)n, B, at<void>(ws, L.V), at<void>(ws, L.X), 1, with_x, at<void>(ws, L.W), ctl,
                      1, 1));
-    if (prof) CK(hipEventRecord(h->prof[3 * nprof], st));
+    if (prof) CK(hipEventRecord(h->prof[4 * nprof], st));
+    if (late) {
+      // A W; TSQR of [A_V A_X A_W]; the Rayleigh-Ritz and V_new; the new
+      // A_V = A_T C_V; A^* A_V (the Gram pass) reduced into G3's first block;
+      // then the residual, the stopping rule, X and V <- V_new
+      CK(launch_astream_aw(st, cplx, B, A, lda, m, (int)n, at<void>(ws, L.W), at<void>(ws, L.AW), ctl));
+      if (prof) CK(hipEventRecord(h->prof[4 * nprof + 1], st));
+      CK(launch_tsqr(st, cplx, AVcur, B, with_x ? at<void>(ws, L.AX) : nullptr, with_x ? B : 0, at<void>(ws, L.AW),
+                     B, m, at<void>(ws, L.tsA), at<void>(ws, L.tsB), &Rt, ctl, 1));
+      CK(launch_rr(st, cplx, (int)n, B, 0, with_x, Rt, at<void>(ws, L.V), at<void>(ws, L.X), at<void>(ws, L.W),
+                   at<void>(ws, L.G3), at<void>(ws, L.Vn), at<void>(ws, L.Rres), at<void>(ws, L.CV),
+                   at<void>(ws, L.CX), at<double>(ws, L.thb), at<double>(ws, L.ht), at<double>(ws, L.hr), ctl, 1,
+                   at<double>(ws, L.Cst)));
+      CK(launch_panel(st, cplx, AVcur, at<void>(ws, L.AX), at<void>(ws, L.AW), m, B, at<void>(ws, L.CV),
+                      at<void>(ws, L.CX), ctl, 1, AVoth));
+      int64_t np = 0;
+      if (prof) CK(hipEventRecord(h->prof[4 * nprof + 2], st));
+      CK(launch_astream_gram(st, cplx, B, A, lda, m, (int)n, AVoth, at<double>(ws, L.Gpart), ctl, &np));
+      if (prof) {
+        CK(hipEventRecord(h->prof[4 * nprof + 3], st));
+        h->prof_mid[nprof] = 2;
+        ++nprof;
+      }
+      CK(launch_astream_reduce(st, cplx, B, (int)n, np, at<double>(ws, L.Gpart), at<double>(ws, L.Gtmp),
+                               at<double>(ws, L.G3), ctl));
+      CK(launch_rr(st, cplx, (int)n, B, 0, with_x, Rt, at<void>(ws, L.V), at<void>(ws, L.X), at<void>(ws, L.W),
+                   at<void>(ws, L.G3), at<void>(ws, L.Vn), at<void>(ws, L.Rres), at<void>(ws, L.CV),
+                   at<void>(ws, L.CX), at<double>(ws, L.thb), at<double>(ws, L.ht), at<double>(ws, L.hr), ctl, 2,
+                   at<double>(ws, L.Cst)));
+      std::swap(AVcur, AVoth);
+    } else {
     // the pass, then its partial sums reduced beside the TSQR of [A_V A_X A_W]
     // (the first reduction level runs inside the first TSQR launch)
     int64_t np = 0;
     bool mid = false;
     CK(launch_astream_pass(st, cplx, B, dot2, A, lda, m, (int)n, at<void>(ws, L.W), at<void>(ws, L.AW),
-                           at<void>(ws, L.AV), with_x ? at<void>(ws, L.AX) : nullptr, 0, at<double>(ws, L.Gpart),
-                           ctl, &np, prof ? h->prof[3 * nprof + 1] : nullptr, &mid));
+                           AVcur, with_x ? at<void>(ws, L.AX) : nullptr, 0, at<double>(ws, L.Gpart),
+                           ctl, &np, prof ? h->prof[4 * nprof + 1] : nullptr, &mid));
     if (prof) {
-      CK(hipEventRecord(h->prof[3 * nprof + 2], st));
+      CK(hipEventRecord(h->prof[4 * nprof + 3], st));
       h->prof_mid[nprof] = mid ? 1 : 0;
       ++nprof;
     }
@@ -444,6 +499,7 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
     CK(launch_rr(st, cplx, (int)n, B, 0, with_x, Rt, at<void>(ws, L.V), at<void>(ws, L.X), at<void>(ws, L.W),
                  at<void>(ws, L.G3), at<void>(ws, L.Vn), at<void>(ws, L.Rres), at<void>(ws, L.CV), at<void>(ws, L.CX),
                  at<double>(ws, L.thb), at<double>(ws, L.ht), at<double>(ws, L.hr), ctl));
+    }
     const bool can_stop = (o.stop_rule == RL_STOP_TOL) || (o.stop_rule == RL_STOP_PAPER && it % o.check_every == 0);
     if (can_stop) {
       CK(launch_publish(st, ctl, h->host_ctl_dev));
@@ -472,8 +528,18 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
                           at<double>(ws, L.thb), sigma, Vout, ldv, Uout, ldu, ctl));
   } else {
     CK(launch_final_n(st, cplx, (int)n, B, k, at<void>(ws, L.V), at<double>(ws, L.thb), sigma, Vout, ldv, ctl));
+    void* AVlast = at<void>(ws, L.AV);
+    if (late && Uout) {
+      // the A_V of the last Rayleigh-Ritz's A_T: iteration j (counted on the
+      // device; iterations queued after the stop flag did nothing) used
+      // L.AV for even j and L.AV2 for odd j
+      CK(launch_publish(st, ctl, h->host_ctl_dev));
+      CK(hipStreamSynchronize(st));
+      const int done_iters = h->host_ctl->iter;
+      if (done_iters > 0 && ((done_iters - 1) & 1)) AVlast = at<void>(ws, L.AV2);
+    }
     if (Uout)
-      CK(launch_final_u(st, cplx, at<void>(ws, L.AV), at<void>(ws, L.AX), at<void>(ws, L.AW), m, B, k,
+      CK(launch_final_u(st, cplx, AVlast, at<void>(ws, L.AX), at<void>(ws, L.AW), m, B, k,
                         at<void>(ws, L.CV), at<double>(ws, L.thb), Uout, ldu, ctl));
   }
   CK(hipEventRecord(h->ev[3], st));
@@ -505,13 +571,22 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
     info->t_astream_us = 0.0;
     info->n_pass_g = 0;
     info->t_pass_g_us = 0.0;
+    // events per launch: start, after A W, before the Gram kernel (late
+    // form), end; prof_mid 0: one kernel, 1: A W then the Gram kernel back to
+    // back, 2: the late form (its two reads apart)
     for (int q = 0; prof && q < nprof; ++q) {
-      float ka = 0.f;
-      (void)hipEventElapsedTime(&ka, h->prof[3 * q], h->prof[3 * q + 2]);
+      float ka = 0.f, kg = 0.f;
+      if (h->prof_mid[q] == 2) {
+        float k1 = 0.f;
+        (void)hipEventElapsedTime(&k1, h->prof[4 * q], h->prof[4 * q + 1]);
+        (void)hipEventElapsedTime(&kg, h->prof[4 * q + 2], h->prof[4 * q + 3]);
+        ka = k1 + kg;
+      } else {
+        (void)hipEventElapsedTime(&ka, h->prof[4 * q], h->prof[4 * q + 3]);
+        if (h->prof_mid[q]) (void)hipEventElapsedTime(&kg, h->prof[4 * q + 1], h->prof[4 * q + 3]);
+      }
       info->t_astream_us += 1e3 * ka;
       if (h->prof_mid[q]) {
-        float kg = 0.f;
-        (void)hipEventElapsedTime(&kg, h->prof[3 * q + 1], h->prof[3 * q + 2]);
         info->t_pass_g_us += 1e3 * kg;
         ++info->n_pass_g;
       }
@@ -532,6 +607,7 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
 static int64_t planned_bytes(bool cplx, int64_t m, int64_t n, int32_t k, const rl_opts& o, int64_t lds_budget) {
   Problem p{m, n, o.d, o.block, k, o.zeta, cplx, (size_t)(cplx ? 16 : 8), o.max_iter, o.sketch_prec,
             o.loop_precond};
+  p.late = late_shape(cplx, o.dot2 != 0, n);
   return (int64_t)plan(p, lds_budget).total;
 }
 

@@ -78,3 +78,36 @@ def test_real_clustered_wide(rl, b):
     banner(f"parity real 10000x2000 clustered spectrum (Sec. 5.2) k=1 b={b}, plain products")
     A, _, s = planted_numpy(10_000, 2000, spectrum_clustered(2000), 1600)
     _check(rl, A, 1, seed=2600, normA=s[0], block=b, dot2=False, gap_ok=False)
+
+
+def test_complex_wide_plain_without_refresh(rl):
+    """The late-residual loop (A W, the Rayleigh-Ritz, then A^* A_{V_{i+1}}
+    on its own) with refresh = 0: U-hat comes from the A_V buffer of the last
+    Rayleigh-Ritz, which the two-buffer scheme must find after a stop between
+    host checks."""
+    banner("parity complex 6000x300 k=3 plain products, refresh off (late-residual loop)")
+    A, _, s = planted_numpy(6000, 300, spectrum_gap(300, 3, 1e-4, 10.0), 1700, is_complex=True)
+    _check(rl, A, 3, seed=2700, normA=s[0], dot2=False, refresh=False)
+
+
+def test_complex_wide_plain_locked(rl):
+    """Locking on the late-residual loop: the Gram pass after the
+    Rayleigh-Ritz, then the lock update, against the oracle's locked solve."""
+    from oracle import termination
+    from oracle.rlobpcg import default_tau
+    from .gpu_util import sin_angle, to_np
+    import numpy as np
+    banner("parity complex 6000x300 k=4 plain products, locking (late-residual loop)")
+    n, k = 300, 4
+    A, _, s = planted_numpy(6000, n, spectrum_gap(n, k, 1e-3, 10.0), 1710, is_complex=True)
+    r = rl.rl_svds_smallest(torch.from_numpy(A).cuda(), k, seed=2710, dot2=False, lock=True)
+    o = rlobpcg(A, k, seed=2710, dot2=False, lock=True)
+    banner(f"  gpu iters {r.iters} status {r.status} locked {r.n_locked}; oracle iters {o.iters}")
+    sg, Vg, Ug = to_np(r.sigma), to_np(r.V), to_np(r.U)
+    assert np.max(np.abs(sg - o.sigma)) <= 1e-12 * s[0]
+    assert np.linalg.norm(A @ Vg - Ug * sg[None, :], axis=0).max() <= 1e-12 * s[0]
+    assert sin_angle(Vg, o.V) <= 1e-8
+    tau = default_tau(n)
+    th = [r.theta_hist[j] for j in range(r.iters + 1)]
+    rn = [r.rnorm_hist[j] for j in range(r.iters + 1)]
+    assert r.status == 0 and termination.first_stop_locked(th, rn, r.sigma1, tau) == r.iters - 1
