@@ -73,17 +73,30 @@ __global__ __launch_bounds__(256) void k_panel(const T* AV, T* AVout, T* __restr
       at[2 * B + j] = (mode == 2) ? AW[r * B + j] : zero<T>();
     }
     // the coefficient loop stays rolled for wider blocks so the t x B
-    // coefficients are read from LDS per row instead of held in registers
+    // coefficients are read from LDS per row instead of held in registers;
+    // a block that is not kept is not formed
+    if (vupd && xupd) {
 #pragma unroll(B <= 2 ? B : 1)
-    for (int j = 0; j < B; ++j) {
-      T sv = zero<T>(), sx = zero<T>();
+      for (int j = 0; j < B; ++j) {
+        T sv = zero<T>(), sx = zero<T>();
 #pragma unroll
-      for (int c = 0; c < 3 * B; ++c) {
-        sv = fmac(at[c], CV[c * B + j], sv);
-        sx = fmac(at[c], CX[c * B + j], sx);
+        for (int c = 0; c < 3 * B; ++c) {
+          sv = fmac(at[c], CV[c * B + j], sv);
+          sx = fmac(at[c], CX[c * B + j], sx);
+        }
+        AVout[r * B + j] = sv;
+        AX[r * B + j] = sx;
       }
-      if (vupd) AVout[r * B + j] = sv;
-      if (xupd) AX[r * B + j] = sx;
+    } else if (vupd || xupd) {
+      const T* Cm = vupd ? CV : CX;
+      T* out = vupd ? AVout : AX;
+#pragma unroll(B <= 2 ? B : 1)
+      for (int j = 0; j < B; ++j) {
+        T sv = zero<T>();
+#pragma unroll
+        for (int c = 0; c < 3 * B; ++c) sv = fmac(at[c], Cm[c * B + j], sv);
+        out[r * B + j] = sv;
+      }
     }
   }
 }

@@ -21,6 +21,9 @@ hipError_t launch_sketch(hipStream_t st, const double* A, int64_t lda_d, int64_t
 // before the inverses are formed.
 hipError_t launch_qr_lowp(hipStream_t st, float* Yf, int d, int n, float* Tmf, double* Y, double* Rrow, double* RH,
                           double* Rinv, double* RinvH, bool bf16, hipEvent_t r_ready = nullptr);
+// elements of the T workspace launch_qr and launch_qr_lowp take (the panel's
+// T factor and, for sketches over 4096 rows, its leaves')
+constexpr int QR_TM_ELEMS = 32 * 32 * 22;
 hipError_t launch_qr(hipStream_t st, bool cplx, void* Y, int d, int n, void* Tm, void* Rrow, void* RH, void* Rinv,
                      void* RinvH, hipEvent_t r_ready = nullptr);
 

@@ -614,6 +614,220 @@ __global__ __launch_bounds__(256) void k_trinv(const T* __restrict__ Y, int ld, 
   }
 }
 
+// Panels taller than the register-resident panel holds (over 4096 rows):
+// leaves of LW columns (8 rows per thread of a 1024-thread workgroup, up to
+// 8192 rows), each followed by the update of the panel's remaining columns,
+// then the compact-WY T factor of the whole panel, so the trailing update
+// keeps its QR_NB-wide panels.  The T factor is rebuilt from the Gram matrix
+// of the panel's reflectors, Gm(l, j) = V(:, l)^* V(:, j) over rows [p, d),
+// and the leaves' tau_q (their T factors' diagonals), by the same recurrence
+// the panel kernels use.
+constexpr int QRT_THREADS = 512;  // one thread per pair l < j of a 32-column panel
+constexpr int QRT_RC = 64;        // rows per LDS chunk
+
+constexpr int QRL_ROWS = 1024;  // rows per workgroup of the row-split panel kernels (256 threads x 4)
+constexpr int QRL_MAXBLK = QRP_THREADS * 8 / QRL_ROWS;
+
+__device__ inline void qr_pair_of(int tid, int nb, int& pl, int& pj) {
+  pl = -1;
+  pj = -1;
+  int c = tid;
+  for (int j = 1; j < nb; ++j) {
+    if (c < j) {
+      pl = c;
+      pj = j;
+      return;
+    }
+    c -= j;
+  }
+}
+
+// Partial Gram matrices of the panel's reflectors, one per block of
+// QRL_ROWS rows: Gpart[blk * 512 + pair] = sum over the block's rows of
+// V(r, l)^* V(r, j) (pair -> (l, j), l < j < nb).
+template <typename T>
+__global__ __launch_bounds__(QRT_THREADS) void k_qr_gram_part(const T* __restrict__ Y, int ld, int d, int p, int nb,
+                                                              T* __restrict__ Gpart) {
+  __shared__ T Vs[QRT_RC][QR_NB + 1];
+  const int tid = threadIdx.x;
+  int pl, pj;
+  qr_pair_of(tid, nb, pl, pj);
+  const int rb0 = p + blockIdx.x * QRL_ROWS;
+  const int rb1 = min(rb0 + QRL_ROWS, d);
+  T acc = zero<T>();
+  for (int r0 = rb0; r0 < rb1; r0 += QRT_RC) {
+    __syncthreads();
+    for (int e = tid; e < QRT_RC * QR_NB; e += QRT_THREADS) {
+      const int rr = e % QRT_RC, q = e / QRT_RC, r = r0 + rr;
+      Vs[rr][q] = (q < nb && r < rb1) ? vpanel(Y, ld, p, q, r) : zero<T>();
+    }
+    __syncthreads();
+    if (pl >= 0) {
+#pragma unroll 8
+      for (int rr = 0; rr < QRT_RC; ++rr) acc = cfmac(Vs[rr][pl], Vs[rr][pj], acc);
+    }
+  }
+  Gpart[(int64_t)blockIdx.x * QRT_THREADS + tid] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(QRT_THREADS) void k_qr_tfactor(const T* __restrict__ Gpart, int nblk, int nb,
+                                                            const T* __restrict__ Tleaf, int lw,
+                                                            T* __restrict__ Tm) {
+  __shared__ T Gm[QR_NB * QR_NB];
+  __shared__ T taus[QR_NB];
+  __shared__ T Tl[QR_NB * QR_NB];
+  const int tid = threadIdx.x;
+  int pl, pj;
+  qr_pair_of(tid, nb, pl, pj);
+  if (pl >= 0) {
+    T acc = zero<T>();
+    for (int b = 0; b < nblk; ++b) acc = add(acc, Gpart[(int64_t)b * QRT_THREADS + tid]);
+    Gm[pl * QR_NB + pj] = acc;
+  }
+  if (tid < nb) {
+    const int q = tid % lw;
+    taus[tid] = Tleaf[(int64_t)(tid / lw) * QR_NB * QR_NB + q + q * QR_NB];
+  }
+  __syncthreads();
+  if (tid < QR_NB) {
+    const int q = tid;
+    for (int jj = 0; jj < QR_NB; ++jj) {
+      T val = zero<T>();
+      if (jj < nb) {
+        if (jj == q) {
+          val = taus[q];
+        } else if (jj > q) {
+          T a = zero<T>();
+          for (int l = q; l < jj; ++l) a = fmac(Tl[q + l * QR_NB], Gm[l * QR_NB + jj], a);
+          val = neg(mul(taus[jj], a));
+        }
+      }
+      Tl[q + jj * QR_NB] = val;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < QR_NB * QR_NB; i += QRT_THREADS) Tm[i] = Tl[i];
+}
+
+// The update of a leaf's panel columns [c0, c1) by its reflectors (rows from
+// pl on; lw <= LW columns of V), split over row blocks: part[blk][c][q] =
+// sum over the block's rows of V(r, q)^* C(r, c), then C -= V T^* W with W
+// the blocks' partials summed in block order (the same arithmetic as
+// k_qr_update, with the rows spread over the grid).
+template <typename T, int LW>
+__global__ __launch_bounds__(256) void k_qr_leafupd_part(const T* __restrict__ Y, int ld, int d, int pl, int lw,
+                                                         int c0, int c1, T* __restrict__ part) {
+  constexpr int G = 4;  // columns per batched reduction
+  __shared__ T scratch[(256 / 16) * LW * G];
+  __shared__ T outs[LW * G];
+  const int tid = threadIdx.x;
+  const int rb0 = pl + blockIdx.x * QRL_ROWS;
+  T v[4][LW];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int r = rb0 + tid + 256 * s;
+#pragma unroll
+    for (int q = 0; q < LW; ++q) v[s][q] = (r < d && q < lw) ? vpanel(Y, ld, pl, q, r) : zero<T>();
+  }
+  const int ncol = c1 - c0;
+  for (int g0 = 0; g0 < ncol; g0 += G) {
+    T vals[LW * G];
+#pragma unroll
+    for (int e = 0; e < LW * G; ++e) vals[e] = zero<T>();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int r = rb0 + tid + 256 * s;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const T cv = (r < d && g0 + g < ncol) ? Y[(int64_t)(c0 + g0 + g) * ld + r] : zero<T>();
+#pragma unroll
+        for (int q = 0; q < LW; ++q) vals[g * LW + q] = cfmac(v[s][q], cv, vals[g * LW + q]);
+      }
+    }
+    block_sum_many<T, LW * G>(vals, LW * G, scratch, outs);
+    if (tid < LW * G && g0 + tid / LW < ncol)
+      part[((int64_t)blockIdx.x * QR_NB + g0 + tid / LW) * LW + tid % LW] = outs[tid];
+  }
+}
+
+template <typename T, int LW>
+__global__ __launch_bounds__(256) void k_qr_leafupd_apply(T* __restrict__ Y, int ld, int d, int pl, int lw, int c0,
+                                                          int c1, const T* __restrict__ part, int nblk,
+                                                          const T* __restrict__ Tq) {
+  __shared__ T Wt[QR_NB][LW];
+  __shared__ T Wt2[QR_NB][LW];
+  const int tid = threadIdx.x;
+  const int ncol = c1 - c0;
+  if (tid < ncol * LW) {
+    const int c = tid / LW, q = tid % LW;
+    T acc = zero<T>();
+    for (int b = 0; b < nblk; ++b) acc = add(acc, part[((int64_t)b * QR_NB + c) * LW + q]);
+    Wt[c][q] = acc;
+  }
+  __syncthreads();
+  if (tid < ncol * LW) {
+    const int c = tid / LW, q = tid % LW;
+    T sacc = zero<T>();
+    for (int l = 0; l <= q && l < lw; ++l) sacc = cfmac(Tq[l + q * QR_NB], Wt[c][l], sacc);
+    Wt2[c][q] = (q < lw) ? sacc : zero<T>();
+  }
+  __syncthreads();
+  const int rb0 = pl + blockIdx.x * QRL_ROWS;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int r = rb0 + tid + 256 * s;
+    if (r >= d) continue;
+    T vr[LW];
+#pragma unroll
+    for (int q = 0; q < LW; ++q) vr[q] = (q < lw) ? vpanel(Y, ld, pl, q, r) : zero<T>();
+    for (int c = 0; c < ncol; ++c) {
+      T y = Y[(int64_t)(c0 + c) * ld + r];
+#pragma unroll
+      for (int q = 0; q < LW; ++q) y = fnmac(vr[q], Wt2[c][q], y);
+      Y[(int64_t)(c0 + c) * ld + r] = y;
+    }
+  }
+}
+
+template <typename T>
+static bool qr_leaf_fits(int rows) {
+  return rows <= QRP_THREADS * 8;
+}
+
+// The T workspace (QR_TM_ELEMS elements): the panel's T factor, the
+// leaves' T factors, the leaf updates' partial sums, the Gram partials.
+constexpr int QR_TM_LEAVES = QR_NB * QR_NB;                       // offset of the leaves' T factors
+constexpr int QR_TM_UPD = QR_TM_LEAVES + 16 * QR_NB * QR_NB;      // leaf-update partials
+constexpr int QR_TM_GRAM = QR_TM_UPD + QRL_MAXBLK * QR_NB * 4;    // Gram partials
+static_assert(QR_TM_GRAM + QRL_MAXBLK * QRT_THREADS <= QR_TM_ELEMS, "T workspace");
+
+template <typename T>
+static void qr_panel_leaves(hipStream_t st, T* Y, int d, int p, int nb, T* Tm) {
+  constexpr int LW = (sizeof(T) == 16) ? 2 : 4;
+  static_assert(QR_NB / LW <= 16 && LW <= 4, "leaf T factors and partials fit the T workspace");
+  T* Tleaf = Tm + QR_TM_LEAVES;
+  T* upd = Tm + QR_TM_UPD;
+  T* gram = Tm + QR_TM_GRAM;
+  for (int q = 0; q < nb; q += LW) {
+    const int lw = min(LW, nb - q);
+    T* Tq = Tleaf + (int64_t)(q / LW) * QR_NB * QR_NB;
+    hipLaunchKernelGGL((k_qr_panel_reg<T, 8, LW>), dim3(1), dim3(QRP_THREADS), 0, st, Y, d, d, p + q, lw, Tq);
+    const int c0 = p + q + lw, c1 = p + nb;
+    if (c1 > c0) {  // the panel's own columns: full precision, as the panel kernels
+      const int nblk = (d - (p + q) + QRL_ROWS - 1) / QRL_ROWS;
+      hipLaunchKernelGGL((k_qr_leafupd_part<T, LW>), dim3(nblk), dim3(256), 0, st, (const T*)Y, d, d, p + q, lw, c0,
+                         c1, upd);
+      hipLaunchKernelGGL((k_qr_leafupd_apply<T, LW>), dim3(nblk), dim3(256), 0, st, Y, d, d, p + q, lw, c0, c1,
+                         (const T*)upd, nblk, (const T*)Tq);
+    }
+  }
+  const int nblk = (d - p + QRL_ROWS - 1) / QRL_ROWS;
+  hipLaunchKernelGGL(k_qr_gram_part<T>, dim3(nblk), dim3(QRT_THREADS), 0, st, (const T*)Y, d, d, p, nb, gram);
+  hipLaunchKernelGGL(k_qr_tfactor<T>, dim3(1), dim3(QRT_THREADS), 0, st, (const T*)gram, nblk, nb, (const T*)Tleaf,
+                     LW, Tm);
+}
+
 // Blocked Householder factorization of the d x n column-major Y in place.
 template <typename T, bool BF16IN = false>
 static void qr_factor(hipStream_t st, T* Y, int d, int n, T* Tm) {
@@ -628,6 +842,8 @@ static void qr_factor(hipStream_t st, T* Y, int d, int n, T* Tm) {
       nb = min(nbr > 0 ? nbr : QR_NB, n - p);
       if (nbr > 0)
         qr_panel_launch<T>(st, Y, d, p, nb, rpt, Tm);
+      else if (qr_leaf_fits<T>(d - p))
+        qr_panel_leaves<T>(st, Y, d, p, nb, Tm);
       else
         hipLaunchKernelGGL(k_qr_panel<T>, dim3(1), dim3(QR_THREADS), 0, st, Y, d, d, n, p, nb, Tm);
     }

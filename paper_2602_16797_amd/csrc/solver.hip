@@ -142,10 +142,10 @@ static Layout plan(const Problem& p, int64_t lds_budget) {
   L.Y = a.take(es * (size_t)p.d * n);
   if (p.sketch_prec != RL_SKETCH_F64) {
     L.Yf = a.take(sizeof(float) * (size_t)p.d * n);
-    L.Tmf = a.take(sizeof(float) * 32 * 32);
+    L.Tmf = a.take(sizeof(float) * QR_TM_ELEMS);
   }
   L.part = a.take(sizeof(double) * (size_t)std::max<int64_t>(partd, 1));
-  L.Tm = a.take(es * 32 * 32);
+  L.Tm = a.take(es * QR_TM_ELEMS);
   L.Rrow = a.take(es * (size_t)n * n);
   L.RH = a.take(es * (size_t)n * n);
   L.Rinv = a.take(es * (size_t)n * n);
@@ -891,7 +891,7 @@ int rl_step_qr(rl_handle h, int is_complex, int64_t d, int64_t n, const double* 
   const int es = is_complex ? 2 : 1;
   const size_t esb = 8 * (size_t)es;
   Arena a;
-  const size_t o_yc = a.take(esb * d * n), o_tm = a.take(esb * 32 * 32), o_rh = a.take(esb * n * n),
+  const size_t o_yc = a.take(esb * d * n), o_tm = a.take(esb * QR_TM_ELEMS), o_rh = a.take(esb * n * n),
                o_rih = a.take(esb * n * n);
   int rc = ensure_ws(h, a.off + 256);
   if (rc != RL_OK) return rc;
@@ -937,7 +937,7 @@ int rl_step_qr_lowp(rl_handle h, int64_t d, int64_t n, const float* Y, int64_t l
   if (sketch_prec != RL_SKETCH_F32 && sketch_prec != RL_SKETCH_BF16) return RL_ERR_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;
   Arena a;
-  const size_t o_yf = a.take(sizeof(float) * d * n), o_tm = a.take(sizeof(float) * 32 * 32),
+  const size_t o_yf = a.take(sizeof(float) * d * n), o_tm = a.take(sizeof(float) * QR_TM_ELEMS),
                o_y = a.take(sizeof(double) * d * n), o_rh = a.take(sizeof(double) * n * n),
                o_rih = a.take(sizeof(double) * n * n);
   int rc = ensure_ws(h, a.off + 256);

@@ -59,7 +59,7 @@ def test_sketch_f32_rounding_bound(rl):
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-@pytest.mark.parametrize("d,n", [(800, 200), (150, 37), (2000, 120)])
+@pytest.mark.parametrize("d,n", [(800, 200), (150, 37), (2000, 120), (5000, 90)])
 def test_qr_lowp_backward_error(rl, prec, d, n):
     banner(f"qr {prec} d={d} n={n}")
     rng = np.random.default_rng(d + n)
