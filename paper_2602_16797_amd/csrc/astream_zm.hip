@@ -52,6 +52,18 @@ __device__ inline zm_v4d zm_mfma(double a, double b, zm_v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// v_mfma_f64_4x4x4f64: four independent 4 x 4 x 4 products, block beta =
+// (lane / 4) % 4; lane 16 k + 4 beta + i supplies A_beta(i, k), lane
+// 16 k + 4 beta + j supplies B_beta(k, j), and lane 16 i + 4 beta + j holds
+// D_beta(i, j) (checked on gfx950).  With the same A operand as a 16 x 16 x 4
+// tile (lane (q, t) = (lane / 16, lane % 16) supplies row t of the tile at
+// contraction index q), block beta takes the tile's rows 4 beta .. 4 beta + 3,
+// so one instruction forms a 16 x 4 tail tile: the last 1..4 columns of an
+// N dimension of 16 NT + 1..4 without a padded 16-column tile.
+__device__ inline double zm_mfma4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
 constexpr int ZM_AW_THREADS = 1024;  // 16 waves: one workgroup per CU holds W in LDS
 constexpr int ZM_G_THREADS = 256;    // 4 waves: 256 real columns per workgroup
 constexpr int ZM_G_RC = 32;          // rows of Tr per LDS chunk
@@ -65,7 +77,10 @@ constexpr int ZM_G_RC = 32;          // rows of Tr per LDS chunk
 // CPLX = false is the same kernel for real A (lda2 = lda, Ar = A, Wr = W):
 // the 16-byte pair a lane loads holds two consecutive columns k, k + 1, and
 // the B operands are W(k, j) and W(k + 1, j).
-template <bool CPLX, int NT, int KH>
+//
+// TAIL: the output columns 16 NT .. 16 NT + 3 form a 4-column tail tile
+// (zm_mfma4) instead of a padded 16-column tile.
+template <bool CPLX, int NT, int KH, bool TAIL = false>
 __global__ __launch_bounds__(ZM_AW_THREADS) void k_zm_aw(const double* __restrict__ A, int64_t lda2, int64_t m,
                                                          int n, int B, const double* __restrict__ W,
                                                          double* __restrict__ AW, const Ctl* __restrict__ ctl) {
@@ -82,9 +97,11 @@ __global__ __launch_bounds__(ZM_AW_THREADS) void k_zm_aw(const double* __restric
   const int nkb = (n2 + KBW - 1) / KBW;
   // this lane's output columns per N tile: complex: vector v, part r (Wr's
   // sign pattern); real: vector 16 nt + t
-  int vcol[NT];
+  constexpr int NTS = NT + (TAIL ? 1 : 0);  // B operands per step (the tail's last)
+  int vcol[NTS];
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) vcol[nt] = CPLX ? (16 * nt + t) >> 1 : 16 * nt + t;
+  if constexpr (TAIL) vcol[NT] = CPLX ? (16 * NT + (t & 3)) >> 1 : 16 * NT + (t & 3);
   const int rpart = t & 1;
   const int64_t ntile = (m + 31) / 32;
   const int64_t gw = (int64_t)blockIdx.x * (ZM_AW_THREADS / 64) + wave;
@@ -114,6 +131,7 @@ __global__ __launch_bounds__(ZM_AW_THREADS) void k_zm_aw(const double* __restric
       }
     };
     zm_v4d acc[2][NT];
+    double acct[2] = {0.0, 0.0};  // the tail tile (TAIL)
 #pragma unroll
     for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
@@ -124,12 +142,12 @@ __global__ __launch_bounds__(ZM_AW_THREADS) void k_zm_aw(const double* __restric
     auto step = [&](const double2 (&a)[2][KH], int kb) {
 #pragma unroll
       for (int h = 0; h < KH; ++h) {
-        double b_re[NT], b_im[NT];
+        double b_re[NTS], b_im[NTS];
         if constexpr (CPLX) {
           const int c = (KBW / 2) * kb + KH * q + h;
           const cd* Ws = reinterpret_cast<const cd*>(zm_lds);
 #pragma unroll
-          for (int nt = 0; nt < NT; ++nt) {
+          for (int nt = 0; nt < NTS; ++nt) {
             const bool wok = c < n && vcol[nt] < B;
             const int wi = wok ? c * B + vcol[nt] : 0;
             const cd w = Ws[wi];
@@ -141,7 +159,7 @@ __global__ __launch_bounds__(ZM_AW_THREADS) void k_zm_aw(const double* __restric
           // the pair holds columns k and k + 1 (n may be odd: k + 1 < n is checked on its own)
           const int k = KBW * kb + 2 * KH * q + 2 * h;
 #pragma unroll
-          for (int nt = 0; nt < NT; ++nt) {
+          for (int nt = 0; nt < NTS; ++nt) {
             const bool ok0 = k < n && vcol[nt] < B, ok1 = k + 1 < n && vcol[nt] < B;
             const double w0 = zm_lds[ok0 ? k * B + vcol[nt] : 0];
             const double w1 = zm_lds[ok1 ? (k + 1) * B + vcol[nt] : 0];
@@ -157,6 +175,10 @@ __global__ __launch_bounds__(ZM_AW_THREADS) void k_zm_aw(const double* __restric
           for (int nt = 0; nt < NT; ++nt) {
             acc[mt][nt] = zm_mfma(a[mt][h].x, b_re[nt], acc[mt][nt]);
             acc[mt][nt] = zm_mfma(a[mt][h].y, b_im[nt], acc[mt][nt]);
+          }
+          if constexpr (TAIL) {
+            acct[mt] = zm_mfma4(a[mt][h].x, b_re[NT], acct[mt]);
+            acct[mt] = zm_mfma4(a[mt][h].y, b_im[NT], acct[mt]);
           }
         }
       }
@@ -185,6 +207,15 @@ __global__ __launch_bounds__(ZM_AW_THREADS) void k_zm_aw(const double* __restric
           const int col = 16 * nt + t;
           if (orow < m && col < B2) AW[orow * B2 + col] = acc[mt][nt][r];
         }
+    if constexpr (TAIL) {
+      // the tail tile: lane (q, t) holds row 4 (t / 4) + q, column 16 NT + t % 4
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        const int64_t orow = r0 + 16 * mt + 4 * (t >> 2) + q;
+        const int col = 16 * NT + (t & 3);
+        if (orow < m && col < B2) AW[orow * B2 + col] = acct[mt];
+      }
+    }
   }
 }
 
@@ -194,8 +225,9 @@ __global__ __launch_bounds__(ZM_AW_THREADS) void k_zm_aw(const double* __restric
 // Tr plane g goes to record plane g (init: the single plane A_W to plane 0).
 //
 // CPLX = false is the same kernel for real A (Ar = A, Tr = [A_V A_X A_W], no
-// 2 x 2 combination: Gr is A^T T itself).
-template <bool CPLX, int NT>
+// 2 x 2 combination: Gr is A^T T itself).  TAIL: the Tr columns 16 NT ..
+// 16 NT + 3 form a 4-column tail tile (zm_mfma4) instead of a padded one.
+template <bool CPLX, int NT, bool TAIL = false>
 __global__ __launch_bounds__(ZM_G_THREADS, 2) void k_zm_g(const double* __restrict__ A, int64_t lda2, int64_t m, int n,
                                                        int B, const double* __restrict__ P0,
                                                        const double* __restrict__ P1, const double* __restrict__ P2,
@@ -203,7 +235,8 @@ __global__ __launch_bounds__(ZM_G_THREADS, 2) void k_zm_g(const double* __restri
                                                        int64_t rows_per_range, int64_t nrr, int nslice,
                                                        const Ctl* __restrict__ ctl) {
   if (ctl != nullptr && ctl->done) return;
-  constexpr int TW = 16 * NT;  // Tr columns staged per row
+  constexpr int NTS = NT + (TAIL ? 1 : 0);  // staged 16-column groups (the tail's last)
+  constexpr int TW = 16 * NTS;               // Tr columns staged per row
   __shared__ double Ts[2][ZM_G_RC * TW];
   // block -> (row range, column slice): the slices of a row range are
   // neighbouring blocks of one XCD, so the staged rows of Tr come from L2
@@ -251,11 +284,12 @@ __global__ __launch_bounds__(ZM_G_THREADS, 2) void k_zm_g(const double* __restri
       const int e = threadIdx.x + i * ZM_G_THREADS;
       if (e < ZM_G_RC * TW) {
         const int rw = e / TW, col = e - (e / TW) * TW;
-        Ts[buf][rw * TW + (col & 15) * NT + (col >> 4)] = valid(e, cb) ? v[i] : 0.0;
+        Ts[buf][rw * TW + (col & 15) * NTS + (col >> 4)] = valid(e, cb) ? v[i] : 0.0;
       }
     }
   };
   zm_v4d acc[4][NT];
+  double acct[4] = {0.0, 0.0, 0.0, 0.0};  // the tail tile (TAIL)
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -292,7 +326,7 @@ __global__ __launch_bounds__(ZM_G_THREADS, 2) void k_zm_g(const double* __restri
       const double* Tb = Ts[buf];
 #pragma unroll
       for (int ks = 0; ks < ZM_G_RC / 4; ++ks) {
-        const double* tr = Tb + (4 * ks + q) * TW + t * NT;
+        const double* tr = Tb + (4 * ks + q) * TW + t * NTS;
         double bv[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) bv[nt] = tr[nt];
@@ -304,6 +338,12 @@ __global__ __launch_bounds__(ZM_G_THREADS, 2) void k_zm_g(const double* __restri
         for (int u = 0; u < 4; ++u)
 #pragma unroll
           for (int nt = 0; nt < NT; ++nt) acc[u][nt] = zm_mfma(av[u], bv[nt], acc[u][nt]);
+        if constexpr (TAIL) {
+          // Tr column 16 NT + t % 4, the same for the four blocks
+          const double bt = Tb[(4 * ks + q) * TW + (t & 3) * NTS + NT];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) acct[u] = zm_mfma4(av[u], bt, acct[u]);
+        }
         loada(ab[ks & 3], cb + 4 * ks + 16 + q);
       }
     }
@@ -339,6 +379,25 @@ __global__ __launch_bounds__(ZM_G_THREADS, 2) void k_zm_g(const double* __restri
             dst[1] = im;
           }
         }
+    if constexpr (TAIL) {
+      // tail tile: lane (q, t) holds real column kw + 16 (t / 4) + 4 q + u of
+      // A against Tr column 16 NT + t % 4; u = 2h, 2h + 1 are the re and im
+      // rows of complex column c, and Tr columns 2v, 2v + 1 lanes t, t + 1
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const double x0 = acct[2 * h], x1 = acct[2 * h + 1];
+        const double y0 = dpp_d<0xB1>(x0), y1 = dpp_d<0xB1>(x1);
+        const int c = (kw + 16 * (t >> 2) + 4 * q) / 2 + h;
+        const int colr = 16 * NT + (t & 3);
+        if (rp == 0 && c < n && colr < ncol) {
+          const int g = colr / B2, vv = (colr - g * B2) >> 1;
+          const int pl = init ? 0 : g;
+          double* dst = gp + (int64_t)pl * plane + 2 * ((int64_t)c * B + vv);
+          dst[0] = x0 + y1;
+          dst[1] = y0 - x1;
+        }
+      }
+    }
     // the planes this pass does not form, and the error plane, are zero
     for (int cc = lane; cc < 32 * B; cc += 64) {
       const int c = kw / 2 + cc / B, vv = cc - (cc / B) * B;
@@ -368,6 +427,17 @@ __global__ __launch_bounds__(ZM_G_THREADS, 2) void k_zm_g(const double* __restri
             gp[(int64_t)(init ? 0 : g) * plane + (int64_t)c * B + vv] = acc[u][nt][r];
           }
         }
+    if constexpr (TAIL) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = kw + 16 * (t >> 2) + 4 * q + u;
+        const int colr = 16 * NT + (t & 3);
+        if (c < n && colr < ncol) {
+          const int g = colr / B2, vv = colr - g * B2;
+          gp[(int64_t)(init ? 0 : g) * plane + (int64_t)c * B + vv] = acct[u];
+        }
+      }
+    }
     for (int cc = lane; cc < 64 * B; cc += 64) {
       const int c = kw + cc / B, vv = cc - (cc / B) * B;
       if (c < n) {
@@ -389,24 +459,65 @@ bool astream_rm_fits(int B, int n, bool aligned, int64_t lds_max) {
 
 constexpr int ZM_AW_KH = 2;  // 32 contiguous bytes per row and lane per k block
 
-template <bool CPLX, int NT>
+template <bool CPLX, int NT, bool TAIL = false>
 static hipError_t zm_aw_go(hipStream_t st, int grid, const double* A, int64_t lda2, int64_t m, int n, int B,
                            const double* W, double* AW, const Ctl* ctl) {
   const size_t lds = (CPLX ? 16 : 8) * (size_t)n * B;
-  const hipError_t e = hipFuncSetAttribute((const void*)k_zm_aw<CPLX, NT, ZM_AW_KH>,
+  const hipError_t e = hipFuncSetAttribute((const void*)k_zm_aw<CPLX, NT, ZM_AW_KH, TAIL>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_zm_aw<CPLX, NT, ZM_AW_KH>), dim3((unsigned)grid), dim3(ZM_AW_THREADS), lds, st, A, lda2, m,
-                     n, B, W, AW, ctl);
+  hipLaunchKernelGGL((k_zm_aw<CPLX, NT, ZM_AW_KH, TAIL>), dim3((unsigned)grid), dim3(ZM_AW_THREADS), lds, st, A,
+                     lda2, m, n, B, W, AW, ctl);
   return hipGetLastError();
 }
 
-template <bool CPLX, int NT>
+// A W for B2 output columns: one 16-column tile, one and a 4-column tail
+// (17..20), or two tiles
+template <bool CPLX>
+static hipError_t zm_aw_cols(hipStream_t st, int grid, const double* A, int64_t lda2, int64_t m, int n, int B,
+                             const double* W, double* AW, const Ctl* ctl) {
+  const int B2 = CPLX ? 2 * B : B;
+  if (B2 <= 16) return zm_aw_go<CPLX, 1>(st, grid, A, lda2, m, n, B, W, AW, ctl);
+  if (B2 <= 20) return zm_aw_go<CPLX, 1, true>(st, grid, A, lda2, m, n, B, W, AW, ctl);
+  return zm_aw_go<CPLX, 2>(st, grid, A, lda2, m, n, B, W, AW, ctl);
+}
+
+template <bool CPLX, int NT, bool TAIL = false>
 static void zm_g_go(hipStream_t st, int64_t nblk, const double* A, int64_t lda2, int64_t m, int n, int B,
                     const double* P0, const double* P1, const double* P2, int np, int init, double* Gpart,
                     int64_t rows, int64_t nrr, int nslice, const Ctl* ctl) {
-  hipLaunchKernelGGL((k_zm_g<CPLX, NT>), dim3((unsigned)nblk), dim3(ZM_G_THREADS), 0, st, A, lda2, m, n, B, P0, P1,
-                     P2, np, init, Gpart, rows, nrr, nslice, ctl);
+  hipLaunchKernelGGL((k_zm_g<CPLX, NT, TAIL>), dim3((unsigned)nblk), dim3(ZM_G_THREADS), 0, st, A, lda2, m, n, B, P0,
+                     P1, P2, np, init, Gpart, rows, nrr, nslice, ctl);
+}
+
+// The Gram kernel for ncol used Tr columns: full 16-column tiles, and a
+// 4-column tail tile when 1..4 columns are left past at least one full tile.
+template <bool CPLX>
+static bool zm_g_cols(hipStream_t st, int64_t nblk, const double* A, int64_t lda2, int64_t m, int n, int B,
+                      const double* P0, const double* P1, const double* P2, int np, int init, double* Gpart,
+                      int64_t rows, int64_t nrr, int nslice, const Ctl* ctl) {
+  const int ncol = np * (CPLX ? 2 * B : B);
+  const int full = ncol / 16, rest = ncol % 16;
+#define RL_ZMG(NTV, TL) \
+  zm_g_go<CPLX, NTV, TL>(st, nblk, A, lda2, m, n, B, P0, P1, P2, np, init, Gpart, rows, nrr, nslice, ctl)
+  if (full >= 1 && rest >= 1 && rest <= 4) {
+    switch (full) {
+      case 1: RL_ZMG(1, true); break;
+      case 2: RL_ZMG(2, true); break;
+      case 3: RL_ZMG(3, true); break;
+      default: return false;
+    }
+  } else {
+    switch ((ncol + 15) / 16) {
+      case 1: RL_ZMG(1, false); break;
+      case 2: RL_ZMG(2, false); break;
+      case 3: RL_ZMG(3, false); break;
+      case 4: RL_ZMG(4, false); break;
+      default: return false;
+    }
+  }
+#undef RL_ZMG
+  return true;
 }
 
 // A_W = A W, then the partial records of A^* [A_V A_X A_W] (init: A^* A_W in
@@ -423,11 +534,7 @@ static bool zm_dispatch(int init, int B, hipStream_t st, int64_t nrr, const void
   int grid = n_cu > 0 ? n_cu : 256;
   if ((int64_t)grid * (ZM_AW_THREADS / 64) > tiles) grid = (int)((tiles + 15) / 16);
   if (grid < 1) grid = 1;
-  hipError_t e;
-  if (B2 <= 16)
-    e = zm_aw_go<CPLX, 1>(st, grid, Ad, lda2, m, n, B, (const double*)W, (double*)AW, ctl);
-  else
-    e = zm_aw_go<CPLX, 2>(st, grid, Ad, lda2, m, n, B, (const double*)W, (double*)AW, ctl);
+  const hipError_t e = zm_aw_cols<CPLX>(st, grid, Ad, lda2, m, n, B, (const double*)W, (double*)AW, ctl);
   if (e != hipSuccess) return false;
   // the second kernel's start, for timing the Gram contraction on its own
   if (mid != nullptr && hipEventRecord(mid, st) != hipSuccess) return false;
@@ -438,14 +545,8 @@ static bool zm_dispatch(int init, int B, hipStream_t st, int64_t nrr, const void
   const double* P1 = init ? nullptr : (const double*)AXp;
   const double* P2 = init ? nullptr : (const double*)AW;
   const int np = init ? 1 : 3;
-  const int nt = (np * B2 + 15) / 16;
-  switch (nt) {
-    case 1: zm_g_go<CPLX, 1>(st, nblk, Ad, lda2, m, n, B, P0, P1, P2, np, init, Gpart, rows, nrr, nslice, ctl); break;
-    case 2: zm_g_go<CPLX, 2>(st, nblk, Ad, lda2, m, n, B, P0, P1, P2, np, init, Gpart, rows, nrr, nslice, ctl); break;
-    case 3: zm_g_go<CPLX, 3>(st, nblk, Ad, lda2, m, n, B, P0, P1, P2, np, init, Gpart, rows, nrr, nslice, ctl); break;
-    case 4: zm_g_go<CPLX, 4>(st, nblk, Ad, lda2, m, n, B, P0, P1, P2, np, init, Gpart, rows, nrr, nslice, ctl); break;
-    default: return false;
-  }
+  if (!zm_g_cols<CPLX>(st, nblk, Ad, lda2, m, n, B, P0, P1, P2, np, init, Gpart, rows, nrr, nslice, ctl))
+    return false;
   return hipGetLastError() == hipSuccess;
 }
 
@@ -462,11 +563,9 @@ static bool zm_gram(int B, hipStream_t st, int64_t nrr, const void* A, int64_t l
   const int nslice = (n2 + 255) / 256;
   const int64_t nblk = ((nrr + 7) / 8) * 8 * nslice;
   const double* P = (const double*)P0;
-  switch ((B2 + 15) / 16) {
-    case 1: zm_g_go<CPLX, 1>(st, nblk, Ad, lda2, m, n, B, P, nullptr, nullptr, 1, 1, Gpart, rows, nrr, nslice, ctl); break;
-    case 2: zm_g_go<CPLX, 2>(st, nblk, Ad, lda2, m, n, B, P, nullptr, nullptr, 1, 1, Gpart, rows, nrr, nslice, ctl); break;
-    default: return false;
-  }
+  (void)B2;
+  if (!zm_g_cols<CPLX>(st, nblk, Ad, lda2, m, n, B, P, nullptr, nullptr, 1, 1, Gpart, rows, nrr, nslice, ctl))
+    return false;
   return hipGetLastError() == hipSuccess;
 }
 
@@ -481,12 +580,8 @@ static bool zm_aw_only(int B, hipStream_t st, const void* A, int64_t lda, int64_
   int grid = n_cu > 0 ? n_cu : 256;
   if ((int64_t)grid * (ZM_AW_THREADS / 64) > tiles) grid = (int)((tiles + 15) / 16);
   if (grid < 1) grid = 1;
-  hipError_t e;
-  if (B2 <= 16)
-    e = zm_aw_go<CPLX, 1>(st, grid, Ad, lda2, m, n, B, (const double*)W, (double*)AW, ctl);
-  else
-    e = zm_aw_go<CPLX, 2>(st, grid, Ad, lda2, m, n, B, (const double*)W, (double*)AW, ctl);
-  return e == hipSuccess;
+  (void)B2;
+  return zm_aw_cols<CPLX>(st, grid, Ad, lda2, m, n, B, (const double*)W, (double*)AW, ctl) == hipSuccess;
 }
 
 bool dispatch_zm_aw_only(bool cplx, int B, hipStream_t st, const void* A, int64_t lda, int64_t m, int n,
