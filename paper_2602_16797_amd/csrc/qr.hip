@@ -580,6 +580,123 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr_update(T* Y, int ld, int d, i
   }
 }
 
+// The trailing update of the reduced-precision (FP32) factorisation on the
+// FP32 matrix cores: C <- C - V T^T (V^T C) on 16 trailing columns per
+// workgroup, the rows walked in chunks of QRM_RC staged in LDS.  First V^T C
+// (32 x 16; wave w takes V columns 16 (w & 1) .. + 15 over the chunk's row
+// half w >> 1, the halves summed at the end), then W2 = T^T (V^T C) on the
+// vector units, then C -= V W2 chunk by chunk (wave w takes rows 16 w ..
+// 16 w + 15 of the chunk).  BF16IN: V, C and W2 enter the products rounded
+// to bfloat16 (v_mfma_f32_16x16x16bf16), the sums and C stay FP32; else FP32
+// inputs (v_mfma_f32_16x16x4f32).  Lane layouts (checked on gfx950): FP32:
+// lane 16 k + i supplies A(i, k), lane 16 k + j supplies B(k, j); BF16:
+// lane 16 (k / 4) + i supplies A(i, k) in its element k % 4, and B alike;
+// both: register r of lane l holds D(4 (l / 16) + r, l % 16).
+typedef float qrm_v4f __attribute__((ext_vector_type(4)));
+typedef short qrm_v4s __attribute__((ext_vector_type(4)));
+constexpr int QRM_RC = 64;  // rows per staged chunk
+constexpr int QRM_CB = 16;  // trailing columns per workgroup
+
+__device__ inline short qrm_bf16(float x) { return (short)(__float_as_uint(bf16_round(x)) >> 16); }
+
+template <bool BF16IN>
+__device__ inline qrm_v4f qrm_mma(const float* a4, const float* b4, qrm_v4f c) {
+  // a4 / b4: this lane's 4 (BF16) or 1 (FP32) operand values
+  if constexpr (BF16IN) {
+    qrm_v4s a, b;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      a[e] = qrm_bf16(a4[e]);
+      b[e] = qrm_bf16(b4[e]);
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  } else {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a4[0], b4[0], c, 0, 0, 0);
+  }
+}
+
+template <bool BF16IN>
+__global__ __launch_bounds__(256) void k_qr_update_mfma(float* __restrict__ Y, int ld, int d, int n, int p, int nb,
+                                                        const float* __restrict__ Tm) {
+  __shared__ float Vs[QRM_RC][QR_NB + 1];
+  __shared__ float Cs[QRM_RC][QRM_CB + 1];
+  __shared__ float Wh[2][QR_NB][QRM_CB];  // the two row halves' V^T C
+  __shared__ float W2[QR_NB][QRM_CB + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int c0 = p + nb + blockIdx.x * QRM_CB;
+  const int ncb = min(QRM_CB, n - c0);
+  // K steps per MFMA: 16 rows (BF16, 4 per lane) or 4 rows (FP32, 1 per lane)
+  constexpr int KS = BF16IN ? 16 : 4;
+  auto stage = [&](int r0) {
+    for (int e = tid; e < QRM_RC * QR_NB; e += 256) {
+      const int rr = e % QRM_RC, q = e / QRM_RC, r = r0 + rr;
+      Vs[rr][q] = (q < nb && r < d) ? vpanel(Y, ld, p, q, r) : 0.0f;
+    }
+    for (int e = tid; e < QRM_RC * QRM_CB; e += 256) {
+      const int rr = e % QRM_RC, c = e / QRM_RC, r = r0 + rr;
+      Cs[rr][c] = (c < ncb && r < d) ? Y[(int64_t)(c0 + c) * ld + r] : 0.0f;
+    }
+  };
+  // pass 1: V^T C
+  qrm_v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  const int mi = wave & 1, kh = wave >> 1;
+  for (int r0 = p; r0 < d; r0 += QRM_RC) {
+    __syncthreads();
+    stage(r0);
+    __syncthreads();
+#pragma unroll
+    for (int k0 = 0; k0 < QRM_RC / 2; k0 += KS) {
+      float a4[4], b4[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        // A(i, k) = V(row k, column 16 mi + i), B(k, j) = C(row k, column j)
+        const int kk = BF16IN ? 4 * lk + e : lk;
+        const int row = kh * (QRM_RC / 2) + k0 + kk;
+        a4[e] = (BF16IN || e == 0) ? Vs[row][16 * mi + li] : 0.0f;
+        b4[e] = (BF16IN || e == 0) ? Cs[row][li] : 0.0f;
+      }
+      acc = qrm_mma<BF16IN>(a4, b4, acc);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) Wh[kh][16 * mi + 4 * lk + r][li] = acc[r];
+  __syncthreads();
+  // W2 = T^T (V^T C): W2[q][c] = sum over l <= q of T(l, q) (V^T C)[l][c]
+  for (int e = tid; e < QR_NB * QRM_CB; e += 256) {
+    const int q = e / QRM_CB, c = e % QRM_CB;
+    float sacc = 0.0f;
+    for (int l = 0; l <= q && l < nb; ++l) sacc = fmaf(Tm[l + q * QR_NB], Wh[0][l][c] + Wh[1][l][c], sacc);
+    W2[q][c] = (q < nb) ? sacc : 0.0f;
+  }
+  // pass 2: C -= V W2, wave w on rows 16 w .. 16 w + 15 of each chunk
+  for (int r0 = p; r0 < d; r0 += QRM_RC) {
+    __syncthreads();
+    stage(r0);
+    __syncthreads();
+    qrm_v4f dv = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k0 = 0; k0 < QR_NB; k0 += KS) {
+      float a4[4], b4[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        // A(i, k) = V(row 16 w + i, column k), B(k, j) = W2(k, j)
+        const int kk = k0 + (BF16IN ? 4 * lk + e : lk);
+        a4[e] = (BF16IN || e == 0) ? Vs[16 * wave + li][kk] : 0.0f;
+        b4[e] = (BF16IN || e == 0) ? W2[kk][li] : 0.0f;
+      }
+      dv = qrm_mma<BF16IN>(a4, b4, dv);
+    }
+    // lane l, register r: row 16 w + 4 (l / 16) + r of the chunk, column l % 16
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = 16 * wave + 4 * lk + r;
+      const int row = r0 + rr;
+      if (row < d && li < ncb) Y[(int64_t)(c0 + li) * ld + row] = Cs[rr][li] - dv[r];
+    }
+  }
+}
+
 template <typename T>
 __global__ void k_qr_extract(const T* __restrict__ Y, int ld, int n, T* __restrict__ Rrow, T* __restrict__ RH) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -848,9 +965,14 @@ static void qr_factor(hipStream_t st, T* Y, int d, int n, T* Tm) {
         hipLaunchKernelGGL(k_qr_panel<T>, dim3(1), dim3(QR_THREADS), 0, st, Y, d, d, n, p, nb, Tm);
     }
     const int rest = n - p - nb;
-    if (rest > 0)
-      hipLaunchKernelGGL((k_qr_update<T, BF16IN>), dim3((rest + QR_CB - 1) / QR_CB), dim3(QR_THREADS), 0, st, Y, d,
-                         d, n, p, nb, (const T*)Tm);
+    if (rest > 0) {
+      if constexpr (sizeof(T) == 4)  // the reduced-precision factorisation: on the matrix cores
+        hipLaunchKernelGGL((k_qr_update_mfma<BF16IN>), dim3((rest + QRM_CB - 1) / QRM_CB), dim3(256), 0, st,
+                           (float*)Y, d, d, n, p, nb, (const float*)Tm);
+      else
+        hipLaunchKernelGGL((k_qr_update<T, BF16IN>), dim3((rest + QR_CB - 1) / QR_CB), dim3(QR_THREADS), 0, st, Y,
+                           d, d, n, p, nb, (const T*)Tm);
+    }
     p += nb;
   }
 }
