@@ -203,7 +203,7 @@ def served(args):
     gb = sum(q.m * q.n * 8 for q in reqs) / 1e9
     log(f"staged {gb:.1f} GB in {time.perf_counter() - t0:.1f} s")
     budget = int(args.served_budget_gb * (1 << 30))
-    kw = dict(sketch_prec=args.sketch_prec)
+    kw = dict(sketch_prec=args.sketch_prec, lock=args.lock)
 
     def run(srv, arrivals):
         tickets = []
@@ -246,7 +246,7 @@ def served(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "served-256-poisson", "requests": len(reqs), "slots": args.served_slots,
-                   "hbm_budget_gb": args.served_budget_gb, "sketch_prec": args.sketch_prec,
+                   "hbm_budget_gb": args.served_budget_gb, "sketch_prec": args.sketch_prec, "lock": args.lock,
                    "a_bytes_gb": round(gb, 2)},
         "lambda_per_s": round(lam, 3),
         "p50_ms": round(float(np.percentile(lat, 50)), 3),
@@ -277,6 +277,9 @@ def main(argv=None):
     ap.add_argument("--no-dot2", action="store_true", help="same as --dot2 off")
     ap.add_argument("--cpu-sample-rows", type=int, default=0,
                     help="rows of A in the oracle's timed sample (default: about 15 s of oracle work)")
+    ap.add_argument("--lock", action="store_true",
+                    help="locking of converged columns (Sec. 2.3; off in the paper's runs): a column whose residual "
+                         "meets the tolerance gets no more search directions, and the solve ends once all are locked")
     ap.add_argument("--orth", default="cgs2", choices=["cgs2", "svqb"],
                     help="Orth of the new search block after its block projections: CGS2 (the method) or SVQB")
     ap.add_argument("--loop-precond", default="sketch", choices=["sketch", "diag", "none"],
@@ -321,7 +324,7 @@ def main(argv=None):
     log(f"drew A in {time.perf_counter() - t_draw:.1f} s")
     es = 16 if cplx else 8
     kw = dict(seed=sseed, d=d, zeta=zeta, sketch_prec=args.sketch_prec, dot2=dot2,
-              loop_precond=args.loop_precond, orth=args.orth)
+              loop_precond=args.loop_precond, orth=args.orth, lock=args.lock)
     if args.block:
         kw["block"] = args.block
 
@@ -400,7 +403,8 @@ def main(argv=None):
     n_g = sum(r.n_pass_g for r in results)
     traffic = (measured_traffic(args.workload)
                if (args.sketch_prec == "f64" and dot2 == DEFAULT_DOT2.get(args.workload, True)
-                   and args.loop_precond == "sketch" and args.orth == "cgs2" and not args.block) else None)
+                   and args.loop_precond == "sketch" and args.orth == "cgs2" and not args.block
+                   and not args.lock) else None)
     if n_g > 0:
         # the second kernel of the two-read passes is the Gram contraction on
         # the matrix cores; in a solve it forms one m x b block per launch
@@ -465,7 +469,8 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": args.workload, "m": m, "n": n, "k": k, "block": last.block, "d": d, "zeta": zeta,
                    "spectrum": list(spec), "stop_rule": "paper", "dot2": dot2,
-                   "sketch_prec": args.sketch_prec, "loop_precond": args.loop_precond, "orth": args.orth},
+                   "sketch_prec": args.sketch_prec, "loop_precond": args.loop_precond, "orth": args.orth,
+                   "lock": args.lock},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "detail": {"iters": last.iters, "a_passes": last.a_passes, "matvecs": last.a_passes * last.block,

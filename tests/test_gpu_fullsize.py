@@ -110,34 +110,45 @@ def _sampled_rows_gate(A, sg, Vg, Ug, normA, seed=7):
     assert np.max(np.abs(Av - Ug[rows] * sg[None, :])) <= 1e-12 * normA
 
 
-def test_full_size_complex_nullspace_block10(rl):
+@pytest.mark.parametrize("lock", [False, True])
+def test_full_size_complex_nullspace_block10(rl, lock):
     """The bench's default workload at full size, in its launch
     configuration: 10^6 x 1000 complex, rank 990 plus complex Gaussian noise
     of std 1e-14, k = b = 10, d = 3n, plain sums (matrix-core passes,
-    late-residual loop).  The noise moves the null space's sigma to about
-    noise sqrt(m) = 1e-11, so sigma is gated at 10 noise sqrt(m); the
-    subspace against the planted null space at 1e-6 (the noise moves it by
-    about noise (sqrt(m) + sqrt(n)) / sigma_990 = 1e-7); residual and sampled
-    rows at 1e-12 ||A||."""
+    late-residual loop), without and with locking.  The noise moves the null
+    space's sigma to about noise sqrt(m) = 1e-11, so sigma is gated at
+    10 noise sqrt(m); the subspace against the planted null space at 1e-6
+    without locking (the noise moves it by about
+    noise (sqrt(m) + sqrt(n)) / sigma_990 = 1e-7) and, with locking, which
+    stops once every residual meets Sigma~(1,1)^2 tau, at the Davis-Kahan
+    bound of that tolerance, sqrt(k) Sigma~(1,1)^2 tau / sigma_990^2
+    (about 4e-6); residual and sampled rows at 1e-12 ||A||."""
     from workloads import spectrum_nullspace
     m, n, k, d, noise = 1_000_000, 1000, 10, 3000, 1e-14
-    banner(f"full size complex null space m={m} n={n} k={k}")
+    banner(f"full size complex null space m={m} n={n} k={k} lock={lock}")
     sig = spectrum_nullspace(n, k, 1e-4)
     A, Vp, _ = planted_torch(m, n, sig, 1003, device="cuda", is_complex=True, noise_std=noise)
     torch.cuda.synchronize()
-    r = rl.rl_svds_smallest(A, k, seed=2003, d=d, zeta=8, dot2=False)
+    r = rl.rl_svds_smallest(A, k, seed=2003, d=d, zeta=8, dot2=False, lock=lock)
     torch.cuda.synchronize()
     normA = float(np.max(sig))
     sg, Vg, Ug = to_np(r.sigma), to_np(r.V), to_np(r.U)
     with torch.no_grad():
         res = torch.linalg.norm(A @ r.V - r.U * r.sigma[None, :], dim=0).max().item()
     ang = sin_angle(Vg, to_np(Vp)[:, np.argsort(sig)[:k]])
-    banner(f"  iters {r.iters} status {r.status}; sigma max {sg.max():.2e}; residual {res:.2e}; sin angle {ang:.2e}")
+    banner(f"  iters {r.iters} status {r.status} locked {r.n_locked}; sigma max {sg.max():.2e}; residual {res:.2e}; "
+           f"sin angle {ang:.2e}")
     assert r.status in (0, 1) and r.iters >= 1
     assert np.all(sg <= 10 * noise * np.sqrt(m)) and np.all(np.diff(sg) >= 0)
     assert res <= 1e-12 * normA
     assert np.linalg.norm(Vg.conj().T @ Vg - np.eye(k)) <= 1e-12
-    assert ang <= 1e-6
+    if lock:
+        tau = 2.0 * np.sqrt(n) * 2.0 ** -52
+        sig_next = np.sort(sig)[k]
+        assert r.status == 0 and r.n_locked == k
+        assert ang <= np.sqrt(k) * r.sigma1 ** 2 * tau / sig_next ** 2
+    else:
+        assert ang <= 1e-6
     _sampled_rows_gate(A, sg, Vg, Ug, normA)
     del A
     torch.cuda.empty_cache()
