@@ -260,7 +260,7 @@ hipError_t launch_astream_pass(hipStream_t st, bool cplx, int B, bool dot2, cons
   int64_t np = nb * 4;  // partial records
   bool ok;
   const bool aligned = (lda % 2 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
-  if (!cplx && astream_r2_fits(B, n, aligned)) {
+  if (!cplx && astream_r2_fits(B, n, aligned, m, lda)) {
     nb = astream_r2_blocks(m);
     np = nb;
     ok = dispatch_astream_r2(dot2, init, B, st, nb, (const double*)A, lda, m, n, (const double*)W, (double*)AW,

@@ -192,36 +192,23 @@ struct BatchShape {
   static constexpr int LOG2V = V2 == 1 ? 0 : V2 == 2 ? 1 : V2 == 4 ? 2 : V2 == 8 ? 3 : V2 == 16 ? 4 : V2 == 32 ? 5 : 6;
 };
 
-// rows [rb, rb+RB) of the wave's batch, columns (2 lane + 128 s, +1); zero
-// for rows at or past r1.  n is even, A 16-byte aligned with even lda.  A lane
-// whose column pair lies past n reads pair 0 of the same row instead (cl[s]);
-// its W entries are zero, so it adds nothing to the row sums, and its column
-// sums are never written.  Row validity is wave-uniform, so the only branch
-// is a scalar one.
-template <int RB>
-__device__ inline void r2_load(double2 (&a)[RB][2], const double* __restrict__ A, int64_t lda, const int (&cl)[2],
-                               int64_t rb, int64_t r1) {
-#pragma unroll
-  for (int q = 0; q < RB; ++q) {
-    const int64_t row = rb + q;
-    if (row < r1) {
-#pragma unroll
-      for (int s = 0; s < 2; ++s) a[q][s] = ld_stream2(A + row * lda + cl[s]);
-    } else {
-#pragma unroll
-      for (int s = 0; s < 2; ++s) a[q][s] = make_double2(0.0, 0.0);
-    }
-  }
-}
-
 // Real data, even n <= 256, b <= 2, 16-byte aligned rows: lane l owns the column
 // pairs (2l, 2l+1) and (2l+128, 2l+129).  Each wave walks batches of RB rows
-// and loads the next batch before it works on the current one.  The row sums
-// of the batch are reduced together by the compensated transpose-reduction
-// and broadcast with scalar readlanes.  The four waves' column sums are
-// combined through LDS (compensated for the A_V group) and each workgroup
-// writes one record [G_V | G_X | G_W | G_V error] of 4 n b doubles.
-// INIT: the start pass (A_V = A V_0 and A^* A_V only).
+// with two register buffers: the loads of the next batch are issued before
+// the current batch is worked on (the scheduling barrier keeps them there), so
+// one batch is always in flight.  A is read through a bounds-checked buffer
+// resource that covers the workgroup's rows: rows past its end read as zero,
+// so no branch guards the loads, and a lane whose column pair lies past n
+// reads pair 0 of the row (its W entries are zero, its column sums are never
+// written).  The row values of A_V and A_X are wave-uniform scalar loads (row
+// indices clamped into the workgroup's range; the clamped rows multiply zero
+// rows of A).  The row sums of a batch are reduced together by the compensated
+// transpose-reduction; the lanes that end up holding a finished sum store it
+// to A_W, and the sums are broadcast with scalar readlanes for the column sums.
+// The four waves' column sums are combined through LDS (compensated for the
+// A_V group) and each workgroup writes one record [G_V | G_X | G_W | G_V
+// error] of 4 n b doubles.  INIT: the start pass (A_V = A V_0 and A^* A_V
+// only).  rows_per_block * lda * 8 must stay below 2^31 (the buffer's range).
 template <int B, bool DOT2, bool INIT>
 __global__ __launch_bounds__(256) void k_astream_r2(const double* __restrict__ A, int64_t lda, int64_t m, int n,
                                                     const double* __restrict__ W, double* __restrict__ AW,
@@ -231,6 +218,7 @@ __global__ __launch_bounds__(256) void k_astream_r2(const double* __restrict__ A
   if (ctl != nullptr && ctl->done) return;
   using SH = BatchShape<B>;
   constexpr int RB = SH::RB, V = SH::V, V2 = SH::V2, LOG2V = SH::LOG2V;
+  constexpr int STEP = 4 * RB;
   __shared__ double red[4][2][256 * B];
   const int lane = threadIdx.x & 63, wave = wave_index();
   const bool has_x = AXp != nullptr;
@@ -252,33 +240,46 @@ __global__ __launch_bounds__(256) void k_astream_r2(const double* __restrict__ A
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t r1 = (r0 + rows_per_block < m) ? r0 + rows_per_block : m;
   int64_t rb = r0 + (int64_t)wave * RB;
-  int cl[2];
+  const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<double*>(A + r0 * lda), 0, (int)((r1 - r0) * lda * 8), BUFFER_RSRC_WORD3);
+  const uint32_t rowbytes = (uint32_t)lda * 8u;
+  uint32_t voff[2];
 #pragma unroll
-  for (int s = 0; s < 2; ++s) cl[s] = (2 * lane + 128 * s < n) ? 2 * lane + 128 * s : 0;
-  double2 a[RB][2], an[RB][2];
-  r2_load<RB>(an, A, lda, cl, rb, r1);
-  double avn = 0.0, axn = 0.0;
-  if (!INIT && lane < V && rb + lane / B < r1) {
-    avn = AVp[rb * B + lane];
-    if (has_x) axn = AXp[rb * B + lane];
-  }
-  for (; rb < r1; rb += 4 * RB) {
+  for (int s = 0; s < 2; ++s) voff[s] = 16u * (uint32_t)((2 * lane + 128 * s < n) ? lane + 64 * s : 0);
+  auto load_rows = [&](double2 (&a)[RB][2], int64_t r) {
+    const uint32_t sb = (uint32_t)(r - r0) * rowbytes;
 #pragma unroll
-    for (int q = 0; q < RB; ++q) {
-      a[q][0] = an[q][0];
-      a[q][1] = an[q][1];
+    for (int q = 0; q < RB; ++q)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) a[q][s] = ld_buf_stream2(rsrc, voff[s], sb + q * rowbytes);
+  };
+  auto load_uniform = [&](const double* __restrict__ P, int64_t r, double (&o)[V]) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      int64_t i = r + v / B;
+      if (i >= r1) i = r1 - 1;
+      o[v] = P[i * B + v % B];
     }
-    const double avl = avn, axl = axn;
-    const int64_t rn = rb + 4 * RB;
-    r2_load<RB>(an, A, lda, cl, rn, r1);
-    if (!INIT) {
-      avn = 0.0;
-      axn = 0.0;
-      if (lane < V && rn + lane / B < r1) {
-        avn = AVp[rn * B + lane];
-        if (has_x) axn = AXp[rn * B + lane];
+  };
+  auto load_av_ax = [&](int64_t r, double (&av)[V], double (&ax)[V]) {
+    if constexpr (!INIT) {
+      load_uniform(AVp, r, av);
+      if (has_x) {
+        load_uniform(AXp, r, ax);
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) ax[v] = 0.0;
       }
     }
+  };
+  // after the transpose-reduction lane l holds row sum v when its top LOG2V
+  // bits are v bit-reversed; the lane of that group with the low bits clear
+  // stores it
+  int myv = 0;
+#pragma unroll
+  for (int st = 0; st < LOG2V; ++st) myv |= ((lane >> (5 - st)) & 1) << (LOG2V - 1 - st);
+  const bool writer = (lane & ((1 << (6 - LOG2V)) - 1)) == 0 && myv < V;
+  auto batch = [&](const double2 (&a)[RB][2], const double (&avs)[V], const double (&axs)[V], int64_t r) {
     // row sums of A W for the batch
     double ys[V2], ye[V2];
 #pragma unroll
@@ -307,22 +308,15 @@ __global__ __launch_bounds__(256) void k_astream_r2(const double* __restrict__ A
     if constexpr (DOT2) tr_reduce_dot2<V2, LOG2V>(ys, ye, lane);
     else tr_reduce_plain<V2, LOG2V>(ys, lane);
     const double mine = DOT2 ? ys[0] + ye[0] : ys[0];
-    double y[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) y[v] = readlane_d(mine, tr_src_lane<LOG2V>(v));
-    double out = 0.0;
-#pragma unroll
-    for (int v = 0; v < V; ++v)
-      if (lane == v) out = y[v];
-    if (lane < V && rb + lane / B < r1) AW[rb * B + lane] = out;
+    if (writer && r + myv / B < r1) AW[r * B + myv] = mine;
     // column sums: A^* A_V (Dot2; A^* A_W in the start pass), A^* A_X, A^* A_W
 #pragma unroll
     for (int q = 0; q < RB; ++q)
 #pragma unroll
       for (int j = 0; j < B; ++j) {
         const int v = q * B + j;
-        const double yv = y[v];
-        const double av = INIT ? yv : readlane_d(avl, v);
+        const double yv = readlane_d(mine, tr_src_lane<LOG2V>(v));
+        const double av = INIT ? yv : avs[v];
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
           if constexpr (DOT2) {
@@ -333,7 +327,7 @@ __global__ __launch_bounds__(256) void k_astream_r2(const double* __restrict__ A
             g1s[s][j].y = fma(a[q][s].y, av, g1s[s][j].y);
           }
           if constexpr (!INIT) {
-            const double ax = readlane_d(axl, v);
+            const double ax = axs[v];
             gx[s][j].x = fma(a[q][s].x, ax, gx[s][j].x);
             gx[s][j].y = fma(a[q][s].y, ax, gx[s][j].y);
             gw[s][j].x = fma(a[q][s].x, yv, gw[s][j].x);
@@ -341,6 +335,23 @@ __global__ __launch_bounds__(256) void k_astream_r2(const double* __restrict__ A
           }
         }
       }
+  };
+  double2 a0[RB][2], a1[RB][2];
+  double av0[V], ax0[V], av1[V], ax1[V];
+  load_rows(a0, rb);
+  load_av_ax(rb, av0, ax0);
+  while (rb < r1) {
+    load_rows(a1, rb + STEP);
+    load_av_ax(rb + STEP, av1, ax1);
+    __builtin_amdgcn_sched_barrier(0);
+    batch(a0, av0, ax0, rb);
+    rb += STEP;
+    if (rb >= r1) break;
+    load_rows(a0, rb + STEP);
+    load_av_ax(rb + STEP, av0, ax0);
+    __builtin_amdgcn_sched_barrier(0);
+    batch(a1, av1, ax1, rb);
+    rb += STEP;
   }
   // combine the four waves through LDS, two planes at a time
   const int64_t plane = (int64_t)n * B;

@@ -29,7 +29,14 @@ int64_t astream_r2_blocks(int64_t m) {
   return (m + rows - 1) / rows;
 }
 
-bool astream_r2_fits(int B, int n, bool aligned) { return aligned && n % 2 == 0 && n <= 256 && B >= 1 && B <= 2; }
+// The kernel reads a workgroup's rows through one buffer resource, whose byte
+// range is a signed 32-bit count.
+bool astream_r2_fits(int B, int n, bool aligned, int64_t m, int64_t lda) {
+  if (!(aligned && n % 2 == 0 && n <= 256 && B >= 1 && B <= 2)) return false;
+  const int64_t nb = astream_r2_blocks(m);
+  const int64_t rows = nb > 0 ? (m + nb - 1) / nb : 0;
+  return rows * lda * 8 < ((int64_t)1 << 31);
+}
 
 bool dispatch_astream_r2(bool dot2, int init, int B, hipStream_t st, int64_t nb, const double* A, int64_t lda,
                          int64_t m, int n, const double* W, double* AW, const double* AVp, const double* AXp,

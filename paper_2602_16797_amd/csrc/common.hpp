@@ -103,6 +103,18 @@ __device__ inline double2 ld_stream2(const double* p) {
   return make_double2(v.x, v.y);
 }
 
+// Buffer-resource loads.  Word 3 of a raw (stride 0, untyped) gfx9-family
+// buffer resource: DATA_FORMAT = 32 bits (bits 15..18 = 4); the hardware
+// returns zero for any lane whose access lies past the resource's byte range
+// (word 2), so kernels can read a range's tail without branches.
+constexpr int BUFFER_RSRC_WORD3 = 0x00020000;
+// 16-byte non-temporal load at byte offset voff + soff of a buffer resource
+__device__ inline double2 ld_buf_stream2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 2 /* non-temporal */);
+  return make_double2(__builtin_bit_cast(double, ((unsigned long long)v[1] << 32) | v[0]),
+                      __builtin_bit_cast(double, ((unsigned long long)v[3] << 32) | v[2]));
+}
+
 // Index of the calling wave in its workgroup, known to the compiler to be
 // wave-uniform (scalar register), so branches on it are scalar branches.
 __device__ inline int wave_index() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }

@@ -71,7 +71,7 @@ int64_t astream_cs_blocks(int64_t m, int n);
 bool dispatch_astream_cs(bool dot2, int init, int B, hipStream_t st, int64_t nb, const double* A, int64_t lda,
                          int64_t m, int n, const double* W, double* AW, const double* AVp, const double* AXp,
                          double* Gpart, const Ctl* ctl);
-bool astream_r2_fits(int B, int n, bool aligned);
+bool astream_r2_fits(int B, int n, bool aligned, int64_t m, int64_t lda);
 bool dispatch_astream_r2(bool dot2, int init, int B, hipStream_t st, int64_t nb, const double* A, int64_t lda,
                          int64_t m, int n, const double* W, double* AW, const double* AVp, const double* AXp,
                          double* Gpart, const Ctl* ctl);
