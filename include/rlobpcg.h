@@ -234,6 +234,20 @@ int rl_step_astream_iter_noalloc(rl_handle h, int is_complex, int64_t m, int64_t
  * (Alg. rlopcg, svd of A_T). */
 int rl_step_tall_svd(rl_handle h, int is_complex, int64_t m, int32_t t, const double* P, double* sigma, double* C);
 
+/* The search block's orthonormalisation (Alg. rlobpcg, the two block
+ * projections of eq:search-direction's block against span[V X], then Orth;
+ * b = 1: Normalize, Alg. rlopcg).  V and X are device n x b row-major blocks
+ * with orthonormal columns (X may be NULL when with_x = 0; both are ignored
+ * when project = 0); W (device, n x b row-major) is overwritten in place with
+ * the orthonormal basis: W <- Orth((I - Y Y^*)^2 W), Y = [V X], computed by
+ * classical Gram-Schmidt (two block passes against Y, then CGS2 column by
+ * column).  A column that vanishes is replaced by the first unit vector that
+ * keeps norm above 1/2 after the same projections, and *degenerate (host) is
+ * set to 1; else 0.  Requires 1 <= b <= 16, 1 <= n; synchronises the stream.
+ * Errors: RL_ERR_ARG on a bad size or NULL pointer. */
+int rl_step_orth(rl_handle h, int is_complex, int64_t n, int32_t b, const double* V, const double* X,
+                 int32_t project, int32_t with_x, double* W, int32_t* degenerate);
+
 /* ---- Served form: continuous batching of solves of different shapes.
  *
  * Callers that stream many solves (different m, n, k) hand them to a server

@@ -42,7 +42,7 @@ EXPORTED = (
     "rl_create", "rl_destroy", "rl_set_stream", "rl_default_opts",
     "rl_svds_smallest_d", "rl_svds_smallest_z",
     "rl_step_sketch", "rl_step_qr", "rl_step_astream", "rl_step_astream_iter", "rl_step_astream_iter_noalloc",
-    "rl_step_tall_svd",
+    "rl_step_tall_svd", "rl_step_orth",
     "rl_step_sketch_f32", "rl_step_qr_lowp", "rl_status_string",
     "rl_server_create", "rl_server_submit", "rl_server_poll", "rl_server_wait", "rl_server_destroy",
 )
@@ -160,6 +160,7 @@ def load_library() -> ctypes.CDLL:
     lib.rl_step_astream_iter.argtypes = [P, ctypes.c_int, I64, I64, P, I64, I32, P, P, P, P, P, I32]
     lib.rl_step_astream_iter_noalloc.argtypes = [P, ctypes.c_int, I64, I64, P, I64, I32, P, P, P, P, P, I32]
     lib.rl_step_tall_svd.argtypes = [P, ctypes.c_int, I64, I32, P, P, P]
+    lib.rl_step_orth.argtypes = [P, ctypes.c_int, I64, I32, P, P, I32, I32, P, ctypes.POINTER(I32)]
     lib.rl_status_string.argtypes = [ctypes.c_int]
     lib.rl_server_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.c_size_t, I32]
     lib.rl_server_submit.argtypes = [P, ctypes.POINTER(RlRequest), ctypes.POINTER(U64)]
@@ -490,6 +491,27 @@ def rl_step_tall_svd(P):
     if rc != RL_OK:
         raise RlError(rc, "rl_step_tall_svd")
     return sigma, C
+
+
+def rl_step_orth(W, V=None, X=None):
+    """Orthonormal basis of W's block after two block projections against
+    [V X] (V None: no projection).  Returns (Q, degenerate); W is not changed."""
+    torch = _torch()
+    Q = W.contiguous().clone()
+    n, b = Q.shape
+    for t in (V, X):
+        if t is not None and (t.shape != (n, b) or t.dtype != Q.dtype):
+            raise ValueError("rl_step_orth: V and X must be n x b of W's dtype")
+    Vc = V.contiguous() if V is not None else None
+    Xc = X.contiguous() if X is not None else None
+    h = handle(Q.device.index or 0)
+    deg = ctypes.c_int32(0)
+    rc = h.lib.rl_step_orth(h.h, int(Q.is_complex()), n, b, _ptr(Vc) if Vc is not None else None,
+                            _ptr(Xc) if Xc is not None else None, int(Vc is not None), int(Xc is not None),
+                            _ptr(Q), ctypes.byref(deg))
+    if rc != RL_OK:
+        raise RlError(rc, "rl_step_orth")
+    return Q, bool(deg.value)
 
 
 @dataclass

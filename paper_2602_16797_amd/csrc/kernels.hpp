@@ -139,6 +139,12 @@ hipError_t launch_orth_svqb(hipStream_t st, bool cplx, int n, int B, const void*
                             int with_x, void* W, Ctl* ctl, int check_done);
 // masked = 1: with locking on (ctl->lock), the locked columns of W are set
 // to zero instead of orthonormalised
+// The register-resident Orth (k_orth_reg) when n and B fit it (n <= 2048
+// real, n <= 1024 complex, B <= 10); false when they do not (nothing launched).
+bool launch_orth_reg_d(hipStream_t st, int n, int B, const void* V, const void* X, int project, int with_x, void* W,
+                       Ctl* ctl, int check_done, int masked);
+bool launch_orth_reg_c(hipStream_t st, int n, int B, const void* V, const void* X, int project, int with_x, void* W,
+                       Ctl* ctl, int check_done, int masked);
 hipError_t launch_orth(hipStream_t st, bool cplx, int n, int B, const void* V, const void* X, int project, int with_x,
                        void* W, Ctl* ctl, int check_done, int masked = 0);
 // phase 0: the whole Rayleigh-Ritz step; 1: Rayleigh-Ritz and V_new (into

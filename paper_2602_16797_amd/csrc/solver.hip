@@ -1028,6 +1028,27 @@ int rl_step_tall_svd(rl_handle h, int is_complex, int64_t m, int32_t t, const do
   return RL_OK;
 }
 
+int rl_step_orth(rl_handle h, int is_complex, int64_t n, int32_t b, const double* V, const double* X,
+                 int32_t project, int32_t with_x, double* W, int32_t* degenerate) {
+  if (!h || !W || !degenerate || n < 1 || n > INT32_MAX || b < 1 || b > 16) return RL_ERR_ARG;
+  if (project && (!V || (with_x && !X))) return RL_ERR_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return RL_ERR_DEVICE;
+  Arena a;
+  const size_t o_ctl = a.take(sizeof(Ctl));
+  int rc = ensure_ws(h, a.off + 256);
+  if (rc != RL_OK) return rc;
+  hipStream_t st = h->stream;
+  Ctl* ctl = at<Ctl>(h->ws, o_ctl);
+  CK(hipMemsetAsync(ctl, 0, sizeof(Ctl), st));
+  CK(launch_orth(st, is_complex != 0, (int)n, b, V, project ? X : nullptr, project ? 1 : 0, (project && with_x) ? 1 : 0,
+                 W, ctl, 0, 0));
+  Ctl hc;
+  CK(hipMemcpyAsync(&hc, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  *degenerate = hc.degenerate ? 1 : 0;
+  return RL_OK;
+}
+
 int rl_server_create(rl_server_h* out, int device, size_t hbm_budget_bytes, int32_t max_inflight) {
   if (!out || max_inflight < 1 || max_inflight > 64 || hbm_budget_bytes == 0) return RL_ERR_ARG;
   *out = nullptr;

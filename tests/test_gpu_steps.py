@@ -260,3 +260,70 @@ def test_tall_svd(rl, m, t, cplx):
     _, sl, Vlh = np.linalg.svd(Rl)
     ref = np.max(np.abs(np.linalg.norm(P @ Vlh.conj().T, axis=0) - sl))
     assert np.all(np.abs(np.linalg.norm(P @ C, axis=0) - sg) <= max(1e-14 * s[0], 2 * ref))
+
+
+# The search block's orthonormalisation (S5): two block projections against
+# [V X], then Orth.  Register-resident kernel (real n <= 2048, complex
+# n <= 1024, b <= 10; one to eight rows per thread, ragged tails) and the
+# global-memory kernel (complex n > 1024, b > 10); no X, no projection.
+@pytest.mark.parametrize("n,b,cplx,proj,with_x", [
+    (200, 1, False, True, True), (1000, 10, True, True, True), (500, 5, False, True, True),
+    (2000, 10, False, True, True), (1500, 3, True, True, True), (300, 7, True, True, False),
+    (257, 4, False, False, False), (64, 16, False, True, True), (1025, 2, False, True, True),
+    (33, 9, True, True, True)])
+def test_orth_step(rl, n, b, cplx, proj, with_x):
+    from oracle.rlobpcg import _orth, search_block
+    banner(f"orth step n={n} b={b} complex={cplx} project={proj} with_x={with_x}")
+    rng = np.random.default_rng(1000 * n + b)
+    nb = (2 if with_x else 1) * b if proj else 0
+    Y, _ = np.linalg.qr(_rand(rng, (n, max(nb, 1)), cplx))
+    basis = Y[:, :nb]
+    # graded columns with components along [V X] up to 10^4.5 times the part
+    # the projections keep (column scaling does not change the Q factor)
+    W = _rand(rng, (n, b), cplx) * np.logspace(0, -3, b)
+    if nb:
+        W = W + basis @ (10.0 * _rand(rng, (nb, b), cplx))
+    dev = lambda M: torch.from_numpy(np.ascontiguousarray(M)).cuda()
+    V = dev(basis[:, :b]) if proj else None
+    X = dev(basis[:, b:2 * b]) if proj and with_x else None
+    Q, deg = rl.rl_step_orth(dev(W), V, X)
+    Q = to_np(Q)
+    Qo, flag = search_block(W, lambda M: M, basis, _orth)
+    assert not deg and not flag
+    assert np.linalg.norm(Q.conj().T @ Q - np.eye(b)) <= 1e-13
+    if nb:
+        assert np.linalg.norm(basis.conj().T @ Q) <= 1e-13
+    # the same orthonormal basis column by column (QR's Q is unique up to a
+    # unit-modulus factor per column).  Any projection leaves an error of
+    # about u ||w_j|| in the kept part, so a column agrees to about
+    # u ||w_j|| / ||(I - Y Y^*) w_j||: the bound scales with the largest such
+    # ratio (kappa), with room for the sqrt(n b) growth of the sums
+    Wp = W - basis @ (basis.conj().T @ W) if nb else W
+    kappa = float(np.max(np.linalg.norm(W, axis=0) / np.linalg.norm(Wp, axis=0)))
+    tol = 64 * U * np.sqrt(n * b) * kappa + 1e-13
+    ph = np.einsum("ij,ij->j", Qo.conj(), Q)
+    assert np.all(np.abs(np.abs(ph) - 1.0) <= tol)
+    assert np.linalg.norm(Q - Qo * (ph / np.abs(ph))) <= tol
+
+
+@pytest.mark.parametrize("n,b,cplx", [(300, 1, False), (400, 4, True), (1500, 3, True), (2000, 6, False)])
+def test_orth_step_degenerate(rl, n, b, cplx):
+    """A zero last column: the flag is raised, the column is completed by a
+    unit vector projected against [V X] and the earlier columns; the other
+    columns are the oracle's."""
+    from oracle.rlobpcg import _orth, search_block
+    banner(f"orth step degenerate n={n} b={b} complex={cplx}")
+    rng = np.random.default_rng(77 + n + b)
+    Y, _ = np.linalg.qr(_rand(rng, (n, 2 * b), cplx))
+    W = _rand(rng, (n, b), cplx)
+    W[:, -1] = 0.0
+    dev = lambda M: torch.from_numpy(np.ascontiguousarray(M)).cuda()
+    Q, deg = rl.rl_step_orth(dev(W), dev(Y[:, :b]), dev(Y[:, b:]))
+    Q = to_np(Q)
+    assert deg
+    assert np.linalg.norm(Q.conj().T @ Q - np.eye(b)) <= 1e-13
+    assert np.linalg.norm(Y.conj().T @ Q) <= 1e-13
+    if b > 1:
+        Qo, _ = search_block(W[:, :-1], lambda M: M, Y, _orth)
+        ph = np.einsum("ij,ij->j", Qo.conj(), Q[:, :-1])
+        assert np.linalg.norm(Q[:, :-1] - Qo * (ph / np.abs(ph))) <= 1e-10

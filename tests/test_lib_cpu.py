@@ -29,7 +29,7 @@ def _declared():
 def test_header_declares_the_boundary():
     names = _declared()
     for must in ("rl_create", "rl_destroy", "rl_default_opts", "rl_svds_smallest_d", "rl_svds_smallest_z",
-                 "rl_step_sketch", "rl_step_qr", "rl_step_astream", "rl_step_astream_iter", "rl_step_tall_svd", "rl_status_string",
+                 "rl_step_sketch", "rl_step_qr", "rl_step_astream", "rl_step_astream_iter", "rl_step_tall_svd", "rl_step_orth", "rl_status_string",
                  "rl_step_sketch_f32", "rl_step_qr_lowp", "rl_server_create", "rl_server_submit",
                  "rl_server_poll", "rl_server_wait", "rl_server_destroy"):
         assert must in names
