@@ -43,14 +43,27 @@ __global__ __launch_bounds__(256) void k_colsum2(ColsumJob J) { colsum2_block(J,
 
 
 // Row-local panel update.  mode: 0 A_T = [A_V] (t = B), 1 [A_V A_W] (t = 2B),
-// 2 [A_V A_X A_W] (t = 3B).  C_V, C_X are t x B row-major.  Each thread owns
-// rows; the row of A_T sits in registers.  pmode 0: A_V <- A_T C_V and
-// A_X <- A_T C_X in place (AVout == AV); 1: AVout <- A_T C_V only, A_T left
-// as it is; 2: A_X <- A_T C_X only (the late-residual form, whose new A_V was
-// formed by pmode 1 before the Gram pass).
+// 2 [A_V A_X A_W] (t = 3B).  C_V, C_X are t x B row-major.  pmode 0:
+// A_V <- A_T C_V and A_X <- A_T C_X in place (AVout == AV); 1: AVout <- A_T C_V
+// only, A_T left as it is; 2: A_X <- A_T C_X only (the late-residual form,
+// whose new A_V was formed by pmode 1 before the Gram pass).
+// Each wave takes chunks of 64 rows: a panel's chunk (64 B contiguous values)
+// is read with coalesced loads into the wave's LDS slot and each lane picks
+// its row out of it; the lane's output row goes back through the slot and
+// out with coalesced stores.  (A lane reading its own B-value row straight
+// from memory touches 64 scattered rows per load instruction.)  A chunk is
+// read in full before any of it is written, so the in-place forms are safe.
+// Lanes of one wave exchange values through LDS: a compiler fence at wave
+// scope between the writes and the other lanes' reads (DS instructions of a
+// wave execute in order, so no wait is needed beyond it).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <typename T, int B>
-__global__ __launch_bounds__(256) void k_panel(const T* AV, T* AVout, T* __restrict__ AX, const T* __restrict__ AW,
-                                               int64_t m, const T* __restrict__ CVg, const T* __restrict__ CXg,
+__global__ __launch_bounds__(256) void k_panel(const T* AV, T* AVout, T* AX, const T* AW, int64_t m,
+                                               const T* __restrict__ CVg, const T* __restrict__ CXg,
                                                const Ctl* __restrict__ ctl, int pmode) {
   if (ctl->done) return;
   const int mode = ctl->rr_mode;
@@ -59,45 +72,57 @@ __global__ __launch_bounds__(256) void k_panel(const T* AV, T* AVout, T* __restr
   const int t = (mode == 0) ? B : (mode == 1 ? 2 * B : 3 * B);
   __shared__ T CV[3 * B * B];
   __shared__ T CX[3 * B * B];
+  __shared__ T stage[4][64 * B];
   for (int i = threadIdx.x; i < 3 * B * B; i += blockDim.x) {
     CV[i] = (i < t * B) ? CVg[i] : zero<T>();
     CX[i] = (xupd && i < t * B) ? CXg[i] : zero<T>();
   }
   __syncthreads();
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & 63, wave = wave_index();
+  T* slot = stage[wave];
+  const T* panels[3] = {AV, mode == 2 ? AX : (mode == 1 ? AW : nullptr), mode == 2 ? AW : nullptr};
+  const int64_t nchunk = (m + 63) / 64;
+  for (int64_t ch = (int64_t)blockIdx.x * 4 + wave; ch < nchunk; ch += (int64_t)gridDim.x * 4) {
+    const int64_t r0 = ch * 64;
+    const int cnt = (int)((m - r0 < 64 ? m - r0 : 64) * B);  // values of the chunk per panel
     T at[3 * B];
 #pragma unroll
-    for (int j = 0; j < B; ++j) {
-      at[j] = AV[r * B + j];
-      at[B + j] = (mode == 2) ? AX[r * B + j] : ((mode == 1) ? AW[r * B + j] : zero<T>());
-      at[2 * B + j] = (mode == 2) ? AW[r * B + j] : zero<T>();
-    }
-    // the coefficient loop stays rolled for wider blocks so the t x B
-    // coefficients are read from LDS per row instead of held in registers;
-    // a block that is not kept is not formed
-    if (vupd && xupd) {
-#pragma unroll(B <= 2 ? B : 1)
-      for (int j = 0; j < B; ++j) {
-        T sv = zero<T>(), sx = zero<T>();
+    for (int p = 0; p < 3; ++p) {
+      const T* P = panels[p];
+      if (P != nullptr) {
 #pragma unroll
-        for (int c = 0; c < 3 * B; ++c) {
-          sv = fmac(at[c], CV[c * B + j], sv);
-          sx = fmac(at[c], CX[c * B + j], sx);
+        for (int u = 0; u < B; ++u) {
+          const int e = lane + 64 * u;
+          slot[e] = (e < cnt) ? P[r0 * B + e] : zero<T>();
         }
-        AVout[r * B + j] = sv;
-        AX[r * B + j] = sx;
+        wave_lds_sync();
+#pragma unroll
+        for (int j = 0; j < B; ++j) at[p * B + j] = slot[lane * B + j];
+        wave_lds_sync();
+      } else {
+#pragma unroll
+        for (int j = 0; j < B; ++j) at[p * B + j] = zero<T>();
       }
-    } else if (vupd || xupd) {
-      const T* Cm = vupd ? CV : CX;
-      T* out = vupd ? AVout : AX;
+    }
+    // the lane's output row through the slot, then coalesced stores
+    auto emit = [&](const T* Cm, T* out) {
 #pragma unroll(B <= 2 ? B : 1)
       for (int j = 0; j < B; ++j) {
         T sv = zero<T>();
 #pragma unroll
         for (int c = 0; c < 3 * B; ++c) sv = fmac(at[c], Cm[c * B + j], sv);
-        out[r * B + j] = sv;
+        slot[lane * B + j] = sv;
       }
-    }
+      wave_lds_sync();
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int e = lane + 64 * u;
+        if (e < cnt) out[r0 * B + e] = slot[e];
+      }
+      wave_lds_sync();
+    };
+    if (vupd) emit(CV, AVout);
+    if (xupd) emit(CX, AX);
   }
 }
 

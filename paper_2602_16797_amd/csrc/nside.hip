@@ -32,7 +32,7 @@ namespace rl {
 constexpr int RR_TMAX = 32;
 constexpr int RR_BMAX = 16;
 static_assert(RR_CST_DOUBLES >= RR_TMAX * 32 * 2 + 2 * RR_TMAX, "saved Rayleigh-Ritz data of k_rr's phases");
-constexpr int RR_PRE_B = 4;  // k_rr loads a trial row's values together up to this B
+constexpr int RR_PRE_B = 4;  // k_rr loads a trial row's 3B values together up to this B
 
 __device__ inline double absval(double a) { return fabs(a); }
 __device__ inline double absval(cd a) { return hypot(a.x, a.y); }
@@ -223,10 +223,13 @@ __device__ bool dev_should_stop(int i, const double* __restrict__ ht, const doub
 // per sweep, and the 16 lanes of one DPP row take one pair (lane i holds rows
 // i and i + 16), so a round is three 16-lane sums and one rotation per pair
 // with one barrier.  Vj accumulates the rotations.  Same rotation formulas as
-// the cyclic order; the sweep stops when no pair was rotated.
+// the cyclic order; the test |gamma|^2 > tol^2 alpha beta is the usual
+// |gamma| > tol sqrt(alpha beta) without its square roots, and 1/|gamma| is
+// formed once; the sweep stops when no pair was rotated.
 template <typename T>
 __device__ void jacobi_block(T* M, T* Vj, int t) {
   const double tol = sqrt((double)t) * 2.220446049250313e-16;
+  const double tol2 = tol * tol;
   const int grp = threadIdx.x >> 4, li = threadIdx.x & 15;
   const int tp = t + (t & 1);
   for (int sweep = 0; sweep < 60; ++sweep) {
@@ -249,11 +252,12 @@ __device__ void jacobi_block(T* M, T* Vj, int t) {
           const double al = row_sum16(abs2(mp0) + abs2(mp1));
           const double be = row_sum16(abs2(mq0) + abs2(mq1));
           const T ga = row_sum16(cfmac(mp1, mq1, cfmac(mp0, mq0, zero<T>())));
-          const double g = absval(ga);
-          if (g > tol * sqrt(al) * sqrt(be) && g != 0.0) {
+          const double g2 = abs2(ga);
+          if (g2 > tol2 * al * be && g2 != 0.0) {
             rotated = 1;
-            const T eg = scal(ga, 1.0 / g);  // unit phase of gamma
-            const double zeta = (be - al) / (2.0 * g);
+            const double ig = 1.0 / sqrt(g2);
+            const T eg = scal(ga, ig);  // unit phase of gamma
+            const double zeta = (be - al) * 0.5 * ig;
             const double tn = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             const double c = 1.0 / sqrt(1.0 + tn * tn), s = c * tn;
 #pragma unroll
@@ -279,7 +283,6 @@ __device__ void jacobi_block(T* M, T* Vj, int t) {
   }
 }
 
-
 template <typename T, int B>
 __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int with_x, const T* __restrict__ Rt,
                                                    T* __restrict__ V, T* __restrict__ X, const T* __restrict__ W,
@@ -303,6 +306,7 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
   __shared__ int stop_s;
   __shared__ int newact_s;
   __shared__ int padsorted[RR_TMAX];  // sorted column c is a locked index's zero column
+  __shared__ int rank_s[RR_TMAX];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int mode = init_mode ? 0 : (with_x ? 2 : 1);
   const int t = (mode == 0) ? B : (mode == 1 ? 2 * B : 3 * B);
@@ -335,32 +339,30 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
   }
   __syncthreads();
   jacobi_block<T>(M, Vj, t);
-  if (wid == 0) {
-    // column norms, then a descending sort (lane 0)
-    for (int c = 0; c < t; ++c) {
-      const T v = (lane < t) ? M[c * 32 + lane] : zero<T>();
-      const double s = wave_sum(abs2(v));
-      if (lane == 0) sig[c] = sqrt(s);
+  // column norms (thread c), then the descending order: column c goes to
+  // the number of columns ranked before it (larger key, or an equal key and
+  // a lower index: the order a stable selection sort gives)
+  if (tid < t) {
+    double s2 = 0.0;
+    for (int r = 0; r < t; ++r) s2 += abs2(M[tid * 32 + r]);
+    sig[tid] = sqrt(s2);
+  }
+  __syncthreads();
+  if (tid < t) {
+    const double kc = padded(tid) ? INFINITY : sig[tid];
+    int rk = 0;
+    for (int q = 0; q < t; ++q) {
+      const double kq = padded(q) ? INFINITY : sig[q];
+      rk += (kq > kc || (kq == kc && q < tid)) ? 1 : 0;
     }
-    if (lane == 0) {
-      int used[RR_TMAX];
-      for (int c = 0; c < t; ++c) used[c] = 0;
-      for (int c = 0; c < t; ++c) {
-        int best = -1;
-        double kb = 0.0;
-        for (int q = 0; q < t; ++q) {
-          const double kq = padded(q) ? INFINITY : sig[q];
-          if (!used[q] && (best < 0 || kq > kb)) {
-            best = q;
-            kb = kq;
-          }
-        }
-        used[best] = 1;
-        th[c] = sig[best];
-        padsorted[c] = padded(best) ? 1 : 0;
-        for (int r = 0; r < t; ++r) C[c * 32 + r] = Vj[best * 32 + r];
-      }
-    }
+    rank_s[tid] = rk;
+    th[rk] = sig[tid];
+    padsorted[rk] = padded(tid) ? 1 : 0;
+  }
+  __syncthreads();
+  for (int e = tid; e < t * 32; e += blockDim.x) {
+    const int c = e / 32, r = e % 32;
+    if (r < t) C[rank_s[c] * 32 + r] = Vj[c * 32 + r];
   }
   __syncthreads();
   }
@@ -385,12 +387,22 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
       T v[B];
 #pragma unroll
       for (int j = 0; j < B; ++j) v[j] = zero<T>();
-      for (int c = 0; c < t; ++c) {
-        const int blk = c / B, jc = c - (c / B) * B;
-        const int64_t e = (int64_t)r * B + jc;
-        const T trc = (blk == 0) ? V[e] : ((blk == 1) ? T1[e] : W[e]);
+      // a block's B row values are loaded together, then consumed one at a
+      // time from the front of the (rotated) register array, so only one
+      // coefficient row is live at once
+      for (int blk = 0; blk * B < t; ++blk) {
+        const T* P = (blk == 0) ? V : ((blk == 1) ? T1 : W);
+        T tr[B];
 #pragma unroll
-        for (int j = 0; j < B; ++j) v[j] = fmac(trc, CV[c * B + j], v[j]);
+        for (int jc = 0; jc < B; ++jc) tr[jc] = P[(int64_t)r * B + jc];
+#pragma unroll 1
+        for (int jc = 0; jc < B; ++jc) {
+          const T a = tr[0];
+#pragma unroll
+          for (int q = 0; q + 1 < B; ++q) tr[q] = tr[q + 1];
+#pragma unroll
+          for (int j = 0; j < B; ++j) v[j] = fmac(a, CV[(blk * B + jc) * B + j], v[j]);
+        }
       }
 #pragma unroll
       for (int j = 0; j < B; ++j) Vn[(int64_t)r * B + j] = v[j];
@@ -449,15 +461,30 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
           }
         }
       } else {
-        for (int c = 0; c < t; ++c) {
-          const int blk = c / B, jc = c - (c / B) * B;
-          const int64_t e = (int64_t)r * B + jc;
-          const T trc = (blk == 0) ? V[e] : ((blk == 1) ? T1[e] : W[e]);
-          const T grc = (blk == 0) ? GV[e] : ((blk == 1) ? G1[e] : GW[e]);
+        // a block's B row values (and their G_T rows) are loaded together and
+        // consumed from the front of the rotated register arrays
+        for (int blk = 0; blk * B < t; ++blk) {
+          const T* P = (blk == 0) ? V : ((blk == 1) ? T1 : W);
+          const T* Gb = (blk == 0) ? GV : ((blk == 1) ? G1 : GW);
+          T tr[B], gr[B];
 #pragma unroll
-          for (int j = 0; j < B; ++j) {
-            v[j] = fmac(trc, CV[c * B + j], v[j]);
-            g[j] = fmac(grc, CV[c * B + j], g[j]);
+          for (int jc = 0; jc < B; ++jc) {
+            tr[jc] = P[(int64_t)r * B + jc];
+            gr[jc] = Gb[(int64_t)r * B + jc];
+          }
+#pragma unroll 1
+          for (int jc = 0; jc < B; ++jc) {
+            const T a = tr[0], ga = gr[0];
+#pragma unroll
+            for (int q = 0; q + 1 < B; ++q) {
+              tr[q] = tr[q + 1];
+              gr[q] = gr[q + 1];
+            }
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+              v[j] = fmac(a, CV[(blk * B + jc) * B + j], v[j]);
+              g[j] = fmac(ga, CV[(blk * B + jc) * B + j], g[j]);
+            }
           }
         }
       }
@@ -563,12 +590,19 @@ __global__ __launch_bounds__(NS_THREADS) void k_rr(int n, int init_mode, int wit
           }
         }
       } else {
-        for (int c = 0; c < t; ++c) {
-          const int blk = c / B, jc = c - (c / B) * B;
-          const int64_t e = (int64_t)r * B + jc;
-          const T trc = (blk == 0) ? V[e] : ((blk == 1) ? T1[e] : W[e]);
+        for (int blk = 0; blk * B < t; ++blk) {
+          const T* P = (blk == 0) ? V : ((blk == 1) ? T1 : W);
+          T tr[B];
 #pragma unroll
-          for (int j = 0; j < B; ++j) x[j] = fmac(trc, CX[c * B + j], x[j]);
+          for (int jc = 0; jc < B; ++jc) tr[jc] = P[(int64_t)r * B + jc];
+#pragma unroll 1
+          for (int jc = 0; jc < B; ++jc) {
+            const T a = tr[0];
+#pragma unroll
+            for (int q = 0; q + 1 < B; ++q) tr[q] = tr[q + 1];
+#pragma unroll
+            for (int j = 0; j < B; ++j) x[j] = fmac(a, CX[(blk * B + jc) * B + j], x[j]);
+          }
         }
       }
 #pragma unroll
@@ -1100,24 +1134,26 @@ __global__ __launch_bounds__(NS_THREADS) void k_rt_svd(int t, const T* __restric
   }
   __syncthreads();
   jacobi_block<T>(M, Vj, t);
-  if (threadIdx.x >= 64) return;
-  for (int c = 0; c < t; ++c) {
-    const T v = (lane < t) ? M[c * 32 + lane] : zero<T>();
-    const double s = wave_sum(abs2(v));
-    if (lane == 0) sig[c] = sqrt(s);
+  // column norms, then each column's place in the descending order (the
+  // number ranked before it: larger, or equal with a lower index)
+  __shared__ int rank_s[RR_TMAX];
+  const int tid = threadIdx.x;
+  if (tid < t) {
+    double s2 = 0.0;
+    for (int r = 0; r < t; ++r) s2 += abs2(M[tid * 32 + r]);
+    sig[tid] = sqrt(s2);
   }
-  __builtin_amdgcn_wave_barrier();
-  if (lane == 0) {
-    int used[RR_TMAX];
-    for (int c = 0; c < t; ++c) used[c] = 0;
-    for (int c = 0; c < t; ++c) {
-      int best = -1;
-      for (int q = 0; q < t; ++q)
-        if (!used[q] && (best < 0 || sig[q] > sig[best])) best = q;
-      used[best] = 1;
-      sigma[c] = sig[best];
-      for (int r = 0; r < t; ++r) Cout[r * t + c] = Vj[best * 32 + r];
-    }
+  __syncthreads();
+  if (tid < t) {
+    int rk = 0;
+    for (int q = 0; q < t; ++q) rk += (sig[q] > sig[tid] || (sig[q] == sig[tid] && q < tid)) ? 1 : 0;
+    rank_s[tid] = rk;
+    sigma[rk] = sig[tid];
+  }
+  __syncthreads();
+  for (int e = tid; e < t * 32; e += blockDim.x) {
+    const int c = e / 32, r = e % 32;
+    if (r < t) Cout[r * t + rank_s[c]] = Vj[c * 32 + r];
   }
 }
 
