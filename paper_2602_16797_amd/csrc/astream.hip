@@ -328,15 +328,17 @@ hipError_t launch_astream_pass(hipStream_t st, bool cplx, int B, bool dot2, cons
 // The levels of the compensated reduction of the np partial records into G3
 // (n x 3B): level 0 reads the records, each later level the previous level's
 // (sum, error) pairs, the last writes G3.  Returns the number of levels.
+// first_only: only the first plane of each record is read (its error plane
+// is not), and only G3's first block is written (the Gram pass alone).
 int astream_reduce_plan(bool cplx, int B, int n, int64_t np, const double* Gpart, double* tmp, double* G3,
-                        const Ctl* ctl, ColsumJob* lev, int maxlev) {
+                        const Ctl* ctl, ColsumJob* lev, int maxlev, bool first_only) {
   const int es_d = cplx ? 2 : 1;
   const int64_t plen = (int64_t)n * B * es_d;
-  const int64_t len = 3 * plen;
+  const int64_t len = first_only ? plen : 3 * plen;
   const int64_t g1 = (np + 63) / 64;
   const double* cur_s = Gpart;
-  const double* cur_e = Gpart + len;
-  int64_t stride = 4 * plen, elen = plen;
+  const double* cur_e = Gpart + 3 * plen;
+  int64_t stride = 4 * plen, elen = first_only ? 0 : plen;
   int flip = 0, nl = 0;
   while (nl < maxlev) {
     const int64_t groups = (np + 63) / 64;
@@ -362,9 +364,9 @@ hipError_t launch_colsum_job(hipStream_t st, const ColsumJob& J) {
 }
 
 hipError_t launch_astream_reduce(hipStream_t st, bool cplx, int B, int n, int64_t np, const double* Gpart,
-                                 double* tmp, double* G3, const Ctl* ctl) {
+                                 double* tmp, double* G3, const Ctl* ctl, bool first_only) {
   ColsumJob lev[16];
-  const int nl = astream_reduce_plan(cplx, B, n, np, Gpart, tmp, G3, ctl, lev, 16);
+  const int nl = astream_reduce_plan(cplx, B, n, np, Gpart, tmp, G3, ctl, lev, 16, first_only);
   if (nl < 1) return hipErrorInvalidValue;
   for (int i = 0; i < nl; ++i) {
     const hipError_t e = launch_colsum_job(st, lev[i]);

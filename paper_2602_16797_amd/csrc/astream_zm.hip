@@ -399,7 +399,8 @@ __global__ __launch_bounds__(ZM_G_THREADS, 2) void k_zm_g(const double* __restri
       }
     }
     // the planes this pass does not form, and the error plane, are zero
-    for (int cc = lane; cc < 32 * B; cc += 64) {
+    // (init 2: the Gram pass alone, whose reduction reads plane 0 only)
+    for (int cc = lane; init != 2 && cc < 32 * B; cc += 64) {
       const int c = kw / 2 + cc / B, vv = cc - (cc / B) * B;
       if (c < n) {
         const int64_t e = 2 * ((int64_t)c * B + vv);
@@ -438,7 +439,7 @@ __global__ __launch_bounds__(ZM_G_THREADS, 2) void k_zm_g(const double* __restri
         }
       }
     }
-    for (int cc = lane; cc < 64 * B; cc += 64) {
+    for (int cc = lane; init != 2 && cc < 64 * B; cc += 64) {
       const int c = kw + cc / B, vv = cc - (cc / B) * B;
       if (c < n) {
         const int64_t e = (int64_t)c * B + vv;
@@ -551,7 +552,8 @@ static bool zm_dispatch(int init, int B, hipStream_t st, int64_t nrr, const void
 }
 
 // The Gram contraction alone: the partial records of A^* P0 over nrr row
-// ranges (plane 0; the other planes zero), for the late residual
+// ranges (plane 0 only: the other planes are not written, and the reduction
+// of these records reads plane 0 alone), for the late residual
 // A^* A_{V_{i+1}} of an iteration whose A W came from its own pass.
 template <bool CPLX>
 static bool zm_gram(int B, hipStream_t st, int64_t nrr, const void* A, int64_t lda, int64_t m, int n, const void* P0,
@@ -564,7 +566,7 @@ static bool zm_gram(int B, hipStream_t st, int64_t nrr, const void* A, int64_t l
   const int64_t nblk = ((nrr + 7) / 8) * 8 * nslice;
   const double* P = (const double*)P0;
   (void)B2;
-  if (!zm_g_cols<CPLX>(st, nblk, Ad, lda2, m, n, B, P, nullptr, nullptr, 1, 1, Gpart, rows, nrr, nslice, ctl))
+  if (!zm_g_cols<CPLX>(st, nblk, Ad, lda2, m, n, B, P, nullptr, nullptr, 1, 2, Gpart, rows, nrr, nslice, ctl))
     return false;
   return hipGetLastError() == hipSuccess;
 }

@@ -86,7 +86,7 @@ hipError_t launch_astream_pass(hipStream_t st, bool cplx, int B, bool dot2, cons
                                double* Gpart, const Ctl* ctl, int64_t* np_out, hipEvent_t mid = nullptr,
                                bool* mid_recorded = nullptr);
 hipError_t launch_astream_reduce(hipStream_t st, bool cplx, int B, int n, int64_t np, const double* Gpart,
-                                 double* tmp, double* G3, const Ctl* ctl);
+                                 double* tmp, double* G3, const Ctl* ctl, bool first_only = false);
 // One level of that reduction (k_colsum2): grid gx x gy of 256 threads.
 struct ColsumJob {
   const double* in_s;
@@ -99,7 +99,7 @@ struct ColsumJob {
   int gx, gy;
 };
 int astream_reduce_plan(bool cplx, int B, int n, int64_t np, const double* Gpart, double* tmp, double* G3,
-                        const Ctl* ctl, ColsumJob* lev, int maxlev);
+                        const Ctl* ctl, ColsumJob* lev, int maxlev, bool first_only = false);
 hipError_t launch_colsum_job(hipStream_t st, const ColsumJob& J);
 hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const void* A, int64_t lda, int64_t m, int n,
                           const void* W, void* AW, const void* AVp, const void* AXp, int init, double* Gpart,

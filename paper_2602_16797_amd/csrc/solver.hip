@@ -470,7 +470,7 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
         ++nprof;
       }
       CK(launch_astream_reduce(st, cplx, B, (int)n, np, at<double>(ws, L.Gpart), at<double>(ws, L.Gtmp),
-                               at<double>(ws, L.G3), ctl));
+                               at<double>(ws, L.G3), ctl, true));
       CK(launch_rr(st, cplx, (int)n, B, 0, with_x, Rt, at<void>(ws, L.V), at<void>(ws, L.X), at<void>(ws, L.W),
                    at<void>(ws, L.G3), at<void>(ws, L.Vn), at<void>(ws, L.Rres), at<void>(ws, L.CV),
                    at<void>(ws, L.CX), at<double>(ws, L.thb), at<double>(ws, L.ht), at<double>(ws, L.hr), ctl, 2,

@@ -505,12 +505,14 @@ static hipError_t tsqr_cw_impl(hipStream_t st, const T* P0, int b0, const T* P1,
   if (e != hipSuccess) return e;
   T* cur = bufA;
   T* nxt = bufB;
-  // reduce the stacked factors until one remains
+  // reduce the stacked factors until one remains: each workgroup takes as
+  // many whole factors as one tile holds, so every launch is one tile deep
+  // (a tile's column steps are the latency of a launch)
+  const int64_t per = (64 * RPL) / t >= 2 ? (64 * RPL) / t : 2;
   while (g > 1) {
     const int64_t mm = g * t;
-    int64_t g2 = tsqr_cw_groups(mm, t, cplx);
-    if (g2 >= g) g2 = g / 2 > 0 ? g / 2 : 1;
-    rows = (mm + g2 - 1) / g2;
+    const int64_t g2 = (g + per - 1) / per;
+    rows = per * t;
     hipLaunchKernelGGL((k_tsqr_cw<T, TT, NW, RPL>), dim3((unsigned)g2), dim3(NW * 64), 0, st, (const T*)cur, t,
                        (const T*)cur, 0, (const T*)cur, 0, mm, rows, nxt, ctl, check_done);
     e = hipGetLastError();
