@@ -19,12 +19,16 @@ namespace rl {
 //  * BCGS2 against [V X]: two block projections W -= [V X]([V X]^* W), one
 //    round each (the second also yields the column norms before it);
 //  * Orth(W): CGS2 column by column; column j takes one round for its dots
-//    with the earlier columns and its norm, one for the second pass's dots
-//    and the norm after the first, and the norm after the second follows by
+//    with the earlier columns and its norm, and one for the second pass's
+//    dots and the norm after the first; when the first pass removes most of
+//    the column (its rounding then leaves parts along [V X] as well, which
+//    orth_block's joint passes remove) that round takes the dots with
+//    [V X W(:, 0:j)] jointly.  The norm after the second pass follows by
 //    Pythagoras (the second pass removes a tiny part whenever the
-//    twice-is-enough test passes; a third round runs when it does not).  A
-//    column that the block projections shrank below half is projected on
-//    [V X] once more, the same test as orth_block applies to its passes.
+//    twice-is-enough test passes; a third, joint round runs when it does
+//    not).  A column that the block projections shrank below half is
+//    projected on [V X] once more, the same test as orth_block applies to its
+//    passes (the first column's norm is then formed afresh).
 // A column that vanishes (or turns non-finite) hands the block, written back,
 // to orth_block, which completes it with a unit vector and sets the
 // degenerate flag.  Locked columns (bit clear in `keep`) are zero.
@@ -97,10 +101,12 @@ __global__ __launch_bounds__(NS_THREADS) void k_orth_reg(int n, const T* __restr
                                                          Ctl* __restrict__ ctl, int check_done, int masked) {
   if (check_done && ctl->done) return;
   constexpr int ND = NDbl<T>::v;
-  constexpr int NVMAX = 2 * B * B * ND + B;  // the second block projection's sums
+  // the second block projection's sums, or a joint round's
+  constexpr int NVMAX = (2 * B * B * ND + B) > ((3 * B - 1) * ND + 1) ? (2 * B * B * ND + B) : ((3 * B - 1) * ND + 1);
   constexpr int VB = Pow2Up<B * ND>::v, LB = Pow2Up<B * ND>::log;          // one [V X] column's dots
   constexpr int VJ = Pow2Up<(B - 1) * ND + 1>::v, LJ = Pow2Up<(B - 1) * ND + 1>::log;  // column rounds
   constexpr int VX = Pow2Up<2 * B * ND>::v, LX = Pow2Up<2 * B * ND>::log;  // one column against [V X]
+  constexpr int VJX = Pow2Up<(3 * B - 1) * ND + 1>::v, LJX = Pow2Up<(3 * B - 1) * ND + 1>::log;  // joint rounds
   __shared__ double part[(NS_THREADS / 64) * NVMAX];
   __shared__ double sums[NVMAX];
   __shared__ double n1sq[B];
@@ -194,10 +200,59 @@ __global__ __launch_bounds__(NS_THREADS) void k_orth_reg(int n, const T* __restr
 #pragma unroll
         for (int c = 0; c < j; ++c) w[i][j] = fnmac(w[i][c], get_t<T>(h, c), w[i][j]);
     };
+    // joint round: dots of column j with the columns c < j (out[0 .. j ND)),
+    // its squared norm (out[j ND]) and its dots with [V X] (out[j ND + 1 ..),
+    // k < nvx); every register offset is fixed at compile time
+    auto joint_round = [&](double* out) __attribute__((always_inline)) {
+      double v[VJX];
+#pragma unroll
+      for (int e = 0; e < VJX; ++e) v[e] = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+#pragma unroll
+        for (int c = 0; c < j; ++c) {
+          T d = get_t<T>(v, c);
+          d = cfmac(w[i][c], w[i][j], d);
+          put_d(v, c, d);
+        }
+        v[j * ND] += abs2(w[i][j]);
+        const int r = tid + NS_THREADS * i;
+        if (r < n) {
+#pragma unroll
+          for (int k = 0; k < 2 * B; ++k) {
+            if (k < nvx) {
+              T d = get_t<T>(v + j * ND + 1, k);
+              d = cfmac(yval(r, k), w[i][j], d);
+              put_d(v + j * ND + 1, k, d);
+            }
+          }
+        }
+      }
+      wave_sums_to<VJX, LJX>(v, (nvx + j) * ND + 1, lane, mypart);
+      waves_sum(part, NVMAX, (nvx + j) * ND + 1, out);
+    };
+    auto project_joint = [&](const double* h) __attribute__((always_inline)) {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int r = tid + NS_THREADS * i;
+        if (r < n) {
+          for (int k = 0; k < nvx; ++k) w[i][j] = fnmac(yval(r, k), get_t<T>(h + j * ND + 1, k), w[i][j]);
+        }
+#pragma unroll
+        for (int c = 0; c < j; ++c) w[i][j] = fnmac(w[i][c], get_t<T>(h, c), w[i][j]);
+      }
+    };
     auto removed = [&](const double* h) __attribute__((always_inline)) {
       double s2 = 0.0;
 #pragma unroll
       for (int c = 0; c < j; ++c) s2 += abs2(get_t<T>(h, c));
+      return s2;
+    };
+    auto removed_joint = [&](const double* h) __attribute__((always_inline)) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int c = 0; c < j; ++c) s2 += abs2(get_t<T>(h, c));
+      for (int k = 0; k < nvx; ++k) s2 += abs2(get_t<T>(h + j * ND + 1, k));
       return s2;
     };
     column_round(sums);
@@ -233,19 +288,40 @@ __global__ __launch_bounds__(NS_THREADS) void k_orth_reg(int n, const T* __restr
       }
       for (int k = 0; k < nvx; ++k) g2 += abs2(get_t<T>(gsum, k));
       sq -= g2;
+      // what this pass removed need not be small next to what is left, so the
+      // first column's norm is formed afresh (a later column's comes from its
+      // own rounds below)
+      if (j == 0) {
+        column_round(sums);
+        sq = sums[0];
+      }
     }
     double nrmsq = sq;
     if (j > 0) {
+      // first pass against the earlier columns; when it removes most of the
+      // column its rounding leaves parts along [V X] as well, and the later
+      // passes run against [V X W(:, 0:j)] jointly
+      // the first pass's share of the column (by Pythagoras from round one's
+      // dots: a decision, not a norm) says whether it cancels
+      const bool cancels = sq - removed(sums) < 0.25 * sq;
       project_prev(sums);
-      column_round(sums);
-      const double n1 = sums[j * ND];
-      project_prev(sums);
-      nrmsq = n1 - removed(sums);
-      if (nrmsq < 0.25 * n1) {
+      double n1;
+      if (cancels) {
+        joint_round(sums);
+        n1 = sums[j * ND];
+        project_joint(sums);
+        nrmsq = n1 - removed_joint(sums);
+      } else {
         column_round(sums);
-        const double n2 = sums[j * ND];
+        n1 = sums[j * ND];
         project_prev(sums);
-        nrmsq = n2 - removed(sums);
+        nrmsq = n1 - removed(sums);
+      }
+      if (nrmsq < 0.25 * n1) {
+        joint_round(sums);
+        const double n2 = sums[j * ND];
+        project_joint(sums);
+        nrmsq = n2 - removed_joint(sums);
       }
     }
     if (!(nrmsq > 0.0) || !isfinite(nrmsq)) {
