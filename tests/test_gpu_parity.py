@@ -97,6 +97,19 @@ def test_block(rl, m, n, k, cplx, gamma):
     _check(rl, A, k, seed=3 + k, normA=s[0])
 
 
+def test_trial_space_near_n(rl):
+    """A served-stream shape whose trial space nearly fills the columns
+    (n = 36, k = b = 10: t = 30): the search block lives in a 16-dimensional
+    complement of [V X], so its orthonormalisation meets heavy cancellation
+    (the paper's rule need not fire here: the oracle too runs to max_iter on
+    this matrix)."""
+    from workloads import request_spectrum, served_requests
+    q = served_requests(count=256)[229]
+    banner(f"parity served shape m={q.m} n={q.n} k={q.k}")
+    A, _, s = planted_numpy(q.m, q.n, request_spectrum(q), q.data_seed)
+    _check(rl, A, q.k, seed=q.sketch_seed, normA=s[0])
+
+
 def test_complex_nullspace_small(rl):
     """cfg3's structure (rank n-k plus complex noise 1e-14) at a small size."""
     banner("parity complex nullspace 8000x60 k=4")
