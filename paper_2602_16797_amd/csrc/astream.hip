@@ -61,7 +61,7 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <typename T, int B>
+template <typename T, int B, bool ONE>
 __global__ __launch_bounds__(256) void k_panel(const T* AV, T* AVout, T* AX, const T* AW, int64_t m,
                                                const T* __restrict__ CVg, const T* __restrict__ CXg,
                                                const Ctl* __restrict__ ctl, int pmode) {
@@ -85,6 +85,45 @@ __global__ __launch_bounds__(256) void k_panel(const T* AV, T* AVout, T* AX, con
   for (int64_t ch = (int64_t)blockIdx.x * 4 + wave; ch < nchunk; ch += (int64_t)gridDim.x * 4) {
     const int64_t r0 = ch * 64;
     const int cnt = (int)((m - r0 < 64 ? m - r0 : 64) * B);  // values of the chunk per panel
+    if constexpr (ONE) {
+      // one output block (pmode 1 or 2): the panels are consumed one at a
+      // time into B accumulators, so only B values of the row are live
+      const T* Cm = vupd ? CV : CX;
+      T* out = vupd ? AVout : AX;
+      if (!vupd && !xupd) continue;
+      T acc[B];
+#pragma unroll
+      for (int j = 0; j < B; ++j) acc[j] = zero<T>();
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        const T* P = panels[p];
+        if (P == nullptr) continue;
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          const int e = lane + 64 * u;
+          slot[e] = (e < cnt) ? P[r0 * B + e] : zero<T>();
+        }
+        wave_lds_sync();
+        T at[B];
+#pragma unroll
+        for (int c = 0; c < B; ++c) at[c] = slot[lane * B + c];
+        wave_lds_sync();
+#pragma unroll
+        for (int j = 0; j < B; ++j)
+#pragma unroll
+          for (int c = 0; c < B; ++c) acc[j] = fmac(at[c], Cm[(p * B + c) * B + j], acc[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < B; ++j) slot[lane * B + j] = acc[j];
+      wave_lds_sync();
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int e = lane + 64 * u;
+        if (e < cnt) out[r0 * B + e] = slot[e];
+      }
+      wave_lds_sync();
+      continue;
+    }
     T at[3 * B];
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
@@ -392,8 +431,12 @@ hipError_t launch_astream(hipStream_t st, bool cplx, int B, bool dot2, const voi
 template <typename T, int B>
 static void panel_go(hipStream_t st, int64_t nb, const void* AV, void* AVout, void* AX, const void* AW, int64_t m,
                      const void* CV, const void* CX, const Ctl* ctl, int pmode) {
-  hipLaunchKernelGGL((k_panel<T, B>), dim3((unsigned)nb), dim3(256), 0, st, (const T*)AV, (T*)AVout, (T*)AX,
-                     (const T*)AW, m, (const T*)CV, (const T*)CX, ctl, pmode);
+  if (pmode == 0)
+    hipLaunchKernelGGL((k_panel<T, B, false>), dim3((unsigned)nb), dim3(256), 0, st, (const T*)AV, (T*)AVout,
+                       (T*)AX, (const T*)AW, m, (const T*)CV, (const T*)CX, ctl, pmode);
+  else
+    hipLaunchKernelGGL((k_panel<T, B, true>), dim3((unsigned)nb), dim3(256), 0, st, (const T*)AV, (T*)AVout,
+                       (T*)AX, (const T*)AW, m, (const T*)CV, (const T*)CX, ctl, pmode);
 }
 
 template <typename T>
