@@ -955,7 +955,12 @@ static void qr_factor(hipStream_t st, T* Y, int d, int n, T* Tm) {
       nb = min(QR_NB, n - p);
       qr_panel_cw_launch<T>(st, Y, d, p, nb, rpl, Tm);
     } else {
-      const int nbr = qr_pick_panel<T>(d - p, &rpt);
+      int nbr = qr_pick_panel<T>(d - p, &rpt);
+      // a register panel narrower than half a block would cost a trailing
+      // update (a full pass over the rest of the sketch) every few columns:
+      // such heights take 32-column panels factored in leaves instead
+      if constexpr (sizeof(T) != 4)
+        if (nbr > 0 && nbr < QR_NB / 2 && qr_leaf_fits<T>(d - p)) nbr = 0;
       nb = min(nbr > 0 ? nbr : QR_NB, n - p);
       if (nbr > 0)
         qr_panel_launch<T>(st, Y, d, p, nb, rpt, Tm);

@@ -57,6 +57,7 @@ def test_sketch_strided_lda(rl):
 @pytest.mark.parametrize("d,n,cplx", [(800, 200, False), (150, 37, False), (96, 33, True), (64, 64, False),
                                       (3000, 70, True), (1024, 300, False), (500, 100, True), (256, 256, True),
                                       (65, 60, False), (2000, 500, False), (1536, 512, True), (3000, 1000, True),
+                                      (3500, 300, False),
                                       # sketches over 4096 rows: panels factored in leaves
                                       (6000, 700, False), (8000, 2000, False), (4500, 64, True)])
 def test_qr_and_inverse(rl, d, n, cplx):
