@@ -470,9 +470,13 @@ __global__ __launch_bounds__(NW * 64) void k_tsqr_cw(const T* __restrict__ P0, i
 }
 
 template <typename T, int TT>
-struct CwCfg {  // waves, rows per lane of the column-wave TSQR (64 register values per lane)
-  static constexpr int NW = 4;
-  static constexpr int RPL = (TT == 32 ? 8 : 16) / (sizeof(T) == 16 ? 2 : 1);
+struct CwCfg {  // waves, rows per lane of the column-wave TSQR
+  // 16 real values per lane and column (tiles of 1024 real or 512 complex
+  // rows); the waves split the columns, fewer per wave the more there are to
+  // update (one or two complex columns per wave at t > 16, within the 128
+  // registers a 1024-thread workgroup allows)
+  static constexpr int NW = sizeof(T) == 16 ? (TT == 32 ? 16 : 8) : (TT == 32 ? 8 : 4);
+  static constexpr int RPL = 16 / (int)(sizeof(T) / 8);
 };
 
 static int64_t tsqr_cw_fresh(int t, bool cplx) {
