@@ -28,6 +28,29 @@ constexpr int TS_TMAX = 32;
 __device__ inline double ts_im(double) { return 0.0; }
 __device__ inline double ts_im(cd a) { return a.y; }
 
+// Householder coefficients for a real beta with |beta| = |(alpha, x)| and the
+// sign opposite to re(alpha): tau = (beta - alpha) / beta and
+// sc = 1 / (alpha - beta), the scale of the reflector's tail.  For complex
+// alpha the quotient by alpha - beta = z takes one real reciprocal,
+// conj(z) / |z|^2, where |z|^2 is representable (|re z| = |re alpha| + |beta|
+// bounds |z| within a factor sqrt(2)), else Smith's quotient.
+__device__ inline void hh_coef(double alpha, double beta, double& tau, double& sc) {
+  tau = (beta - alpha) / beta;
+  sc = 1.0 / (alpha - beta);
+}
+__device__ inline void hh_coef(cd alpha, double beta, cd& tau, cd& sc) {
+  const double ib = 1.0 / beta;
+  tau = cd{(beta - alpha.x) * ib, -alpha.y * ib};
+  const double zx = alpha.x - beta, zy = alpha.y;
+  const double az = fabs(zx);
+  if (az > 1e-140 && az < 1e140) {
+    const double iz = 1.0 / (zx * zx + zy * zy);
+    sc = cd{zx * iz, -zy * iz};
+  } else {
+    sc = divs(cd{1.0, 0.0}, cd{zx, zy});
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Register TSQR for t <= 8: a wave holds a tile of 64*RPL rows, RPL rows per
 // lane (t values each in registers).  Rows 0..t-1 of the tile (lanes 0..t-1,
@@ -78,8 +101,8 @@ __device__ __forceinline__ void tw_tile_qr(T (&x)[RPL][TT], int t, int lane) {
     if (noref) continue;  // the column is already zero below the diagonal
     const double nrm = sqrt(abs2(alpha) + n2);
     const double beta = (re_(alpha) >= 0.0) ? -nrm : nrm;
-    const T tau = divs(sub(from_real<T>(beta), alpha), from_real<T>(beta));
-    const T sc = divs(from_real<T>(1.0), sub(alpha, from_real<T>(beta)));
+    T tau, sc;
+    hh_coef(alpha, beta, tau, sc);
     const T ct = conj_(tau), csc = conj_(sc);
     T v[RPL];
 #pragma unroll
@@ -371,8 +394,8 @@ __global__ __launch_bounds__(NW * 64) void k_tsqr_cw(const T* __restrict__ P0, i
     }
     const double nrm = sqrt(abs2(alpha) + n2);
     const double beta = (re_(alpha) >= 0.0) ? -nrm : nrm;
-    const T tau = divs(sub(from_real<T>(beta), alpha), from_real<T>(beta));
-    const T sc = divs(from_real<T>(1.0), sub(alpha, from_real<T>(beta)));
+    T tau, sc;
+    hh_coef(alpha, beta, tau, sc);
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
       const int r = lane + 64 * s;
@@ -410,10 +433,12 @@ __global__ __launch_bounds__(NW * 64) void k_tsqr_cw(const T* __restrict__ P0, i
         if (j >= t) break;
         __syncthreads();
         const T ct = tbuf[j & 1];
-        if (!(re_(ct) == 0.0 && ts_im(ct) == 0.0)) {
-          T v[RPL];
+        // the reflector is read before the test so the loads overlap; a wave
+        // whose columns all lie left of j + 1 has nothing to update
+        T v[RPL];
 #pragma unroll
-          for (int s = 0; s < RPL; ++s) v[s] = vbuf[j & 1][lane + 64 * s];
+        for (int s = 0; s < RPL; ++s) v[s] = vbuf[j & 1][lane + 64 * s];
+        if (wave + NW * (CPW - 1) > j && !(re_(ct) == 0.0 && ts_im(ct) == 0.0)) {
           double ys[NV];
 #pragma unroll
           for (int q = 0; q < NV; ++q) ys[q] = 0.0;
