@@ -422,10 +422,16 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
   void* AVcur = at<void>(ws, L.AV);
   void* AVoth = at<void>(ws, L.AV2);
   for (; it < o.max_iter; ++it) {
-    if (late && it > 0) {
-      // A_X <- A_T C_X with the previous iteration's A_T (its A_V is AVoth)
-      CK(launch_panel(st, cplx, AVoth, at<void>(ws, L.AX), at<void>(ws, L.AW), m, B, at<void>(ws, L.CV),
+    const bool x_beside = late && it > 0;
+    if (x_beside) {
+      // A_X <- A_T C_X with the previous iteration's A_T (its A_V is AVoth),
+      // on the second stream beside the preconditioner and Orth, which touch
+      // only n-side blocks; A W overwrites A_W, so it waits for the join
+      CK(hipEventRecord(h->fork, st));
+      CK(hipStreamWaitEvent(h->aux, h->fork, 0));
+      CK(launch_panel(h->aux, cplx, AVoth, at<void>(ws, L.AX), at<void>(ws, L.AW), m, B, at<void>(ws, L.CV),
                       at<void>(ws, L.CX), ctl, 2));
+      CK(hipEventRecord(h->join, h->aux));
     } else {
       CK(launch_panel(st, cplx, AVcur, at<void>(ws, L.AX), at<void>(ws, L.AW), m, B, at<void>(ws, L.CV),
                       at<void>(ws, L.CX), ctl));
@@ -446,6 +452,7 @@ static int solve(rl_ctx* h, bool cplx, int64_t m, int64_t n, const void* A, int6
     else
       CK(launch_orth(st, cplx, (int)n, B, at<void>(ws, L.V), at<void>(ws, L.X), 1, with_x, at<void>(ws, L.W), ctl,
                      1, 1));
+    if (x_beside) CK(hipStreamWaitEvent(st, h->join, 0));
     if (prof) CK(hipEventRecord(h->prof[4 * nprof], st));
     if (late) {
       // A W; TSQR of [A_V A_X A_W]; the Rayleigh-Ritz and V_new; the new
