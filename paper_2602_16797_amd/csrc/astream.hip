@@ -80,50 +80,83 @@ __global__ __launch_bounds__(256) void k_panel(const T* AV, T* AVout, T* AX, con
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = wave_index();
   T* slot = stage[wave];
-  const T* panels[3] = {AV, mode == 2 ? AX : (mode == 1 ? AW : nullptr), mode == 2 ? AW : nullptr};
   const int64_t nchunk = (m + 63) / 64;
-  for (int64_t ch = (int64_t)blockIdx.x * 4 + wave; ch < nchunk; ch += (int64_t)gridDim.x * 4) {
-    const int64_t r0 = ch * 64;
-    const int cnt = (int)((m - r0 < 64 ? m - r0 : 64) * B);  // values of the chunk per panel
-    if constexpr (ONE) {
-      // one output block (pmode 1 or 2): the panels are consumed one at a
-      // time into B accumulators, so only B values of the row are live
-      const T* Cm = vupd ? CV : CX;
-      T* out = vupd ? AVout : AX;
-      if (!vupd && !xupd) continue;
-      T acc[B];
-#pragma unroll
-      for (int j = 0; j < B; ++j) acc[j] = zero<T>();
-#pragma unroll
-      for (int p = 0; p < 3; ++p) {
-        const T* P = panels[p];
-        if (P == nullptr) continue;
-#pragma unroll
-        for (int u = 0; u < B; ++u) {
-          const int e = lane + 64 * u;
-          slot[e] = (e < cnt) ? P[r0 * B + e] : zero<T>();
-        }
-        wave_lds_sync();
-        T at[B];
-#pragma unroll
-        for (int c = 0; c < B; ++c) at[c] = slot[lane * B + c];
-        wave_lds_sync();
-#pragma unroll
-        for (int j = 0; j < B; ++j)
-#pragma unroll
-          for (int c = 0; c < B; ++c) acc[j] = fmac(at[c], Cm[(p * B + c) * B + j], acc[j]);
-      }
-#pragma unroll
-      for (int j = 0; j < B; ++j) slot[lane * B + j] = acc[j];
-      wave_lds_sync();
+  if constexpr (ONE) {
+    // one output block (pmode 1 or 2): the panels are consumed one at a time
+    // into B accumulators, so only B values of the row are live, and the
+    // next (chunk, panel) unit is loaded while the current one is added
+    const T* Cm = vupd ? CV : CX;
+    T* out = vupd ? AVout : AX;
+    if (!vupd && !xupd) return;
+    const int np = (mode == 0) ? 1 : (mode == 1 ? 2 : 3);
+    const T* P1 = mode == 2 ? AX : AW;
+    const T* P2 = AW;
+    const int64_t stride = (int64_t)gridDim.x * 4;
+    int64_t ch = (int64_t)blockIdx.x * 4 + wave;
+    if (ch >= nchunk) return;
+    auto load = [&](T (&v)[B], int64_t c, const T* P) __attribute__((always_inline)) {
+      const int64_t r0 = c * 64;
+      const int cnt = (int)((m - r0 < 64 ? m - r0 : 64) * B);
 #pragma unroll
       for (int u = 0; u < B; ++u) {
         const int e = lane + 64 * u;
-        if (e < cnt) out[r0 * B + e] = slot[e];
+        v[u] = (e < cnt) ? P[r0 * B + e] : zero<T>();
+      }
+    };
+    T cur[B], acc[B];
+    load(cur, ch, AV);
+#pragma unroll
+    for (int j = 0; j < B; ++j) acc[j] = zero<T>();
+    int p = 0;
+    for (;;) {
+      // the unit's values go to the slot, and the registers take the next
+      // unit's loads, which stay in flight while this one is added
+#pragma unroll
+      for (int u = 0; u < B; ++u) slot[lane + 64 * u] = cur[u];
+      int pn = p + 1;
+      int64_t chn = ch;
+      if (pn == np) {
+        pn = 0;
+        chn = ch + stride;
+      }
+      const bool more = chn < nchunk;
+      if (more) load(cur, chn, pn == 0 ? AV : (pn == 1 ? P1 : P2));
+      wave_lds_sync();
+      // row values read back one at a time (a rolled loop keeps the
+      // coefficient reads from being hoisted into registers)
+      const T* Cp = Cm + p * B * B;
+#pragma unroll 1
+      for (int c = 0; c < B; ++c) {
+        const T a = slot[lane * B + c];
+#pragma unroll
+        for (int j = 0; j < B; ++j) acc[j] = fmac(a, Cp[c * B + j], acc[j]);
       }
       wave_lds_sync();
-      continue;
+      if (p == np - 1) {
+        // the lane's output row through the slot, then coalesced stores
+        const int64_t r0 = ch * 64;
+        const int cnt = (int)((m - r0 < 64 ? m - r0 : 64) * B);
+#pragma unroll
+        for (int j = 0; j < B; ++j) slot[lane * B + j] = acc[j];
+        wave_lds_sync();
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          const int e = lane + 64 * u;
+          if (e < cnt) out[r0 * B + e] = slot[e];
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int j = 0; j < B; ++j) acc[j] = zero<T>();
+      }
+      if (!more) break;
+      p = pn;
+      ch = chn;
     }
+  } else {
+  const T* panels[3] = {AV, mode == 2 ? AX : (mode == 1 ? AW : nullptr), mode == 2 ? AW : nullptr};
+  for (int64_t ch = (int64_t)blockIdx.x * 4 + wave; ch < nchunk; ch += (int64_t)gridDim.x * 4) {
+    const int64_t r0 = ch * 64;
+    const int cnt = (int)((m - r0 < 64 ? m - r0 : 64) * B);  // values of the chunk per panel
     T at[3 * B];
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
@@ -162,6 +195,7 @@ __global__ __launch_bounds__(256) void k_panel(const T* AV, T* AVout, T* AX, con
     };
     if (vupd) emit(CV, AVout);
     if (xupd) emit(CX, AX);
+  }
   }
 }
 
