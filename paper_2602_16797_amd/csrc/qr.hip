@@ -71,8 +71,7 @@ __global__ __launch_bounds__(QR_THREADS) void k_qr_panel(T* Y, int ld, int d, in
     if (!noref) {
       const double nrm = sqrt(abs2(alpha) + xs);
       beta = (re_(alpha) >= 0.0) ? -nrm : nrm;
-      tau = divs(sub(from_real<T>(beta), alpha), from_real<T>(beta));
-      sc = divs(from_real<T>(1.0), sub(alpha, from_real<T>(beta)));
+      hh_coef(alpha, beta, tau, sc);
     }
     __syncthreads();  // alpha read by all before it is overwritten
     if (!noref) {
@@ -176,8 +175,7 @@ __global__ __launch_bounds__(QRP_THREADS) void k_qr_panel_reg(T* Y, int ld, int 
     if (!noref) {
       const double nrm = sqrt(abs2(alpha) + xs);
       beta = (re_(alpha) >= 0.0) ? -nrm : nrm;
-      tau = divs(sub(from_real<T>(beta), alpha), from_real<T>(beta));
-      sc = divs(from_real<T>(1.0), sub(alpha, from_real<T>(beta)));
+      hh_coef(alpha, beta, tau, sc);
     }
     // v (the reflector), row by row: 1 at rel == jj, scaled entries below, 0 above
     T v[RPT];
@@ -312,8 +310,7 @@ __global__ __launch_bounds__(NW * 64) void k_qr_panel_cw(T* Y, int ld, int d, in
     if (!noref) {
       const double nrm = sqrt(abs2(alpha) + n2);
       beta = (re_(alpha) >= 0.0) ? -nrm : nrm;
-      tau = divs(sub(from_real<T>(beta), alpha), from_real<T>(beta));
-      sc = divs(from_real<T>(1.0), sub(alpha, from_real<T>(beta)));
+      hh_coef(alpha, beta, tau, sc);
     }
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
@@ -919,9 +916,8 @@ constexpr int QR_TM_UPD = QR_TM_LEAVES + 16 * QR_NB * QR_NB;      // leaf-update
 constexpr int QR_TM_GRAM = QR_TM_UPD + QRL_MAXBLK * QR_NB * 4;    // Gram partials
 static_assert(QR_TM_GRAM + QRL_MAXBLK * QRT_THREADS <= QR_TM_ELEMS, "T workspace");
 
-template <typename T>
-static void qr_panel_leaves(hipStream_t st, T* Y, int d, int p, int nb, T* Tm) {
-  constexpr int LW = (sizeof(T) == 16) ? 2 : 4;
+template <typename T, int LW, int RPT>
+static void qr_panel_leaves_go(hipStream_t st, T* Y, int d, int p, int nb, T* Tm) {
   static_assert(QR_NB / LW <= 16 && LW <= 4, "leaf T factors and partials fit the T workspace");
   T* Tleaf = Tm + QR_TM_LEAVES;
   T* upd = Tm + QR_TM_UPD;
@@ -929,7 +925,7 @@ static void qr_panel_leaves(hipStream_t st, T* Y, int d, int p, int nb, T* Tm) {
   for (int q = 0; q < nb; q += LW) {
     const int lw = min(LW, nb - q);
     T* Tq = Tleaf + (int64_t)(q / LW) * QR_NB * QR_NB;
-    hipLaunchKernelGGL((k_qr_panel_reg<T, 8, LW>), dim3(1), dim3(QRP_THREADS), 0, st, Y, d, d, p + q, lw, Tq);
+    hipLaunchKernelGGL((k_qr_panel_reg<T, RPT, LW>), dim3(1), dim3(QRP_THREADS), 0, st, Y, d, d, p + q, lw, Tq);
     const int c0 = p + q + lw, c1 = p + nb;
     if (c1 > c0) {  // the panel's own columns: full precision, as the panel kernels
       const int nblk = (d - (p + q) + QRL_ROWS - 1) / QRL_ROWS;
@@ -943,6 +939,19 @@ static void qr_panel_leaves(hipStream_t st, T* Y, int d, int p, int nb, T* Tm) {
   hipLaunchKernelGGL(k_qr_gram_part<T>, dim3(nblk), dim3(QRT_THREADS), 0, st, (const T*)Y, d, d, p, nb, gram);
   hipLaunchKernelGGL(k_qr_tfactor<T>, dim3(1), dim3(QRT_THREADS), 0, st, (const T*)gram, nblk, nb, (const T*)Tleaf,
                      LW, Tm);
+}
+
+// Leaves of 4 columns (complex: of 2 where the rows need 8 per thread, the
+// register budget of a 1024-thread workgroup): each leaf costs three launches
+// whatever its width.
+template <typename T>
+static void qr_panel_leaves(hipStream_t st, T* Y, int d, int p, int nb, T* Tm) {
+  if constexpr (sizeof(T) == 16) {
+    if (d - p <= QRP_THREADS * 4) qr_panel_leaves_go<T, 4, 4>(st, Y, d, p, nb, Tm);
+    else qr_panel_leaves_go<T, 2, 8>(st, Y, d, p, nb, Tm);
+  } else {
+    qr_panel_leaves_go<T, 4, 8>(st, Y, d, p, nb, Tm);
+  }
 }
 
 // Blocked Householder factorization of the d x n column-major Y in place.
