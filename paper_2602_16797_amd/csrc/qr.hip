@@ -17,6 +17,7 @@
 //   k_trinv      R^{-1} by column-oriented back substitution, one wave per
 //                column of the identity; writes R^{-1} and R^{-*} row-major.
 #include "common.hpp"
+#include "householder.hpp"
 #include "kernels.hpp"
 #include "tr_reduce.hpp"
 

@@ -17,6 +17,7 @@
 // workgroup tiles with the columns dealt out over the waves for 8 < t <= 32
 // (k_tsqr_cw).
 #include "common.hpp"
+#include "householder.hpp"
 #include "kernels.hpp"
 #include "colsum.hpp"
 #include "tr_reduce.hpp"
